@@ -1,0 +1,20 @@
+"""Shared pytest configuration: the ``gpu`` marker and seeded fixtures."""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long CPU run")
+
+
+@pytest.fixture
+def rng():
+    import numpy as np
+    return np.random.default_rng(12345)
