@@ -1,0 +1,163 @@
+/*
+ * ot_dyn.h -- C ABI of the MI355X (gfx950) dynamic optimal transport solver.
+ *
+ * The library runs Algorithm 1 of Fitschen, Laus and Steidl, "Dynamic
+ * Optimal Transport with Mixed Boundary Conditions for Color Image
+ * Processing" (the PDHG iteration of Sec. 3) on the staggered grid of Sec. 2
+ * extended to 4D (Remark 2): Neumann boundaries in x, y and time, periodic
+ * (by default) in the colour axis.  Each iteration is
+ *   Step 1  a = x - tau sigma K^T b_bar;  x = a - A^T (A A^T)^+ (A a - f_b^-)
+ *           (the pseudo-inverse by fast transforms, Sec. 3 and Remark 2),
+ *   Step 2  z = prox of J / sigma at K x + c + b (the cubic of Sec. 3),
+ *   Steps 3-4  b += K x + c - z;  b_bar = b + theta (b - b_old).
+ *
+ * Conventions for every entry point:
+ *   - All functions return an int status: 0 = OT_OK, < 0 an error, > 0 a
+ *     warning.  No exception or longjmp crosses this boundary.
+ *   - Pointers named f0, f1, F, Mx, My, Mc, workspace are DEVICE pointers
+ *     (hipMalloc'd or torch CUDA tensors on the plan's device).  Pointers to
+ *     ot_dyn_desc, ot_dyn_report and ot_dyn_plan* are HOST pointers.
+ *   - The library never allocates device memory: all device storage is the
+ *     caller's (state buffers and one workspace of ot_dyn_workspace_size
+ *     bytes, 256-byte aligned).  The plan object is host memory owned by the
+ *     library (ot_dyn_create / ot_dyn_destroy).
+ *   - A plan is bound to one HIP stream; calls on one plan must not overlap
+ *     from several host threads.
+ *
+ * Buffer layout (FP32, x fastest, `batch` independent problems of the same
+ * shape stacked outermost):
+ *   F   [batch][P+1][C][Y][X]  density at times k/P.  Slices 0 and P hold f0
+ *                              and f1 (written by ot_dyn_init, read-only to
+ *                              the solver); slices 1..P-1 are the unknowns.
+ *   Mx  [batch][P][C][Y][X]    x-momentum at half-time (k+1/2)/P; slot x is
+ *                              the face between cells x-1 and x.  Neumann:
+ *                              slot 0 is the wall and stays 0 (face X is
+ *                              implicit).  Periodic: slot 0 is the face
+ *                              between cells X-1 and 0.
+ *   My  [batch][P][C][Y][X]    same along y.
+ *   Mc  [batch][P][C][Y][X]    same along the colour axis.
+ */
+#ifndef OT_DYN_H
+#define OT_DYN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define OT_OK               0
+#define OT_NOT_CONVERGED    1   /* warning: max_iters reached before tolerance */
+#define OT_ERR_PARAM       -1   /* tau, sigma, theta, tolerances out of range  */
+#define OT_ERR_SHAPE       -2   /* sizes out of range or buffer too small      */
+#define OT_ERR_INPUT       -3   /* negative or non-finite density              */
+#define OT_ERR_MASS        -4   /* |M0 - M1| / M0 above tol_mass               */
+#define OT_ERR_HIP         -5   /* a HIP runtime call failed                   */
+#define OT_ERR_NONFINITE   -6   /* non-finite residual during the iteration    */
+#define OT_ERR_STATE       -7   /* call out of order (e.g. step before init)   */
+
+/* boundary condition of a spatial axis (Sec. 2: kappa = 1 Neumann, 0 periodic) */
+#define OT_BC_NEUMANN   0
+#define OT_BC_PERIODIC  1
+
+/* initialisation modes of ot_dyn_init */
+#define OT_INIT_COLD         0  /* Algorithm 1: m = 0, f = 0, b = b_bar = 0          */
+#define OT_INIT_PRIMAL       1  /* caller-filled (F, M), b = b_bar = 0               */
+#define OT_INIT_PRIMAL_DUAL  2  /* caller-filled (F, M); b = b_bar = grad J(Kx+c)/sigma */
+
+typedef struct ot_dyn_desc {
+    int X, Y, C, P;        /* grid: X x Y pixels, C channels, P time steps; an
+                              axis of size 1 is absent.  P >= 2.              */
+    int bc[3];             /* per spatial axis (x, y, colour): OT_BC_*        */
+    double extent[3];      /* physical length per spatial axis (default 1):
+                              the difference factor is size / extent          */
+    double tau, sigma;     /* step sizes, tau * sigma < 1 (Algorithm 1)       */
+    double theta;          /* extrapolation, 0 <= theta <= 1 (1 in the paper) */
+    int check_every;       /* ot_dyn_solve: residual check interval (>= 1)    */
+    double tol_res;        /* stop when max(r_prim, r_dual) < tol_res ...     */
+    double tol_div;        /* ... and r_div < tol_div                         */
+    double tol_mass;       /* admissible |M0 - M1| / M0 of the end densities  */
+    int refine;            /* projection refinement: 0 off, 1 every
+                              iteration, 2 once max(r_prim, r_dual) < 1e-4    */
+    int batch;             /* number of stacked problems of this shape (>= 1) */
+} ot_dyn_desc;
+
+typedef struct ot_dyn_report {
+    int iterations;        /* iterations run by this call                     */
+    int converged;         /* 1 if the tolerances were met                    */
+    int total_iterations;  /* iterations since the last ot_dyn_init           */
+    int worst_problem;     /* batch index with the largest residual           */
+    double r_prim;         /* ||Kx + c - z|| / ||z||          (max over batch) */
+    double r_dual;         /* ||x_new - x_old|| / ||x_new||   (max over batch) */
+    double r_div;          /* ||A x - f_b^-|| / ||f_b^-||     (max over batch) */
+    double cost;           /* cell volume * sum J(z)  (problem 0)             */
+    double e_mass;         /* max_k |sum f(., k/P) - M0| / M0 (max over batch) */
+    double mass0, mass1;   /* FP64 masses of f0 and f1 (problem 0)            */
+    double ms;             /* wall time of the call in milliseconds           */
+} ot_dyn_report;
+
+typedef struct ot_dyn_plan ot_dyn_plan;
+
+/* Fill *d with the defaults for an X x Y x C x P grid: bc = {Neumann,
+ * Neumann, periodic}, extent = 1, tau = 10, sigma = 0.099, theta = 1,
+ * check_every = 50, tol_res = 1e-6, tol_div = 1e-6, tol_mass = 1e-5,
+ * refine = 1, batch = 1. */
+int ot_dyn_default_desc(ot_dyn_desc* d, int X, int Y, int C, int P);
+
+/* Bytes of device workspace a plan for *d needs (OT_ERR_SHAPE/PARAM if *d
+ * is invalid). */
+int ot_dyn_workspace_size(const ot_dyn_desc* d, size_t* bytes);
+
+/* Create a plan for *d bound to `stream` (a hipStream_t; NULL = default
+ * stream) over the caller's device workspace of ws_bytes bytes.  Uploads
+ * the transform tables (DCT-II along Neumann axes, discrete Hartley along
+ * periodic axes -- a real basis that diagonalises the periodic Laplacian
+ * like the Fourier matrix of Sec. 3 -- and the eigenvalues of A A^T).
+ * On error *out is NULL. */
+int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace,
+                  size_t ws_bytes, ot_dyn_plan** out);
+
+/* Copy the end densities f0, f1 ([batch][C][Y][X], device) into the plan
+ * (Sec. 2: f^0, f^1 >= 0 with equal l1 mass), compute their FP64 masses and
+ * check them.  Returns OT_ERR_INPUT for a negative or non-finite value and
+ * OT_ERR_MASS when |M0 - M1| / M0 > tol_mass; synchronises the stream. */
+int ot_dyn_set_boundary(ot_dyn_plan* p, const float* f0, const float* f1);
+
+/* Initialise the iteration state.  Writes slices 0 and P of F, the Neumann
+ * wall slots of Mx/My/Mc and, for OT_INIT_COLD, zeros the unknowns
+ * (Algorithm 1 initialisation).  The duals live in the workspace. */
+int ot_dyn_init(ot_dyn_plan* p, int mode, float* F, float* Mx, float* My, float* Mc);
+
+/* Run `iters` iterations of Algorithm 1 on the plan's stream without host
+ * synchronisation.  (F, Mx, My, Mc) must be the buffers passed to
+ * ot_dyn_init (or copies of them); they are updated in place. */
+int ot_dyn_step(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc, int iters);
+
+/* Iterate until certified (max(r_prim, r_dual) < tol_res and r_div <
+ * tol_div, checked every check_every iterations) or max_iters.  Returns
+ * OT_OK when certified, OT_NOT_CONVERGED otherwise, OT_ERR_NONFINITE on a
+ * non-finite residual.  Synchronous.  rep may be NULL. */
+int ot_dyn_solve(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
+                 int max_iters, ot_dyn_report* rep);
+
+/* Residuals of the current state: runs one iteration with the residual
+ * reductions enabled (FP64 accumulation) and fills *rep.  Synchronous. */
+int ot_dyn_residuals(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
+                     ot_dyn_report* rep);
+
+/* Release the plan (host memory only; device buffers stay the caller's). */
+int ot_dyn_destroy(ot_dyn_plan* p);
+
+/* Static description of a status code. */
+const char* ot_dyn_status_str(int status);
+
+/* Last error message recorded on the plan (never NULL). */
+const char* ot_dyn_last_error(const ot_dyn_plan* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OT_DYN_H */

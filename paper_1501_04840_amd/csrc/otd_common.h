@@ -1,0 +1,99 @@
+// Shared declarations of the HIP kernels and the host plan code.
+//
+// Layout (FP32, x fastest, batch outermost):
+//   centred fields   [B][P][C][Y][X]   (duals b, b_bar, the residual r / phi,
+//                                       the staggered work arrays a_*)
+//   F                [B][P+1][C][Y][X] (times 0..P; 0 and P are f0 and f1)
+//   Mx, My, Mc       [B][P][C][Y][X]   (slot i = face between cells i-1, i)
+// The work array a_f uses the centred shape with slice k holding time k
+// (slot 0 unused), so that a_f and F share (k, c, y, x) offsets.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace otd {
+
+struct Geom {
+    int B, X, Y, C, P;
+    int perx, pery, perc;        // 1 if the axis is periodic (size > 1 only)
+    float sx, sy, sc, st;        // difference factors n / extent, P
+    long long plane;             // X * Y
+    long long slice;             // C * X * Y
+    long long nc;                // P * slice   (centred, per problem)
+    long long nf;                // (P + 1) * slice (F, per problem)
+};
+
+// Reduction slots written by the update kernel (one FP64 partial per block).
+enum RedSlot {
+    RS_DB2 = 0,     // sum |b_new - b|^2  = |K x + c - z|^2
+    RS_Z2,          // sum |z|^2
+    RS_DX2,         // sum |x_new - x_old|^2
+    RS_X2,          // sum |x_new|^2
+    RS_J,           // sum J(z)
+    RS_COUNT
+};
+
+// Transform tables (device), one set per axis; `n` = 1 means absent.
+struct AxisTab {
+    int n;
+    int periodic;
+    const float* mat;    // n x n forward matrix M[j][k] (row j = frequency)
+    const float* lam;    // n eigenvalues of A A^T along this axis
+};
+
+struct StepArgs {
+    Geom g;
+    float tau_sigma;     // tau * sigma
+    float sigma;
+    float theta;
+    // state
+    float* F; float* Mx; float* My; float* Mc;
+    float* b[4]; float* bb[4];
+    float* A[4];         // staggered work arrays a_x, a_y, a_c, a_f
+    float* R;            // residual r, transformed in place into phi
+    double* part_slice;  // [B*P*C][nbx] FP64 slice sums of r
+    double* part_red;    // [RS_COUNT][B][P*C*nbx] FP64 residual partials
+    double* part_mass;   // [B*P*C][nbx] FP64 slice sums of f_new
+    double* part_div;    // [B*P*C][nbx] FP64 sum of (A x - f_b^-)^2
+    int nbx;             // blocks per (b, k, c) slice in the stencil kernels
+};
+
+// ---- stencil kernels (stencil.hip) -------------------------------------
+// mode 0: a from (x, b_bar); writes A and r.  mode 1: a = A (refinement).
+void launch_div(const StepArgs& s, int mode, hipStream_t st);
+// x = a + grad(phi) in place in A (first half of a refined projection).
+void launch_grad_inplace(const StepArgs& s, hipStream_t st);
+// x = a + grad(phi), prox, dual update; residual partials if `check`.
+void launch_update(const StepArgs& s, int check, hipStream_t st);
+// FP64 partials of |A x - f_b^-|^2 and of the slice masses of F.
+void launch_resid_div(const StepArgs& s, hipStream_t st);
+// Boundary slices, wall slots and (optionally) zero unknowns.
+void launch_init_state(const StepArgs& s, const float* f0, const float* f1,
+                       int zero_unknowns, hipStream_t st);
+// b = b_bar = grad J(K x + c) / sigma from a caller-filled primal.
+void launch_init_dual(const StepArgs& s, hipStream_t st);
+// zero the dual fields
+void launch_zero_dual(const StepArgs& s, hipStream_t st);
+// FP64 mass partials and input checks of f0, f1 ([B][C][Y][X]).
+void launch_boundary_stats(const Geom& g, const float* f0, const float* f1,
+                           double* part, int nblk, hipStream_t st);
+
+// ---- transforms (transform.hip) ----------------------------------------
+// Forward or inverse orthonormal transform along x (contiguous rows).
+void launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStream_t st);
+// Forward or inverse transform along a strided axis: data [outer][L][inner].
+void launch_cols(float* R, long long outer, long long inner, const AxisTab& t,
+                 int inverse, hipStream_t st);
+// Colour and time transforms, division by the eigenvalues of A A^T, inverse
+// transforms; the spatial-DC line is solved in FP64 from the slice sums.
+void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
+               const AxisTab& tc, const AxisTab& tt, const double* tc64,
+               const double* tt64, const double* part_slice, int nbx,
+               hipStream_t st);
+
+// ---- reductions (stencil.hip) ------------------------------------------
+// out[q] = sum_j part[q * n + j] in FP64, for q < nq.
+void launch_reduce(const double* part, long long n, int nq, double* out, hipStream_t st);
+
+}  // namespace otd

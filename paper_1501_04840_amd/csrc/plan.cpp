@@ -1,0 +1,569 @@
+// Host side of the C ABI: plan creation over a caller-owned workspace, the
+// launch sequence of one PDHG iteration (Algorithm 1 of the paper, Sec. 3),
+// FP64 residual reductions and the certified solve loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ot_dyn.h"
+#include "otd_common.h"
+
+using namespace otd;
+
+struct ot_dyn_plan {
+    ot_dyn_desc d;
+    Geom g;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    // workspace carve
+    float* b[4];
+    float* bb[4];
+    float* A[4];
+    float* R;
+    float* f0;
+    float* f1;
+    AxisTab tab[4];          // x, y, c, t
+    double* tc64;
+    double* tt64;
+    double* part_slice;
+    double* part_red;
+    double* part_div;
+    double* part_mass;
+    double* part_bnd;
+    double* red_out;
+    int nbx;
+    int nblk_bnd;
+    // host state
+    bool have_boundary;
+    bool have_init;
+    int total_iters;
+    std::vector<double> mass0, mass1, fbm2;
+    std::vector<double> r_prim, r_dual, r_div, cost, e_mass;
+    double last_res;         // max(r_prim, r_dual) of the last check
+    std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t off_b, off_bb, off_A, off_R, off_f, off_tab[4], off_tc64, off_tt64;
+    size_t off_pslice, off_pred, off_pdiv, off_pmass, off_pbnd, off_red;
+    size_t total;
+    int nbx, nblk_bnd;
+};
+
+int axis_size(const ot_dyn_desc& d, int a) { return a == 0 ? d.X : (a == 1 ? d.Y : d.C); }
+
+Geom make_geom(const ot_dyn_desc& d) {
+    Geom g;
+    g.B = d.batch; g.X = d.X; g.Y = d.Y; g.C = d.C; g.P = d.P;
+    g.perx = d.X > 1 && d.bc[0] == OT_BC_PERIODIC;
+    g.pery = d.Y > 1 && d.bc[1] == OT_BC_PERIODIC;
+    g.perc = d.C > 1 && d.bc[2] == OT_BC_PERIODIC;
+    g.sx = (float)(d.X / d.extent[0]);
+    g.sy = (float)(d.Y / d.extent[1]);
+    g.sc = (float)(d.C / d.extent[2]);
+    g.st = (float)d.P;
+    g.plane = (long long)d.X * d.Y;
+    g.slice = g.plane * d.C;
+    g.nc = g.slice * d.P;
+    g.nf = g.slice * (d.P + 1);
+    return g;
+}
+
+int validate(const ot_dyn_desc* d, std::string* why) {
+    if (!d) { if (why) *why = "null descriptor"; return OT_ERR_PARAM; }
+    if (d->X < 1 || d->Y < 1 || d->C < 1 || d->P < 2 || d->batch < 1) {
+        if (why) *why = "sizes must satisfy X, Y, C >= 1, P >= 2, batch >= 1";
+        return OT_ERR_SHAPE;
+    }
+    if (d->X > 8192 || d->Y > 8192 || d->C > 64 || d->P > 1024 ||
+        (long long)d->P * d->C > 8192) {
+        if (why) *why = "sizes beyond the supported range (X, Y <= 8192, C <= 64, P <= 1024, P*C <= 8192)";
+        return OT_ERR_SHAPE;
+    }
+    const long long slices = (long long)d->batch * d->P * d->C;
+    if (slices > 65535) {
+        if (why) *why = "batch * P * C must not exceed 65535";
+        return OT_ERR_SHAPE;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (d->bc[a] != OT_BC_NEUMANN && d->bc[a] != OT_BC_PERIODIC) {
+            if (why) *why = "bc must be OT_BC_NEUMANN or OT_BC_PERIODIC";
+            return OT_ERR_PARAM;
+        }
+        if (!(d->extent[a] > 0.0) || !std::isfinite(d->extent[a])) {
+            if (why) *why = "extent must be positive and finite";
+            return OT_ERR_PARAM;
+        }
+    }
+    if (!(d->tau > 0.0) || !(d->sigma > 0.0) || !(d->tau * d->sigma < 1.0) ||
+        !std::isfinite(d->tau) || !std::isfinite(d->sigma)) {
+        if (why) *why = "need tau > 0, sigma > 0 and tau * sigma < 1";
+        return OT_ERR_PARAM;
+    }
+    if (!(d->theta >= 0.0 && d->theta <= 1.0)) {
+        if (why) *why = "theta must lie in [0, 1]";
+        return OT_ERR_PARAM;
+    }
+    if (d->check_every < 1 || !(d->tol_res > 0.0) || !(d->tol_div > 0.0) ||
+        !(d->tol_mass >= 0.0) || d->refine < 0 || d->refine > 2) {
+        if (why) *why = "need check_every >= 1, tol_res > 0, tol_div > 0, tol_mass >= 0, refine in {0,1,2}";
+        return OT_ERR_PARAM;
+    }
+    return OT_OK;
+}
+
+Layout layout_of(const ot_dyn_desc& d) {
+    const Geom g = make_geom(d);
+    Layout L;
+    const long long ncT = (long long)g.B * g.nc;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    L.off_b = take(4 * ncT * sizeof(float));
+    L.off_bb = take(4 * ncT * sizeof(float));
+    L.off_A = take(4 * ncT * sizeof(float));
+    L.off_R = take(ncT * sizeof(float));
+    L.off_f = take(2 * (size_t)g.B * g.slice * sizeof(float));
+    const int ns[4] = {d.X, d.Y, d.C, d.P};
+    for (int a = 0; a < 4; ++a)
+        L.off_tab[a] = take((2 * (size_t)ns[a] * ns[a] + ns[a]) * sizeof(float));
+    L.off_tc64 = take(((size_t)d.C * d.C + d.C) * sizeof(double));
+    L.off_tt64 = take(((size_t)d.P * d.P + d.P) * sizeof(double));
+    L.nbx = (int)((g.plane + 255) / 256);
+    const size_t nslot = (size_t)g.B * g.P * g.C * L.nbx;
+    L.off_pslice = take(nslot * sizeof(double));
+    L.off_pred = take(RS_COUNT * nslot * sizeof(double));
+    L.off_pdiv = take(nslot * sizeof(double));
+    L.off_pmass = take(nslot * sizeof(double));
+    L.nblk_bnd = (int)std::min<long long>(64, (g.slice + 255) / 256);
+    L.off_pbnd = take(5 * (size_t)g.B * L.nblk_bnd * sizeof(double));
+    L.off_red = take(((size_t)RS_COUNT * g.B + g.B + (size_t)g.B * g.P + 5 * g.B) * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+// Orthonormal DCT-II (Neumann axis, Sec. 3: C_p) or discrete Hartley
+// (periodic axis) matrix M[j][k], built in FP64.
+void axis_matrix(int n, int periodic, std::vector<double>& M) {
+    M.assign((size_t)n * n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) {
+            double v;
+            if (periodic) {
+                const long long jk = ((long long)j * k) % n;
+                const double ang = 2.0 * pi * (double)jk / n;
+                v = (std::cos(ang) + std::sin(ang)) / std::sqrt((double)n);
+            } else {
+                const long long q = ((long long)j * (2 * k + 1)) % (4LL * n);
+                v = std::sqrt(2.0 / n) * std::cos(pi * (double)q / (2.0 * n));
+                if (j == 0) v /= std::sqrt(2.0);
+            }
+            M[(size_t)j * n + k] = v;
+        }
+}
+
+// Eigenvalues of s^2 Delta along one axis: 4 s^2 sin^2(pi j / n) periodic,
+// 4 s^2 sin^2(pi j / (2 n)) Neumann (Sec. 3).
+void axis_eigs(int n, int periodic, double s, std::vector<double>& lam) {
+    lam.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int j = 0; j < n; ++j) {
+        const double sn = std::sin(pi * j / (periodic ? n : 2.0 * n));
+        lam[j] = 4.0 * s * s * sn * sn;
+    }
+}
+
+int hip_fail(ot_dyn_plan* p, hipError_t e, const char* what) {
+    if (p) p->err = std::string(what) + ": " + hipGetErrorString(e);
+    return OT_ERR_HIP;
+}
+
+#define HIPCHK(p, call)                                  \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return hip_fail(p, e_, #call); \
+    } while (0)
+
+StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
+    StepArgs s;
+    s.g = p->g;
+    s.tau_sigma = (float)(p->d.tau * p->d.sigma);
+    s.sigma = (float)p->d.sigma;
+    s.theta = (float)p->d.theta;
+    s.F = F; s.Mx = Mx; s.My = My; s.Mc = Mc;
+    for (int q = 0; q < 4; ++q) { s.b[q] = p->b[q]; s.bb[q] = p->bb[q]; s.A[q] = p->A[q]; }
+    s.R = p->R;
+    s.part_slice = p->part_slice;
+    s.part_red = p->part_red;
+    s.part_mass = p->part_mass;
+    s.part_div = p->part_div;
+    s.nbx = p->nbx;
+    return s;
+}
+
+// phi = (A A^T)^+ r in place on R.
+void poisson(ot_dyn_plan* p) {
+    const Geom& g = p->g;
+    hipStream_t st = p->stream;
+    const long long B = g.B;
+    if (g.X > 1) launch_rows(p->R, B * g.P * g.C * g.Y, p->tab[0], 0, st);
+    if (g.Y > 1) launch_cols(p->R, B * g.P * g.C, g.X, p->tab[1], 0, st);
+    launch_tc(g, p->R, p->tab[0], p->tab[1], p->tab[2], p->tab[3], p->tc64, p->tt64,
+              p->part_slice, p->nbx, st);
+    if (g.Y > 1) launch_cols(p->R, B * g.P * g.C, g.X, p->tab[1], 1, st);
+    if (g.X > 1) launch_rows(p->R, B * g.P * g.C * g.Y, p->tab[0], 1, st);
+}
+
+bool refine_now(const ot_dyn_plan* p) {
+    if (p->d.refine == 1) return true;
+    if (p->d.refine == 2) return p->last_res < 1e-4;
+    return false;
+}
+
+// One iteration of Algorithm 1; residual partials when `check`.
+void iterate(ot_dyn_plan* p, const StepArgs& s, bool check) {
+    hipStream_t st = p->stream;
+    launch_div(s, 0, st);                  // a = x - tau sigma K^T b_bar, r = A a - f_b^-
+    poisson(p);                            // phi = (A A^T)^+ r
+    if (refine_now(p)) {                   // FP32 refinement of the projection
+        launch_grad_inplace(s, st);        // a <- a + grad phi
+        launch_div(s, 1, st);              // r' = A a - f_b^-
+        poisson(p);
+    }
+    launch_update(s, check ? 1 : 0, st);   // x = a + grad phi; prox; duals
+}
+
+// Reduce the residual partials of the last check iteration and of the
+// divergence/mass kernel, then fill the per-problem host arrays.
+int collect(ot_dyn_plan* p, const StepArgs& s, bool have_iter) {
+    const Geom& g = p->g;
+    hipStream_t st = p->stream;
+    const int B = g.B;
+    const long long nslot = (long long)g.P * g.C * p->nbx;       // per problem
+    launch_resid_div(s, st);
+    double* out_red = p->red_out;
+    double* out_div = out_red + RS_COUNT * B;
+    double* out_mass = out_div + B;
+    if (have_iter) launch_reduce(p->part_red, nslot, RS_COUNT * B, out_red, st);
+    launch_reduce(p->part_div, nslot, B, out_div, st);
+    launch_reduce(p->part_mass, (long long)g.C * p->nbx, B * g.P, out_mass, st);
+    std::vector<double> h((size_t)RS_COUNT * B + B + (size_t)B * g.P);
+    HIPCHK(p, hipMemcpyAsync(h.data(), out_red, h.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+    HIPCHK(p, hipGetLastError());
+    const double vol = [&] {
+        double v = 1.0 / g.P;
+        for (int a = 0; a < 3; ++a) v *= p->d.extent[a] / axis_size(p->d, a);
+        return v;
+    }();
+    bool finite = true;
+    for (int b = 0; b < B; ++b) {
+        if (have_iter) {
+            const double db2 = h[RS_DB2 * B + b], z2 = h[RS_Z2 * B + b];
+            const double dx2 = h[RS_DX2 * B + b], x2 = h[RS_X2 * B + b];
+            p->r_prim[b] = std::sqrt(db2) / std::max(std::sqrt(z2), 1e-300);
+            p->r_dual[b] = std::sqrt(dx2) / std::max(std::sqrt(x2), 1e-300);
+            p->cost[b] = vol * h[RS_J * B + b];
+        }
+        p->r_div[b] = std::sqrt(h[RS_COUNT * B + b]) / std::max(std::sqrt(p->fbm2[b]), 1e-300);
+        double em = 0.0;
+        for (int k = 1; k < g.P; ++k) {
+            const double mk = h[(size_t)RS_COUNT * B + B + (size_t)b * g.P + k];
+            em = std::max(em, std::fabs(mk - p->mass0[b]) / p->mass0[b]);
+            if (!std::isfinite(mk)) finite = false;
+        }
+        p->e_mass[b] = em;
+        if (!std::isfinite(p->r_prim[b]) || !std::isfinite(p->r_dual[b]) ||
+            !std::isfinite(p->r_div[b]) || !std::isfinite(p->cost[b]))
+            finite = false;
+    }
+    if (!finite) {
+        p->err = "non-finite residual";
+        return OT_ERR_NONFINITE;
+    }
+    return OT_OK;
+}
+
+void fill_report(const ot_dyn_plan* p, ot_dyn_report* rep) {
+    if (!rep) return;
+    const int B = p->g.B;
+    int worst = 0;
+    double wv = -1.0;
+    rep->r_prim = rep->r_dual = rep->r_div = rep->e_mass = 0.0;
+    for (int b = 0; b < B; ++b) {
+        rep->r_prim = std::max(rep->r_prim, p->r_prim[b]);
+        rep->r_dual = std::max(rep->r_dual, p->r_dual[b]);
+        rep->r_div = std::max(rep->r_div, p->r_div[b]);
+        rep->e_mass = std::max(rep->e_mass, p->e_mass[b]);
+        const double v = std::max(p->r_prim[b], p->r_dual[b]);
+        if (v > wv) { wv = v; worst = b; }
+    }
+    rep->worst_problem = worst;
+    rep->cost = p->cost[0];
+    rep->mass0 = p->mass0[0];
+    rep->mass1 = p->mass1[0];
+    rep->total_iterations = p->total_iters;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ot_dyn_default_desc(ot_dyn_desc* d, int X, int Y, int C, int P) {
+    if (!d) return OT_ERR_PARAM;
+    std::memset(d, 0, sizeof(*d));
+    d->X = X; d->Y = Y; d->C = C; d->P = P;
+    d->bc[0] = OT_BC_NEUMANN; d->bc[1] = OT_BC_NEUMANN; d->bc[2] = OT_BC_PERIODIC;
+    d->extent[0] = d->extent[1] = d->extent[2] = 1.0;
+    d->tau = 10.0; d->sigma = 0.099; d->theta = 1.0;
+    d->check_every = 50;
+    d->tol_res = 1e-6; d->tol_div = 1e-6; d->tol_mass = 1e-5;
+    d->refine = 1;
+    d->batch = 1;
+    return OT_OK;
+}
+
+int ot_dyn_workspace_size(const ot_dyn_desc* d, size_t* bytes) {
+    const int st = validate(d, nullptr);
+    if (st != OT_OK) return st;
+    if (!bytes) return OT_ERR_PARAM;
+    *bytes = layout_of(*d).total;
+    return OT_OK;
+}
+
+int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws_bytes,
+                  ot_dyn_plan** out) {
+    if (!out) return OT_ERR_PARAM;
+    *out = nullptr;
+    const int st = validate(d, nullptr);
+    if (st != OT_OK) return st;
+    const Layout L = layout_of(*d);
+    if (!workspace || ws_bytes < L.total || ((uintptr_t)workspace % kAlign) != 0)
+        return OT_ERR_SHAPE;
+    ot_dyn_plan* p = new (std::nothrow) ot_dyn_plan();
+    if (!p) return OT_ERR_PARAM;
+    p->d = *d;
+    p->g = make_geom(*d);
+    p->stream = (hipStream_t)stream;
+    p->ws = (char*)workspace;
+    p->ws_bytes = ws_bytes;
+    const long long ncT = (long long)p->g.B * p->g.nc;
+    for (int q = 0; q < 4; ++q) {
+        p->b[q] = (float*)(p->ws + L.off_b) + q * ncT;
+        p->bb[q] = (float*)(p->ws + L.off_bb) + q * ncT;
+        p->A[q] = (float*)(p->ws + L.off_A) + q * ncT;
+    }
+    p->R = (float*)(p->ws + L.off_R);
+    p->f0 = (float*)(p->ws + L.off_f);
+    p->f1 = p->f0 + (long long)p->g.B * p->g.slice;
+    p->tc64 = (double*)(p->ws + L.off_tc64);
+    p->tt64 = (double*)(p->ws + L.off_tt64);
+    p->part_slice = (double*)(p->ws + L.off_pslice);
+    p->part_red = (double*)(p->ws + L.off_pred);
+    p->part_div = (double*)(p->ws + L.off_pdiv);
+    p->part_mass = (double*)(p->ws + L.off_pmass);
+    p->part_bnd = (double*)(p->ws + L.off_pbnd);
+    p->red_out = (double*)(p->ws + L.off_red);
+    p->nbx = L.nbx;
+    p->nblk_bnd = L.nblk_bnd;
+    const int B = p->g.B;
+    p->mass0.assign(B, 0); p->mass1.assign(B, 0); p->fbm2.assign(B, 0);
+    p->r_prim.assign(B, 0); p->r_dual.assign(B, 0); p->r_div.assign(B, 0);
+    p->cost.assign(B, 0); p->e_mass.assign(B, 0);
+    p->last_res = 1.0;
+    p->total_iters = 0;
+    p->have_boundary = p->have_init = false;
+
+    // transform tables, built in FP64 and uploaded once
+    const int ns[4] = {d->X, d->Y, d->C, d->P};
+    const int per[4] = {p->g.perx, p->g.pery, p->g.perc, 0};
+    const double sc[4] = {d->X / d->extent[0], d->Y / d->extent[1], d->C / d->extent[2],
+                          (double)d->P};
+    std::vector<double> M, lam;
+    for (int a = 0; a < 4; ++a) {
+        const int n = ns[a];
+        axis_matrix(n, per[a], M);
+        axis_eigs(n, per[a], sc[a], lam);
+        std::vector<float> h(2 * (size_t)n * n + n);
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                h[(size_t)k * n + j] = (float)M[(size_t)j * n + k];              // M^T
+                h[(size_t)n * n + (size_t)k * n + j] = (float)M[(size_t)k * n + j];  // M
+            }
+        for (int j = 0; j < n; ++j) h[2 * (size_t)n * n + j] = (float)lam[j];
+        float* dst = (float*)(p->ws + L.off_tab[a]);
+        hipError_t e = hipMemcpyAsync(dst, h.data(), h.size() * sizeof(float),
+                                      hipMemcpyHostToDevice, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) { delete p; return OT_ERR_HIP; }
+        p->tab[a].n = n;
+        p->tab[a].periodic = per[a];
+        p->tab[a].mat = dst;
+        p->tab[a].lam = dst + 2 * (size_t)n * n;
+        if (a == 2 || a == 3) {
+            std::vector<double> h64((size_t)n * n + n);
+            std::copy(M.begin(), M.end(), h64.begin());
+            std::copy(lam.begin(), lam.end(), h64.begin() + (size_t)n * n);
+            double* d64 = a == 2 ? p->tc64 : p->tt64;
+            e = hipMemcpyAsync(d64, h64.data(), h64.size() * sizeof(double),
+                               hipMemcpyHostToDevice, p->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+            if (e != hipSuccess) { delete p; return OT_ERR_HIP; }
+        }
+    }
+    *out = p;
+    return OT_OK;
+}
+
+int ot_dyn_set_boundary(ot_dyn_plan* p, const float* f0, const float* f1) {
+    if (!p || !f0 || !f1) return OT_ERR_PARAM;
+    const Geom& g = p->g;
+    const int B = g.B;
+    hipStream_t st = p->stream;
+    const size_t bytes = (size_t)B * g.slice * sizeof(float);
+    HIPCHK(p, hipMemcpyAsync(p->f0, f0, bytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(p, hipMemcpyAsync(p->f1, f1, bytes, hipMemcpyDeviceToDevice, st));
+    launch_boundary_stats(g, p->f0, p->f1, p->part_bnd, p->nblk_bnd, st);
+    launch_reduce(p->part_bnd, p->nblk_bnd, 5 * B, p->red_out, st);
+    std::vector<double> h(5 * (size_t)B);
+    HIPCHK(p, hipMemcpyAsync(h.data(), p->red_out, h.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+    HIPCHK(p, hipGetLastError());
+    p->have_boundary = false;
+    for (int b = 0; b < B; ++b) {
+        const double m0 = h[b], m1 = h[B + b], bad = h[2 * B + b];
+        if (bad > 0.0 || !std::isfinite(m0) || !std::isfinite(m1) || !(m0 > 0.0)) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "problem %d: negative or non-finite density (%.0f entries)", b, bad);
+            p->err = buf;
+            return OT_ERR_INPUT;
+        }
+        if (std::fabs(m0 - m1) / m0 > p->d.tol_mass) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "problem %d: |M0 - M1| / M0 = %.3e exceeds tol_mass", b,
+                          std::fabs(m0 - m1) / m0);
+            p->err = buf;
+            return OT_ERR_MASS;
+        }
+        p->mass0[b] = m0;
+        p->mass1[b] = m1;
+        p->fbm2[b] = (double)g.st * g.st * (h[3 * B + b] + h[4 * B + b]);
+    }
+    p->have_boundary = true;
+    return OT_OK;
+}
+
+int ot_dyn_init(ot_dyn_plan* p, int mode, float* F, float* Mx, float* My, float* Mc) {
+    if (!p || !F || !Mx || !My || !Mc) return OT_ERR_PARAM;
+    if (!p->have_boundary) { p->err = "ot_dyn_set_boundary must succeed first"; return OT_ERR_STATE; }
+    if (mode < OT_INIT_COLD || mode > OT_INIT_PRIMAL_DUAL) return OT_ERR_PARAM;
+    const StepArgs s = step_args(p, F, Mx, My, Mc);
+    launch_init_state(s, p->f0, p->f1, mode == OT_INIT_COLD ? 1 : 0, p->stream);
+    if (mode == OT_INIT_PRIMAL_DUAL) launch_init_dual(s, p->stream);
+    else launch_zero_dual(s, p->stream);
+    HIPCHK(p, hipGetLastError());
+    p->have_init = true;
+    p->total_iters = 0;
+    p->last_res = 1.0;
+    return OT_OK;
+}
+
+int ot_dyn_step(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc, int iters) {
+    if (!p || !F || !Mx || !My || !Mc || iters < 0) return OT_ERR_PARAM;
+    if (!p->have_init) { p->err = "ot_dyn_init must succeed first"; return OT_ERR_STATE; }
+    const StepArgs s = step_args(p, F, Mx, My, Mc);
+    for (int i = 0; i < iters; ++i) iterate(p, s, false);
+    p->total_iters += iters;
+    HIPCHK(p, hipGetLastError());
+    return OT_OK;
+}
+
+int ot_dyn_solve(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc, int max_iters,
+                 ot_dyn_report* rep) {
+    if (!p || !F || !Mx || !My || !Mc || max_iters < 1) return OT_ERR_PARAM;
+    if (!p->have_init) { p->err = "ot_dyn_init must succeed first"; return OT_ERR_STATE; }
+    const auto t0 = std::chrono::steady_clock::now();
+    const StepArgs s = step_args(p, F, Mx, My, Mc);
+    int done = 0, status = OT_NOT_CONVERGED;
+    while (done < max_iters) {
+        const int chunk = std::min(p->d.check_every, max_iters - done);
+        for (int i = 0; i + 1 < chunk; ++i) iterate(p, s, false);
+        iterate(p, s, true);
+        done += chunk;
+        p->total_iters += chunk;
+        const int cs = collect(p, s, true);
+        if (cs != OT_OK) { status = cs; break; }
+        double worst = 0.0, worst_div = 0.0;
+        for (int b = 0; b < p->g.B; ++b) {
+            worst = std::max(worst, std::max(p->r_prim[b], p->r_dual[b]));
+            worst_div = std::max(worst_div, p->r_div[b]);
+        }
+        p->last_res = worst;
+        if (worst < p->d.tol_res && worst_div < p->d.tol_div) { status = OT_OK; break; }
+    }
+    if (rep) {
+        fill_report(p, rep);
+        rep->iterations = done;
+        rep->converged = status == OT_OK;
+        rep->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+int ot_dyn_residuals(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
+                     ot_dyn_report* rep) {
+    if (!p || !F || !Mx || !My || !Mc) return OT_ERR_PARAM;
+    if (!p->have_init) { p->err = "ot_dyn_init must succeed first"; return OT_ERR_STATE; }
+    const auto t0 = std::chrono::steady_clock::now();
+    const StepArgs s = step_args(p, F, Mx, My, Mc);
+    const int cs = collect(p, s, false);
+    if (rep) {
+        fill_report(p, rep);
+        rep->iterations = 0;
+        rep->converged = 0;
+        rep->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return cs;
+}
+
+int ot_dyn_destroy(ot_dyn_plan* p) {
+    delete p;
+    return OT_OK;
+}
+
+const char* ot_dyn_status_str(int status) {
+    switch (status) {
+        case OT_OK: return "ok";
+        case OT_NOT_CONVERGED: return "not converged within max_iters";
+        case OT_ERR_PARAM: return "invalid parameter";
+        case OT_ERR_SHAPE: return "invalid shape or buffer size";
+        case OT_ERR_INPUT: return "negative or non-finite input density";
+        case OT_ERR_MASS: return "masses of f0 and f1 differ beyond tol_mass";
+        case OT_ERR_HIP: return "HIP runtime error";
+        case OT_ERR_NONFINITE: return "non-finite residual";
+        case OT_ERR_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+const char* ot_dyn_last_error(const ot_dyn_plan* p) {
+    return p ? p->err.c_str() : "null plan";
+}
+
+}  // extern "C"

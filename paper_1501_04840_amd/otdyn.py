@@ -1,0 +1,246 @@
+"""Python binding of the ot_dyn C ABI (include/ot_dyn.h).
+
+The functions below carry the C names and only marshal arguments: every step
+of the solver runs in the HIP kernels of libotdyn.so.  Device pointers may be
+given as torch CUDA tensors (their data_ptr is passed) or as integers.
+PyTorch is used for device memory and streams only.
+
+There is no CPU fallback: importing works without a GPU, but any call needs
+the built library and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libotdyn.so")
+
+OT_OK = 0
+OT_NOT_CONVERGED = 1
+OT_ERR_PARAM = -1
+OT_ERR_SHAPE = -2
+OT_ERR_INPUT = -3
+OT_ERR_MASS = -4
+OT_ERR_HIP = -5
+OT_ERR_NONFINITE = -6
+OT_ERR_STATE = -7
+
+OT_BC_NEUMANN = 0
+OT_BC_PERIODIC = 1
+
+OT_INIT_COLD = 0
+OT_INIT_PRIMAL = 1
+OT_INIT_PRIMAL_DUAL = 2
+
+
+class ot_dyn_desc(ctypes.Structure):
+    _fields_ = [
+        ("X", c_int), ("Y", c_int), ("C", c_int), ("P", c_int),
+        ("bc", c_int * 3),
+        ("extent", c_double * 3),
+        ("tau", c_double), ("sigma", c_double), ("theta", c_double),
+        ("check_every", c_int),
+        ("tol_res", c_double), ("tol_div", c_double), ("tol_mass", c_double),
+        ("refine", c_int),
+        ("batch", c_int),
+    ]
+
+
+class ot_dyn_report(ctypes.Structure):
+    _fields_ = [
+        ("iterations", c_int), ("converged", c_int), ("total_iterations", c_int),
+        ("worst_problem", c_int),
+        ("r_prim", c_double), ("r_dual", c_double), ("r_div", c_double),
+        ("cost", c_double), ("e_mass", c_double),
+        ("mass0", c_double), ("mass1", c_double), ("ms", c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class OtDynError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ot_dyn status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = [
+    "ot_dyn_default_desc", "ot_dyn_workspace_size", "ot_dyn_create",
+    "ot_dyn_set_boundary", "ot_dyn_init", "ot_dyn_step", "ot_dyn_solve",
+    "ot_dyn_residuals", "ot_dyn_destroy", "ot_dyn_status_str", "ot_dyn_last_error",
+]
+
+
+def lib() -> ctypes.CDLL:
+    """Load libotdyn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+            "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    L.ot_dyn_default_desc.argtypes = [POINTER(ot_dyn_desc), c_int, c_int, c_int, c_int]
+    L.ot_dyn_workspace_size.argtypes = [POINTER(ot_dyn_desc), POINTER(c_size_t)]
+    L.ot_dyn_create.argtypes = [POINTER(ot_dyn_desc), P, P, c_size_t, POINTER(c_void_p)]
+    L.ot_dyn_set_boundary.argtypes = [P, P, P]
+    L.ot_dyn_init.argtypes = [P, c_int, P, P, P, P]
+    L.ot_dyn_step.argtypes = [P, P, P, P, P, c_int]
+    L.ot_dyn_solve.argtypes = [P, P, P, P, P, c_int, POINTER(ot_dyn_report)]
+    L.ot_dyn_residuals.argtypes = [P, P, P, P, P, POINTER(ot_dyn_report)]
+    L.ot_dyn_destroy.argtypes = [P]
+    L.ot_dyn_status_str.argtypes = [c_int]
+    L.ot_dyn_status_str.restype = c_char_p
+    L.ot_dyn_last_error.argtypes = [P]
+    L.ot_dyn_last_error.restype = c_char_p
+    for name in EXPORTS:
+        if name not in ("ot_dyn_status_str", "ot_dyn_last_error"):
+            getattr(L, name).restype = c_int
+    _lib = L
+    return L
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _check(status: int, plan=None) -> int:
+    if status < 0:
+        L = lib()
+        msg = L.ot_dyn_status_str(status).decode()
+        if plan:
+            extra = L.ot_dyn_last_error(plan).decode()
+            if extra:
+                msg += f" ({extra})"
+        raise OtDynError(status, msg)
+    return status
+
+
+# ---- the C entry points ---------------------------------------------------
+
+def ot_dyn_default_desc(X: int, Y: int, C: int, P: int) -> ot_dyn_desc:
+    d = ot_dyn_desc()
+    _check(lib().ot_dyn_default_desc(byref(d), X, Y, C, P))
+    return d
+
+
+def ot_dyn_workspace_size(d: ot_dyn_desc) -> int:
+    n = c_size_t(0)
+    _check(lib().ot_dyn_workspace_size(byref(d), byref(n)))
+    return int(n.value)
+
+
+def ot_dyn_create(d: ot_dyn_desc, stream, workspace, ws_bytes: int) -> int:
+    out = c_void_p(0)
+    _check(lib().ot_dyn_create(byref(d), _ptr(stream), _ptr(workspace), ws_bytes, byref(out)))
+    return out.value
+
+
+def ot_dyn_set_boundary(plan: int, f0, f1) -> int:
+    return _check(lib().ot_dyn_set_boundary(plan, _ptr(f0), _ptr(f1)), plan)
+
+
+def ot_dyn_init(plan: int, mode: int, F, Mx, My, Mc) -> int:
+    return _check(lib().ot_dyn_init(plan, mode, _ptr(F), _ptr(Mx), _ptr(My), _ptr(Mc)), plan)
+
+
+def ot_dyn_step(plan: int, F, Mx, My, Mc, iters: int) -> int:
+    return _check(lib().ot_dyn_step(plan, _ptr(F), _ptr(Mx), _ptr(My), _ptr(Mc), iters), plan)
+
+
+def ot_dyn_solve(plan: int, F, Mx, My, Mc, max_iters: int):
+    rep = ot_dyn_report()
+    st = _check(lib().ot_dyn_solve(plan, _ptr(F), _ptr(Mx), _ptr(My), _ptr(Mc), max_iters,
+                                   byref(rep)), plan)
+    return st, rep
+
+
+def ot_dyn_residuals(plan: int, F, Mx, My, Mc):
+    rep = ot_dyn_report()
+    st = _check(lib().ot_dyn_residuals(plan, _ptr(F), _ptr(Mx), _ptr(My), _ptr(Mc),
+                                       byref(rep)), plan)
+    return st, rep
+
+
+def ot_dyn_destroy(plan: int) -> int:
+    return _check(lib().ot_dyn_destroy(plan))
+
+
+def ot_dyn_status_str(status: int) -> str:
+    return lib().ot_dyn_status_str(status).decode()
+
+
+def ot_dyn_last_error(plan: int) -> str:
+    return lib().ot_dyn_last_error(plan).decode()
+
+
+# ---- device buffers for one plan (torch for memory and streams only) -------
+
+class Problem:
+    """Owns the device buffers of one plan: F, Mx, My, Mc and the workspace.
+
+    Shapes follow the C layout: F [B, P+1, C, Y, X], M* [B, P, C, Y, X].
+    """
+
+    def __init__(self, desc: ot_dyn_desc, device="cuda", stream=None):
+        import torch
+        self.desc = desc
+        self.device = torch.device(device)
+        B, P, C, Y, X = desc.batch, desc.P, desc.C, desc.Y, desc.X
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.F = torch.zeros((B, P + 1, C, Y, X), **f32)
+        self.Mx = torch.zeros((B, P, C, Y, X), **f32)
+        self.My = torch.zeros((B, P, C, Y, X), **f32)
+        self.Mc = torch.zeros((B, P, C, Y, X), **f32)
+        self.ws_bytes = ot_dyn_workspace_size(desc)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.plan = ot_dyn_create(desc, self.stream.cuda_stream, self.ws_ptr, self.ws_bytes)
+
+    def state(self):
+        return (self.F, self.Mx, self.My, self.Mc)
+
+    def set_boundary(self, f0, f1):
+        import torch
+        B, C, Y, X = self.desc.batch, self.desc.C, self.desc.Y, self.desc.X
+        f0 = torch.as_tensor(f0, dtype=torch.float32).reshape(B, C, Y, X).to(self.device).contiguous()
+        f1 = torch.as_tensor(f1, dtype=torch.float32).reshape(B, C, Y, X).to(self.device).contiguous()
+        self._f0, self._f1 = f0, f1
+        torch.cuda.current_stream(self.device).synchronize()
+        return ot_dyn_set_boundary(self.plan, f0, f1)
+
+    def init(self, mode: int = OT_INIT_COLD):
+        return ot_dyn_init(self.plan, mode, *self.state())
+
+    def step(self, iters: int):
+        return ot_dyn_step(self.plan, *self.state(), iters)
+
+    def solve(self, max_iters: int):
+        return ot_dyn_solve(self.plan, *self.state(), max_iters)
+
+    def residuals(self):
+        return ot_dyn_residuals(self.plan, *self.state())
+
+    def close(self):
+        if getattr(self, "plan", None):
+            ot_dyn_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,88 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and the host-side validation rejects bad descriptors (no GPU call)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1501_04840_amd import otdyn
+    if not os.path.exists(otdyn.LIB_PATH):
+        from paper_1501_04840_amd import build
+        build.build()
+    return otdyn
+
+
+def _declared(header):
+    src = open(os.path.join(ROOT, "include", header)).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ot_\w+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    import ctypes
+    lib = ctypes.CDLL(L.LIB_PATH)
+    names = [n for h in os.listdir(os.path.join(ROOT, "include")) for n in _declared(h)]
+    assert "ot_dyn_create" in names and "ot_dyn_step" in names and "ot_dyn_solve" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_default_desc_and_workspace(L):
+    d = L.ot_dyn_default_desc(256, 256, 3, 32)
+    assert (d.X, d.Y, d.C, d.P) == (256, 256, 3, 32)
+    assert list(d.bc) == [L.OT_BC_NEUMANN, L.OT_BC_NEUMANN, L.OT_BC_PERIODIC]
+    assert d.tau * d.sigma < 1 and d.theta == 1.0 and d.batch == 1
+    n = L.ot_dyn_workspace_size(d)
+    N = 256 * 256 * 3 * 32
+    assert n >= 13 * N * 4          # b, b_bar, a (4 fields each) and r
+    assert n < 14 * N * 4 + (1 << 24)
+    d.batch = 3
+    assert L.ot_dyn_workspace_size(d) > 3 * 13 * N * 4
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("P", 1, -2), ("X", 0, -2), ("C", 100, -2), ("tau", 20.0, -1), ("sigma", -1.0, -1),
+    ("theta", 1.5, -1), ("check_every", 0, -1), ("refine", 3, -1), ("batch", 0, -2),
+])
+def test_descriptor_validation(L, field, value, status):
+    d = L.ot_dyn_default_desc(16, 16, 3, 8)
+    setattr(d, field, value)
+    with pytest.raises(L.OtDynError) as e:
+        L.ot_dyn_workspace_size(d)
+    assert e.value.status == status
+
+
+def test_bad_bc_and_extent(L):
+    d = L.ot_dyn_default_desc(16, 16, 3, 8)
+    d.bc[2] = 7
+    with pytest.raises(L.OtDynError):
+        L.ot_dyn_workspace_size(d)
+    d = L.ot_dyn_default_desc(16, 16, 3, 8)
+    d.extent[0] = 0.0
+    with pytest.raises(L.OtDynError):
+        L.ot_dyn_workspace_size(d)
+
+
+def test_create_rejects_small_or_misaligned_workspace(L):
+    d = L.ot_dyn_default_desc(16, 16, 3, 8)
+    n = L.ot_dyn_workspace_size(d)
+    with pytest.raises(L.OtDynError) as e:
+        L.ot_dyn_create(d, 0, 0, n)            # null workspace
+    assert e.value.status == L.OT_ERR_SHAPE
+    with pytest.raises(L.OtDynError) as e:
+        L.ot_dyn_create(d, 0, 1 << 20, n - 1)  # too small: rejected before any HIP call
+    assert e.value.status == L.OT_ERR_SHAPE
+    with pytest.raises(L.OtDynError) as e:
+        L.ot_dyn_create(d, 0, (1 << 20) + 8, n)  # misaligned
+    assert e.value.status == L.OT_ERR_SHAPE
+
+
+def test_status_strings(L):
+    for s in (0, 1, -1, -2, -3, -4, -5, -6, -7):
+        assert L.ot_dyn_status_str(s)
+    assert L.ot_dyn_status_str(-99) == "unknown status"

@@ -1,0 +1,265 @@
+"""GPU parity of the HIP solver against the FP64 CPU oracle, through the C ABI.
+
+Inputs are the seeded FP32-rounded densities of synth.inputs; the oracle gets
+the same arrays upcast to FP64.  Tolerance for floating-point results: 1e-5
+relative (L2) on the density and the transport cost, constraint residual
+below 1e-6 with the projection refinement on.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import grid as G
+from oracle import pdhg
+from synth import inputs
+from tests.layout import rel, to_natural
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def otdyn():
+    import torch
+    from paper_1501_04840_amd import otdyn as o
+    assert torch.cuda.is_available()
+    o.lib()
+    return o
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def run_gpu(o, g, f0, f1, iters, tau=10.0, sigma=0.099, refine=1, batch=None):
+    import torch
+    d = o.ot_dyn_default_desc(g.X, g.Y, g.C, g.P)
+    d.bc[0], d.bc[1], d.bc[2] = g.bc
+    d.tau, d.sigma, d.refine = tau, sigma, refine
+    B = 1 if batch is None else batch
+    d.batch = B
+    prob = o.Problem(d, "cuda")
+    f0t = torch.as_tensor(np.asarray(f0, np.float32)).reshape(B, g.C, g.Y, g.X)
+    f1t = torch.as_tensor(np.asarray(f1, np.float32)).reshape(B, g.C, g.Y, g.X)
+    prob.set_boundary(f0t, f1t)
+    prob.init(o.OT_INIT_COLD)
+    if iters > 0:
+        prob.step(iters)
+    torch.cuda.synchronize()
+    return prob
+
+
+def host(prob, b=0):
+    return tuple(t[b].double().cpu().numpy() for t in prob.state())
+
+
+def oracle(g, f0, f1, iters, tau=10.0, sigma=0.099):
+    return pdhg.solve(g, np.asarray(f0, np.float64), np.asarray(f1, np.float64), tau, sigma,
+                      iters, record_every=iters)
+
+
+SHAPES = [
+    # X, Y, C, P, bc, iterations
+    (16, 16, 3, 8, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),
+    (20, 13, 3, 5, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),   # ragged block tail
+    (7, 5, 3, 4, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),     # odd sizes
+    (12, 1, 1, 6, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),     # 1D Neumann
+    (9, 1, 1, 5, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),     # 1D periodic (hue-like)
+    (8, 6, 3, 4, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),      # Neumann colour
+    (6, 5, 2, 3, (G.PERIODIC, G.NEUMANN, G.PERIODIC), 12),    # periodic x, C = 2
+    (33, 31, 3, 6, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),   # several blocks + tail
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:4])))
+def test_iterates_match_oracle(otdyn, shape):
+    X, Y, C, P, bc, iters = shape
+    _say(f"parity shape {shape}")
+    g = G.Grid(X, Y, C, P, bc)
+    f0, f1 = inputs.random_pair(7 + X * Y + P, X, Y, C)
+    prob = run_gpu(otdyn, g, f0, f1, iters)
+    F, Mx, My, Mc = host(prob)
+    st = oracle(g, f0, f1, iters)
+    gx = to_natural(g, F, Mx, My, Mc)
+    assert rel(gx[3], st.x[3]) < TOL
+    for a in range(3):
+        if st.x[a].size:
+            assert rel(gx[a], st.x[a]) < TOL, a
+    # boundary slices untouched, Neumann walls zero
+    np.testing.assert_array_equal(F[0], f0.astype(np.float32))
+    np.testing.assert_array_equal(F[P], f1.astype(np.float32))
+    if g.axis_bc(0) == G.NEUMANN:
+        assert np.all(Mx[..., 0] == 0)
+    if g.axis_bc(2) == G.NEUMANN:
+        assert np.all(Mc[:, 0] == 0)
+    prob.close()
+
+
+def test_cfg1_300_iterations(otdyn):
+    """16 x 16 x 3 x 8, three anisotropic Gaussians per channel, 300 its."""
+    _say("cfg1 300 iterations")
+    g = G.Grid(16, 16, 3, 8)
+    f0, f1 = inputs.cfg1_pair()
+    prob = run_gpu(otdyn, g, f0, f1, 299)
+    st = oracle(g, f0, f1, 300)
+    _, rep = prob.solve(1)       # the 300th iteration, with residuals
+    F = host(prob)[0]
+    assert rel(F[1:8], st.x[3]) < TOL
+    h = st.hist[-1]
+    assert abs(rep.cost - h["cost"]) <= TOL * abs(h["cost"])
+    assert rep.r_div < 1e-6
+    assert rep.e_mass < 1e-6
+    assert abs(rep.r_prim - h["r_prim"]) <= 1e-3 * h["r_prim"] + 1e-7
+    prob.close()
+
+
+def test_cfg2_2000_iterations_against_stored_oracle(otdyn):
+    """64 x 64 x 3 x 16 RGB bumps, 2000 its, against values written by
+    tests/golden/make_golden.py (oracle only)."""
+    _say("cfg2 2000 iterations")
+    gold = json.load(open(os.path.join(HERE, "golden", "cfg2_2000.json")))
+    X, Y, C, P = gold["grid"]
+    g = G.Grid(X, Y, C, P)
+    f0, f1 = inputs.cfg2_pair()
+    prob = run_gpu(otdyn, g, f0, f1, gold["iters"] - 1, gold["tau"], gold["sigma"])
+    _, rep = prob.solve(1)
+    F = host(prob)[0]
+    f = F[1:P]
+    idx = np.asarray(gold["sample_index"])
+    assert rel(f.ravel()[idx], gold["sample_f"]) < TOL
+    assert abs(np.linalg.norm(f) - gold["f_norm"]) <= TOL * gold["f_norm"]
+    fn = [np.linalg.norm(f[k]) for k in range(P - 1)]
+    np.testing.assert_allclose(fn, gold["frame_norms"], rtol=TOL)
+    assert abs(rep.cost - gold["cost"]) <= TOL * gold["cost"]
+    assert rep.r_div < 1e-6
+    assert rep.e_mass < 1e-6
+    prob.close()
+
+
+def test_cfg3_full_size_iterations(otdyn):
+    """256 x 256 x 3 x 32 (the throughput workload, same launch shapes as the
+    benchmark): three iterations compared element by element."""
+    _say("cfg3 3 iterations")
+    g = G.Grid(256, 256, 3, 32)
+    f0, f1 = inputs.cfg3_pair()
+    prob = run_gpu(otdyn, g, f0, f1, 3)
+    gx = to_natural(g, *host(prob))
+    st = oracle(g, f0, f1, 3)
+    assert rel(gx[3], st.x[3]) < TOL
+    for a in range(3):
+        assert rel(gx[a], st.x[a]) < TOL, a
+    prob.close()
+
+
+def test_mass_and_divergence_invariants(otdyn):
+    _say("invariants")
+    g = G.Grid(32, 24, 3, 10)
+    f0, f1 = inputs.cfg2_pair(X=32, Y=24)
+    prob = run_gpu(otdyn, g, f0, f1, 49)
+    _, rep = prob.solve(1)
+    assert rep.r_div < 1e-6
+    assert rep.e_mass < 1e-6
+    F = host(prob)[0]
+    M0 = float(np.sum(f0, dtype=np.float64))
+    for k in range(1, g.P):
+        assert abs(F[k].sum() - M0) / M0 < 1e-6
+    prob.close()
+
+
+def test_time_reversal_and_colour_shift(otdyn):
+    _say("symmetries")
+    g = G.Grid(24, 20, 3, 8)
+    f0, f1 = inputs.cfg2_pair(X=24, Y=20)
+    a = host(run_gpu(otdyn, g, f0, f1, 60))
+    b = host(run_gpu(otdyn, g, f1, f0, 60))
+    assert rel(b[0][::-1], a[0]) < TOL
+    sh = lambda z: np.roll(z, 1, axis=-3)
+    c = host(run_gpu(otdyn, g, sh(f0), sh(f1), 60))
+    assert rel(c[0], sh(a[0])) < TOL
+    assert rel(c[3], sh(a[3])) < TOL
+
+
+def test_batch_equals_single_problems(otdyn):
+    _say("batch")
+    g = G.Grid(20, 16, 3, 6)
+    pairs = [inputs.random_pair(s, 20, 16) for s in (1, 2, 3)]
+    f0 = np.stack([p[0] for p in pairs])
+    f1 = np.stack([p[1] for p in pairs])
+    pb = run_gpu(otdyn, g, f0, f1, 25, batch=3)
+    for b in range(3):
+        ps = run_gpu(otdyn, g, f0[b], f1[b], 25)
+        for u, v in zip(host(pb, b), host(ps)):
+            np.testing.assert_array_equal(u, v)
+        ps.close()
+    pb.close()
+
+
+def test_determinism_and_resume(otdyn):
+    _say("determinism")
+    g = G.Grid(24, 20, 3, 8)
+    f0, f1 = inputs.cfg2_pair(X=24, Y=20)
+    a = host(run_gpu(otdyn, g, f0, f1, 30))
+    b = host(run_gpu(otdyn, g, f0, f1, 30))
+    p = run_gpu(otdyn, g, f0, f1, 10)
+    p.step(20)
+    import torch
+    torch.cuda.synchronize()
+    c = host(p)
+    for u, v, w in zip(a, b, c):
+        np.testing.assert_array_equal(u, v)
+        np.testing.assert_array_equal(u, w)
+
+
+def test_solve_certifies_and_reports(otdyn):
+    _say("certified solve")
+    import torch
+    g = G.Grid(16, 16, 3, 8)
+    f0, f1 = inputs.cfg1_pair()
+    d = otdyn.ot_dyn_default_desc(16, 16, 3, 8)
+    d.check_every = 100
+    prob = otdyn.Problem(d, "cuda")
+    prob.set_boundary(torch.from_numpy(f0), torch.from_numpy(f1))
+    prob.init()
+    status, rep = prob.solve(20000)
+    assert status == otdyn.OT_OK and rep.converged == 1
+    assert max(rep.r_prim, rep.r_dual) < 1e-6 and rep.r_div < 1e-6
+    st = oracle(g, f0, f1, rep.iterations)
+    assert abs(rep.cost - st.hist[-1]["cost"]) <= TOL * st.hist[-1]["cost"]
+    assert rel(host(prob)[0][1:8], st.x[3]) < TOL
+    prob.close()
+
+
+def test_error_paths(otdyn):
+    _say("error paths")
+    import torch
+    d = otdyn.ot_dyn_default_desc(8, 8, 3, 4)
+    prob = otdyn.Problem(d, "cuda")
+    with pytest.raises(otdyn.OtDynError) as e:
+        prob.step(1)
+    assert e.value.status == otdyn.OT_ERR_STATE
+    f0 = torch.ones(3, 8, 8)
+    f1 = torch.ones(3, 8, 8)
+    f1[0, 0, 0] = -1.0
+    with pytest.raises(otdyn.OtDynError) as e:
+        prob.set_boundary(f0, f1)
+    assert e.value.status == otdyn.OT_ERR_INPUT
+    f1 = torch.ones(3, 8, 8)
+    f1[1, 2, 3] = float("nan")
+    with pytest.raises(otdyn.OtDynError) as e:
+        prob.set_boundary(f0, f1)
+    assert e.value.status == otdyn.OT_ERR_INPUT
+    with pytest.raises(otdyn.OtDynError) as e:
+        prob.set_boundary(f0, 1.01 * torch.ones(3, 8, 8))
+    assert e.value.status == otdyn.OT_ERR_MASS
+    f1 = torch.ones(3, 8, 8)
+    f1[:, :4] = 1.5
+    f1[:, 4:] = 0.5
+    prob.set_boundary(f0, f1)
+    prob.init()
+    status, rep = prob.solve(3)
+    assert status == otdyn.OT_NOT_CONVERGED and rep.iterations == 3
+    prob.close()
