@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Throughput of the PDHG iteration on one MI355X.
+
+Workload: RGB transport at 256 x 256 x 3 colours x 32 time steps (Neumann x,
+y, t; periodic colour), seeded smooth random densities (Gaussian-filtered
+uniform noise, sigma 4 px, exponentiated, normalised).  A step is one full
+iteration of Algorithm 1 (projection with refinement, prox, dual steps).
+
+Prints one JSON line: cell-iters/s (cells = X Y C P centred nodes), the
+per-phase split measured with HIP events on the solver's stream, the HBM
+roofline of the dominant kernel and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
+
+# Algorithmic traffic of each phase in FP32 words per centred node and launch
+# (each array element read or written once): see the design doc.
+WORDS = {
+    "div": {0: 13, 1: 5},      # mode 0: read x (4) + b_bar (4), write a (4) + r (1)
+    "xform_x": 2, "xform_y": 2, "tc": 2,
+    "grad": 9,                 # read a (4) + phi (1), write a (4)
+    "update": 21,              # read a (4) + phi (1) + b (4), write x (4) + b (4) + b_bar (4)
+}
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1501_04840_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1501_04840_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("sources") != kernel_sources_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(f0, f1, X, Y, C, P, iters):
+    import numpy as np
+    from oracle import grid as G, pdhg
+    g = G.Grid(X, Y, C, P)
+    a0, a1 = f0.astype(np.float64), f1.astype(np.float64)
+    t0 = time.perf_counter()
+    pdhg.solve(g, a0, a1, 10.0, 0.099, iters)
+    dt = time.perf_counter() - t0
+    return {
+        "value": X * Y * C * P * iters / dt, "unit": "cell-iters/s", "cores": 1,
+        "kind": "oracle",
+        "sample": f"{iters} iterations of the {X}x{Y}x{C}x{P} workload, FP64 NumPy/SciPy oracle "
+                  f"(single-threaded), {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--refine", type=int, default=1)
+    ap.add_argument("--size", type=int, nargs=4, default=[256, 256, 3, 32],
+                    metavar=("X", "Y", "C", "P"))
+    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver has no "
+              "multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1501_04840_amd import otdyn
+    from synth import inputs
+
+    if not os.path.exists(otdyn.LIB_PATH):
+        from paper_1501_04840_amd import build
+        build.build()
+    X, Y, C, P = args.size
+    if (X, Y) == (256, 256):
+        f0, f1 = inputs.cfg3_pair()
+    else:
+        f0, f1 = inputs.cfg3_pair(X, Y)
+    N = X * Y * C * P
+    d = otdyn.ot_dyn_default_desc(X, Y, C, P)
+    d.refine = args.refine
+    prob = otdyn.Problem(d, "cuda:0")
+    prob.set_boundary(torch.from_numpy(f0), torch.from_numpy(f1))
+    prob.init(otdyn.OT_INIT_COLD)
+    prob.step(args.warmup)
+    torch.cuda.synchronize()
+
+    # timed region: every phase bracketed by HIP events on the solver stream
+    otdyn.ot_dyn_profile(prob.plan, (1 << otdyn.OT_PHASE_COUNT) - 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    phases = otdyn.ot_dyn_profile_read(prob.plan)
+    otdyn.ot_dyn_profile(prob.plan, 0)
+    _, rep = prob.residuals()
+    prob.close()
+
+    K = args.steps
+    words_per_iter = {
+        "div": WORDS["div"][0] + (WORDS["div"][1] if args.refine == 1 else 0),
+        "xform_x": 2 * 2 * (2 if args.refine == 1 else 1),
+        "xform_y": 2 * 2 * (2 if args.refine == 1 else 1),
+        "tc": 2 * (2 if args.refine == 1 else 1),
+        "grad": WORDS["grad"] if args.refine == 1 else 0,
+        "update": WORDS["update"],
+    }
+    split = {}
+    for name, (ms, n) in phases.items():
+        if n == 0:
+            continue
+        gbs = words_per_iter[name] * 4.0 * N * K / (ms * 1e-3) / 1e9
+        split[name] = {"ms_per_iter": ms / K, "launches": n, "avg_launch_us": 1e3 * ms / n,
+                       "algorithmic_GBs": gbs}
+    dom = max(split, key=lambda k: split[k]["ms_per_iter"])
+    per_launch_bytes = words_per_iter[dom] * 4.0 * N * K / split[dom]["launches"]
+    achieved = per_launch_bytes / (split[dom]["avg_launch_us"] * 1e-6) / 1e9
+    kernel_name = {"div": "k_div", "xform_x": "k_rows", "xform_y": "k_cols", "tc": "k_tc",
+                   "grad": "k_grad_inplace", "update": "k_update"}[dom]
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name),
+            "kernel": kernel_name, "algorithmic_bytes_per_launch": per_launch_bytes}
+    iter_bytes = sum(words_per_iter.values()) * 4.0 * N
+    out = {
+        "metric": "cell-iters/s at 256x256x3x32",
+        "value": N * K / dt,
+        "unit": "cell-iters/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": f"rgb_{X}x{Y}x{C}x{P}", "X": X, "Y": Y, "C": C, "P": P,
+            "bc": "neumann x,y,t; periodic colour", "refine": args.refine,
+            "tau": d.tau, "sigma": d.sigma, "iteration_GBs_algorithmic": iter_bytes * K / dt / 1e9,
+            "iteration_hbm_frac": iter_bytes * K / dt / 1e9 / HBM_PEAK_GBS,
+            "phases": split, "r_div": rep.r_div, "e_mass": rep.e_mass,
+        },
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(f0, f1, X, Y, C, P, args.cpu_iters)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

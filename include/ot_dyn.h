@@ -147,6 +147,26 @@ int ot_dyn_solve(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
 int ot_dyn_residuals(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
                      ot_dyn_report* rep);
 
+/* ---- phase timing ----------------------------------------------------
+ * When a phase is enabled, every launch of it by ot_dyn_step / ot_dyn_solve
+ * is bracketed by two HIP events recorded on the plan's stream.  Phases:   */
+#define OT_PHASE_DIV      0  /* adjoint averages and divergence: a, r (Step 1)    */
+#define OT_PHASE_XFORM_X  1  /* transforms along x (forward and inverse)          */
+#define OT_PHASE_XFORM_Y  2  /* transforms along y (forward and inverse)          */
+#define OT_PHASE_TC       3  /* colour/time transforms and eigenvalue division    */
+#define OT_PHASE_GRAD     4  /* refinement: a += grad phi                         */
+#define OT_PHASE_UPDATE   5  /* x = a + grad phi, prox, dual steps (Steps 2-4)    */
+#define OT_PHASE_COUNT    6
+
+/* Enable event timing for the phases in bit mask `mask` (0 disables) and
+ * reset the accumulators. */
+int ot_dyn_profile(ot_dyn_plan* p, int mask);
+
+/* Synchronise the stream and return, per phase (n <= OT_PHASE_COUNT
+ * entries), the accumulated milliseconds and launch counts since the last
+ * ot_dyn_profile call.  ms and launches are host arrays of n entries. */
+int ot_dyn_profile_read(ot_dyn_plan* p, double* ms, long long* launches, int n);
+
 /* Release the plan (host memory only; device buffers stay the caller's). */
 int ot_dyn_destroy(ot_dyn_plan* p);
 

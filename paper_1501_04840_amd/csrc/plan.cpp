@@ -49,6 +49,13 @@ struct ot_dyn_plan {
     std::vector<double> r_prim, r_dual, r_div, cost, e_mass;
     double last_res;         // max(r_prim, r_dual) of the last check
     std::string err;
+    // phase timing
+    int prof_mask;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_phase;   // phase of each recorded (start, stop) pair
+    size_t ev_used;              // events in use (2 per launch)
+    double prof_ms[OT_PHASE_COUNT];
+    long long prof_n[OT_PHASE_COUNT];
 };
 
 namespace {
@@ -215,17 +222,44 @@ StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     return s;
 }
 
+hipEvent_t next_event(ot_dyn_plan* p) {
+    if (p->ev_used == p->ev_pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p->ev_pool.push_back(e);
+    }
+    return p->ev_pool[p->ev_used++];
+}
+
+// Launch `fn`, bracketed by events when `phase` is being timed.
+template <class Fn>
+void timed(ot_dyn_plan* p, int phase, Fn&& fn) {
+    if (!((p->prof_mask >> phase) & 1)) { fn(); return; }
+    hipEvent_t a = next_event(p), b = next_event(p);
+    if (!a || !b) { fn(); return; }
+    hipEventRecord(a, p->stream);
+    fn();
+    hipEventRecord(b, p->stream);
+    p->ev_phase.push_back(phase);
+}
+
 // phi = (A A^T)^+ r in place on R.
 void poisson(ot_dyn_plan* p) {
     const Geom& g = p->g;
     hipStream_t st = p->stream;
     const long long B = g.B;
-    if (g.X > 1) launch_rows(p->R, B * g.P * g.C * g.Y, p->tab[0], 0, st);
-    if (g.Y > 1) launch_cols(p->R, B * g.P * g.C, g.X, p->tab[1], 0, st);
-    launch_tc(g, p->R, p->tab[0], p->tab[1], p->tab[2], p->tab[3], p->tc64, p->tt64,
-              p->part_slice, p->nbx, st);
-    if (g.Y > 1) launch_cols(p->R, B * g.P * g.C, g.X, p->tab[1], 1, st);
-    if (g.X > 1) launch_rows(p->R, B * g.P * g.C * g.Y, p->tab[0], 1, st);
+    if (g.X > 1)
+        timed(p, OT_PHASE_XFORM_X, [&] { launch_rows(p->R, B * g.P * g.C * g.Y, p->tab[0], 0, st); });
+    if (g.Y > 1)
+        timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(p->R, B * g.P * g.C, g.X, p->tab[1], 0, st); });
+    timed(p, OT_PHASE_TC, [&] {
+        launch_tc(g, p->R, p->tab[0], p->tab[1], p->tab[2], p->tab[3], p->tc64, p->tt64,
+                  p->part_slice, p->nbx, st);
+    });
+    if (g.Y > 1)
+        timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(p->R, B * g.P * g.C, g.X, p->tab[1], 1, st); });
+    if (g.X > 1)
+        timed(p, OT_PHASE_XFORM_X, [&] { launch_rows(p->R, B * g.P * g.C * g.Y, p->tab[0], 1, st); });
 }
 
 bool refine_now(const ot_dyn_plan* p) {
@@ -237,14 +271,16 @@ bool refine_now(const ot_dyn_plan* p) {
 // One iteration of Algorithm 1; residual partials when `check`.
 void iterate(ot_dyn_plan* p, const StepArgs& s, bool check) {
     hipStream_t st = p->stream;
-    launch_div(s, 0, st);                  // a = x - tau sigma K^T b_bar, r = A a - f_b^-
+    // a = x - tau sigma K^T b_bar, r = A a - f_b^-
+    timed(p, OT_PHASE_DIV, [&] { launch_div(s, 0, st); });
     poisson(p);                            // phi = (A A^T)^+ r
     if (refine_now(p)) {                   // FP32 refinement of the projection
-        launch_grad_inplace(s, st);        // a <- a + grad phi
-        launch_div(s, 1, st);              // r' = A a - f_b^-
+        timed(p, OT_PHASE_GRAD, [&] { launch_grad_inplace(s, st); });   // a <- a + grad phi
+        timed(p, OT_PHASE_DIV, [&] { launch_div(s, 1, st); });          // r' = A a - f_b^-
         poisson(p);
     }
-    launch_update(s, check ? 1 : 0, st);   // x = a + grad phi; prox; duals
+    // x = a + grad phi; prox; duals
+    timed(p, OT_PHASE_UPDATE, [&] { launch_update(s, check ? 1 : 0, st); });
 }
 
 // Reduce the residual partials of the last check iteration and of the
@@ -388,6 +424,9 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->last_res = 1.0;
     p->total_iters = 0;
     p->have_boundary = p->have_init = false;
+    p->prof_mask = 0;
+    p->ev_used = 0;
+    for (int q = 0; q < OT_PHASE_COUNT; ++q) { p->prof_ms[q] = 0.0; p->prof_n[q] = 0; }
 
     // transform tables, built in FP64 and uploaded once
     const int ns[4] = {d->X, d->Y, d->C, d->P};
@@ -542,7 +581,35 @@ int ot_dyn_residuals(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
     return cs;
 }
 
+int ot_dyn_profile(ot_dyn_plan* p, int mask) {
+    if (!p) return OT_ERR_PARAM;
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    p->prof_mask = mask;
+    p->ev_used = 0;
+    p->ev_phase.clear();
+    for (int q = 0; q < OT_PHASE_COUNT; ++q) { p->prof_ms[q] = 0.0; p->prof_n[q] = 0; }
+    return OT_OK;
+}
+
+int ot_dyn_profile_read(ot_dyn_plan* p, double* ms, long long* launches, int n) {
+    if (!p || n < 0 || n > OT_PHASE_COUNT || (n > 0 && (!ms || !launches))) return OT_ERR_PARAM;
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    for (size_t i = 0; i < p->ev_phase.size(); ++i) {
+        float t = 0.f;
+        HIPCHK(p, hipEventElapsedTime(&t, p->ev_pool[2 * i], p->ev_pool[2 * i + 1]));
+        p->prof_ms[p->ev_phase[i]] += t;
+        p->prof_n[p->ev_phase[i]] += 1;
+    }
+    p->ev_phase.clear();
+    p->ev_used = 0;
+    for (int q = 0; q < n; ++q) { ms[q] = p->prof_ms[q]; launches[q] = p->prof_n[q]; }
+    return OT_OK;
+}
+
 int ot_dyn_destroy(ot_dyn_plan* p) {
+    if (!p) return OT_OK;
+    (void)hipStreamSynchronize(p->stream);
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     delete p;
     return OT_OK;
 }

@@ -30,6 +30,15 @@ OT_ERR_STATE = -7
 OT_BC_NEUMANN = 0
 OT_BC_PERIODIC = 1
 
+OT_PHASE_DIV = 0
+OT_PHASE_XFORM_X = 1
+OT_PHASE_XFORM_Y = 2
+OT_PHASE_TC = 3
+OT_PHASE_GRAD = 4
+OT_PHASE_UPDATE = 5
+OT_PHASE_COUNT = 6
+PHASE_NAMES = ["div", "xform_x", "xform_y", "tc", "grad", "update"]
+
 OT_INIT_COLD = 0
 OT_INIT_PRIMAL = 1
 OT_INIT_PRIMAL_DUAL = 2
@@ -73,6 +82,7 @@ EXPORTS = [
     "ot_dyn_default_desc", "ot_dyn_workspace_size", "ot_dyn_create",
     "ot_dyn_set_boundary", "ot_dyn_init", "ot_dyn_step", "ot_dyn_solve",
     "ot_dyn_residuals", "ot_dyn_destroy", "ot_dyn_status_str", "ot_dyn_last_error",
+    "ot_dyn_profile", "ot_dyn_profile_read",
 ]
 
 
@@ -96,6 +106,8 @@ def lib() -> ctypes.CDLL:
     L.ot_dyn_solve.argtypes = [P, P, P, P, P, c_int, POINTER(ot_dyn_report)]
     L.ot_dyn_residuals.argtypes = [P, P, P, P, P, POINTER(ot_dyn_report)]
     L.ot_dyn_destroy.argtypes = [P]
+    L.ot_dyn_profile.argtypes = [P, c_int]
+    L.ot_dyn_profile_read.argtypes = [P, POINTER(c_double), POINTER(ctypes.c_longlong), c_int]
     L.ot_dyn_status_str.argtypes = [c_int]
     L.ot_dyn_status_str.restype = c_char_p
     L.ot_dyn_last_error.argtypes = [P]
@@ -171,6 +183,18 @@ def ot_dyn_residuals(plan: int, F, Mx, My, Mc):
     st = _check(lib().ot_dyn_residuals(plan, _ptr(F), _ptr(Mx), _ptr(My), _ptr(Mc),
                                        byref(rep)), plan)
     return st, rep
+
+
+def ot_dyn_profile(plan: int, mask: int) -> int:
+    return _check(lib().ot_dyn_profile(plan, mask), plan)
+
+
+def ot_dyn_profile_read(plan: int):
+    """{phase name: (milliseconds, launches)} accumulated since ot_dyn_profile."""
+    ms = (c_double * OT_PHASE_COUNT)()
+    n = (ctypes.c_longlong * OT_PHASE_COUNT)()
+    _check(lib().ot_dyn_profile_read(plan, ms, n, OT_PHASE_COUNT), plan)
+    return {PHASE_NAMES[i]: (ms[i], n[i]) for i in range(OT_PHASE_COUNT)}
 
 
 def ot_dyn_destroy(plan: int) -> int:
