@@ -29,10 +29,10 @@ FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
 # Algorithmic traffic of each phase in FP32 words per centred node and launch
 # (each array element read or written once): see the design doc.
 WORDS = {
-    "div": {0: 13, 1: 5},      # mode 0: read x (4) + b_bar (4), write a (4) + r (1)
+    "div": 13,                 # read x (4) + b_bar (4), write a (4) + r (1)
     "xform_x": 2, "xform_y": 2, "tc": 2,
-    "grad": 9,                 # read a (4) + phi (1), write a (4)
-    "update": 21,              # read a (4) + phi (1) + b (4), write x (4) + b (4) + b_bar (4)
+    "refine": 6,               # read a (4) + phi_1 (1), write r' (1)
+    "update": {1: 21, 2: 22},  # read a (4) + phi(s) + b (4), write x (4) + b (4) + b_bar (4)
 }
 
 
@@ -125,12 +125,12 @@ def main():
 
     K = args.steps
     words_per_iter = {
-        "div": WORDS["div"][0] + (WORDS["div"][1] if args.refine == 1 else 0),
+        "div": WORDS["div"],
         "xform_x": 2 * 2 * (2 if args.refine == 1 else 1),
         "xform_y": 2 * 2 * (2 if args.refine == 1 else 1),
         "tc": 2 * (2 if args.refine == 1 else 1),
-        "grad": WORDS["grad"] if args.refine == 1 else 0,
-        "update": WORDS["update"],
+        "refine": WORDS["refine"] if args.refine == 1 else 0,
+        "update": WORDS["update"][2 if args.refine == 1 else 1],
     }
     split = {}
     for name, (ms, n) in phases.items():
@@ -142,8 +142,8 @@ def main():
     dom = max(split, key=lambda k: split[k]["ms_per_iter"])
     per_launch_bytes = words_per_iter[dom] * 4.0 * N * K / split[dom]["launches"]
     achieved = per_launch_bytes / (split[dom]["avg_launch_us"] * 1e-6) / 1e9
-    kernel_name = {"div": "k_div", "xform_x": "k_rows", "xform_y": "k_cols", "tc": "k_tc",
-                   "grad": "k_grad_inplace", "update": "k_update"}[dom]
+    kernel_name = {"div": "k_div<0>", "xform_x": "k_rows_fft", "xform_y": "k_cols_fft",
+                   "tc": "k_tc_reg", "refine": "k_div<1>", "update": "k_update"}[dom]
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name),
             "kernel": kernel_name, "algorithmic_bytes_per_launch": per_launch_bytes}

@@ -154,8 +154,8 @@ int ot_dyn_residuals(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
 #define OT_PHASE_XFORM_X  1  /* transforms along x (forward and inverse)          */
 #define OT_PHASE_XFORM_Y  2  /* transforms along y (forward and inverse)          */
 #define OT_PHASE_TC       3  /* colour/time transforms and eigenvalue division    */
-#define OT_PHASE_GRAD     4  /* refinement: a += grad phi                         */
-#define OT_PHASE_UPDATE   5  /* x = a + grad phi, prox, dual steps (Steps 2-4)    */
+#define OT_PHASE_REFINE   4  /* refinement: residual of a + grad phi_1           */
+#define OT_PHASE_UPDATE   5  /* x = a + grad phi(s), prox, dual steps (Steps 2-4) */
 #define OT_PHASE_COUNT    6
 
 /* Enable event timing for the phases in bit mask `mask` (0 disables) and

@@ -40,6 +40,7 @@ struct AxisTab {
     int periodic;
     const float* mat;    // n x n forward matrix M[j][k] (row j = frequency)
     const float* lam;    // n eigenvalues of A A^T along this axis
+    const float2* tw;    // fast path: tw[j] = e^{-i pi j / (2n)}, j < 4n; else null
 };
 
 struct StepArgs {
@@ -51,8 +52,9 @@ struct StepArgs {
     float* F; float* Mx; float* My; float* Mc;
     float* b[4]; float* bb[4];
     float* A[4];         // staggered work arrays a_x, a_y, a_c, a_f
-    float* R;            // residual r, transformed in place into phi
-    double* part_slice;  // [B*P*C][nbx] FP64 slice sums of r
+    float* R;            // residual r, transformed in place into phi_1
+    float* R2;           // refinement: residual of x' = a + grad phi_1 -> phi_2
+    double* part_slice;  // [B*P*C][nbx] FP64 block partials of the plane sums of r
     double* part_red;    // [RS_COUNT][B][P*C*nbx] FP64 residual partials
     double* part_mass;   // [B*P*C][nbx] FP64 slice sums of f_new
     double* part_div;    // [B*P*C][nbx] FP64 sum of (A x - f_b^-)^2
@@ -60,12 +62,12 @@ struct StepArgs {
 };
 
 // ---- stencil kernels (stencil.hip) -------------------------------------
-// mode 0: a from (x, b_bar); writes A and r.  mode 1: a = A (refinement).
+// mode 0: a from (x, b_bar); writes A and r into R.  mode 1 (refinement):
+// residual of x' = A + grad R into R2.
 void launch_div(const StepArgs& s, int mode, hipStream_t st);
-// x = a + grad(phi) in place in A (first half of a refined projection).
-void launch_grad_inplace(const StepArgs& s, hipStream_t st);
-// x = a + grad(phi), prox, dual update; residual partials if `check`.
-void launch_update(const StepArgs& s, int check, hipStream_t st);
+// x = a + grad(phi_1) (+ grad(phi_2) if nphi == 2), prox, dual update;
+// residual partials if `check`.
+void launch_update(const StepArgs& s, int check, int nphi, hipStream_t st);
 // FP64 partials of |A x - f_b^-|^2 and of the slice masses of F.
 void launch_resid_div(const StepArgs& s, hipStream_t st);
 // Boundary slices, wall slots and (optionally) zero unknowns.
@@ -89,8 +91,13 @@ void launch_cols(float* R, long long outer, long long inner, const AxisTab& t,
 // transforms; the spatial-DC line is solved in FP64 from the slice sums.
 void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
                const AxisTab& tc, const AxisTab& tt, const double* tc64,
-               const double* tt64, const double* part_slice, int nbx,
-               hipStream_t st);
+               const double* tt64, const double* part_slice, int nbx, hipStream_t st);
+
+// Fast power-of-two passes (fastdct.hip); kind 0 DCT-II, 1 DCT-III, 2 Hartley.
+bool fast_len(int L);
+void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st);
+void launch_cols_fast(float* R, long long outer, long long inner, int L, const float2* tw, int kind,
+                      hipStream_t st);
 
 // ---- reductions (stencil.hip) ------------------------------------------
 // out[q] = sum_j part[q * n + j] in FP64, for q < nq.

@@ -28,6 +28,7 @@ struct ot_dyn_plan {
     float* bb[4];
     float* A[4];
     float* R;
+    float* R2;
     float* f0;
     float* f1;
     AxisTab tab[4];          // x, y, c, t
@@ -65,7 +66,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t off_b, off_bb, off_A, off_R, off_f, off_tab[4], off_tc64, off_tt64;
+    size_t off_b, off_bb, off_A, off_R, off_R2, off_f, off_tab[4], off_tw[4], off_tc64, off_tt64;
     size_t off_pslice, off_pred, off_pdiv, off_pmass, off_pbnd, off_red;
     size_t total;
     int nbx, nblk_bnd;
@@ -143,10 +144,13 @@ Layout layout_of(const ot_dyn_desc& d) {
     L.off_bb = take(4 * ncT * sizeof(float));
     L.off_A = take(4 * ncT * sizeof(float));
     L.off_R = take(ncT * sizeof(float));
+    L.off_R2 = take(ncT * sizeof(float));
     L.off_f = take(2 * (size_t)g.B * g.slice * sizeof(float));
     const int ns[4] = {d.X, d.Y, d.C, d.P};
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
         L.off_tab[a] = take((2 * (size_t)ns[a] * ns[a] + ns[a]) * sizeof(float));
+        L.off_tw[a] = take(4 * (size_t)ns[a] * 2 * sizeof(float));
+    }
     L.off_tc64 = take(((size_t)d.C * d.C + d.C) * sizeof(double));
     L.off_tt64 = take(((size_t)d.P * d.P + d.P) * sizeof(double));
     L.nbx = (int)((g.plane + 255) / 256);
@@ -214,6 +218,7 @@ StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     s.F = F; s.Mx = Mx; s.My = My; s.Mc = Mc;
     for (int q = 0; q < 4; ++q) { s.b[q] = p->b[q]; s.bb[q] = p->bb[q]; s.A[q] = p->A[q]; }
     s.R = p->R;
+    s.R2 = p->R2;
     s.part_slice = p->part_slice;
     s.part_red = p->part_red;
     s.part_mass = p->part_mass;
@@ -244,22 +249,22 @@ void timed(ot_dyn_plan* p, int phase, Fn&& fn) {
 }
 
 // phi = (A A^T)^+ r in place on R.
-void poisson(ot_dyn_plan* p) {
+void poisson(ot_dyn_plan* p, float* R) {
     const Geom& g = p->g;
     hipStream_t st = p->stream;
     const long long B = g.B;
     if (g.X > 1)
-        timed(p, OT_PHASE_XFORM_X, [&] { launch_rows(p->R, B * g.P * g.C * g.Y, p->tab[0], 0, st); });
+        timed(p, OT_PHASE_XFORM_X, [&] { launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 0, st); });
     if (g.Y > 1)
-        timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(p->R, B * g.P * g.C, g.X, p->tab[1], 0, st); });
+        timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(R, B * g.P * g.C, g.X, p->tab[1], 0, st); });
     timed(p, OT_PHASE_TC, [&] {
-        launch_tc(g, p->R, p->tab[0], p->tab[1], p->tab[2], p->tab[3], p->tc64, p->tt64,
+        launch_tc(g, R, p->tab[0], p->tab[1], p->tab[2], p->tab[3], p->tc64, p->tt64,
                   p->part_slice, p->nbx, st);
     });
     if (g.Y > 1)
-        timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(p->R, B * g.P * g.C, g.X, p->tab[1], 1, st); });
+        timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(R, B * g.P * g.C, g.X, p->tab[1], 1, st); });
     if (g.X > 1)
-        timed(p, OT_PHASE_XFORM_X, [&] { launch_rows(p->R, B * g.P * g.C * g.Y, p->tab[0], 1, st); });
+        timed(p, OT_PHASE_XFORM_X, [&] { launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 1, st); });
 }
 
 bool refine_now(const ot_dyn_plan* p) {
@@ -273,14 +278,15 @@ void iterate(ot_dyn_plan* p, const StepArgs& s, bool check) {
     hipStream_t st = p->stream;
     // a = x - tau sigma K^T b_bar, r = A a - f_b^-
     timed(p, OT_PHASE_DIV, [&] { launch_div(s, 0, st); });
-    poisson(p);                            // phi = (A A^T)^+ r
-    if (refine_now(p)) {                   // FP32 refinement of the projection
-        timed(p, OT_PHASE_GRAD, [&] { launch_grad_inplace(s, st); });   // a <- a + grad phi
-        timed(p, OT_PHASE_DIV, [&] { launch_div(s, 1, st); });          // r' = A a - f_b^-
-        poisson(p);
+    poisson(p, p->R);                      // phi_1 = (A A^T)^+ r
+    const bool refine = refine_now(p);
+    if (refine) {                          // FP32 refinement of the projection:
+        // r' = A (a + grad phi_1) - f_b^-, phi_2 = (A A^T)^+ r'
+        timed(p, OT_PHASE_REFINE, [&] { launch_div(s, 1, st); });
+        poisson(p, p->R2);
     }
-    // x = a + grad phi; prox; duals
-    timed(p, OT_PHASE_UPDATE, [&] { launch_update(s, check ? 1 : 0, st); });
+    // x = a + grad phi_1 (+ grad phi_2); prox; duals
+    timed(p, OT_PHASE_UPDATE, [&] { launch_update(s, check ? 1 : 0, refine ? 2 : 1, st); });
 }
 
 // Reduce the residual partials of the last check iteration and of the
@@ -405,6 +411,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
         p->A[q] = (float*)(p->ws + L.off_A) + q * ncT;
     }
     p->R = (float*)(p->ws + L.off_R);
+    p->R2 = (float*)(p->ws + L.off_R2);
     p->f0 = (float*)(p->ws + L.off_f);
     p->f1 = p->f0 + (long long)p->g.B * p->g.slice;
     p->tc64 = (double*)(p->ws + L.off_tc64);
@@ -454,6 +461,23 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
         p->tab[a].periodic = per[a];
         p->tab[a].mat = dst;
         p->tab[a].lam = dst + 2 * (size_t)n * n;
+        // twiddles e^{-i pi j / (2n)}, j < 4n, for the power-of-two fast paths
+        const bool fast = (a < 2 && fast_len(n)) || (a == 3 && (n == 8 || n == 16 || n == 32));
+        p->tab[a].tw = nullptr;
+        if (fast) {
+            std::vector<float> tw(8 * (size_t)n);
+            const double pi = 3.14159265358979323846;
+            for (int j = 0; j < 4 * n; ++j) {
+                tw[2 * j] = (float)std::cos(pi * j / (2.0 * n));
+                tw[2 * j + 1] = (float)-std::sin(pi * j / (2.0 * n));
+            }
+            float* tdst = (float*)(p->ws + L.off_tw[a]);
+            e = hipMemcpyAsync(tdst, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice,
+                               p->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+            if (e != hipSuccess) { delete p; return OT_ERR_HIP; }
+            p->tab[a].tw = (const float2*)tdst;
+        }
         if (a == 2 || a == 3) {
             std::vector<double> h64((size_t)n * n + n);
             std::copy(M.begin(), M.end(), h64.begin());

@@ -57,7 +57,8 @@ __device__ inline Node node_of(const Geom& g) {
 
 // ---- the staggered work array a (Step 1 input) ---------------------------
 // a = x - tau sigma K^T b_bar on unknown faces; walls and absent faces are 0.
-// MODE 0 computes it from (x, b_bar), MODE 1 reads it from s.A.
+// MODE 0 computes it from (x, b_bar).  MODE 1 (refinement) reads the first
+// projection x' = a + grad phi_1 from A and phi_1 = R on the fly.
 template <int MODE>
 struct FaceA {
     const StepArgs& s;
@@ -69,8 +70,8 @@ struct FaceA {
         if (!g.perx) { if (xx <= 0 || xx >= g.X) return 0.f; }
         else if (xx == g.X) xx = 0;
         const long long row = n.cb + (long long)n.y * g.X;
-        if (MODE == 1) return s.A[0][row + xx];
         const int xm = xx == 0 ? g.X - 1 : xx - 1;
+        if (MODE == 1) return s.A[0][row + xx] + g.sx * (s.R[row + xx] - s.R[row + xm]);
         return s.Mx[row + xx] - ts * (s.bb[0][row + xm] + s.bb[0][row + xx]);
     }
     __device__ float y(int yy) const {
@@ -78,31 +79,34 @@ struct FaceA {
         if (!g.pery) { if (yy <= 0 || yy >= g.Y) return 0.f; }
         else if (yy == g.Y) yy = 0;
         const long long i = n.cb + (long long)yy * g.X + n.x;
-        if (MODE == 1) return s.A[1][i];
         const int ym = yy == 0 ? g.Y - 1 : yy - 1;
-        return s.My[i] - ts * (s.bb[1][n.cb + (long long)ym * g.X + n.x] + s.bb[1][i]);
+        const long long im = n.cb + (long long)ym * g.X + n.x;
+        if (MODE == 1) return s.A[1][i] + g.sy * (s.R[i] - s.R[im]);
+        return s.My[i] - ts * (s.bb[1][im] + s.bb[1][i]);
     }
     __device__ float c(int cc) const {
         const Geom& g = s.g;
         if (!g.perc) { if (cc <= 0 || cc >= g.C) return 0.f; }
         else if (cc == g.C) cc = 0;
         const long long i = cidx(g, n.b, n.k, cc, n.p);
-        if (MODE == 1) return s.A[2][i];
         const int cm = cc == 0 ? g.C - 1 : cc - 1;
-        return s.Mc[i] - ts * (s.bb[2][cidx(g, n.b, n.k, cm, n.p)] + s.bb[2][i]);
+        const long long im = cidx(g, n.b, n.k, cm, n.p);
+        if (MODE == 1) return s.A[2][i] + g.sc * (s.R[i] - s.R[im]);
+        return s.Mc[i] - ts * (s.bb[2][im] + s.bb[2][i]);
     }
     __device__ float f(int kk) const {   // time kk in [0, P]
         const Geom& g = s.g;
         if (kk == 0 || kk == g.P) return s.F[fidx(g, n.b, kk, n.c, n.p)];
         const long long i = cidx(g, n.b, kk, n.c, n.p);
-        if (MODE == 1) return s.A[3][i];
-        return s.F[fidx(g, n.b, kk, n.c, n.p)] -
-               ts * (s.bb[3][cidx(g, n.b, kk - 1, n.c, n.p)] + s.bb[3][i]);
+        const long long im = cidx(g, n.b, kk - 1, n.c, n.p);
+        if (MODE == 1) return s.A[3][i] + g.st * (s.R[i] - s.R[im]);
+        return s.F[fidx(g, n.b, kk, n.c, n.p)] - ts * (s.bb[3][im] + s.bb[3][i]);
     }
 };
 
-// r = A a - f_b^- (Step 1) with f_b^- folded in through F[0], F[P]; writes
-// the own faces of a (MODE 0) and the FP64 plane sum of r.
+// r = A a - f_b^- (Step 1) with f_b^- folded in through F[0], F[P], and its
+// FP64 plane sums.  MODE 0 writes the own faces of a to A and r to R; MODE 1
+// writes the residual of the first projection to R2.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_div(StepArgs s) {
     const Geom& g = s.g;
@@ -121,35 +125,14 @@ __global__ void __launch_bounds__(kBlock) k_div(StepArgs s) {
             s.A[1][i] = ay0;
             s.A[2][i] = ac0;
             s.A[3][i] = n.k > 0 ? af0 : 0.f;
+            s.R[i] = r;
+        } else {
+            s.R2[i] = r;
         }
-        s.R[i] = r;
         acc = (double)r;
     }
     const double t = block_sum(acc);
     if (threadIdx.x == 0) s.part_slice[(long long)blockIdx.y * s.nbx + blockIdx.x] = t;
-}
-
-// x = a + grad phi on the own faces, in place in A (refined projection).
-__global__ void __launch_bounds__(kBlock) k_grad_inplace(StepArgs s) {
-    const Geom& g = s.g;
-    const Node n = node_of(g);
-    if (!n.live) return;
-    const long long i = n.cb + n.p;
-    const float ph = s.R[i];
-    const long long row = n.cb + (long long)n.y * g.X;
-    if (g.perx || n.x > 0) {
-        const int xm = n.x == 0 ? g.X - 1 : n.x - 1;
-        s.A[0][i] += g.sx * (ph - s.R[row + xm]);
-    }
-    if (g.pery || n.y > 0) {
-        const int ym = n.y == 0 ? g.Y - 1 : n.y - 1;
-        s.A[1][i] += g.sy * (ph - s.R[n.cb + (long long)ym * g.X + n.x]);
-    }
-    if (g.perc || n.c > 0) {
-        const int cm = n.c == 0 ? g.C - 1 : n.c - 1;
-        s.A[2][i] += g.sc * (ph - s.R[cidx(g, n.b, n.k, cm, n.p)]);
-    }
-    if (n.k > 0) s.A[3][i] += g.st * (ph - s.R[cidx(g, n.b, n.k - 1, n.c, n.p)]);
 }
 
 // Pointwise prox of J / sigma (Step 2): (0, 0) if 2 a_f + sigma |a_m|^2 <= 0,
@@ -184,8 +167,9 @@ __device__ inline void prox_J(float mx, float my, float mc, float af, float sigm
     v = vv;
 }
 
-// x^{r+1} = a + grad phi, z = prox(K x + c + b), b and b_bar updates.
-template <int CHECK>
+// x^{r+1} = a + grad phi_1 (+ grad phi_2 when refined), z = prox(K x + c + b),
+// b and b_bar updates.
+template <int CHECK, int NPHI>
 __global__ void __launch_bounds__(kBlock) k_update(StepArgs s) {
     const Geom& g = s.g;
     const Node n = node_of(g);
@@ -194,30 +178,35 @@ __global__ void __launch_bounds__(kBlock) k_update(StepArgs s) {
         const long long i = n.cb + n.p;
         const long long row = n.cb + (long long)n.y * g.X;
         const float* R = s.R;
+        const float* R2 = s.R2;
+        // grad of phi_1 (+ phi_2) between centred offsets j and jm
+        auto dphi = [&](long long j, long long jm) -> float {
+            return NPHI == 2 ? (R[j] - R[jm]) + (R2[j] - R2[jm]) : R[j] - R[jm];
+        };
         auto mx = [&](int xx) -> float {
             if (!g.perx) { if (xx <= 0 || xx >= g.X) return 0.f; }
             else if (xx == g.X) xx = 0;
             const int xm = xx == 0 ? g.X - 1 : xx - 1;
-            return s.A[0][row + xx] + g.sx * (R[row + xx] - R[row + xm]);
+            return s.A[0][row + xx] + g.sx * dphi(row + xx, row + xm);
         };
         auto my = [&](int yy) -> float {
             if (!g.pery) { if (yy <= 0 || yy >= g.Y) return 0.f; }
             else if (yy == g.Y) yy = 0;
             const int ym = yy == 0 ? g.Y - 1 : yy - 1;
             const long long j = n.cb + (long long)yy * g.X + n.x;
-            return s.A[1][j] + g.sy * (R[j] - R[n.cb + (long long)ym * g.X + n.x]);
+            return s.A[1][j] + g.sy * dphi(j, n.cb + (long long)ym * g.X + n.x);
         };
         auto mc = [&](int cc) -> float {
             if (!g.perc) { if (cc <= 0 || cc >= g.C) return 0.f; }
             else if (cc == g.C) cc = 0;
             const int cm = cc == 0 ? g.C - 1 : cc - 1;
             const long long j = cidx(g, n.b, n.k, cc, n.p);
-            return s.A[2][j] + g.sc * (R[j] - R[cidx(g, n.b, n.k, cm, n.p)]);
+            return s.A[2][j] + g.sc * dphi(j, cidx(g, n.b, n.k, cm, n.p));
         };
         auto ff = [&](int kk) -> float {
             if (kk == 0 || kk == g.P) return s.F[fidx(g, n.b, kk, n.c, n.p)];
             const long long j = cidx(g, n.b, kk, n.c, n.p);
-            return s.A[3][j] + g.st * (R[j] - R[cidx(g, n.b, kk - 1, n.c, n.p)]);
+            return s.A[3][j] + g.st * dphi(j, cidx(g, n.b, kk - 1, n.c, n.p));
         };
         const float mx0 = mx(n.x), my0 = my(n.y), mc0 = mc(n.c), f0 = ff(n.k);
         const float mx1 = mx(n.x + 1), my1 = my(n.y + 1), mc1 = mc(n.c + 1);
@@ -415,13 +404,15 @@ void launch_div(const StepArgs& s, int mode, hipStream_t st) {
     else hipLaunchKernelGGL(k_div<1>, node_grid(s.g), dim3(kBlock), 0, st, s);
 }
 
-void launch_grad_inplace(const StepArgs& s, hipStream_t st) {
-    hipLaunchKernelGGL(k_grad_inplace, node_grid(s.g), dim3(kBlock), 0, st, s);
-}
-
-void launch_update(const StepArgs& s, int check, hipStream_t st) {
-    if (check) hipLaunchKernelGGL(k_update<1>, node_grid(s.g), dim3(kBlock), 0, st, s);
-    else hipLaunchKernelGGL(k_update<0>, node_grid(s.g), dim3(kBlock), 0, st, s);
+void launch_update(const StepArgs& s, int check, int nphi, hipStream_t st) {
+    const dim3 gr = node_grid(s.g), bl(kBlock);
+    if (nphi == 2) {
+        if (check) hipLaunchKernelGGL((k_update<1, 2>), gr, bl, 0, st, s);
+        else hipLaunchKernelGGL((k_update<0, 2>), gr, bl, 0, st, s);
+    } else {
+        if (check) hipLaunchKernelGGL((k_update<1, 1>), gr, bl, 0, st, s);
+        else hipLaunchKernelGGL((k_update<0, 1>), gr, bl, 0, st, s);
+    }
 }
 
 void launch_resid_div(const StepArgs& s, hipStream_t st) {

@@ -15,6 +15,7 @@
 // These are dense contractions with the n x n matrix (table T[k][j], lanes
 // over j, so table reads are coalesced and LDS reads are broadcasts).
 #include "otd_common.h"
+#include "fft_common.h"
 
 namespace otd {
 
@@ -76,10 +77,13 @@ struct TcArgs {
     const double* tt64;      // P x P forward matrix M[j][k] (FP64)
     const double* lamc64;
     const double* lamt64;
-    const double* part_slice;
+    const double* part_slice;  // [B][P][C][nbx] FP64 block partials of the plane sums
     int nbx;
     int W;
+    const float2* twt;       // time-axis twiddles e^{-i pi j / (2P)}, j < 4P
 };
+
+__device__ void dc_line_fp64(const TcArgs& a, int b, double* d1);
 
 __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
     extern __shared__ float lds[];
@@ -145,27 +149,61 @@ __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
         base[(long long)k * g.slice + (long long)c * g.plane + i] = acc;
     }
     if (!dc_block) return;
-    // spatial-DC line in FP64: S[k][c] = sum_{x,y} r, then the (c, t) Poisson
-    // problem with eigenvalues lam_c + lam_t, scaled by 1 / sqrt(X Y).
     __syncthreads();
-    double* d1 = reinterpret_cast<double*>(lds);
+    dc_line_fp64(a, b, reinterpret_cast<double*>(lds));
+}
+
+// Spatial-DC line (jx, jy) = (0, 0) in FP64: S[k][c] = sum_{x,y} r from the
+// FP64 plane sums, then the (colour, time) Poisson problem with eigenvalues
+// lam_c + lam_t (zero mode dropped), scaled by 1 / sqrt(X Y); writes the
+// line at p = 0 of problem b.  Called by a whole block; d1 holds 2 P C doubles.
+__device__ void dc_line_fp64(const TcArgs& a, int b, double* d1) {
+    const Geom& g = a.g;
+    const int P = g.P, C = g.C;
+    const int nt = blockDim.x;
+    float* base = a.R + (long long)b * g.nc;
     double* d2 = d1 + P * C;
     const int m = P * C;
-    for (int e = threadIdx.x; e < m; e += kT) {
-        const double* pp = a.part_slice + ((long long)b * m + e) * a.nbx;
-        double s = 0.0;
-        for (int j = 0; j < a.nbx; ++j) s += pp[j];
-        d1[e] = s;                                   // [k][c]
+    // plane sums d1[k][c]: each wave takes 8 planes at a time and issues all
+    // of their coalesced partial loads before reducing (no dependent chains)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwave = nt >> 6;
+    constexpr int kPl = 8, kLd = 2;                       // planes per chunk, loads per lane
+    for (int e0 = wv * kPl; e0 < m; e0 += nwave * kPl) {
+        double acc[kPl];
+#pragma unroll
+        for (int q = 0; q < kPl; ++q) acc[q] = 0.0;
+        for (int j0 = 0; j0 < a.nbx; j0 += 64 * kLd) {
+            double v[kPl][kLd];
+#pragma unroll
+            for (int q = 0; q < kPl; ++q) {
+                const double* pp = a.part_slice + ((long long)b * m + e0 + q) * a.nbx;
+#pragma unroll
+                for (int l = 0; l < kLd; ++l) {
+                    const int j = j0 + 64 * l + lane;
+                    v[q][l] = (e0 + q < m && j < a.nbx) ? pp[j] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kPl; ++q)
+#pragma unroll
+                for (int l = 0; l < kLd; ++l) acc[q] += v[q][l];
+        }
+#pragma unroll
+        for (int q = 0; q < kPl; ++q) {
+            double s = acc[q];
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+            if (lane == 0 && e0 + q < m) d1[e0 + q] = s;
+        }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < m; e += kT) {      // colour forward
+    for (int e = threadIdx.x; e < m; e += nt) {      // colour forward
         const int k = e / C, jc = e - k * C;
         double acc = 0.0;
         for (int c = 0; c < C; ++c) acc += a.tc64[jc * C + c] * d1[k * C + c];
         d2[e] = acc;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < m; e += kT) {      // time forward, divide
+    for (int e = threadIdx.x; e < m; e += nt) {      // time forward, divide
         const int jt = e / C, jc = e - jt * C;
         double acc = 0.0;
         for (int k = 0; k < P; ++k) acc += a.tt64[jt * P + k] * d2[k * C + jc];
@@ -173,7 +211,7 @@ __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
         d1[e] = lam > 0.0 ? acc / lam : 0.0;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < m; e += kT) {      // time inverse
+    for (int e = threadIdx.x; e < m; e += nt) {      // time inverse
         const int k = e / C, jc = e - k * C;
         double acc = 0.0;
         for (int jt = 0; jt < P; ++jt) acc += a.tt64[jt * P + k] * d1[jt * C + jc];
@@ -181,7 +219,7 @@ __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
     }
     __syncthreads();
     const double scale = 1.0 / sqrt((double)g.plane);
-    for (int e = threadIdx.x; e < m; e += kT) {      // colour inverse, store
+    for (int e = threadIdx.x; e < m; e += nt) {      // colour inverse, store
         const int k = e / C, c = e - k * C;
         double acc = 0.0;
         for (int jc = 0; jc < C; ++jc) acc += a.tc64[jc * C + c] * d2[k * C + jc];
@@ -189,7 +227,146 @@ __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
     }
 }
 
+// Orthonormal DCT-II of a register line of length P (Makhoul's reordering
+// and a P/2-point packed DFT; every index is a compile-time constant).
+template <int P>
+__device__ __forceinline__ void dct2_reg(float (&x)[P], const float2* tw4) {
+    constexpr int M = P / 2;
+    float2 z[M];
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+        const int m0 = 2 * n, m1 = 2 * n + 1;
+        z[n] = make_float2(x[m0 < M ? 2 * m0 : 2 * P - 1 - 2 * m0],
+                           x[m1 < M ? 2 * m1 : 2 * P - 1 - 2 * m1]);
+    }
+    dft<M>(z);
+    const float sc = sqrtf(2.f / P), sc0 = sqrtf(1.f / P);
+#pragma unroll
+    for (int k = 0; k <= M; ++k) {
+        const float2 zk = z[k % M], zm = z[(M - k) % M];
+        const float2 ve = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+        const float2 vo = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+        const float2 V = k < M ? cadd(ve, cmul(tw4[4 * k], vo)) : csub(ve, vo);
+        const float2 w = cmul(tw4[k], V);
+        x[k] = w.x * (k == 0 ? sc0 : sc);
+        if (k > 0 && k < M) x[P - k] = -w.y * sc;
+    }
+}
+
+// Orthonormal DCT-III (inverse of dct2_reg) of a register line.
+template <int P>
+__device__ __forceinline__ void dct3_reg(float (&x)[P], const float2* tw4) {
+    constexpr int M = P / 2;
+    const float isc = 1.f / sqrtf(2.f / P), isc0 = 1.f / sqrtf(1.f / P);
+    auto X = [&](int k) -> float { return k >= P ? 0.f : x[k] * (k == 0 ? isc0 : isc); };
+    auto V = [&](int k) -> float2 { return cmul(cconj(tw4[k]), make_float2(X(k), -X(P - k))); };
+    float2 zc[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const float2 v = V(k), vm = cconj(V(M - k));
+        const float2 ve = make_float2(0.5f * (v.x + vm.x), 0.5f * (v.y + vm.y));
+        const float2 vo = cmul(make_float2(0.5f * (v.x - vm.x), 0.5f * (v.y - vm.y)),
+                               cconj(tw4[4 * k]));
+        zc[k] = make_float2(ve.x - vo.y, -(ve.y + vo.x));
+    }
+    dft<M>(zc);
+    const float im = 1.f / M;
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+        const int m0 = 2 * n, m1 = 2 * n + 1;
+        x[m0 < M ? 2 * m0 : 2 * (P - 1 - m0) + 1] = zc[n].x * im;
+        x[m1 < M ? 2 * m1 : 2 * (P - 1 - m1) + 1] = -zc[n].y * im;
+    }
+}
+
+// Colour and time pass for power-of-two P: a block covers 64 consecutive
+// (x, y) points; wave c loads colour c of them (coalesced) and, after a
+// colour transform through LDS, owns colour mode c: time DCT-II in registers,
+// division by the eigenvalues of A A^T, inverse DCT; the inverse colour
+// transform goes back through LDS.  Block 0 of each problem instead solves
+// the spatial-DC line (p = 0) in FP64.
+template <int P, int C>
+__global__ void __launch_bounds__(64 * C) k_tc_reg(TcArgs a) {
+    extern __shared__ double dsh[];
+    float* buf = reinterpret_cast<float*>(dsh);        // [C][P][64]
+    const Geom& g = a.g;
+    const int b = blockIdx.y;
+    if (blockIdx.x == 0) {
+        dc_line_fp64(a, b, dsh);
+        return;
+    }
+    const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+    const long long p = (long long)(blockIdx.x - 1) * 64 + lane;
+    const bool live = p < g.plane;
+    float* base = a.R + (long long)b * g.nc + (live ? p : 0) + (long long)c * g.plane;
+    float u[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) u[k] = live ? base[(long long)k * g.slice] : 0.f;
+    if constexpr (C > 1) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) buf[(c * P + k) * 64 + lane] = u[k];
+        __syncthreads();
+        const float* Tc = a.tc.mat;                    // Tc[c' * C + jc] = M[jc][c']
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            float acc = 0.f;
+#pragma unroll
+            for (int cc = 0; cc < C; ++cc) acc = fmaf(Tc[cc * C + c], buf[(cc * P + k) * 64 + lane], acc);
+            u[k] = acc;
+        }
+    }
+    dct2_reg<P>(u, a.twt);
+    const int jy = live ? (int)(p / g.X) : 0, jx = live ? (int)(p - (long long)jy * g.X) : 0;
+    const float lc = a.tx.lam[jx] + a.ty.lam[jy] + a.tc.lam[c];
+#pragma unroll
+    for (int jt = 0; jt < P; ++jt) {
+        const float lam = lc + a.tt.lam[jt];     // > 0 except the DC mode of p = 0
+        u[jt] = lam > 0.f ? u[jt] * __builtin_amdgcn_rcpf(lam) : 0.f;
+    }
+    dct3_reg<P>(u, a.twt);
+    if constexpr (C > 1) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < P; ++k) buf[(c * P + k) * 64 + lane] = u[k];
+        __syncthreads();
+        const float* Uc = a.tc.mat + C * C;            // Uc[jc * C + c'] = M[jc][c']
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            float acc = 0.f;
+#pragma unroll
+            for (int jc = 0; jc < C; ++jc) acc = fmaf(Uc[jc * C + c], buf[(jc * P + k) * 64 + lane], acc);
+            u[k] = acc;
+        }
+    }
+    if (!live || p == 0) return;
+#pragma unroll
+    for (int k = 0; k < P; ++k) base[(long long)k * g.slice] = u[k];
+}
+
+template <int P, int C>
+static void tc_reg_launch(const TcArgs& a, hipStream_t st) {
+    const unsigned nb = (unsigned)((a.g.plane + 63) / 64) + 1;
+    size_t sh = (size_t)C * P * 64 * sizeof(float);
+    const size_t sh64 = (size_t)2 * P * C * sizeof(double);
+    if (sh64 > sh) sh = sh64;
+    hipLaunchKernelGGL((k_tc_reg<P, C>), dim3(nb, (unsigned)a.g.B), dim3(64 * C), sh, st, a);
+}
+
+static bool tc_reg_dispatch(const TcArgs& a, hipStream_t st) {
+    if (!a.twt) return false;
+    const int P = a.g.P, C = a.g.C;
+#define OTD_TC(PP, CC) if (P == PP && C == CC) { tc_reg_launch<PP, CC>(a, st); return true; }
+    OTD_TC(8, 1) OTD_TC(16, 1) OTD_TC(32, 1)
+    OTD_TC(8, 3) OTD_TC(16, 3) OTD_TC(32, 3)
+#undef OTD_TC
+    return false;
+}
+
 void launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStream_t st) {
+    if (t.tw) {
+        launch_rows_fast(R, rows, t.n, t.tw, t.periodic ? 2 : (inverse ? 1 : 0), st);
+        return;
+    }
     const int L = t.n;
     int rb = kTileFloats / L;
     if (rb < 1) rb = 1;
@@ -200,6 +377,10 @@ void launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStr
 
 void launch_cols(float* R, long long outer, long long inner, const AxisTab& t, int inverse,
                  hipStream_t st) {
+    if (t.tw) {
+        launch_cols_fast(R, outer, inner, t.n, t.tw, t.periodic ? 2 : (inverse ? 1 : 0), st);
+        return;
+    }
     const int L = t.n;
     int W = 64;
     while (W > 1 && L * W > kTileFloats) W >>= 1;
@@ -220,6 +401,8 @@ void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty, co
     a.lamt64 = tt64 + (long long)g.P * g.P;
     a.part_slice = part_slice;
     a.nbx = nbx;
+    a.twt = tt.tw;
+    if (tc_reg_dispatch(a, st)) return;
     int W = 64;
     while (W > 1 && 2 * g.P * g.C * W > 2 * kTileFloats) W >>= 1;
     a.W = W;

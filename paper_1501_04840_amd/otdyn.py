@@ -34,10 +34,10 @@ OT_PHASE_DIV = 0
 OT_PHASE_XFORM_X = 1
 OT_PHASE_XFORM_Y = 2
 OT_PHASE_TC = 3
-OT_PHASE_GRAD = 4
+OT_PHASE_REFINE = 4
 OT_PHASE_UPDATE = 5
 OT_PHASE_COUNT = 6
-PHASE_NAMES = ["div", "xform_x", "xform_y", "tc", "grad", "update"]
+PHASE_NAMES = ["div", "xform_x", "xform_y", "tc", "refine", "update"]
 
 OT_INIT_COLD = 0
 OT_INIT_PRIMAL = 1

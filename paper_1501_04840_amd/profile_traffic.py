@@ -1,0 +1,110 @@
+"""Workload for the HBM traffic counters of the solver kernels.
+
+Run under rocprofv3 with one counter per pass, for example
+
+    rocprofv3 --pmc FETCH_SIZE -d OUT --output-format csv -- python3 paper_1501_04840_amd/profile_traffic.py
+    rocprofv3 --pmc WRITE_SIZE -d OUT --output-format csv -- python3 paper_1501_04840_amd/profile_traffic.py
+
+It runs a few iterations of the 256 x 256 x 3 x 32 workload and then a plain
+elementwise copy of known size (256 MiB read, 256 MiB written), whose
+counter values calibrate the solver kernels' readings.  ``summarise`` turns
+the two counter CSVs into bytes per launch per kernel.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+COPY_ELEMS = 64 * 1024 * 1024          # float32 elements of the calibration copy
+
+
+def run(iters: int = 3, size=(256, 256, 3, 32)):
+    import torch
+    from paper_1501_04840_amd import otdyn
+    from synth import inputs
+    X, Y, C, P = size
+    f0, f1 = inputs.cfg3_pair(X, Y)
+    d = otdyn.ot_dyn_default_desc(X, Y, C, P)
+    prob = otdyn.Problem(d, "cuda:0")
+    prob.set_boundary(torch.from_numpy(f0), torch.from_numpy(f1))
+    prob.init(otdyn.OT_INIT_COLD)
+    prob.step(iters)
+    torch.cuda.synchronize()
+    src = torch.rand(COPY_ELEMS, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    prob.close()
+    print("profile_traffic: done", flush=True)
+
+
+def _sources_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1501_04840_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _read(dirname: str, counter: str):
+    """{kernel name: [value per dispatch]} from a rocprofv3 counter CSV."""
+    files = glob.glob(os.path.join(dirname, "**", "*counter_collection.csv"), recursive=True)
+    out = {}
+    for fn in files:
+        with open(fn) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                name = row["Kernel_Name"].split("(")[0].replace("void ", "")
+                out.setdefault(name, []).append(float(row["Counter_Value"]))
+    return out
+
+
+def summarise(fetch_dir: str, write_dir: str, out_json: str, out_md: str, cmd: str):
+    fetch = _read(fetch_dir, "FETCH_SIZE")
+    write = _read(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "AUnaryFunctor" in k or "MulFunctor" in k]
+    if not copy:
+        raise SystemExit("calibration copy kernel not found")
+    ck = copy[0]
+    nbytes = COPY_ELEMS * 4
+    # counters are in KiB per dispatch; scale so the copy reads and writes nbytes
+    f_scale = nbytes / (max(fetch[ck]) * 1024.0)
+    w_scale = nbytes / (max(write[ck]) * 1024.0)
+    kernels = {}
+    for k in fetch:
+        if not k.startswith("otd::"):
+            continue
+        fv = sum(fetch[k]) / len(fetch[k]) * 1024.0 * f_scale
+        wv = sum(write.get(k, [0.0])) / max(1, len(write.get(k, []))) * 1024.0 * w_scale
+        kernels[k.replace("otd::", "")] = {"fetch_bytes": fv, "write_bytes": wv,
+                                           "bytes_per_launch": fv + wv,
+                                           "dispatches": len(fetch[k])}
+    res = {"sources": _sources_hash(), "workload": "rgb_256x256x3x32",
+           "calibration": {"kernel": ck, "bytes_each_way": nbytes,
+                           "fetch_scale": f_scale, "write_scale": w_scale},
+           "kernels": kernels}
+    with open(out_json, "w") as fh:
+        json.dump(res, fh, indent=1)
+    lines = ["# HBM traffic per launch: RGB transport 256x256x3x32", "",
+             "Commands (repository root, one MI355X):", "", f"    {cmd}", "",
+             f"Calibration: `{ck}` copies {nbytes} B each way; FETCH_SIZE scale "
+             f"{f_scale:.4f}, WRITE_SIZE scale {w_scale:.4f}.", "",
+             "| kernel | fetch MB | write MB | total MB / launch |", "|---|---|---|---|"]
+    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["bytes_per_launch"]):
+        lines.append(f"| `{k}` | {v['fetch_bytes'] / 1e6:.1f} | {v['write_bytes'] / 1e6:.1f} | "
+                     f"{v['bytes_per_launch'] / 1e6:.1f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    run()

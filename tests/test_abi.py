@@ -39,10 +39,10 @@ def test_default_desc_and_workspace(L):
     assert d.tau * d.sigma < 1 and d.theta == 1.0 and d.batch == 1
     n = L.ot_dyn_workspace_size(d)
     N = 256 * 256 * 3 * 32
-    assert n >= 13 * N * 4          # b, b_bar, a (4 fields each) and r
-    assert n < 14 * N * 4 + (1 << 24)
+    assert n >= 14 * N * 4          # b, b_bar, a (4 fields each), r and r'
+    assert n < 15 * N * 4 + (1 << 24)
     d.batch = 3
-    assert L.ot_dyn_workspace_size(d) > 3 * 13 * N * 4
+    assert L.ot_dyn_workspace_size(d) > 3 * 14 * N * 4
 
 
 @pytest.mark.parametrize("field,value,status", [

@@ -72,6 +72,15 @@ SHAPES = [
     (8, 6, 3, 4, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),      # Neumann colour
     (6, 5, 2, 3, (G.PERIODIC, G.NEUMANN, G.PERIODIC), 12),    # periodic x, C = 2
     (33, 31, 3, 6, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),   # several blocks + tail
+    # power-of-two lengths: fast DCT/Hartley passes and register colour-time pass
+    (32, 64, 3, 8, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),   # rows 32, cols 64
+    (128, 32, 1, 16, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),  # rows 128, cols 32, C = 1
+    (64, 1, 1, 32, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),   # Hartley rows, P = 32
+    (512, 2, 1, 8, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),    # rows 512
+    (16, 256, 3, 4, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),  # cols 256, ragged tile
+    (256, 8, 2, 16, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),  # rows 256, C = 2
+    (40, 128, 3, 32, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12), # cols 128, Neumann colour
+    (128, 128, 1, 8, (G.PERIODIC, G.PERIODIC, G.NEUMANN), 12),  # Hartley rows and cols
 ]
 
 
