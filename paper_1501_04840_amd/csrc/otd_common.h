@@ -68,6 +68,13 @@ void launch_div(const StepArgs& s, int mode, hipStream_t st);
 // x = a + grad(phi_1) (+ grad(phi_2) if nphi == 2), prox, dual update;
 // residual partials if `check`.
 void launch_update(const StepArgs& s, int check, int nphi, hipStream_t st);
+// Row-marching variants (stencil_rows.hip), used when 1 <= C <= 4: one
+// thread per (b, k, y, x) for all colours, XCD-aware block order.  Their
+// plane partial stride is Y * ceil(X / row_block(X)).
+int row_block(int X);
+bool rows_ok(const Geom& g);
+void launch_div_rows(const StepArgs& s, int mode, hipStream_t st);
+void launch_update_rows(const StepArgs& s, int check, int nphi, hipStream_t st);
 // FP64 partials of |A x - f_b^-|^2 and of the slice masses of F.
 void launch_resid_div(const StepArgs& s, hipStream_t st);
 // Boundary slices, wall slots and (optionally) zero unknowns.

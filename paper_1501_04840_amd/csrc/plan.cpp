@@ -40,7 +40,9 @@ struct ot_dyn_plan {
     double* part_mass;
     double* part_bnd;
     double* red_out;
-    int nbx;
+    int nbx;                 // plane-partial stride of the divergence kernels
+    int nbx_node;            // blocks per plane of the per-node kernels
+    long long nred;          // residual partials per problem of the update kernel
     int nblk_bnd;
     // host state
     bool have_boundary;
@@ -69,7 +71,8 @@ struct Layout {
     size_t off_b, off_bb, off_A, off_R, off_R2, off_f, off_tab[4], off_tw[4], off_tc64, off_tt64;
     size_t off_pslice, off_pred, off_pdiv, off_pmass, off_pbnd, off_red;
     size_t total;
-    int nbx, nblk_bnd;
+    int nbx, nbx_node, nblk_bnd;
+    long long nred;
 };
 
 int axis_size(const ot_dyn_desc& d, int a) { return a == 0 ? d.X : (a == 1 ? d.Y : d.C); }
@@ -153,12 +156,22 @@ Layout layout_of(const ot_dyn_desc& d) {
     }
     L.off_tc64 = take(((size_t)d.C * d.C + d.C) * sizeof(double));
     L.off_tt64 = take(((size_t)d.P * d.P + d.P) * sizeof(double));
-    L.nbx = (int)((g.plane + 255) / 256);
-    const size_t nslot = (size_t)g.B * g.P * g.C * L.nbx;
-    L.off_pslice = take(nslot * sizeof(double));
-    L.off_pred = take(RS_COUNT * nslot * sizeof(double));
-    L.off_pdiv = take(nslot * sizeof(double));
-    L.off_pmass = take(nslot * sizeof(double));
+    // FP64 partials: per-node kernels write one per 256 nodes of a plane; the
+    // row kernels one per row segment and colour (plane stride Y * nxb)
+    L.nbx_node = (int)((g.plane + 255) / 256);
+    if (rows_ok(g)) {
+        const int bx = row_block(g.X), nxb = (g.X + bx - 1) / bx;
+        L.nbx = g.Y * nxb;
+        L.nred = (long long)g.Y * g.P * nxb;
+    } else {
+        L.nbx = L.nbx_node;
+        L.nred = (long long)g.P * g.C * L.nbx_node;
+    }
+    const size_t nnode = (size_t)g.B * g.P * g.C * L.nbx_node;
+    L.off_pslice = take((size_t)g.B * g.P * g.C * L.nbx * sizeof(double));
+    L.off_pred = take(RS_COUNT * (size_t)g.B * L.nred * sizeof(double));
+    L.off_pdiv = take(nnode * sizeof(double));
+    L.off_pmass = take(nnode * sizeof(double));
     L.nblk_bnd = (int)std::min<long long>(64, (g.slice + 255) / 256);
     L.off_pbnd = take(5 * (size_t)g.B * L.nblk_bnd * sizeof(double));
     L.off_red = take(((size_t)RS_COUNT * g.B + g.B + (size_t)g.B * g.P + 5 * g.B) * sizeof(double));
@@ -295,14 +308,14 @@ int collect(ot_dyn_plan* p, const StepArgs& s, bool have_iter) {
     const Geom& g = p->g;
     hipStream_t st = p->stream;
     const int B = g.B;
-    const long long nslot = (long long)g.P * g.C * p->nbx;       // per problem
+    const long long nslot = (long long)g.P * g.C * p->nbx_node;  // per problem
     launch_resid_div(s, st);
     double* out_red = p->red_out;
     double* out_div = out_red + RS_COUNT * B;
     double* out_mass = out_div + B;
-    if (have_iter) launch_reduce(p->part_red, nslot, RS_COUNT * B, out_red, st);
+    if (have_iter) launch_reduce(p->part_red, p->nred, RS_COUNT * B, out_red, st);
     launch_reduce(p->part_div, nslot, B, out_div, st);
-    launch_reduce(p->part_mass, (long long)g.C * p->nbx, B * g.P, out_mass, st);
+    launch_reduce(p->part_mass, (long long)g.C * p->nbx_node, B * g.P, out_mass, st);
     std::vector<double> h((size_t)RS_COUNT * B + B + (size_t)B * g.P);
     HIPCHK(p, hipMemcpyAsync(h.data(), out_red, h.size() * sizeof(double),
                              hipMemcpyDeviceToHost, st));
@@ -423,6 +436,8 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->part_bnd = (double*)(p->ws + L.off_pbnd);
     p->red_out = (double*)(p->ws + L.off_red);
     p->nbx = L.nbx;
+    p->nbx_node = L.nbx_node;
+    p->nred = L.nred;
     p->nblk_bnd = L.nblk_bnd;
     const int B = p->g.B;
     p->mass0.assign(B, 0); p->mass1.assign(B, 0); p->fbm2.assign(B, 0);

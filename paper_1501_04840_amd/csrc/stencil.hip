@@ -7,31 +7,11 @@
 // Neighbour faces along x and y are re-read by the neighbouring lanes' loads
 // (L1/L2 hits); along colour and time they are separate planes.
 #include "otd_common.h"
+#include "stencil_common.h"
 
 namespace otd {
 
 constexpr int kBlock = 256;
-
-__device__ inline long long cidx(const Geom& g, int b, int k, int c, int p) {
-    return (long long)b * g.nc + (long long)k * g.slice + (long long)c * g.plane + p;
-}
-__device__ inline long long fidx(const Geom& g, int b, int k, int c, int p) {
-    return (long long)b * g.nf + (long long)k * g.slice + (long long)c * g.plane + p;
-}
-
-// Deterministic FP64 sum over the 256 threads of a block (4 waves of 64).
-__device__ inline double block_sum(double v) {
-    __shared__ double red[kBlock / 64];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kBlock / 64; ++i) t += red[i];
-    return t;   // valid in thread 0
-}
 
 struct Node {
     int b, k, c, p, y, x;
@@ -133,38 +113,6 @@ __global__ void __launch_bounds__(kBlock) k_div(StepArgs s) {
     }
     const double t = block_sum(acc);
     if (threadIdx.x == 0) s.part_slice[(long long)blockIdx.y * s.nbx + blockIdx.x] = t;
-}
-
-// Pointwise prox of J / sigma (Step 2): (0, 0) if 2 a_f + sigma |a_m|^2 <= 0,
-// else v is the positive root of 2 (1 + sigma v)^2 (v - a_f) = sigma |a_m|^2,
-// reached by Newton from v0 = max(a_f, 0) + sigma |a_m|^2 / 2 (right of the
-// root, where the cubic is increasing and convex: monotone decrease), and
-// u = sigma v a_m / (1 + sigma v).
-__device__ inline void prox_J(float mx, float my, float mc, float af, float sigma,
-                              float& ux, float& uy, float& uc, float& v) {
-    const float a2 = mx * mx + my * my + mc * mc;
-    if (!(2.f * af + sigma * a2 > 0.f)) {
-        ux = uy = uc = v = 0.f;
-        return;
-    }
-    float vv = fmaxf(af, 0.f) + 0.5f * sigma * a2;
-    for (int it = 0; it < 60; ++it) {
-        const float w = 1.f + sigma * vv;
-        const float d = vv - af;
-        const float gv = 2.f * w * w * d - sigma * a2;
-        const float dg = 4.f * sigma * w * d + 2.f * w * w;
-        float vn = vv - gv / dg;
-        if (!(vn < vv)) break;                 // no further decrease: converged
-        if (vn <= 0.f) vn = 0.5f * vv;
-        const bool done = (vv - vn) <= 1e-6f * vn;
-        vv = vn;
-        if (done) break;
-    }
-    const float sc = sigma * vv / (1.f + sigma * vv);
-    ux = sc * mx;
-    uy = sc * my;
-    uc = sc * mc;
-    v = vv;
 }
 
 // x^{r+1} = a + grad phi_1 (+ grad phi_2 when refined), z = prox(K x + c + b),
@@ -288,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_div(StepArgs s) {
         r2 = r * r;
         mass = f0;
     }
-    const long long o = (long long)blockIdx.y * s.nbx + blockIdx.x;
+    const long long o = (long long)blockIdx.y * gridDim.x + blockIdx.x;
     double t = block_sum(r2);
     if (threadIdx.x == 0) s.part_div[o] = t;
     t = block_sum(mass);
@@ -400,11 +348,13 @@ static dim3 node_grid(const Geom& g) {
 }
 
 void launch_div(const StepArgs& s, int mode, hipStream_t st) {
+    if (rows_ok(s.g)) { launch_div_rows(s, mode, st); return; }
     if (mode == 0) hipLaunchKernelGGL(k_div<0>, node_grid(s.g), dim3(kBlock), 0, st, s);
     else hipLaunchKernelGGL(k_div<1>, node_grid(s.g), dim3(kBlock), 0, st, s);
 }
 
 void launch_update(const StepArgs& s, int check, int nphi, hipStream_t st) {
+    if (rows_ok(s.g)) { launch_update_rows(s, check, nphi, st); return; }
     const dim3 gr = node_grid(s.g), bl(kBlock);
     if (nphi == 2) {
         if (check) hipLaunchKernelGGL((k_update<1, 2>), gr, bl, 0, st, s);
