@@ -44,9 +44,10 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources."""
+def measured_traffic(prefix: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) of the
+    kernels whose names start with `prefix`, from the committed counter
+    summary, if it was taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -54,8 +55,8 @@ def measured_traffic(kernel: str):
         t = json.load(fh)
     if t.get("sources") != kernel_sources_hash():
         return None
-    k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    vals = [v["bytes_per_launch"] for k, v in t.get("kernels", {}).items() if k.startswith(prefix)]
+    return sum(vals) / len(vals) if vals else None
 
 
 def cpu_baseline(f0, f1, X, Y, C, P, iters):
@@ -142,8 +143,9 @@ def main():
     dom = max(split, key=lambda k: split[k]["ms_per_iter"])
     per_launch_bytes = words_per_iter[dom] * 4.0 * N * K / split[dom]["launches"]
     achieved = per_launch_bytes / (split[dom]["avg_launch_us"] * 1e-6) / 1e9
-    kernel_name = {"div": "k_div<0>", "xform_x": "k_rows_fft", "xform_y": "k_cols_fft",
-                   "tc": "k_tc_reg", "refine": "k_div<1>", "update": "k_update"}[dom]
+    kernel_name = {"div": "k_div_rows<0", "xform_x": "k_rows_fft", "xform_y": "k_cols_fft",
+                   "tc": "k_tc_reg", "refine": "k_div_rows<1",
+                   "update": "k_update_rows<0, 2" if args.refine == 1 else "k_update_rows<0, 1"}[dom]
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name),
             "kernel": kernel_name, "algorithmic_bytes_per_launch": per_launch_bytes}
