@@ -170,6 +170,69 @@ int ot_dyn_profile_read(ot_dyn_plan* p, double* ms, long long* launches, int n);
 /* Release the plan (host memory only; device buffers stay the caller's). */
 int ot_dyn_destroy(ot_dyn_plan* p);
 
+/* ---- batched problems of uneven sizes ---------------------------------
+ * Many independent problems (RGB images of different resolutions, 1D
+ * periodic hue histograms of different bin counts -- Sec. 5 of the paper
+ * transports such histograms with X = bins, Y = C = 1, bc[0] periodic)
+ * solved together.  Problems are grouped by shape; each group is one batched
+ * plan, and all groups' iterations run as one captured HIP graph with a
+ * concurrent branch per group.  Per-group launch shapes can be autotuned.
+ *
+ * dims: host array of count x 4 ints (X, Y, C, P) per problem.  The other
+ * descriptor fields (bc, extent, tau, sigma, theta, tolerances, refine,
+ * check_every) come from *base; base->batch is ignored.
+ *
+ * Packed device layout of the caller's arrays (problem i in order):
+ *   f0, f1 : C*Y*X floats each at offset off_h[i]
+ *   F      : (P+1)*C*Y*X floats at offset off_F[i]
+ *   M      : 3*P*C*Y*X floats at offset off_M[i] (Mx, then My, then Mc)
+ * with the per-problem layouts of the single-problem API. */
+typedef struct ot_dyn_batch ot_dyn_batch;
+
+int ot_dyn_batch_workspace_size(const ot_dyn_desc* base, int count, const int* dims,
+                                size_t* bytes);
+
+/* Create the batch over the caller's workspace (no device allocation; the
+ * batch creates one HIP stream per shape group, all of default priority). */
+int ot_dyn_batch_create(const ot_dyn_desc* base, int count, const int* dims, void* stream,
+                        void* workspace, size_t ws_bytes, ot_dyn_batch** out);
+
+/* Packed offsets (host arrays of count + 1 entries; the last is the total). */
+int ot_dyn_batch_offsets(const ot_dyn_batch* bt, long long* off_h, long long* off_F,
+                         long long* off_M);
+
+/* Gather the packed end densities into the groups and check them per
+ * problem (as ot_dyn_set_boundary). */
+int ot_dyn_batch_set_boundary(ot_dyn_batch* bt, const float* f0, const float* f1);
+
+/* Autotune each group's launch shapes (row-stencil block width, FFT or dense
+ * x/y transforms) by timing `trials` iterations per candidate on the group's
+ * own buffers; results are cached in the file named by the environment
+ * variable OT_DYN_TUNE_CACHE when it is set.  Leaves the state cold-started. */
+int ot_dyn_batch_autotune(ot_dyn_batch* bt, int trials);
+
+/* Cold-start every problem and iterate (graph chunks of `chunk` iterations,
+ * residuals checked after each chunk) until every problem is certified or
+ * max_iters.  rep (may be NULL) receives the batch totals: iterations, the
+ * number certified in `converged`, the worst residuals and the wall time.
+ * Returns OT_OK when all are certified, OT_NOT_CONVERGED otherwise. */
+int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report* rep);
+
+/* Per-problem result of the last solve: iterations until certified (or run),
+ * residuals, cost, masses. */
+int ot_dyn_batch_problem(const ot_dyn_batch* bt, int i, ot_dyn_report* rep);
+
+/* Scatter the solution into the caller's packed F and M (device). */
+int ot_dyn_batch_get_state(ot_dyn_batch* bt, float* F, float* M);
+
+/* Selected launch shape of the group holding problem i (row_bx, dense_xy). */
+int ot_dyn_batch_tuning(const ot_dyn_batch* bt, int i, int* row_bx, int* dense_xy);
+
+int ot_dyn_batch_destroy(ot_dyn_batch* bt);
+
+/* Last error message recorded on the batch (never NULL). */
+const char* ot_dyn_batch_last_error(const ot_dyn_batch* bt);
+
 /* Static description of a status code. */
 const char* ot_dyn_status_str(int status);
 

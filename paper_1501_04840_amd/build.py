@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libotdyn.so")
 
-SOURCES = ["stencil.hip", "stencil_rows.hip", "transform.hip", "fastdct.hip", "plan.cpp"]
+SOURCES = ["stencil.hip", "stencil_rows.hip", "transform.hip", "fastdct.hip", "plan.cpp",
+           "batch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -59,6 +59,7 @@ struct StepArgs {
     double* part_mass;   // [B*P*C][nbx] FP64 slice sums of f_new
     double* part_div;    // [B*P*C][nbx] FP64 sum of (A x - f_b^-)^2
     int nbx;             // blocks per (b, k, c) slice in the stencil kernels
+    int row_bx;          // block width of the row stencil kernels (64, 128 or 256)
 };
 
 // ---- stencil kernels (stencil.hip) -------------------------------------
@@ -70,7 +71,8 @@ void launch_div(const StepArgs& s, int mode, hipStream_t st);
 void launch_update(const StepArgs& s, int check, int nphi, hipStream_t st);
 // Row-marching variants (stencil_rows.hip), used when 1 <= C <= 4: one
 // thread per (b, k, y, x) for all colours, XCD-aware block order.  Their
-// plane partial stride is Y * ceil(X / row_block(X)).
+// plane partial stride is Y * ceil(X / row_bx); row_block(X) is the default
+// width (X rounded up to a multiple of 64, at most 256).
 int row_block(int X);
 bool rows_ok(const Geom& g);
 void launch_div_rows(const StepArgs& s, int mode, hipStream_t st);
@@ -105,6 +107,18 @@ bool fast_len(int L);
 void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st);
 void launch_cols_fast(float* R, long long outer, long long inner, int L, const float2* tw, int kind,
                       hipStream_t st);
+
+// ---- plan internals used by the batched solver (plan.cpp) ---------------
+}  // namespace otd
+struct ot_dyn_plan;
+struct ot_dyn_report;
+namespace otd {
+void plan_iterate(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc, bool check);
+int plan_collect(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc);
+void plan_apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy);
+bool plan_has_fast_xy(const ot_dyn_plan* p);
+void plan_problem(const ot_dyn_plan* p, int b, ot_dyn_report* rep);
+void plan_add_iters(ot_dyn_plan* p, int n);
 
 // ---- reductions (stencil.hip) ------------------------------------------
 // out[q] = sum_j part[q * n + j] in FP64, for q < nq.

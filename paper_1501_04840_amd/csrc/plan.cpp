@@ -44,6 +44,10 @@ struct ot_dyn_plan {
     int nbx_node;            // blocks per plane of the per-node kernels
     long long nred;          // residual partials per problem of the update kernel
     int nblk_bnd;
+    // launch shapes (autotuned): row-stencil block width, dense x/y transforms
+    int row_bx;
+    int dense_xy;
+    const float2* tw_fast[2];    // fast-path twiddles of x and y (null if absent)
     // host state
     bool have_boundary;
     bool have_init;
@@ -160,7 +164,8 @@ Layout layout_of(const ot_dyn_desc& d) {
     // row kernels one per row segment and colour (plane stride Y * nxb)
     L.nbx_node = (int)((g.plane + 255) / 256);
     if (rows_ok(g)) {
-        const int bx = row_block(g.X), nxb = (g.X + bx - 1) / bx;
+        // sized for the narrowest row block (64), the most partials
+        const int nxb = (g.X + 63) / 64;
         L.nbx = g.Y * nxb;
         L.nred = (long long)g.Y * g.P * nxb;
     } else {
@@ -237,6 +242,7 @@ StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     s.part_mass = p->part_mass;
     s.part_div = p->part_div;
     s.nbx = p->nbx;
+    s.row_bx = p->row_bx;
     return s;
 }
 
@@ -278,6 +284,21 @@ void poisson(ot_dyn_plan* p, float* R) {
         timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(R, B * g.P * g.C, g.X, p->tab[1], 1, st); });
     if (g.X > 1)
         timed(p, OT_PHASE_XFORM_X, [&] { launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 1, st); });
+}
+
+// Launch shapes: the row-stencil block width (64, 128 or 256; 0 = default)
+// and whether the x/y transforms use the dense path instead of the FFT one.
+void apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy) {
+    const Geom& g = p->g;
+    if (row_bx <= 0) row_bx = row_block(g.X);
+    p->row_bx = row_bx;
+    p->dense_xy = dense_xy;
+    if (rows_ok(g)) {
+        const int nxb = (g.X + row_bx - 1) / row_bx;
+        p->nbx = g.Y * nxb;
+        p->nred = (long long)g.Y * g.P * nxb;
+    }
+    for (int a = 0; a < 2; ++a) p->tab[a].tw = dense_xy ? nullptr : p->tw_fast[a];
 }
 
 bool refine_now(const ot_dyn_plan* p) {
@@ -493,6 +514,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
             if (e != hipSuccess) { delete p; return OT_ERR_HIP; }
             p->tab[a].tw = (const float2*)tdst;
         }
+        if (a < 2) p->tw_fast[a] = p->tab[a].tw;
         if (a == 2 || a == 3) {
             std::vector<double> h64((size_t)n * n + n);
             std::copy(M.begin(), M.end(), h64.begin());
@@ -504,6 +526,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
             if (e != hipSuccess) { delete p; return OT_ERR_HIP; }
         }
     }
+    apply_tuning(p, 0, 0);
     *out = p;
     return OT_OK;
 }
@@ -673,3 +696,38 @@ const char* ot_dyn_last_error(const ot_dyn_plan* p) {
 }
 
 }  // extern "C"
+
+// ---- internal hooks for the batched solver (batch.cpp) ---------------------
+namespace otd {
+
+void plan_iterate(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc, bool check) {
+    const StepArgs s = step_args(p, F, Mx, My, Mc);
+    iterate(p, s, check);
+}
+
+int plan_collect(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
+    const StepArgs s = step_args(p, F, Mx, My, Mc);
+    const int st = collect(p, s, true);
+    double worst = 0.0;
+    for (int b = 0; b < p->g.B; ++b) worst = std::max(worst, std::max(p->r_prim[b], p->r_dual[b]));
+    p->last_res = worst;
+    return st;
+}
+
+void plan_apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy) { apply_tuning(p, row_bx, dense_xy); }
+
+bool plan_has_fast_xy(const ot_dyn_plan* p) { return p->tw_fast[0] || p->tw_fast[1]; }
+
+void plan_problem(const ot_dyn_plan* p, int b, ot_dyn_report* rep) {
+    rep->r_prim = p->r_prim[b];
+    rep->r_dual = p->r_dual[b];
+    rep->r_div = p->r_div[b];
+    rep->cost = p->cost[b];
+    rep->e_mass = p->e_mass[b];
+    rep->mass0 = p->mass0[b];
+    rep->mass1 = p->mass1[b];
+}
+
+void plan_add_iters(ot_dyn_plan* p, int n) { p->total_iters += n; }
+
+}  // namespace otd

@@ -253,14 +253,14 @@ static dim3 row_grid(const Geom& g, int nxb) {
 
 template <int C>
 static void div_rows_c(const StepArgs& s, int mode, hipStream_t st) {
-    const int bx = row_block(s.g.X), nxb = (s.g.X + bx - 1) / bx;
+    const int bx = s.row_bx > 0 ? s.row_bx : row_block(s.g.X), nxb = (s.g.X + bx - 1) / bx;
     if (mode == 0) hipLaunchKernelGGL((k_div_rows<0, C>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
     else hipLaunchKernelGGL((k_div_rows<1, C>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
 }
 
 template <int C>
 static void update_rows_c(const StepArgs& s, int check, int nphi, hipStream_t st) {
-    const int bx = row_block(s.g.X), nxb = (s.g.X + bx - 1) / bx;
+    const int bx = s.row_bx > 0 ? s.row_bx : row_block(s.g.X), nxb = (s.g.X + bx - 1) / bx;
     const dim3 gr = row_grid(s.g, nxb), bl(bx);
     if (nphi == 2) {
         if (check) hipLaunchKernelGGL((k_update_rows<1, 2, C>), gr, bl, 0, st, s, nxb);

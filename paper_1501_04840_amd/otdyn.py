@@ -83,6 +83,10 @@ EXPORTS = [
     "ot_dyn_set_boundary", "ot_dyn_init", "ot_dyn_step", "ot_dyn_solve",
     "ot_dyn_residuals", "ot_dyn_destroy", "ot_dyn_status_str", "ot_dyn_last_error",
     "ot_dyn_profile", "ot_dyn_profile_read",
+    "ot_dyn_batch_workspace_size", "ot_dyn_batch_create", "ot_dyn_batch_offsets",
+    "ot_dyn_batch_set_boundary", "ot_dyn_batch_autotune", "ot_dyn_batch_solve",
+    "ot_dyn_batch_problem", "ot_dyn_batch_get_state", "ot_dyn_batch_tuning",
+    "ot_dyn_batch_destroy", "ot_dyn_batch_last_error",
 ]
 
 
@@ -108,12 +112,27 @@ def lib() -> ctypes.CDLL:
     L.ot_dyn_destroy.argtypes = [P]
     L.ot_dyn_profile.argtypes = [P, c_int]
     L.ot_dyn_profile_read.argtypes = [P, POINTER(c_double), POINTER(ctypes.c_longlong), c_int]
+    LL = ctypes.c_longlong
+    L.ot_dyn_batch_workspace_size.argtypes = [POINTER(ot_dyn_desc), c_int, POINTER(c_int),
+                                              POINTER(c_size_t)]
+    L.ot_dyn_batch_create.argtypes = [POINTER(ot_dyn_desc), c_int, POINTER(c_int), P, P,
+                                      c_size_t, POINTER(c_void_p)]
+    L.ot_dyn_batch_offsets.argtypes = [P, POINTER(LL), POINTER(LL), POINTER(LL)]
+    L.ot_dyn_batch_set_boundary.argtypes = [P, P, P]
+    L.ot_dyn_batch_autotune.argtypes = [P, c_int]
+    L.ot_dyn_batch_solve.argtypes = [P, c_int, c_int, POINTER(ot_dyn_report)]
+    L.ot_dyn_batch_problem.argtypes = [P, c_int, POINTER(ot_dyn_report)]
+    L.ot_dyn_batch_get_state.argtypes = [P, P, P]
+    L.ot_dyn_batch_tuning.argtypes = [P, c_int, POINTER(c_int), POINTER(c_int)]
+    L.ot_dyn_batch_destroy.argtypes = [P]
+    L.ot_dyn_batch_last_error.argtypes = [P]
+    L.ot_dyn_batch_last_error.restype = c_char_p
     L.ot_dyn_status_str.argtypes = [c_int]
     L.ot_dyn_status_str.restype = c_char_p
     L.ot_dyn_last_error.argtypes = [P]
     L.ot_dyn_last_error.restype = c_char_p
     for name in EXPORTS:
-        if name not in ("ot_dyn_status_str", "ot_dyn_last_error"):
+        if name not in ("ot_dyn_status_str", "ot_dyn_last_error", "ot_dyn_batch_last_error"):
             getattr(L, name).restype = c_int
     _lib = L
     return L
@@ -201,6 +220,80 @@ def ot_dyn_destroy(plan: int) -> int:
     return _check(lib().ot_dyn_destroy(plan))
 
 
+def _checkb(status: int, bt) -> int:
+    if status < 0:
+        L = lib()
+        msg = L.ot_dyn_status_str(status).decode()
+        extra = L.ot_dyn_batch_last_error(bt).decode() if bt else ""
+        raise OtDynError(status, msg + (f" ({extra})" if extra else ""))
+    return status
+
+
+def ot_dyn_batch_last_error(bt: int) -> str:
+    return lib().ot_dyn_batch_last_error(bt).decode()
+
+
+def _dims_array(dims):
+    flat = [int(v) for d in dims for v in d]
+    return (c_int * len(flat))(*flat), len(dims)
+
+
+def ot_dyn_batch_workspace_size(base: ot_dyn_desc, dims) -> int:
+    arr, n = _dims_array(dims)
+    out = c_size_t(0)
+    _check(lib().ot_dyn_batch_workspace_size(byref(base), n, arr, byref(out)))
+    return int(out.value)
+
+
+def ot_dyn_batch_create(base: ot_dyn_desc, dims, stream, workspace, ws_bytes: int) -> int:
+    arr, n = _dims_array(dims)
+    out = c_void_p(0)
+    _check(lib().ot_dyn_batch_create(byref(base), n, arr, _ptr(stream), _ptr(workspace),
+                                     ws_bytes, byref(out)))
+    return out.value
+
+
+def ot_dyn_batch_offsets(bt: int, count: int):
+    LL = ctypes.c_longlong
+    a, b, c = (LL * (count + 1))(), (LL * (count + 1))(), (LL * (count + 1))()
+    _checkb(lib().ot_dyn_batch_offsets(bt, a, b, c), bt)
+    return list(a), list(b), list(c)
+
+
+def ot_dyn_batch_set_boundary(bt: int, f0, f1) -> int:
+    return _checkb(lib().ot_dyn_batch_set_boundary(bt, _ptr(f0), _ptr(f1)), bt)
+
+
+def ot_dyn_batch_autotune(bt: int, trials: int) -> int:
+    return _checkb(lib().ot_dyn_batch_autotune(bt, trials), bt)
+
+
+def ot_dyn_batch_solve(bt: int, max_iters: int, chunk: int):
+    rep = ot_dyn_report()
+    st = _checkb(lib().ot_dyn_batch_solve(bt, max_iters, chunk, byref(rep)), bt)
+    return st, rep
+
+
+def ot_dyn_batch_problem(bt: int, i: int) -> ot_dyn_report:
+    rep = ot_dyn_report()
+    _checkb(lib().ot_dyn_batch_problem(bt, i, byref(rep)), bt)
+    return rep
+
+
+def ot_dyn_batch_get_state(bt: int, F, M) -> int:
+    return _checkb(lib().ot_dyn_batch_get_state(bt, _ptr(F), _ptr(M)), bt)
+
+
+def ot_dyn_batch_tuning(bt: int, i: int):
+    a, b = c_int(0), c_int(0)
+    _check(lib().ot_dyn_batch_tuning(bt, i, byref(a), byref(b)))
+    return a.value, b.value
+
+
+def ot_dyn_batch_destroy(bt: int) -> int:
+    return _check(lib().ot_dyn_batch_destroy(bt))
+
+
 def ot_dyn_status_str(status: int) -> str:
     return lib().ot_dyn_status_str(status).decode()
 
@@ -262,6 +355,68 @@ class Problem:
         if getattr(self, "plan", None):
             ot_dyn_destroy(self.plan)
             self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Device buffers of a batch of uneven problems (packed layout of the C
+    API): dims is a list of (X, Y, C, P); f0 / f1 are lists of arrays of
+    shape (C, Y, X)."""
+
+    def __init__(self, base: ot_dyn_desc, dims, device="cuda"):
+        import torch
+        self.base = base
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        self.count = len(self.dims)
+        self.device = torch.device(device)
+        self.ws_bytes = ot_dyn_batch_workspace_size(base, self.dims)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        self.bt = ot_dyn_batch_create(base, self.dims, self.stream.cuda_stream, self.ws_ptr,
+                                      self.ws_bytes)
+        self.off_h, self.off_F, self.off_M = ot_dyn_batch_offsets(self.bt, self.count)
+
+    def set_boundary(self, f0s, f1s):
+        import numpy as np
+        import torch
+        h0 = np.concatenate([np.asarray(a, np.float32).ravel() for a in f0s])
+        h1 = np.concatenate([np.asarray(a, np.float32).ravel() for a in f1s])
+        self._h0 = torch.from_numpy(h0).to(self.device)
+        self._h1 = torch.from_numpy(h1).to(self.device)
+        torch.cuda.synchronize(self.device)
+        return ot_dyn_batch_set_boundary(self.bt, self._h0, self._h1)
+
+    def autotune(self, trials: int = 10):
+        return ot_dyn_batch_autotune(self.bt, trials)
+
+    def solve(self, max_iters: int, chunk: int = 100):
+        return ot_dyn_batch_solve(self.bt, max_iters, chunk)
+
+    def problem(self, i: int) -> ot_dyn_report:
+        return ot_dyn_batch_problem(self.bt, i)
+
+    def state(self, i: int):
+        """(F, Mx, My, Mc) of problem i as host numpy arrays of the C layout."""
+        import torch
+        if not hasattr(self, "_F"):
+            self._F = torch.empty(self.off_F[-1], dtype=torch.float32, device=self.device)
+            self._M = torch.empty(self.off_M[-1], dtype=torch.float32, device=self.device)
+        ot_dyn_batch_get_state(self.bt, self._F, self._M)
+        X, Y, C, P = self.dims[i]
+        F = self._F[self.off_F[i]:self.off_F[i + 1]].reshape(P + 1, C, Y, X)
+        M = self._M[self.off_M[i]:self.off_M[i + 1]].reshape(3, P, C, Y, X)
+        return (F.cpu().numpy(), M[0].cpu().numpy(), M[1].cpu().numpy(), M[2].cpu().numpy())
+
+    def close(self):
+        if getattr(self, "bt", None):
+            ot_dyn_batch_destroy(self.bt)
+            self.bt = None
 
     def __del__(self):
         try:

@@ -1,0 +1,137 @@
+"""GPU tests of the batched solver (problems of uneven sizes in one graph):
+parity with the FP64 oracle, agreement with the single-problem plans,
+autotuning and per-problem certification."""
+import numpy as np
+import pytest
+
+from oracle import grid as G
+from oracle import pdhg
+from synth import inputs
+from tests.layout import rel, to_natural
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def otdyn():
+    import torch
+    from paper_1501_04840_amd import otdyn as o
+    assert torch.cuda.is_available()
+    o.lib()
+    return o
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def hue_problems(count, seed=7, bins=(64, 180, 37, 128), steps=(8, 16)):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice(bins))
+        T = int(rng.choice(steps))
+        h0 = inputs.von_mises_hist(1000 + 2 * i, n)
+        h1 = inputs.von_mises_hist(1001 + 2 * i, n)
+        out.append((n, T, h0, h1))
+    return out
+
+
+def periodic_desc(o, base_refine=1):
+    d = o.ot_dyn_default_desc(1, 1, 1, 2)
+    d.bc[0] = o.OT_BC_PERIODIC
+    d.refine = base_refine
+    return d
+
+
+def test_hue_batch_matches_oracle(otdyn):
+    _say("hue batch parity")
+    probs = hue_problems(10)
+    dims = [(n, 1, 1, T) for n, T, _, _ in probs]
+    bt = otdyn.Batch(periodic_desc(otdyn), dims)
+    bt.set_boundary([p[2].reshape(1, 1, -1) for p in probs], [p[3].reshape(1, 1, -1) for p in probs])
+    iters = 300
+    status, rep = bt.solve(iters, chunk=100)
+    assert rep.iterations == iters
+    for i, (n, T, h0, h1) in enumerate(probs):
+        r = bt.problem(i)
+        assert r.total_iterations == iters
+        g = G.Grid(n, 1, 1, T, (G.PERIODIC, G.NEUMANN, G.NEUMANN))
+        st = pdhg.solve(g, h0.reshape(1, 1, -1), h1.reshape(1, 1, -1), 10.0, 0.099, iters,
+                        record_every=iters)
+        gx = to_natural(g, *bt.state(i))
+        assert rel(gx[3], st.x[3]) < TOL, i
+        assert rel(gx[0], st.x[0]) < TOL, i
+        assert abs(r.cost - st.hist[-1]["cost"]) <= TOL * st.hist[-1]["cost"]
+    bt.close()
+
+
+def test_mixed_batch_equals_single_plans(otdyn):
+    """RGB images of different resolutions plus hue histograms in one batch:
+    each problem's state equals that of its own single-problem plan."""
+    _say("mixed batch vs single plans")
+    import torch
+    shapes = [(16, 16, 3, 8), (24, 20, 3, 8), (16, 16, 3, 8), (64, 1, 1, 16), (30, 1, 1, 8)]
+    f0s, f1s = [], []
+    for i, (X, Y, C, P) in enumerate(shapes):
+        a, b = inputs.random_pair(50 + i, X, Y, C)
+        f0s.append(a)
+        f1s.append(b)
+    base = otdyn.ot_dyn_default_desc(1, 1, 1, 2)
+    bt = otdyn.Batch(base, shapes)
+    bt.set_boundary(f0s, f1s)
+    status, rep = bt.solve(120, chunk=40)
+    for i, (X, Y, C, P) in enumerate(shapes):
+        d = otdyn.ot_dyn_default_desc(X, Y, C, P)
+        prob = otdyn.Problem(d, "cuda")
+        prob.set_boundary(torch.from_numpy(f0s[i]), torch.from_numpy(f1s[i]))
+        prob.init()
+        prob.step(120)
+        torch.cuda.synchronize()
+        single = [t[0].cpu().numpy() for t in prob.state()]
+        batched = bt.state(i)
+        for u, v in zip(batched, single):
+            np.testing.assert_array_equal(u, v)
+        prob.close()
+    bt.close()
+
+
+def test_autotune_keeps_results(otdyn, tmp_path, monkeypatch):
+    _say("autotune")
+    monkeypatch.setenv("OT_DYN_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    probs = hue_problems(6, seed=11, bins=(64, 128), steps=(16,))
+    dims = [(n, 1, 1, T) for n, T, _, _ in probs]
+    bt = otdyn.Batch(periodic_desc(otdyn), dims)
+    bt.set_boundary([p[2].reshape(1, 1, -1) for p in probs], [p[3].reshape(1, 1, -1) for p in probs])
+    bt.autotune(5)
+    for i in range(len(probs)):
+        bx, dense = otdyn.ot_dyn_batch_tuning(bt.bt, i)
+        assert bx in (64, 128, 256) and dense in (0, 1)
+    assert (tmp_path / "tune.txt").exists()
+    iters = 200
+    bt.solve(iters, chunk=100)
+    for i, (n, T, h0, h1) in enumerate(probs):
+        g = G.Grid(n, 1, 1, T, (G.PERIODIC, G.NEUMANN, G.NEUMANN))
+        st = pdhg.solve(g, h0.reshape(1, 1, -1), h1.reshape(1, 1, -1), 10.0, 0.099, iters)
+        gx = to_natural(g, *bt.state(i))
+        assert rel(gx[3], st.x[3]) < TOL, i
+    bt.close()
+
+
+def test_batch_certifies_each_problem(otdyn):
+    _say("batch certification")
+    probs = hue_problems(8, seed=3, bins=(64, 37), steps=(8,))
+    dims = [(n, 1, 1, T) for n, T, _, _ in probs]
+    d = periodic_desc(otdyn)
+    bt = otdyn.Batch(d, dims)
+    bt.set_boundary([p[2].reshape(1, 1, -1) for p in probs], [p[3].reshape(1, 1, -1) for p in probs])
+    status, rep = bt.solve(40000, chunk=200)
+    assert status == otdyn.OT_OK and rep.converged == len(probs)
+    for i in range(len(probs)):
+        r = bt.problem(i)
+        assert r.converged == 1
+        assert max(r.r_prim, r.r_dual) < d.tol_res and r.r_div < d.tol_div
+        assert 0 < r.iterations <= r.total_iterations
+    bt.close()
