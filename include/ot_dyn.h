@@ -215,7 +215,9 @@ int ot_dyn_batch_autotune(ot_dyn_batch* bt, int trials);
  * residuals checked after each chunk) until every problem is certified or
  * max_iters.  rep (may be NULL) receives the batch totals: iterations, the
  * number certified in `converged`, the worst residuals and the wall time.
- * Returns OT_OK when all are certified, OT_NOT_CONVERGED otherwise. */
+ * Returns OT_OK when all are certified, OT_NOT_CONVERGED otherwise.  With
+ * the environment variable OT_DYN_VERBOSE set, one progress line per chunk
+ * goes to stderr. */
 int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report* rep);
 
 /* Per-problem result of the last solve: iterations until certified (or run),

@@ -2,10 +2,11 @@
 //
 // Problems are grouped by shape (X, Y, C, P); a group is one batched plan
 // over group-contiguous buffers inside the caller's workspace.  A chunk of
-// iterations of every active group is captured into one HIP graph: the
-// caller's stream forks into one stream per group (event record / wait), so
-// the small groups run concurrently and the per-kernel launch cost is paid
-// once per graph.  After each chunk the FP64 residuals of every problem are
+// iterations of every active group is captured into a HIP graph on the
+// group's own stream; the groups' graphs are launched on their streams, so
+// the small groups run concurrently on separate hardware queues and the
+// per-kernel launch cost is paid once per graph.  After each chunk the FP64
+// residuals of every problem are
 // collected and certified problems are recorded; a group whose problems are
 // all certified leaves the graph.
 #include <hip/hip_runtime.h>
@@ -45,6 +46,8 @@ struct Group {
     std::vector<int> conv_iter;    // per member: iteration of certification, -1 if none
     std::vector<ot_dyn_report> rep;
     int row_bx = 0, dense_xy = 0;
+    hipGraph_t graph = nullptr;       // chunk of iterations captured on `side`
+    hipGraphExec_t exec = nullptr;
     long long slice() const { return (long long)d.X * d.Y * d.C; }
     long long nc() const { return slice() * d.P; }
     long long nf() const { return slice() * (d.P + 1); }
@@ -132,8 +135,6 @@ struct ot_dyn_batch {
     bool have_boundary = false;
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
     int graph_chunk = 0;
     std::vector<int> graph_groups;
     std::string err;
@@ -152,36 +153,33 @@ int hipfail(ot_dyn_batch* bt, hipError_t e, const char* what) {
     } while (0)
 
 void drop_graph(ot_dyn_batch* bt) {
-    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
-    if (bt->graph) (void)hipGraphDestroy(bt->graph);
-    bt->exec = nullptr;
-    bt->graph = nullptr;
+    for (auto& g : bt->P.groups) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g.exec = nullptr;
+        g.graph = nullptr;
+    }
     bt->graph_groups.clear();
+    bt->graph_chunk = 0;
 }
 
 // Capture `chunk` iterations (the last one with residual partials) of every
-// active group, one concurrent branch per group.
+// active group, one graph per group on the group's own stream; the groups'
+// graphs are launched on their streams and run concurrently.
 int build_graph(ot_dyn_batch* bt, int chunk) {
     drop_graph(bt);
-    BCHK(bt, hipStreamBeginCapture(bt->stream, hipStreamCaptureModeGlobal));
-    hipError_t e = hipEventRecord(bt->ev_fork, bt->stream);
-    for (size_t gi = 0; gi < bt->P.groups.size() && e == hipSuccess; ++gi) {
+    for (size_t gi = 0; gi < bt->P.groups.size(); ++gi) {
         Group& g = bt->P.groups[gi];
         if (!g.active) continue;
-        e = hipStreamWaitEvent(g.side, bt->ev_fork, 0);
-        if (e != hipSuccess) break;
+        BCHK(bt, hipStreamBeginCapture(g.side, hipStreamCaptureModeThreadLocal));
         for (int it = 0; it < chunk; ++it)
             plan_iterate(g.plan, g.F, g.Mx, g.My, g.Mc, it + 1 == chunk);
-        e = hipEventRecord(bt->ev_join[gi], g.side);
-        if (e == hipSuccess) e = hipStreamWaitEvent(bt->stream, bt->ev_join[gi], 0);
+        hipGraph_t graph = nullptr;
+        BCHK(bt, hipStreamEndCapture(g.side, &graph));
+        g.graph = graph;
+        BCHK(bt, hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
         bt->graph_groups.push_back((int)gi);
     }
-    hipGraph_t graph = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(bt->stream, &graph);
-    if (e != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hipfail(bt, e, "graph capture"); }
-    if (e2 != hipSuccess) return hipfail(bt, e2, "hipStreamEndCapture");
-    bt->graph = graph;
-    BCHK(bt, hipGraphInstantiate(&bt->exec, graph, nullptr, nullptr, 0));
     bt->graph_chunk = chunk;
     return OT_OK;
 }
@@ -362,6 +360,7 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
     if (!bt || max_iters < 1 || chunk < 1) return OT_ERR_PARAM;
     if (!bt->have_boundary) { bt->err = "set the boundary first"; return OT_ERR_STATE; }
     const auto t0 = std::chrono::steady_clock::now();
+    const bool verbose = std::getenv("OT_DYN_VERBOSE") != nullptr;
     drop_graph(bt);
     for (auto& g : bt->P.groups) {
         const int st = ot_dyn_init(g.plan, OT_INIT_COLD, g.F, g.Mx, g.My, g.Mc);
@@ -373,12 +372,15 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
     int done = 0, status = OT_NOT_CONVERGED;
     while (done < max_iters) {
         const int k = std::min(chunk, max_iters - done);
-        if (!bt->exec || bt->graph_chunk != k || bt->base.refine == 2) {
+        if (bt->graph_groups.empty() || bt->graph_chunk != k || bt->base.refine == 2) {
             const int st = build_graph(bt, k);
             if (st != OT_OK) return st;
         }
-        BCHK(bt, hipGraphLaunch(bt->exec, bt->stream));
-        BCHK(bt, hipStreamSynchronize(bt->stream));
+        for (int gi : bt->graph_groups) {
+            Group& g = bt->P.groups[gi];
+            BCHK(bt, hipGraphLaunch(g.exec, g.side));
+        }
+        for (int gi : bt->graph_groups) BCHK(bt, hipStreamSynchronize(bt->P.groups[gi].side));
         done += k;
         bool any_active = false, changed = false;
         for (int gi : bt->graph_groups) {
@@ -401,6 +403,16 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
             any_active = any_active || g.active;
         }
         if (changed) drop_graph(bt);
+        if (verbose) {
+            int nconv = 0, nact = 0;
+            for (auto& g : bt->P.groups) {
+                nact += g.active;
+                for (int c : g.conv_iter) nconv += c >= 0;
+            }
+            const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            std::fprintf(stderr, "ot_dyn_batch: %d iterations, %d/%d certified, %d groups active, %.2f s\n",
+                         done, nconv, bt->count, nact, el);
+        }
         if (!any_active) { status = OT_OK; break; }
     }
     if (rep) {
