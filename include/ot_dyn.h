@@ -65,7 +65,9 @@ extern "C" {
 /* initialisation modes of ot_dyn_init */
 #define OT_INIT_COLD         0  /* Algorithm 1: m = 0, f = 0, b = b_bar = 0          */
 #define OT_INIT_PRIMAL       1  /* caller-filled (F, M), b = b_bar = 0               */
-#define OT_INIT_PRIMAL_DUAL  2  /* caller-filled (F, M); b = b_bar = grad J(Kx+c)/sigma */
+#define OT_INIT_PRIMAL_DUAL  2  /* caller-filled (F, M); b = b_bar = grad J(Kx+c)/sigma,
+                                   the centred density floored at 1e-3 times
+                                   the mean of f0 (near-vacuum nodes)        */
 
 typedef struct ot_dyn_desc {
     int X, Y, C, P;        /* grid: X x Y pixels, C channels, P time steps; an
@@ -211,7 +213,16 @@ int ot_dyn_batch_set_boundary(ot_dyn_batch* bt, const float* f0, const float* f1
  * variable OT_DYN_TUNE_CACHE when it is set.  Leaves the state cold-started. */
 int ot_dyn_batch_autotune(ot_dyn_batch* bt, int trials);
 
-/* Cold-start every problem and iterate (graph chunks of `chunk` iterations,
+/* Start the next ot_dyn_batch_solve from the caller's packed F and M
+ * (device, layout of ot_dyn_batch_get_state) instead of a cold start: the
+ * state is copied and initialised with `mode` (OT_INIT_PRIMAL or
+ * OT_INIT_PRIMAL_DUAL, see ot_dyn_init).  Problems whose packed state is
+ * not wanted warm can be given a cold state (zeros).  Consumed by the next
+ * solve. */
+int ot_dyn_batch_set_state(ot_dyn_batch* bt, const float* F, const float* M, int mode);
+
+/* Cold-start every problem (or start from the state of
+ * ot_dyn_batch_set_state) and iterate (graph chunks of `chunk` iterations,
  * residuals checked after each chunk) until every problem is certified or
  * max_iters.  rep (may be NULL) receives the batch totals: iterations, the
  * number certified in `converged`, the worst residuals and the wall time.

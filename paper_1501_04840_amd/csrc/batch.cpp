@@ -133,6 +133,7 @@ struct ot_dyn_batch {
     int count;
     Plan P;
     bool have_boundary = false;
+    bool warm = false;         // the next solve starts from ot_dyn_batch_set_state
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
     int graph_chunk = 0;
@@ -348,6 +349,7 @@ int ot_dyn_batch_autotune(ot_dyn_batch* bt, int trials) {
     if (status != OT_OK) return status;
     save_cache(path, cache);
     drop_graph(bt);
+    bt->warm = false;
     for (auto& g : bt->P.groups) {
         const int st = ot_dyn_init(g.plan, OT_INIT_COLD, g.F, g.Mx, g.My, g.Mc);
         if (st != OT_OK) return st;
@@ -363,11 +365,14 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
     const bool verbose = std::getenv("OT_DYN_VERBOSE") != nullptr;
     drop_graph(bt);
     for (auto& g : bt->P.groups) {
-        const int st = ot_dyn_init(g.plan, OT_INIT_COLD, g.F, g.Mx, g.My, g.Mc);
-        if (st != OT_OK) return st;
+        if (!bt->warm) {
+            const int st = ot_dyn_init(g.plan, OT_INIT_COLD, g.F, g.Mx, g.My, g.Mc);
+            if (st != OT_OK) return st;
+        }
         g.active = true;
         std::fill(g.conv_iter.begin(), g.conv_iter.end(), -1);
     }
+    bt->warm = false;
     for (auto& g : bt->P.groups) BCHK(bt, hipStreamSynchronize(g.side));
     int done = 0, status = OT_NOT_CONVERGED;
     while (done < max_iters) {
@@ -461,6 +466,37 @@ int ot_dyn_batch_get_state(ot_dyn_batch* bt, float* F, float* M) {
         }
         BCHK(bt, hipStreamSynchronize(g.side));
     }
+    return OT_OK;
+}
+
+int ot_dyn_batch_set_state(ot_dyn_batch* bt, const float* F, const float* M, int mode) {
+    if (!bt || !F || !M) return OT_ERR_PARAM;
+    if (mode != OT_INIT_PRIMAL && mode != OT_INIT_PRIMAL_DUAL) {
+        bt->err = "set_state takes OT_INIT_PRIMAL or OT_INIT_PRIMAL_DUAL";
+        return OT_ERR_PARAM;
+    }
+    if (!bt->have_boundary) { bt->err = "set the boundary first"; return OT_ERR_STATE; }
+    bt->warm = false;
+    BCHK(bt, hipStreamSynchronize(bt->user));      // the state was produced on the caller's stream
+    for (auto& g : bt->P.groups) {
+        for (size_t j = 0; j < g.members.size(); ++j) {
+            const int i = g.members[j];
+            BCHK(bt, hipMemcpyAsync(g.F + j * g.nf(), F + bt->P.off_F[i], g.nf() * sizeof(float),
+                                    hipMemcpyDeviceToDevice, g.side));
+            const float* m = M + bt->P.off_M[i];
+            float* dst[3] = {g.Mx, g.My, g.Mc};
+            for (int q = 0; q < 3; ++q)
+                BCHK(bt, hipMemcpyAsync(dst[q] + j * g.nc(), m + q * g.nc(), g.nc() * sizeof(float),
+                                        hipMemcpyDeviceToDevice, g.side));
+        }
+        const int st = ot_dyn_init(g.plan, mode, g.F, g.Mx, g.My, g.Mc);
+        if (st != OT_OK) {
+            bt->err = ot_dyn_last_error(g.plan);
+            return st;
+        }
+        BCHK(bt, hipStreamSynchronize(g.side));
+    }
+    bt->warm = true;
     return OT_OK;
 }
 

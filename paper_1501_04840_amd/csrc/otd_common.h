@@ -83,7 +83,8 @@ void launch_resid_div(const StepArgs& s, hipStream_t st);
 void launch_init_state(const StepArgs& s, const float* f0, const float* f1,
                        int zero_unknowns, hipStream_t st);
 // b = b_bar = grad J(K x + c) / sigma from a caller-filled primal.
-void launch_init_dual(const StepArgs& s, hipStream_t st);
+// vfloor: per problem, the density floor of the velocity u / v (device)
+void launch_init_dual(const StepArgs& s, const double* vfloor, hipStream_t st);
 // zero the dual fields
 void launch_zero_dual(const StepArgs& s, hipStream_t st);
 // FP64 mass partials and input checks of f0, f1 ([B][C][Y][X]).

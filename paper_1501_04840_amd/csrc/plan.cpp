@@ -53,6 +53,7 @@ struct ot_dyn_plan {
     bool have_init;
     int total_iters;
     std::vector<double> mass0, mass1, fbm2;
+    std::vector<double> vfloor;     // per problem: 1e-3 * mean of f0 (warm-start dual)
     std::vector<double> r_prim, r_dual, r_div, cost, e_mass;
     double last_res;         // max(r_prim, r_dual) of the last check
     std::string err;
@@ -462,6 +463,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->nblk_bnd = L.nblk_bnd;
     const int B = p->g.B;
     p->mass0.assign(B, 0); p->mass1.assign(B, 0); p->fbm2.assign(B, 0);
+    p->vfloor.assign(B, 0);
     p->r_prim.assign(B, 0); p->r_dual.assign(B, 0); p->r_div.assign(B, 0);
     p->cost.assign(B, 0); p->e_mass.assign(B, 0);
     p->last_res = 1.0;
@@ -564,6 +566,7 @@ int ot_dyn_set_boundary(ot_dyn_plan* p, const float* f0, const float* f1) {
         }
         p->mass0[b] = m0;
         p->mass1[b] = m1;
+        p->vfloor[b] = 1e-3 * m0 / (double)g.slice;
         p->fbm2[b] = (double)g.st * g.st * (h[3 * B + b] + h[4 * B + b]);
     }
     p->have_boundary = true;
@@ -576,7 +579,12 @@ int ot_dyn_init(ot_dyn_plan* p, int mode, float* F, float* Mx, float* My, float*
     if (mode < OT_INIT_COLD || mode > OT_INIT_PRIMAL_DUAL) return OT_ERR_PARAM;
     const StepArgs s = step_args(p, F, Mx, My, Mc);
     launch_init_state(s, p->f0, p->f1, mode == OT_INIT_COLD ? 1 : 0, p->stream);
-    if (mode == OT_INIT_PRIMAL_DUAL) launch_init_dual(s, p->stream);
+    if (mode == OT_INIT_PRIMAL_DUAL) {
+        // the boundary-statistics scratch is free after set_boundary
+        HIPCHK(p, hipMemcpyAsync(p->part_bnd, p->vfloor.data(), p->vfloor.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, p->stream));
+        launch_init_dual(s, p->part_bnd, p->stream);
+    }
     else launch_zero_dual(s, p->stream);
     HIPCHK(p, hipGetLastError());
     p->have_init = true;

@@ -272,8 +272,10 @@ __global__ void __launch_bounds__(kBlock) k_zero_dual(StepArgs s) {
 }
 
 // b = b_bar = grad J(K x + c) / sigma (the dual that makes a given primal a
-// fixed point of Steps 2-4 when v > 0), with v floored at 1e-8.
-__global__ void __launch_bounds__(kBlock) k_init_dual(StepArgs s) {
+// fixed point of Steps 2-4 where v > 0), with v floored at vfloor[b]: at
+// nodes of (near) vacuum the fixed-point dual is not the gradient, and the
+// floor keeps the velocity u / v there near 0 instead of blowing it up.
+__global__ void __launch_bounds__(kBlock) k_init_dual(StepArgs s, const double* vfloor) {
     const Geom& g = s.g;
     const Node n = node_of(g);
     if (!n.live) return;
@@ -298,7 +300,7 @@ __global__ void __launch_bounds__(kBlock) k_init_dual(StepArgs s) {
     const float uy = 0.5f * (fy(n.y) + fy(n.y + 1));
     const float uc = 0.5f * (fc(n.c) + fc(n.c + 1));
     float v = 0.5f * (s.F[fidx(g, n.b, n.k, n.c, n.p)] + s.F[fidx(g, n.b, n.k + 1, n.c, n.p)]);
-    v = fmaxf(v, 1e-8f);
+    v = fmaxf(v, (float)vfloor[n.b]);
     const float is = 1.f / (s.sigma * v);
     const float bx = ux * is, by = uy * is, bc = uc * is;
     const float bf = -(ux * ux + uy * uy + uc * uc) * 0.5f * is / v;
@@ -375,8 +377,8 @@ void launch_init_state(const StepArgs& s, const float* f0, const float* f1,
                        zero_unknowns);
 }
 
-void launch_init_dual(const StepArgs& s, hipStream_t st) {
-    hipLaunchKernelGGL(k_init_dual, node_grid(s.g), dim3(kBlock), 0, st, s);
+void launch_init_dual(const StepArgs& s, const double* vfloor, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_dual, node_grid(s.g), dim3(kBlock), 0, st, s, vfloor);
 }
 
 void launch_zero_dual(const StepArgs& s, hipStream_t st) {

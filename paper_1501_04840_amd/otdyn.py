@@ -85,8 +85,8 @@ EXPORTS = [
     "ot_dyn_profile", "ot_dyn_profile_read",
     "ot_dyn_batch_workspace_size", "ot_dyn_batch_create", "ot_dyn_batch_offsets",
     "ot_dyn_batch_set_boundary", "ot_dyn_batch_autotune", "ot_dyn_batch_solve",
-    "ot_dyn_batch_problem", "ot_dyn_batch_get_state", "ot_dyn_batch_tuning",
-    "ot_dyn_batch_destroy", "ot_dyn_batch_last_error",
+    "ot_dyn_batch_problem", "ot_dyn_batch_get_state", "ot_dyn_batch_set_state",
+    "ot_dyn_batch_tuning", "ot_dyn_batch_destroy", "ot_dyn_batch_last_error",
 ]
 
 
@@ -123,6 +123,7 @@ def lib() -> ctypes.CDLL:
     L.ot_dyn_batch_solve.argtypes = [P, c_int, c_int, POINTER(ot_dyn_report)]
     L.ot_dyn_batch_problem.argtypes = [P, c_int, POINTER(ot_dyn_report)]
     L.ot_dyn_batch_get_state.argtypes = [P, P, P]
+    L.ot_dyn_batch_set_state.argtypes = [P, P, P, c_int]
     L.ot_dyn_batch_tuning.argtypes = [P, c_int, POINTER(c_int), POINTER(c_int)]
     L.ot_dyn_batch_destroy.argtypes = [P]
     L.ot_dyn_batch_last_error.argtypes = [P]
@@ -284,6 +285,10 @@ def ot_dyn_batch_get_state(bt: int, F, M) -> int:
     return _checkb(lib().ot_dyn_batch_get_state(bt, _ptr(F), _ptr(M)), bt)
 
 
+def ot_dyn_batch_set_state(bt: int, F, M, mode: int) -> int:
+    return _checkb(lib().ot_dyn_batch_set_state(bt, _ptr(F), _ptr(M), mode), bt)
+
+
 def ot_dyn_batch_tuning(bt: int, i: int):
     a, b = c_int(0), c_int(0)
     _check(lib().ot_dyn_batch_tuning(bt, i, byref(a), byref(b)))
@@ -412,6 +417,20 @@ class Batch:
         F = self._F[self.off_F[i]:self.off_F[i + 1]].reshape(P + 1, C, Y, X)
         M = self._M[self.off_M[i]:self.off_M[i + 1]].reshape(3, P, C, Y, X)
         return (F.cpu().numpy(), M[0].cpu().numpy(), M[1].cpu().numpy(), M[2].cpu().numpy())
+
+    def packed_state(self):
+        """Packed (F, M) device tensors of the whole batch (a copy)."""
+        import torch
+        F = torch.empty(self.off_F[-1], dtype=torch.float32, device=self.device)
+        M = torch.empty(self.off_M[-1], dtype=torch.float32, device=self.device)
+        ot_dyn_batch_get_state(self.bt, F, M)
+        return F, M
+
+    def set_state(self, F, M, mode: int = OT_INIT_PRIMAL_DUAL):
+        """Start the next solve from the packed state (F, M) (device)."""
+        import torch
+        torch.cuda.current_stream(self.device).synchronize()
+        return ot_dyn_batch_set_state(self.bt, F, M, mode)
 
     def close(self):
         if getattr(self, "bt", None):
