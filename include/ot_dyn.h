@@ -164,6 +164,14 @@ int ot_dyn_residuals(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
  * reset the accumulators. */
 int ot_dyn_profile(ot_dyn_plan* p, int mask);
 
+/* The dual iterate b of Algorithm 1 (Steps 2-4), copied to or from b
+ * [batch][4][P][C][Y][X] (device; components x, y, colour, time of the
+ * centred grid).  ot_dyn_set_dual also sets b_bar = b; call it after
+ * ot_dyn_init to start from a given primal-dual pair.  Asynchronous on the
+ * plan's stream. */
+int ot_dyn_get_dual(ot_dyn_plan* p, float* b);
+int ot_dyn_set_dual(ot_dyn_plan* p, const float* b);
+
 /* Synchronise the stream and return, per phase (n <= OT_PHASE_COUNT
  * entries), the accumulated milliseconds and launch counts since the last
  * ot_dyn_profile call.  ms and launches are host arrays of n entries. */
@@ -237,6 +245,13 @@ int ot_dyn_batch_problem(const ot_dyn_batch* bt, int i, ot_dyn_report* rep);
 
 /* Scatter the solution into the caller's packed F and M (device). */
 int ot_dyn_batch_get_state(ot_dyn_batch* bt, float* F, float* M);
+
+/* Packed duals (see ot_dyn_get_dual): problem i occupies 4 P_i C_i Y_i X_i
+ * floats at 4/3 of its offset in the packed M.  ot_dyn_batch_set_dual
+ * follows ot_dyn_batch_set_state (mode OT_INIT_PRIMAL) and replaces the
+ * starting dual (and b_bar) of the next solve. */
+int ot_dyn_batch_get_dual(ot_dyn_batch* bt, float* Bd);
+int ot_dyn_batch_set_dual(ot_dyn_batch* bt, const float* Bd);
 
 /* Selected launch shape of the group holding problem i (row_bx, dense_xy). */
 int ot_dyn_batch_tuning(const ot_dyn_batch* bt, int i, int* row_bx, int* dense_xy);

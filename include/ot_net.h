@@ -106,21 +106,41 @@ const char* ot_net_last_error(const ot_net* n);
  *   k * C + c), wall slots included (they read as 0).
  */
 
-/* x[batch][Y][X][2C] from the end densities. */
-int ot_warm_inputs(const ot_dyn_desc* d, int batch, const float* f0, const float* f1, float* x,
-                   void* stream);
+/* Network input x[batch][Y][X][2C (+ OUT)]: f0, f1 and, when base is not
+ * NULL, the OUT = C(P-1) + 3CP channels of base[batch][Y][X][OUT] (a state
+ * in the target layout, e.g. a prolonged coarse solution). */
+int ot_warm_inputs(const ot_dyn_desc* d, int batch, const float* f0, const float* f1,
+                   const float* base, float* x, void* stream);
 
-/* Training target t[batch][Y][X][C(P-1)+3CP] from a solver state. */
+/* Training target t[batch][Y][X][OUT] from a solver state, minus base when
+ * base is not NULL. */
 int ot_warm_targets(const ot_dyn_desc* d, int batch, const float* f0, const float* f1,
                     const float* F, long long sF, const float* Mx, const float* My,
-                    const float* Mc, long long sM, float* t, void* stream);
+                    const float* Mc, long long sM, const float* base, float* t, void* stream);
 
-/* Solver state from a network output y (layout of the targets): writes the
- * unknown slices of F and every slot of Mx, My, Mc (wall slots 0).  F's end
- * slices are written by ot_dyn_init. */
+/* Solver state from a network output y (layout of the targets; base added
+ * when not NULL): writes the unknown slices of F and every slot of Mx, My,
+ * Mc (wall slots 0).  F's end slices are written by ot_dyn_init. */
 int ot_warm_state(const ot_dyn_desc* d, int batch, const float* f0, const float* f1,
-                  const float* y, float* F, long long sF, float* Mx, float* My, float* Mc,
-                  long long sM, void* stream);
+                  const float* y, const float* base, float* F, long long sF, float* Mx,
+                  float* My, float* Mc, long long sM, void* stream);
+
+/* Coarse densities fc[batch][C][Y/2][X/2] = 2 x 2 block means of
+ * f[batch][C][Y][X] (X, Y of the fine desc, both even).  Means keep the
+ * total mass of a unit domain. */
+int ot_warm_restrict(const ot_dyn_desc* fine, int batch, const float* f, float* fc,
+                     void* stream);
+
+/* Prolong a coarse solver state (X/2, Y/2, the same C and boundary
+ * conditions, any P) to the fine grid: bilinear in space for cell-centred
+ * values (Neumann ends clamped, periodic ends wrapped), linear between
+ * faces for the staggered momenta (walls read as 0), linear in time.
+ * Writes the unknown slices of F and every slot of Mx, My, Mc; strides as
+ * above for both states. */
+int ot_warm_prolong(const ot_dyn_desc* coarse, const ot_dyn_desc* fine, int batch,
+                    const float* Fc, long long sFc, const float* Mxc, const float* Myc,
+                    const float* Mcc, long long sMc, float* F, long long sF, float* Mx,
+                    float* My, float* Mc, long long sM, void* stream);
 
 #ifdef __cplusplus
 }

@@ -500,6 +500,35 @@ int ot_dyn_batch_set_state(ot_dyn_batch* bt, const float* F, const float* M, int
     return OT_OK;
 }
 
+// Packed duals: problem i at 4 / 3 of its offset in the packed M.
+int ot_dyn_batch_get_dual(ot_dyn_batch* bt, float* Bd) {
+    if (!bt || !Bd) return OT_ERR_PARAM;
+    for (auto& g : bt->P.groups) {
+        for (size_t j = 0; j < g.members.size(); ++j) {
+            const int i = g.members[j];
+            const int st = plan_copy_dual(g.plan, (int)j, Bd + bt->P.off_M[i] / 3 * 4, 1);
+            if (st != OT_OK) { bt->err = ot_dyn_last_error(g.plan); return st; }
+        }
+        BCHK(bt, hipStreamSynchronize(g.side));
+    }
+    return OT_OK;
+}
+
+int ot_dyn_batch_set_dual(ot_dyn_batch* bt, const float* Bd) {
+    if (!bt || !Bd) return OT_ERR_PARAM;
+    if (!bt->warm) { bt->err = "set_dual follows set_state"; return OT_ERR_STATE; }
+    BCHK(bt, hipStreamSynchronize(bt->user));
+    for (auto& g : bt->P.groups) {
+        for (size_t j = 0; j < g.members.size(); ++j) {
+            const int i = g.members[j];
+            const int st = plan_copy_dual(g.plan, (int)j, const_cast<float*>(Bd + bt->P.off_M[i] / 3 * 4), 0);
+            if (st != OT_OK) { bt->err = ot_dyn_last_error(g.plan); return st; }
+        }
+        BCHK(bt, hipStreamSynchronize(g.side));
+    }
+    return OT_OK;
+}
+
 int ot_dyn_batch_tuning(const ot_dyn_batch* bt, int i, int* row_bx, int* dense_xy) {
     if (!bt || i < 0 || i >= bt->count) return OT_ERR_PARAM;
     const Group& g = bt->P.groups[bt->P.group_of[i]];

@@ -566,36 +566,72 @@ int ot_net_destroy(ot_net* n) {
 
 const char* ot_net_last_error(const ot_net* n) { return n ? n->err.c_str() : "null net"; }
 
-int ot_warm_inputs(const ot_dyn_desc* d, int batch, const float* f0, const float* f1, float* x,
-                   void* stream) {
+int ot_warm_inputs(const ot_dyn_desc* d, int batch, const float* f0, const float* f1,
+                   const float* base, float* x, void* stream) {
     int st = warm_check(d, batch);
     if (st != OT_OK) return st;
     if (!f0 || !f1 || !x) return OT_ERR_PARAM;
-    launch_warm_inputs(warm_geom(d), batch, f0, f1, x, (hipStream_t)stream);
+    launch_warm_inputs(warm_geom(d), batch, f0, f1, base, x, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
 }
 
 int ot_warm_targets(const ot_dyn_desc* d, int batch, const float* f0, const float* f1,
                     const float* F, long long sF, const float* Mx, const float* My,
-                    const float* Mc, long long sM, float* t, void* stream) {
+                    const float* Mc, long long sM, const float* base, float* t, void* stream) {
     int st = warm_check(d, batch);
     if (st != OT_OK) return st;
     if (!f0 || !f1 || !F || !Mx || !My || !Mc || !t) return OT_ERR_PARAM;
     const long long slice = (long long)d->X * d->Y * d->C;
     if (sF < slice * (d->P + 1) || sM < slice * d->P) return OT_ERR_SHAPE;
-    launch_warm_targets(warm_geom(d), batch, f0, f1, F, sF, Mx, My, Mc, sM, t, (hipStream_t)stream);
+    launch_warm_targets(warm_geom(d), batch, f0, f1, F, sF, Mx, My, Mc, sM, base, t,
+                        (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
 }
 
 int ot_warm_state(const ot_dyn_desc* d, int batch, const float* f0, const float* f1,
-                  const float* y, float* F, long long sF, float* Mx, float* My, float* Mc,
-                  long long sM, void* stream) {
+                  const float* y, const float* base, float* F, long long sF, float* Mx,
+                  float* My, float* Mc, long long sM, void* stream) {
     int st = warm_check(d, batch);
     if (st != OT_OK) return st;
     if (!f0 || !f1 || !F || !Mx || !My || !Mc || !y) return OT_ERR_PARAM;
     const long long slice = (long long)d->X * d->Y * d->C;
     if (sF < slice * (d->P + 1) || sM < slice * d->P) return OT_ERR_SHAPE;
-    launch_warm_state(warm_geom(d), batch, f0, f1, y, F, sF, Mx, My, Mc, sM, (hipStream_t)stream);
+    launch_warm_state(warm_geom(d), batch, f0, f1, y, base, F, sF, Mx, My, Mc, sM,
+                      (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
+}
+
+int ot_warm_restrict(const ot_dyn_desc* fine, int batch, const float* f, float* fc, void* stream) {
+    int st = warm_check(fine, batch);
+    if (st != OT_OK) return st;
+    if (!f || !fc) return OT_ERR_PARAM;
+    if (fine->X % 2 || fine->Y % 2) return OT_ERR_SHAPE;
+    otn::WarmGeom gc = warm_geom(fine);
+    gc.X /= 2;
+    gc.Y /= 2;
+    launch_restrict(gc, batch, f, fc, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
+}
+
+int ot_warm_prolong(const ot_dyn_desc* coarse, const ot_dyn_desc* fine, int batch,
+                    const float* Fc, long long sFc, const float* Mxc, const float* Myc,
+                    const float* Mcc, long long sMc, float* F, long long sF, float* Mx,
+                    float* My, float* Mc, long long sM, void* stream) {
+    int st = warm_check(coarse, batch);
+    if (st == OT_OK) st = warm_check(fine, batch);
+    if (st != OT_OK) return st;
+    if (!Fc || !Mxc || !Myc || !Mcc || !F || !Mx || !My || !Mc) return OT_ERR_PARAM;
+    if (fine->X != 2 * coarse->X || fine->Y != 2 * coarse->Y || fine->C != coarse->C)
+        return OT_ERR_SHAPE;
+    for (int a = 0; a < 3; ++a)
+        if (fine->bc[a] != coarse->bc[a]) return OT_ERR_SHAPE;
+    const long long slc = (long long)coarse->X * coarse->Y * coarse->C;
+    const long long slf = (long long)fine->X * fine->Y * fine->C;
+    if (sFc < slc * (coarse->P + 1) || sMc < slc * coarse->P || sF < slf * (fine->P + 1) ||
+        sM < slf * fine->P)
+        return OT_ERR_SHAPE;
+    launch_prolong(warm_geom(coarse), warm_geom(fine), batch, Fc, sFc, Mxc, Myc, Mcc, sMc, F, sF,
+                   Mx, My, Mc, sM, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
 }
 

@@ -70,13 +70,19 @@ struct WarmGeom {
     int X, Y, C, P;
     int perx, pery, perc;
 };
-void launch_warm_inputs(const WarmGeom& g, int nb, const float* f0, const float* f1, float* x,
-                        hipStream_t st);
+void launch_warm_inputs(const WarmGeom& g, int nb, const float* f0, const float* f1,
+                        const float* base, float* x, hipStream_t st);
 void launch_warm_targets(const WarmGeom& g, int nb, const float* f0, const float* f1,
                          const float* F, long long sF, const float* Mx, const float* My,
-                         const float* Mc, long long sM, float* t, hipStream_t st);
+                         const float* Mc, long long sM, const float* base, float* t,
+                         hipStream_t st);
 void launch_warm_state(const WarmGeom& g, int nb, const float* f0, const float* f1,
-                       const float* y, float* F, long long sF, float* Mx, float* My, float* Mc,
-                       long long sM, hipStream_t st);
+                       const float* y, const float* base, float* F, long long sF, float* Mx,
+                       float* My, float* Mc, long long sM, hipStream_t st);
+void launch_restrict(const WarmGeom& gc, int nb, const float* f, float* fc, hipStream_t st);
+void launch_prolong(const WarmGeom& gc, const WarmGeom& gf, int nb, const float* Fc,
+                    long long sFc, const float* Mxc, const float* Myc, const float* Mcc,
+                    long long sMc, float* F, long long sF, float* Mx, float* My, float* Mc,
+                    long long sM, hipStream_t st);
 
 }  // namespace otn

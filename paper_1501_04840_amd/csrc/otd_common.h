@@ -120,6 +120,9 @@ void plan_apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy);
 bool plan_has_fast_xy(const ot_dyn_plan* p);
 void plan_problem(const ot_dyn_plan* p, int b, ot_dyn_report* rep);
 void plan_add_iters(ot_dyn_plan* p, int n);
+// Copy the dual b of problem b to (to_packed = 1) or from (0, also b_bar) a
+// packed [4][P][C][Y][X] array; asynchronous on the plan's stream.
+int plan_copy_dual(ot_dyn_plan* p, int b, float* packed, int to_packed);
 
 // ---- reductions (stencil.hip) ------------------------------------------
 // out[q] = sum_j part[q * n + j] in FP64, for q < nq.

@@ -395,28 +395,35 @@ __global__ void __launch_bounds__(kThreads) k_param_map(const float* src, float*
 
 // ---- solver glue ----------------------------------------------------------
 
+// x[b][y][x] = (f0 channels, f1 channels, then base channels if base is given).
 __global__ void __launch_bounds__(kThreads) k_warm_inputs(WarmGeom g, int nb, const float* f0,
-                                                         const float* f1, float* x) {
+                                                         const float* f1, const float* base,
+                                                         float* x) {
     const long long plane = (long long)g.X * g.Y;
     const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (i >= nb * plane) return;
     const long long b = i / plane, p = i - b * plane;
-    float* o = x + i * 2 * g.C;
+    const int nch = g.C * (g.P - 1) + 3 * g.C * g.P;
+    const int in_ch = 2 * g.C + (base ? nch : 0);
+    float* o = x + i * in_ch;
     for (int c = 0; c < g.C; ++c) {
         o[c] = f0[(b * g.C + c) * plane + p];
         o[g.C + c] = f1[(b * g.C + c) * plane + p];
     }
+    if (base)
+        for (int q = 0; q < nch; ++q) o[2 * g.C + q] = base[i * nch + q];
 }
 
-// One thread per pixel; mode 0 writes the target from the state, mode 1 the
-// state from a network output.
+// One thread per pixel; mode 0 writes the target (state minus base) from
+// the state, mode 1 the state from a network output (plus base).
 template <int MODE>
 __global__ void __launch_bounds__(kThreads) k_warm_map(WarmGeom g, int nb, const float* f0,
                                                       const float* f1, const float* Fr, float* Fw,
                                                       long long sF, const float* Mxr,
                                                       const float* Myr, const float* Mcr,
                                                       float* Mxw, float* Myw, float* Mcw,
-                                                      long long sM, const float* yr, float* tw) {
+                                                      long long sM, const float* yr,
+                                                      const float* base, float* tw) {
     const long long plane = (long long)g.X * g.Y;
     const long long slice = plane * g.C;
     const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
@@ -433,10 +440,11 @@ __global__ void __launch_bounds__(kThreads) k_warm_map(WarmGeom g, int nb, const
             const float lin = (1.f - s) * f0[e] + s * f1[e];
             const long long fi = b * sF + k * slice + (long long)c * plane + p;
             const long long ti = tb + (k - 1) * C + c;
+            const float bs = base ? base[ti] : 0.f;
             if (MODE == 0)
-                tw[ti] = Fr[fi] - lin;
+                tw[ti] = Fr[fi] - lin - bs;
             else
-                Fw[fi] = lin + yr[ti];
+                Fw[fi] = lin + yr[ti] + bs;
         }
     }
     const long long o0 = (long long)C * (P - 1);
@@ -447,14 +455,130 @@ __global__ void __launch_bounds__(kThreads) k_warm_map(WarmGeom g, int nb, const
                 const bool wall = wallrow || (q == 2 && !g.perc && c == 0);
                 const long long mi = b * sM + k * slice + (long long)c * plane + p;
                 const long long ti = tb + o0 + ((long long)q * P + k) * C + c;
+                const float bs = base ? base[ti] : 0.f;
                 if (MODE == 0) {
                     const float* M = q == 0 ? Mxr : (q == 1 ? Myr : Mcr);
-                    tw[ti] = wall ? 0.f : M[mi];
+                    tw[ti] = wall ? 0.f : M[mi] - bs;
                 } else {
                     float* M = q == 0 ? Mxw : (q == 1 ? Myw : Mcw);
-                    M[mi] = wall ? 0.f : yr[ti];
+                    M[mi] = wall ? 0.f : yr[ti] + bs;
                 }
             }
+    }
+}
+
+// fc = 2 x 2 block means of f (coarse X, Y of gc; the fine grid is twice as
+// wide and high).
+__global__ void __launch_bounds__(kThreads) k_restrict(WarmGeom gc, int nb, const float* f,
+                                                      float* fc) {
+    const long long pc = (long long)gc.X * gc.Y;
+    const long long n = nb * gc.C * pc;
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const long long bc = i / pc, p = i - bc * pc;
+    const int x = (int)(p % gc.X), y = (int)(p / gc.X);
+    const int X = 2 * gc.X;
+    const float* s = f + bc * 4 * pc + (long long)(2 * y) * X + 2 * x;
+    fc[i] = 0.25f * (s[0] + s[1] + s[X] + s[X + 1]);
+}
+
+// Linear interpolation weight and the two neighbours of position u on an
+// axis of n samples at integer positions (clamped at the ends, or wrapped).
+struct Lerp {
+    int a, b;
+    float w;
+};
+__device__ inline Lerp lerp_at(float u, int n, int periodic) {
+    int i0 = (int)floorf(u);
+    Lerp r;
+    r.w = u - (float)i0;
+    if (periodic) {
+        r.a = ((i0 % n) + n) % n;
+        r.b = (r.a + 1) % n;
+    } else {
+        r.a = min(max(i0, 0), n - 1);
+        r.b = min(max(i0 + 1, 0), n - 1);
+    }
+    return r;
+}
+
+// Prolong a coarse state (X/2, Y/2, same C, P_c steps) to the fine grid:
+// bilinear in space for cell-centred values, linear between faces for the
+// staggered momenta (walls read as 0), linear in time.  Writes the unknown
+// slices of F and every slot of Mx, My, Mc.
+__global__ void __launch_bounds__(kThreads) k_prolong(WarmGeom gc, WarmGeom gf, int nb,
+                                                     const float* Fc, long long sFc,
+                                                     const float* Mxc, const float* Myc,
+                                                     const float* Mcc, long long sMc, float* F,
+                                                     long long sF, float* Mx, float* My,
+                                                     float* Mc, long long sM) {
+    const long long plane = (long long)gf.X * gf.Y;
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= nb * plane) return;
+    const long long b = i / plane, p = i - b * plane;
+    const int x = (int)(p % gf.X), y = (int)(p / gf.X);
+    const long long pc = (long long)gc.X * gc.Y, slc = pc * gc.C, slf = plane * gf.C;
+    const float rt = (float)gc.P / (float)gf.P;
+    // cell-centred positions of this fine cell on the coarse grid
+    const Lerp cx = lerp_at(0.5f * x - 0.25f, gc.X, gf.perx);
+    const Lerp cy = lerp_at(0.5f * y - 0.25f, gc.Y, gf.pery);
+    auto centred = [&](const float* A, long long off) -> float {
+        const float* r0 = A + off + (long long)cy.a * gc.X;
+        const float* r1 = A + off + (long long)cy.b * gc.X;
+        const float v0 = (1.f - cx.w) * r0[cx.a] + cx.w * r0[cx.b];
+        const float v1 = (1.f - cx.w) * r1[cx.a] + cx.w * r1[cx.b];
+        return (1.f - cy.w) * v0 + cy.w * v1;
+    };
+    // coarse face value along an axis: slot j of n faces, walls at 0 and n
+    auto face = [&](const float* row, int j, int n, int stride, int periodic) -> float {
+        if (periodic) return row[(long long)(((j % n) + n) % n) * stride];
+        return (j <= 0 || j >= n) ? 0.f : row[(long long)j * stride];
+    };
+    for (int k = 1; k < gf.P; ++k) {
+        float s = k * rt;
+        int j0 = min((int)floorf(s), gc.P - 1);
+        const float a = s - (float)j0;
+        for (int c = 0; c < gf.C; ++c) {
+            const long long o0 = b * sFc + j0 * slc + (long long)c * pc;
+            const float v = (1.f - a) * centred(Fc, o0) + a * centred(Fc, o0 + slc);
+            F[b * sF + k * slf + (long long)c * plane + p] = v;
+        }
+    }
+    for (int k = 0; k < gf.P; ++k) {
+        const Lerp ct = lerp_at((k + 0.5f) * rt - 0.5f, gc.P, 0);
+        for (int c = 0; c < gf.C; ++c) {
+            const long long mi = b * sM + k * slf + (long long)c * plane + p;
+            float vt[3] = {0.f, 0.f, 0.f};
+            for (int h = 0; h < 2; ++h) {
+                const int kc = h ? ct.b : ct.a;
+                const float wt = h ? ct.w : 1.f - ct.w;
+                const long long oc = b * sMc + kc * slc + (long long)c * pc;
+                // x faces: fine slot x sits at coarse face position x / 2
+                {
+                    const int j0 = x >> 1;
+                    const float w = (x & 1) ? 0.5f : 0.f;
+                    const float* r0 = Mxc + oc + (long long)cy.a * gc.X;
+                    const float* r1 = Mxc + oc + (long long)cy.b * gc.X;
+                    const float v0 = (1.f - w) * face(r0, j0, gc.X, 1, gf.perx) + w * face(r0, j0 + 1, gc.X, 1, gf.perx);
+                    const float v1 = (1.f - w) * face(r1, j0, gc.X, 1, gf.perx) + w * face(r1, j0 + 1, gc.X, 1, gf.perx);
+                    vt[0] += wt * ((1.f - cy.w) * v0 + cy.w * v1);
+                }
+                {
+                    const int j0 = y >> 1;
+                    const float w = (y & 1) ? 0.5f : 0.f;
+                    const float* c0 = Myc + oc + cx.a;
+                    const float* c1 = Myc + oc + cx.b;
+                    const float v0 = (1.f - w) * face(c0, j0, gc.Y, gc.X, gf.pery) + w * face(c0, j0 + 1, gc.Y, gc.X, gf.pery);
+                    const float v1 = (1.f - w) * face(c1, j0, gc.Y, gc.X, gf.pery) + w * face(c1, j0 + 1, gc.Y, gc.X, gf.pery);
+                    vt[1] += wt * ((1.f - cx.w) * v0 + cx.w * v1);
+                }
+                vt[2] += wt * centred(Mcc, oc);
+            }
+            const bool wx = !gf.perx && x == 0, wy = !gf.pery && y == 0, wc = !gf.perc && c == 0;
+            Mx[mi] = wx ? 0.f : vt[0];
+            My[mi] = wy ? 0.f : vt[1];
+            Mc[mi] = wc ? 0.f : vt[2];
+        }
     }
 }
 
@@ -538,28 +662,43 @@ void launch_param_map(const float* src, float* dst, int taps, int cin_o, int cou
                        cout_o, cin_p, cout_p, to_padded);
 }
 
-void launch_warm_inputs(const WarmGeom& g, int nb, const float* f0, const float* f1, float* x,
-                        hipStream_t st) {
+void launch_warm_inputs(const WarmGeom& g, int nb, const float* f0, const float* f1,
+                        const float* base, float* x, hipStream_t st) {
     const long long n = (long long)nb * g.X * g.Y;
-    hipLaunchKernelGGL(k_warm_inputs, dim3(blocks(n)), dim3(kThreads), 0, st, g, nb, f0, f1, x);
+    hipLaunchKernelGGL(k_warm_inputs, dim3(blocks(n)), dim3(kThreads), 0, st, g, nb, f0, f1, base, x);
 }
 
 void launch_warm_targets(const WarmGeom& g, int nb, const float* f0, const float* f1,
                          const float* F, long long sF, const float* Mx, const float* My,
-                         const float* Mc, long long sM, float* t, hipStream_t st) {
+                         const float* Mc, long long sM, const float* base, float* t,
+                         hipStream_t st) {
     const long long n = (long long)nb * g.X * g.Y;
     hipLaunchKernelGGL(k_warm_map<0>, dim3(blocks(n)), dim3(kThreads), 0, st, g, nb, f0, f1, F,
                        (float*)nullptr, sF, Mx, My, Mc, (float*)nullptr, (float*)nullptr,
-                       (float*)nullptr, sM, (const float*)nullptr, t);
+                       (float*)nullptr, sM, (const float*)nullptr, base, t);
 }
 
 void launch_warm_state(const WarmGeom& g, int nb, const float* f0, const float* f1,
-                       const float* y, float* F, long long sF, float* Mx, float* My, float* Mc,
-                       long long sM, hipStream_t st) {
+                       const float* y, const float* base, float* F, long long sF, float* Mx,
+                       float* My, float* Mc, long long sM, hipStream_t st) {
     const long long n = (long long)nb * g.X * g.Y;
     hipLaunchKernelGGL(k_warm_map<1>, dim3(blocks(n)), dim3(kThreads), 0, st, g, nb, f0, f1,
                        (const float*)nullptr, F, sF, (const float*)nullptr, (const float*)nullptr,
-                       (const float*)nullptr, Mx, My, Mc, sM, y, (float*)nullptr);
+                       (const float*)nullptr, Mx, My, Mc, sM, y, base, (float*)nullptr);
+}
+
+void launch_restrict(const WarmGeom& gc, int nb, const float* f, float* fc, hipStream_t st) {
+    const long long n = (long long)nb * gc.C * gc.X * gc.Y;
+    hipLaunchKernelGGL(k_restrict, dim3(blocks(n)), dim3(kThreads), 0, st, gc, nb, f, fc);
+}
+
+void launch_prolong(const WarmGeom& gc, const WarmGeom& gf, int nb, const float* Fc,
+                    long long sFc, const float* Mxc, const float* Myc, const float* Mcc,
+                    long long sMc, float* F, long long sF, float* Mx, float* My, float* Mc,
+                    long long sM, hipStream_t st) {
+    const long long n = (long long)nb * gf.X * gf.Y;
+    hipLaunchKernelGGL(k_prolong, dim3(blocks(n)), dim3(kThreads), 0, st, gc, gf, nb, Fc, sFc, Mxc,
+                       Myc, Mcc, sMc, F, sF, Mx, My, Mc, sM);
 }
 
 }  // namespace otn

@@ -651,6 +651,29 @@ int ot_dyn_residuals(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
     return cs;
 }
 
+int ot_dyn_get_dual(ot_dyn_plan* p, float* b) {
+    if (!p || !b) return OT_ERR_PARAM;
+    if (!p->have_init) { p->err = "ot_dyn_init must succeed first"; return OT_ERR_STATE; }
+    const size_t nc = (size_t)p->g.nc, w = nc * sizeof(float);
+    for (int q = 0; q < 4; ++q)
+        HIPCHK(p, hipMemcpy2DAsync(b + q * nc, 4 * w, p->b[q], w, w, p->g.B, hipMemcpyDeviceToDevice,
+                                   p->stream));
+    return OT_OK;
+}
+
+int ot_dyn_set_dual(ot_dyn_plan* p, const float* b) {
+    if (!p || !b) return OT_ERR_PARAM;
+    if (!p->have_init) { p->err = "ot_dyn_init must succeed first"; return OT_ERR_STATE; }
+    const size_t nc = (size_t)p->g.nc, w = nc * sizeof(float);
+    for (int q = 0; q < 4; ++q) {
+        HIPCHK(p, hipMemcpy2DAsync(p->b[q], w, b + q * nc, 4 * w, w, p->g.B, hipMemcpyDeviceToDevice,
+                                   p->stream));
+        HIPCHK(p, hipMemcpy2DAsync(p->bb[q], w, b + q * nc, 4 * w, w, p->g.B, hipMemcpyDeviceToDevice,
+                                   p->stream));
+    }
+    return OT_OK;
+}
+
 int ot_dyn_profile(ot_dyn_plan* p, int mask) {
     if (!p) return OT_ERR_PARAM;
     HIPCHK(p, hipStreamSynchronize(p->stream));
@@ -737,5 +760,22 @@ void plan_problem(const ot_dyn_plan* p, int b, ot_dyn_report* rep) {
 }
 
 void plan_add_iters(ot_dyn_plan* p, int n) { p->total_iters += n; }
+
+int plan_copy_dual(ot_dyn_plan* p, int b, float* packed, int to_packed) {
+    if (b < 0 || b >= p->g.B) return OT_ERR_PARAM;
+    const size_t nc = (size_t)p->g.nc, w = nc * sizeof(float);
+    for (int q = 0; q < 4; ++q) {
+        if (to_packed) {
+            HIPCHK(p, hipMemcpyAsync(packed + q * nc, p->b[q] + b * nc, w, hipMemcpyDeviceToDevice,
+                                     p->stream));
+        } else {
+            HIPCHK(p, hipMemcpyAsync(p->b[q] + b * nc, packed + q * nc, w, hipMemcpyDeviceToDevice,
+                                     p->stream));
+            HIPCHK(p, hipMemcpyAsync(p->bb[q] + b * nc, packed + q * nc, w, hipMemcpyDeviceToDevice,
+                                     p->stream));
+        }
+    }
+    return OT_OK;
+}
 
 }  // namespace otd

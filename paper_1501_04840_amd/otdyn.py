@@ -82,10 +82,11 @@ EXPORTS = [
     "ot_dyn_default_desc", "ot_dyn_workspace_size", "ot_dyn_create",
     "ot_dyn_set_boundary", "ot_dyn_init", "ot_dyn_step", "ot_dyn_solve",
     "ot_dyn_residuals", "ot_dyn_destroy", "ot_dyn_status_str", "ot_dyn_last_error",
-    "ot_dyn_profile", "ot_dyn_profile_read",
+    "ot_dyn_profile", "ot_dyn_profile_read", "ot_dyn_get_dual", "ot_dyn_set_dual",
     "ot_dyn_batch_workspace_size", "ot_dyn_batch_create", "ot_dyn_batch_offsets",
     "ot_dyn_batch_set_boundary", "ot_dyn_batch_autotune", "ot_dyn_batch_solve",
     "ot_dyn_batch_problem", "ot_dyn_batch_get_state", "ot_dyn_batch_set_state",
+    "ot_dyn_batch_get_dual", "ot_dyn_batch_set_dual",
     "ot_dyn_batch_tuning", "ot_dyn_batch_destroy", "ot_dyn_batch_last_error",
 ]
 
@@ -124,6 +125,10 @@ def lib() -> ctypes.CDLL:
     L.ot_dyn_batch_problem.argtypes = [P, c_int, POINTER(ot_dyn_report)]
     L.ot_dyn_batch_get_state.argtypes = [P, P, P]
     L.ot_dyn_batch_set_state.argtypes = [P, P, P, c_int]
+    L.ot_dyn_batch_get_dual.argtypes = [P, P]
+    L.ot_dyn_batch_set_dual.argtypes = [P, P]
+    L.ot_dyn_get_dual.argtypes = [P, P]
+    L.ot_dyn_set_dual.argtypes = [P, P]
     L.ot_dyn_batch_tuning.argtypes = [P, c_int, POINTER(c_int), POINTER(c_int)]
     L.ot_dyn_batch_destroy.argtypes = [P]
     L.ot_dyn_batch_last_error.argtypes = [P]
@@ -289,6 +294,22 @@ def ot_dyn_batch_set_state(bt: int, F, M, mode: int) -> int:
     return _checkb(lib().ot_dyn_batch_set_state(bt, _ptr(F), _ptr(M), mode), bt)
 
 
+def ot_dyn_batch_get_dual(bt: int, Bd) -> int:
+    return _checkb(lib().ot_dyn_batch_get_dual(bt, _ptr(Bd)), bt)
+
+
+def ot_dyn_batch_set_dual(bt: int, Bd) -> int:
+    return _checkb(lib().ot_dyn_batch_set_dual(bt, _ptr(Bd)), bt)
+
+
+def ot_dyn_get_dual(plan: int, b) -> int:
+    return _check(lib().ot_dyn_get_dual(plan, _ptr(b)), plan)
+
+
+def ot_dyn_set_dual(plan: int, b) -> int:
+    return _check(lib().ot_dyn_set_dual(plan, _ptr(b)), plan)
+
+
 def ot_dyn_batch_tuning(bt: int, i: int):
     a, b = c_int(0), c_int(0)
     _check(lib().ot_dyn_batch_tuning(bt, i, byref(a), byref(b)))
@@ -397,6 +418,13 @@ class Batch:
         torch.cuda.synchronize(self.device)
         return ot_dyn_batch_set_boundary(self.bt, self._h0, self._h1)
 
+    def set_boundary_packed(self, h0, h1):
+        """Boundary densities already packed in device memory (kept alive)."""
+        import torch
+        self._h0, self._h1 = h0, h1
+        torch.cuda.synchronize(self.device)
+        return ot_dyn_batch_set_boundary(self.bt, h0, h1)
+
     def autotune(self, trials: int = 10):
         return ot_dyn_batch_autotune(self.bt, trials)
 
@@ -425,6 +453,19 @@ class Batch:
         M = torch.empty(self.off_M[-1], dtype=torch.float32, device=self.device)
         ot_dyn_batch_get_state(self.bt, F, M)
         return F, M
+
+    def packed_dual(self):
+        """Packed duals of the whole batch (a copy, device)."""
+        import torch
+        Bd = torch.empty(self.off_M[-1] // 3 * 4, dtype=torch.float32, device=self.device)
+        ot_dyn_batch_get_dual(self.bt, Bd)
+        return Bd
+
+    def set_dual(self, Bd):
+        """Replace the starting dual of the next solve (after set_state)."""
+        import torch
+        torch.cuda.current_stream(self.device).synchronize()
+        return ot_dyn_batch_set_dual(self.bt, Bd)
 
     def set_state(self, F, M, mode: int = OT_INIT_PRIMAL_DUAL):
         """Start the next solve from the packed state (F, M) (device)."""

@@ -25,7 +25,8 @@ EXPORTS = [
     "ot_net_default_desc", "ot_net_param_count", "ot_net_workspace_size", "ot_net_create",
     "ot_net_set_params", "ot_net_get_params", "ot_net_forward", "ot_net_grad",
     "ot_net_train_step", "ot_net_destroy", "ot_net_last_error",
-    "ot_warm_inputs", "ot_warm_targets", "ot_warm_state",
+    "ot_warm_inputs", "ot_warm_targets", "ot_warm_state", "ot_warm_restrict",
+    "ot_warm_prolong",
 ]
 
 _done = False
@@ -52,9 +53,11 @@ def lib() -> ctypes.CDLL:
     L.ot_net_last_error.argtypes = [P]
     L.ot_net_last_error.restype = c_char_p
     DD = POINTER(ot_dyn_desc)
-    L.ot_warm_inputs.argtypes = [DD, c_int, P, P, P, P]
-    L.ot_warm_targets.argtypes = [DD, c_int, P, P, P, LL, P, P, P, LL, P, P]
-    L.ot_warm_state.argtypes = [DD, c_int, P, P, P, P, LL, P, P, P, LL, P]
+    L.ot_warm_inputs.argtypes = [DD, c_int, P, P, P, P, P]
+    L.ot_warm_targets.argtypes = [DD, c_int, P, P, P, LL, P, P, P, LL, P, P, P]
+    L.ot_warm_state.argtypes = [DD, c_int, P, P, P, P, P, LL, P, P, P, LL, P]
+    L.ot_warm_restrict.argtypes = [DD, c_int, P, P, P]
+    L.ot_warm_prolong.argtypes = [DD, DD, c_int, P, LL, P, P, P, LL, P, LL, P, P, P, LL, P]
     for name in EXPORTS:
         if name != "ot_net_last_error":
             getattr(L, name).restype = c_int
@@ -128,20 +131,33 @@ def ot_net_destroy(net) -> int:
     return _check(lib().ot_net_destroy(net))
 
 
-def ot_warm_inputs(d: ot_dyn_desc, batch, f0, f1, x, stream) -> int:
-    return _check(lib().ot_warm_inputs(byref(d), batch, _ptr(f0), _ptr(f1), _ptr(x),
+def ot_warm_inputs(d: ot_dyn_desc, batch, f0, f1, base, x, stream) -> int:
+    return _check(lib().ot_warm_inputs(byref(d), batch, _ptr(f0), _ptr(f1), _ptr(base), _ptr(x),
                                        c_void_p(stream)))
 
 
-def ot_warm_targets(d: ot_dyn_desc, batch, f0, f1, F, sF, Mx, My, Mc, sM, t, stream) -> int:
+def ot_warm_targets(d: ot_dyn_desc, batch, f0, f1, F, sF, Mx, My, Mc, sM, base, t,
+                    stream) -> int:
     return _check(lib().ot_warm_targets(byref(d), batch, _ptr(f0), _ptr(f1), _ptr(F), sF,
-                                        _ptr(Mx), _ptr(My), _ptr(Mc), sM, _ptr(t),
+                                        _ptr(Mx), _ptr(My), _ptr(Mc), sM, _ptr(base), _ptr(t),
                                         c_void_p(stream)))
 
 
-def ot_warm_state(d: ot_dyn_desc, batch, f0, f1, y, F, sF, Mx, My, Mc, sM, stream) -> int:
-    return _check(lib().ot_warm_state(byref(d), batch, _ptr(f0), _ptr(f1), _ptr(y), _ptr(F), sF,
-                                      _ptr(Mx), _ptr(My), _ptr(Mc), sM, c_void_p(stream)))
+def ot_warm_state(d: ot_dyn_desc, batch, f0, f1, y, base, F, sF, Mx, My, Mc, sM, stream) -> int:
+    return _check(lib().ot_warm_state(byref(d), batch, _ptr(f0), _ptr(f1), _ptr(y), _ptr(base),
+                                      _ptr(F), sF, _ptr(Mx), _ptr(My), _ptr(Mc), sM,
+                                      c_void_p(stream)))
+
+
+def ot_warm_restrict(d: ot_dyn_desc, batch, f, fc, stream) -> int:
+    return _check(lib().ot_warm_restrict(byref(d), batch, _ptr(f), _ptr(fc), c_void_p(stream)))
+
+
+def ot_warm_prolong(dc: ot_dyn_desc, df: ot_dyn_desc, batch, Fc, sFc, Mxc, Myc, Mcc, sMc,
+                    F, sF, Mx, My, Mc, sM, stream) -> int:
+    return _check(lib().ot_warm_prolong(byref(dc), byref(df), batch, _ptr(Fc), sFc, _ptr(Mxc),
+                                        _ptr(Myc), _ptr(Mcc), sMc, _ptr(F), sF, _ptr(Mx),
+                                        _ptr(My), _ptr(Mc), sM, c_void_p(stream)))
 
 
 def warm_channels(C: int, P: int) -> int:

@@ -190,22 +190,133 @@ def test_warm_targets_and_state_roundtrip(N):
     t = torch.empty((nb, Y, X, nch), dtype=torch.float32, device="cuda:0")
     sl = X * Y * C
     st = torch.cuda.current_stream().cuda_stream
-    N.ot_warm_targets(d, nb, dev(f0), dev(f1), dF, (P + 1) * sl, *dM, P * sl, t, st)
+    N.ot_warm_targets(d, nb, dev(f0), dev(f1), dF, (P + 1) * sl, *dM, P * sl, None, t, st)
     got = t.cpu().numpy()
     for b in range(nb):
         ref = _warm_targets_ref(F[b].astype(np.float64), *(m[b] for m in Ms), f0[b], f1[b], P)
         np.testing.assert_allclose(got[b], ref, rtol=1e-6, atol=1e-6)
     x = torch.empty((nb, Y, X, 2 * C), dtype=torch.float32, device="cuda:0")
-    N.ot_warm_inputs(d, nb, dev(f0), dev(f1), x, st)
+    N.ot_warm_inputs(d, nb, dev(f0), dev(f1), None, x, st)
     np.testing.assert_array_equal(x.cpu().numpy(),
                                   np.concatenate([f0, f1], axis=1).transpose(0, 2, 3, 1))
+    # with a base: targets subtract it, inputs append it, states add it back
+    base = dev(rng.standard_normal((nb, Y, X, nch)).astype(np.float32))
+    tb = torch.empty_like(t)
+    N.ot_warm_targets(d, nb, dev(f0), dev(f1), dF, (P + 1) * sl, *dM, P * sl, base, tb, st)
+    want = got - base.cpu().numpy()
+    o0 = C * (P - 1)                      # wall slots read as 0 whatever the base
+    want[:, :, 0, o0:o0 + P * C] = 0
+    want[:, 0, :, o0 + P * C:o0 + 2 * P * C] = 0
+    np.testing.assert_allclose(tb.cpu().numpy(), want, rtol=1e-5, atol=1e-5)
+    xb = torch.empty((nb, Y, X, 2 * C + nch), dtype=torch.float32, device="cuda:0")
+    N.ot_warm_inputs(d, nb, dev(f0), dev(f1), base, xb, st)
+    np.testing.assert_array_equal(xb.cpu().numpy()[..., 2 * C:], base.cpu().numpy())
     # state from the targets gives back the unknowns of F and all of M
     F2 = torch.zeros_like(dF)
     M2 = [torch.zeros_like(m) for m in dM]
-    N.ot_warm_state(d, nb, dev(f0), dev(f1), t, F2, (P + 1) * sl, *M2, P * sl, st)
+    N.ot_warm_state(d, nb, dev(f0), dev(f1), t, None, F2, (P + 1) * sl, *M2, P * sl, st)
     np.testing.assert_allclose(F2.cpu().numpy()[:, 1:P], F[:, 1:P], rtol=1e-6, atol=1e-6)
     for a, b in zip(M2, Ms):
         np.testing.assert_array_equal(a.cpu().numpy(), b)
+    F3 = torch.zeros_like(dF)
+    M3 = [torch.zeros_like(m) for m in dM]
+    N.ot_warm_state(d, nb, dev(f0), dev(f1), tb, base, F3, (P + 1) * sl, *M3, P * sl, st)
+    np.testing.assert_allclose(F3.cpu().numpy()[:, 1:P], F[:, 1:P], rtol=1e-5, atol=1e-5)
+    for a, b in zip(M3, Ms):
+        np.testing.assert_allclose(a.cpu().numpy(), b, rtol=1e-5, atol=1e-5)
+
+
+def _lerp(u, n):
+    i0 = int(np.floor(u))
+    w = u - i0
+    return min(max(i0, 0), n - 1), min(max(i0 + 1, 0), n - 1), w
+
+
+def _prolong_ref(Fc, Mxc, Myc, Mcc, X, Y, P):
+    """The prolongation written out from its definition in ot_net.h
+    (Neumann x and y), one fine entry at a time."""
+    Pc1, C, Yc, Xc = Fc.shape
+    Pc = Pc1 - 1
+    F = np.zeros((P + 1, C, Y, X))
+    Ms = [np.zeros((P, C, Y, X)) for _ in range(3)]
+
+    def cen(A, x, y):
+        xa, xb, wx = _lerp(0.5 * x - 0.25, Xc)
+        ya, yb, wy = _lerp(0.5 * y - 0.25, Yc)
+        return ((1 - wy) * ((1 - wx) * A[ya, xa] + wx * A[ya, xb])
+                + wy * ((1 - wx) * A[yb, xa] + wx * A[yb, xb]))
+
+    def xface(A, x, y):
+        fa = lambda row, j: 0.0 if j <= 0 or j >= Xc else row[j]
+        ya, yb, wy = _lerp(0.5 * y - 0.25, Yc)
+        j, w = x // 2, 0.5 * (x % 2)
+        v = [(1 - w) * fa(A[yy], j) + w * fa(A[yy], j + 1) for yy in (ya, yb)]
+        return (1 - wy) * v[0] + wy * v[1]
+
+    def yface(A, x, y):
+        fa = lambda col, j: 0.0 if j <= 0 or j >= Yc else col[j]
+        xa, xb, wx = _lerp(0.5 * x - 0.25, Xc)
+        j, w = y // 2, 0.5 * (y % 2)
+        v = [(1 - w) * fa(A[:, xx], j) + w * fa(A[:, xx], j + 1) for xx in (xa, xb)]
+        return (1 - wx) * v[0] + wx * v[1]
+
+    for k in range(1, P):
+        s = k * Pc / P
+        j0 = min(int(np.floor(s)), Pc - 1)
+        a = s - j0
+        for c in range(C):
+            for y in range(Y):
+                for x in range(X):
+                    F[k, c, y, x] = (1 - a) * cen(Fc[j0, c], x, y) + a * cen(Fc[j0 + 1, c], x, y)
+    for k in range(P):
+        ka, kb, wt = _lerp((k + 0.5) * Pc / P - 0.5, Pc)
+        for c in range(C):
+            for y in range(Y):
+                for x in range(X):
+                    vals = [0.0, 0.0, 0.0]
+                    for kk, ww in ((ka, 1 - wt), (kb, wt)):
+                        vals[0] += ww * xface(Mxc[kk, c], x, y)
+                        vals[1] += ww * yface(Myc[kk, c], x, y)
+                        vals[2] += ww * cen(Mcc[kk, c], x, y)
+                    Ms[0][k, c, y, x] = 0.0 if x == 0 else vals[0]
+                    Ms[1][k, c, y, x] = 0.0 if y == 0 else vals[1]
+                    Ms[2][k, c, y, x] = vals[2]
+    return F, Ms
+
+
+def test_restrict_and_prolong_match_their_definitions(N):
+    import torch
+    from paper_1501_04840_amd import otdyn
+    X, Y, C, P, Pc, nb = 12, 8, 3, 6, 4, 2
+    df = otdyn.ot_dyn_default_desc(X, Y, C, P)
+    dc = otdyn.ot_dyn_default_desc(X // 2, Y // 2, C, Pc)
+    rng = np.random.default_rng(10)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    f = rng.uniform(0, 1, (nb, C, Y, X))
+    fc = torch.empty((nb, C, Y // 2, X // 2), dtype=torch.float32, device="cuda:0")
+    N.ot_warm_restrict(df, nb, dev(f), fc, st)
+    ref = f.reshape(nb, C, Y // 2, 2, X // 2, 2).mean(axis=(3, 5))
+    np.testing.assert_allclose(fc.cpu().numpy(), ref, rtol=1e-6)
+    Fc = rng.standard_normal((nb, Pc + 1, C, Y // 2, X // 2))
+    Mc = [rng.standard_normal((nb, Pc, C, Y // 2, X // 2)) for _ in range(3)]
+    Mc[0][..., 0] = 0
+    Mc[1][..., 0, :] = 0
+    slc, slf = (X // 2) * (Y // 2) * C, X * Y * C
+    F = torch.zeros((nb, P + 1, C, Y, X), dtype=torch.float32, device="cuda:0")
+    Mf = [torch.zeros((nb, P, C, Y, X), dtype=torch.float32, device="cuda:0") for _ in range(3)]
+    N.ot_warm_prolong(dc, df, nb, dev(Fc), (Pc + 1) * slc, *(dev(m) for m in Mc), Pc * slc,
+                      F, (P + 1) * slf, *Mf, P * slf, st)
+    for b in range(nb):
+        Fr, Mr = _prolong_ref(Fc[b], *(m[b] for m in Mc), X, Y, P)
+        np.testing.assert_allclose(F.cpu().numpy()[b, 1:P], Fr[1:P], rtol=1e-5, atol=1e-5)
+        for q in range(3):
+            np.testing.assert_allclose(Mf[q].cpu().numpy()[b], Mr[q], rtol=1e-5, atol=1e-5)
+    # shapes that do not pair up are rejected
+    bad = otdyn.ot_dyn_default_desc(X // 2 + 1, Y // 2, C, Pc)
+    with pytest.raises(otdyn.OtDynError):
+        N.ot_warm_prolong(bad, df, nb, dev(Fc), (Pc + 1) * slc, *(dev(m) for m in Mc), Pc * slc,
+                          F, (P + 1) * slf, *Mf, P * slf, st)
 
 
 def test_warm_started_batch_certifies_at_once_from_a_solution(N):
