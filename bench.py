@@ -4,7 +4,8 @@
 Workload: RGB transport at 256 x 256 x 3 colours x 32 time steps (Neumann x,
 y, t; periodic colour), seeded smooth random densities (Gaussian-filtered
 uniform noise, sigma 4 px, exponentiated, normalised).  A step is one full
-iteration of Algorithm 1 (projection with refinement, prox, dual steps).
+iteration of Algorithm 1 (projection, prox, dual steps) in the library's
+default projection mode (the carried potential: one transform solve).
 
 Prints one JSON line: cell-iters/s (cells = X Y C P centred nodes), the
 per-phase split measured with HIP events on the solver's stream, the HBM
@@ -28,12 +29,33 @@ FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
 
 # Algorithmic traffic of each phase in FP32 words per centred node and launch
 # (each array element read or written once): see the design doc.
+# Algorithmic FP32 words per centred node and launch, per projection mode
+# (refine = 0 off, 1 refinement solve, 3 carried potential Phi):
+#   div     read x (4) + b_bar (4) (+ Phi), write a (4) + r (1)
+#   xform   read and write the potential once per pass
+#   refine  read a (4) + phi_1 (1), write r' (1)
+#   update  read a (4) + phi (1 or 2) + b (4) (+ Phi), write x (4) + b (4)
+#           + b_bar (4) (+ Phi)
+# Mode 3 also refines its first 64 iterations after initialisation; those
+# launches are counted by phase like any other (their update reads one more
+# word, not counted).
 WORDS = {
-    "div": 13,                 # read x (4) + b_bar (4), write a (4) + r (1)
+    "div": {0: 13, 1: 13, 3: 14},
     "xform_x": 2, "xform_y": 2, "tc": 2,
-    "refine": 6,               # read a (4) + phi_1 (1), write r' (1)
-    "update": {1: 21, 2: 22},  # read a (4) + phi(s) + b (4), write x (4) + b (4) + b_bar (4)
+    "refine": 6,
+    "update": {0: 21, 1: 22, 3: 23},
 }
+KERNELS = {                           # kernel name prefixes per phase and mode
+    "div": {0: "k_div_rows<0", 1: "k_div_rows<0", 3: "k_div_rows<2"},
+    "xform_x": "k_rows_fft", "xform_y": "k_cols_fft", "tc": "k_tc_reg",
+    "refine": "k_div_rows<1",
+    "update": {0: "k_update_rows<0, 1", 1: "k_update_rows<0, 2", 3: "k_update_rows<0, 3"},
+}
+
+
+def per_mode(table, name, mode):
+    v = table[name]
+    return v if not isinstance(v, dict) else v[mode]
 
 
 def kernel_sources_hash() -> str:
@@ -73,6 +95,24 @@ def cpu_baseline(f0, f1, X, Y, C, P, iters):
         "sample": f"{iters} iterations of the {X}x{Y}x{C}x{P} workload, FP64 NumPy/SciPy oracle "
                   f"(single-threaded), {dt:.1f} s",
     }
+
+
+def copy_ceiling(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Device-to-device copy rate (read + write bytes / s) of a 1 GiB buffer:
+    the practical HBM ceiling on this GPU, for context."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").uniform_()
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    gbs = 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    return gbs
 
 
 def hue_batch(args):
@@ -157,8 +197,9 @@ def main():
     ap.add_argument("--hue-sigma", type=float, default=0.33)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--refine", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--refine", type=int, default=None, choices=[0, 1, 3],
+                    help="projection mode (default: the library default)")
     ap.add_argument("--size", type=int, nargs=4, default=[256, 256, 3, 32],
                     metavar=("X", "Y", "C", "P"))
     ap.add_argument("--cpu-iters", type=int, default=4)
@@ -186,7 +227,9 @@ def main():
         f0, f1 = inputs.cfg3_pair(X, Y)
     N = X * Y * C * P
     d = otdyn.ot_dyn_default_desc(X, Y, C, P)
-    d.refine = args.refine
+    if args.refine is not None:
+        d.refine = args.refine
+    mode = d.refine
     prob = otdyn.Problem(d, "cuda:0")
     prob.set_boundary(torch.from_numpy(f0), torch.from_numpy(f1))
     prob.init(otdyn.OT_INIT_COLD)
@@ -204,33 +247,27 @@ def main():
     otdyn.ot_dyn_profile(prob.plan, 0)
     _, rep = prob.residuals()
     prob.close()
+    copy_gbs = copy_ceiling()
 
     K = args.steps
-    words_per_iter = {
-        "div": WORDS["div"],
-        "xform_x": 2 * 2 * (2 if args.refine == 1 else 1),
-        "xform_y": 2 * 2 * (2 if args.refine == 1 else 1),
-        "tc": 2 * (2 if args.refine == 1 else 1),
-        "refine": WORDS["refine"] if args.refine == 1 else 0,
-        "update": WORDS["update"][2 if args.refine == 1 else 1],
-    }
     split = {}
+    iter_words = 0.0
     for name, (ms, n) in phases.items():
         if n == 0:
             continue
-        gbs = words_per_iter[name] * 4.0 * N * K / (ms * 1e-3) / 1e9
+        words = per_mode(WORDS, name, mode)
+        iter_words += words * n / K
+        gbs = words * 4.0 * N * n / (ms * 1e-3) / 1e9
         split[name] = {"ms_per_iter": ms / K, "launches": n, "avg_launch_us": 1e3 * ms / n,
-                       "algorithmic_GBs": gbs}
+                       "words_per_launch": words, "algorithmic_GBs": gbs}
     dom = max(split, key=lambda k: split[k]["ms_per_iter"])
-    per_launch_bytes = words_per_iter[dom] * 4.0 * N * K / split[dom]["launches"]
+    per_launch_bytes = split[dom]["words_per_launch"] * 4.0 * N
     achieved = per_launch_bytes / (split[dom]["avg_launch_us"] * 1e-6) / 1e9
-    kernel_name = {"div": "k_div_rows<0", "xform_x": "k_rows_fft", "xform_y": "k_cols_fft",
-                   "tc": "k_tc_reg", "refine": "k_div_rows<1",
-                   "update": "k_update_rows<0, 2" if args.refine == 1 else "k_update_rows<0, 1"}[dom]
+    kernel_name = per_mode(KERNELS, dom, mode)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel_name),
             "kernel": kernel_name, "algorithmic_bytes_per_launch": per_launch_bytes}
-    iter_bytes = sum(words_per_iter.values()) * 4.0 * N
+    iter_bytes = iter_words * 4.0 * N
     out = {
         "metric": "cell-iters/s at 256x256x3x32",
         "value": N * K / dt,
@@ -241,10 +278,11 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {
             "workload": f"rgb_{X}x{Y}x{C}x{P}", "X": X, "Y": Y, "C": C, "P": P,
-            "bc": "neumann x,y,t; periodic colour", "refine": args.refine,
+            "bc": "neumann x,y,t; periodic colour", "refine": mode,
             "tau": d.tau, "sigma": d.sigma, "iteration_GBs_algorithmic": iter_bytes * K / dt / 1e9,
             "iteration_hbm_frac": iter_bytes * K / dt / 1e9 / HBM_PEAK_GBS,
             "phases": split, "r_div": rep.r_div, "e_mass": rep.e_mass,
+            "copy_GBs": copy_gbs,
         },
         "roofline": roof,
     }

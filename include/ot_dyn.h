@@ -69,6 +69,18 @@ extern "C" {
                                    the centred density floored at 1e-3 times
                                    the mean of f0 (near-vacuum nodes)        */
 
+/* FP32 accuracy of the projection onto the continuity constraint (Sec. 3,
+ * Step 1: x = a - A^T (A A^T)^+ (A a - f_b^-)).  The transform solve in FP32
+ * leaves an error proportional to |A a - f_b^-|; the modes differ in how it
+ * is reduced.  The projection is affine and Pi(a) = Pi(a - A^T Phi) for any
+ * potential Phi, which OT_REFINE_CARRY uses with the previous iteration's
+ * potential: the residual it solves for then vanishes as the iteration
+ * converges (one transform solve per iteration; the default). */
+#define OT_REFINE_OFF       0  /* one FP32 solve of the full residual            */
+#define OT_REFINE_ALWAYS    1  /* second solve for the residual of the first     */
+#define OT_REFINE_ADAPTIVE  2  /* OFF until max(r_prim, r_dual) < 1e-4, then ALWAYS */
+#define OT_REFINE_CARRY     3  /* one solve, started from the carried potential  */
+
 typedef struct ot_dyn_desc {
     int X, Y, C, P;        /* grid: X x Y pixels, C channels, P time steps; an
                               axis of size 1 is absent.  P >= 2.              */
@@ -81,8 +93,7 @@ typedef struct ot_dyn_desc {
     double tol_res;        /* stop when max(r_prim, r_dual) < tol_res ...     */
     double tol_div;        /* ... and r_div < tol_div                         */
     double tol_mass;       /* admissible |M0 - M1| / M0 of the end densities  */
-    int refine;            /* projection refinement: 0 off, 1 every
-                              iteration, 2 once max(r_prim, r_dual) < 1e-4    */
+    int refine;            /* FP32 accuracy of the projection: OT_REFINE_*  */
     int batch;             /* number of stacked problems of this shape (>= 1) */
 } ot_dyn_desc;
 
@@ -105,7 +116,7 @@ typedef struct ot_dyn_plan ot_dyn_plan;
 /* Fill *d with the defaults for an X x Y x C x P grid: bc = {Neumann,
  * Neumann, periodic}, extent = 1, tau = 10, sigma = 0.099, theta = 1,
  * check_every = 50, tol_res = 1e-6, tol_div = 1e-6, tol_mass = 1e-5,
- * refine = 1, batch = 1. */
+ * refine = OT_REFINE_CARRY, batch = 1. */
 int ot_dyn_default_desc(ot_dyn_desc* d, int X, int Y, int C, int P);
 
 /* Bytes of device workspace a plan for *d needs (OT_ERR_SHAPE/PARAM if *d

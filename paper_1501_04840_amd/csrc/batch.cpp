@@ -137,6 +137,7 @@ struct ot_dyn_batch {
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
     int graph_chunk = 0;
+    bool graph_varies = false;     // launch sequence changes after this graph
     std::vector<int> graph_groups;
     std::string err;
 };
@@ -169,9 +170,11 @@ void drop_graph(ot_dyn_batch* bt) {
 // graphs are launched on their streams and run concurrently.
 int build_graph(ot_dyn_batch* bt, int chunk) {
     drop_graph(bt);
+    bool varies = false;
     for (size_t gi = 0; gi < bt->P.groups.size(); ++gi) {
         Group& g = bt->P.groups[gi];
         if (!g.active) continue;
+        varies = varies || plan_launch_varies(g.plan);
         BCHK(bt, hipStreamBeginCapture(g.side, hipStreamCaptureModeThreadLocal));
         for (int it = 0; it < chunk; ++it)
             plan_iterate(g.plan, g.F, g.Mx, g.My, g.Mc, it + 1 == chunk);
@@ -182,6 +185,7 @@ int build_graph(ot_dyn_batch* bt, int chunk) {
         bt->graph_groups.push_back((int)gi);
     }
     bt->graph_chunk = chunk;
+    bt->graph_varies = varies;
     return OT_OK;
 }
 
@@ -377,7 +381,7 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
     int done = 0, status = OT_NOT_CONVERGED;
     while (done < max_iters) {
         const int k = std::min(chunk, max_iters - done);
-        if (bt->graph_groups.empty() || bt->graph_chunk != k || bt->base.refine == 2) {
+        if (bt->graph_groups.empty() || bt->graph_chunk != k || bt->graph_varies) {
             const int st = build_graph(bt, k);
             if (st != OT_OK) return st;
         }

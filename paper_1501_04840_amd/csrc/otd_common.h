@@ -54,6 +54,7 @@ struct StepArgs {
     float* A[4];         // staggered work arrays a_x, a_y, a_c, a_f
     float* R;            // residual r, transformed in place into phi_1
     float* R2;           // refinement: residual of x' = a + grad phi_1 -> phi_2
+    float* Phi;          // carried potential (sum of the previous phi_1), or null
     double* part_slice;  // [B*P*C][nbx] FP64 block partials of the plane sums of r
     double* part_red;    // [RS_COUNT][B][P*C*nbx] FP64 residual partials
     double* part_mass;   // [B*P*C][nbx] FP64 slice sums of f_new
@@ -64,10 +65,11 @@ struct StepArgs {
 
 // ---- stencil kernels (stencil.hip) -------------------------------------
 // mode 0: a from (x, b_bar); writes A and r into R.  mode 1 (refinement):
-// residual of x' = A + grad R into R2.
+// residual of x' = A + grad R into R2.  mode 2: as mode 0 with a + grad Phi.
 void launch_div(const StepArgs& s, int mode, hipStream_t st);
-// x = a + grad(phi_1) (+ grad(phi_2) if nphi == 2), prox, dual update;
-// residual partials if `check`.
+// x = a + grad(phi_1) (+ grad(phi_2) if nphi == 2 or 4), prox, dual update;
+// nphi == 3 and 4 also add the potentials into Phi; residual partials if
+// `check`.
 void launch_update(const StepArgs& s, int check, int nphi, hipStream_t st);
 // Row-marching variants (stencil_rows.hip), used when 1 <= C <= 4: one
 // thread per (b, k, y, x) for all colours, XCD-aware block order.  Their
@@ -79,7 +81,8 @@ void launch_div_rows(const StepArgs& s, int mode, hipStream_t st);
 void launch_update_rows(const StepArgs& s, int check, int nphi, hipStream_t st);
 // FP64 partials of |A x - f_b^-|^2 and of the slice masses of F.
 void launch_resid_div(const StepArgs& s, hipStream_t st);
-// Boundary slices, wall slots and (optionally) zero unknowns.
+// Boundary slices, wall slots and (optionally) zero unknowns; zeroes Phi
+// when it is set.
 void launch_init_state(const StepArgs& s, const float* f0, const float* f1,
                        int zero_unknowns, hipStream_t st);
 // b = b_bar = grad J(K x + c) / sigma from a caller-filled primal.
@@ -120,6 +123,10 @@ void plan_apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy);
 bool plan_has_fast_xy(const ot_dyn_plan* p);
 void plan_problem(const ot_dyn_plan* p, int b, ot_dyn_report* rep);
 void plan_add_iters(ot_dyn_plan* p, int n);
+// True while the launch sequence of the next iteration may differ from the
+// one after it (adaptive refinement; the refined start of OT_REFINE_CARRY):
+// a captured graph of iterations must then be captured again.
+bool plan_launch_varies(const ot_dyn_plan* p);
 // Copy the dual b of problem b to (to_packed = 1) or from (0, also b_bar) a
 // packed [4][P][C][Y][X] array; asynchronous on the plan's stream.
 int plan_copy_dual(ot_dyn_plan* p, int b, float* packed, int to_packed);

@@ -29,6 +29,7 @@ struct ot_dyn_plan {
     float* A[4];
     float* R;
     float* R2;
+    float* Phi;              // carried potential (OT_REFINE_CARRY), else null
     float* f0;
     float* f1;
     AxisTab tab[4];          // x, y, c, t
@@ -52,6 +53,7 @@ struct ot_dyn_plan {
     bool have_boundary;
     bool have_init;
     int total_iters;
+    int it_next;             // index of the next iteration to be issued
     std::vector<double> mass0, mass1, fbm2;
     std::vector<double> vfloor;     // per problem: 1e-3 * mean of f0 (warm-start dual)
     std::vector<double> r_prim, r_dual, r_div, cost, e_mass;
@@ -73,7 +75,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t off_b, off_bb, off_A, off_R, off_R2, off_f, off_tab[4], off_tw[4], off_tc64, off_tt64;
+    size_t off_b, off_bb, off_A, off_R, off_R2, off_Phi, off_f, off_tab[4], off_tw[4], off_tc64,
+        off_tt64;
     size_t off_pslice, off_pred, off_pdiv, off_pmass, off_pbnd, off_red;
     size_t total;
     int nbx, nbx_node, nblk_bnd;
@@ -135,8 +138,8 @@ int validate(const ot_dyn_desc* d, std::string* why) {
         return OT_ERR_PARAM;
     }
     if (d->check_every < 1 || !(d->tol_res > 0.0) || !(d->tol_div > 0.0) ||
-        !(d->tol_mass >= 0.0) || d->refine < 0 || d->refine > 2) {
-        if (why) *why = "need check_every >= 1, tol_res > 0, tol_div > 0, tol_mass >= 0, refine in {0,1,2}";
+        !(d->tol_mass >= 0.0) || d->refine < OT_REFINE_OFF || d->refine > OT_REFINE_CARRY) {
+        if (why) *why = "need check_every >= 1, tol_res > 0, tol_div > 0, tol_mass >= 0, refine in {0,1,2,3}";
         return OT_ERR_PARAM;
     }
     return OT_OK;
@@ -153,6 +156,7 @@ Layout layout_of(const ot_dyn_desc& d) {
     L.off_A = take(4 * ncT * sizeof(float));
     L.off_R = take(ncT * sizeof(float));
     L.off_R2 = take(ncT * sizeof(float));
+    L.off_Phi = take(d.refine == OT_REFINE_CARRY ? ncT * sizeof(float) : 0);
     L.off_f = take(2 * (size_t)g.B * g.slice * sizeof(float));
     const int ns[4] = {d.X, d.Y, d.C, d.P};
     for (int a = 0; a < 4; ++a) {
@@ -238,6 +242,7 @@ StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     for (int q = 0; q < 4; ++q) { s.b[q] = p->b[q]; s.bb[q] = p->bb[q]; s.A[q] = p->A[q]; }
     s.R = p->R;
     s.R2 = p->R2;
+    s.Phi = p->Phi;
     s.part_slice = p->part_slice;
     s.part_red = p->part_red;
     s.part_mass = p->part_mass;
@@ -303,14 +308,37 @@ void apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy) {
 }
 
 bool refine_now(const ot_dyn_plan* p) {
-    if (p->d.refine == 1) return true;
-    if (p->d.refine == 2) return p->last_res < 1e-4;
+    if (p->d.refine == OT_REFINE_ALWAYS) return true;
+    if (p->d.refine == OT_REFINE_ADAPTIVE) return p->last_res < 1e-4;
     return false;
 }
+
+// Iterations after ot_dyn_init that OT_REFINE_CARRY also refines: early on
+// the iterates move fast and the carried potential predicts little, so the
+// residual it leaves is as large as the plain one.
+constexpr int kCarryRefine = 64;
 
 // One iteration of Algorithm 1; residual partials when `check`.
 void iterate(ot_dyn_plan* p, const StepArgs& s, bool check) {
     hipStream_t st = p->stream;
+    const int it = p->it_next++;
+    if (p->d.refine == OT_REFINE_CARRY) {
+        // The projection is affine with Pi(a) = Pi(a + grad Phi) for any Phi
+        // (A^T annihilates constants and (A A^T)^+ A A^T Phi = Phi up to a
+        // constant), so start from the previous iterations' potential: a' =
+        // a + grad Phi, r' = A a' - f_b^-, phi_1 = (A A^T)^+ r', x = a' +
+        // grad phi_1, Phi += phi_1.  r' vanishes as the iterates converge,
+        // and with it the FP32 error of the transform solve.
+        timed(p, OT_PHASE_DIV, [&] { launch_div(s, 2, st); });
+        poisson(p, p->R);
+        const bool refine = it < kCarryRefine;
+        if (refine) {   // r'' = A (a' + grad phi_1) - f_b^-, phi_2 = (A A^T)^+ r''
+            timed(p, OT_PHASE_REFINE, [&] { launch_div(s, 1, st); });
+            poisson(p, p->R2);
+        }
+        timed(p, OT_PHASE_UPDATE, [&] { launch_update(s, check ? 1 : 0, refine ? 4 : 3, st); });
+        return;
+    }
     // a = x - tau sigma K^T b_bar, r = A a - f_b^-
     timed(p, OT_PHASE_DIV, [&] { launch_div(s, 0, st); });
     poisson(p, p->R);                      // phi_1 = (A A^T)^+ r
@@ -410,7 +438,7 @@ int ot_dyn_default_desc(ot_dyn_desc* d, int X, int Y, int C, int P) {
     d->tau = 10.0; d->sigma = 0.099; d->theta = 1.0;
     d->check_every = 50;
     d->tol_res = 1e-6; d->tol_div = 1e-6; d->tol_mass = 1e-5;
-    d->refine = 1;
+    d->refine = OT_REFINE_CARRY;
     d->batch = 1;
     return OT_OK;
 }
@@ -447,6 +475,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     }
     p->R = (float*)(p->ws + L.off_R);
     p->R2 = (float*)(p->ws + L.off_R2);
+    p->Phi = d->refine == OT_REFINE_CARRY ? (float*)(p->ws + L.off_Phi) : nullptr;
     p->f0 = (float*)(p->ws + L.off_f);
     p->f1 = p->f0 + (long long)p->g.B * p->g.slice;
     p->tc64 = (double*)(p->ws + L.off_tc64);
@@ -468,6 +497,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->cost.assign(B, 0); p->e_mass.assign(B, 0);
     p->last_res = 1.0;
     p->total_iters = 0;
+    p->it_next = 0;
     p->have_boundary = p->have_init = false;
     p->prof_mask = 0;
     p->ev_used = 0;
@@ -589,6 +619,7 @@ int ot_dyn_init(ot_dyn_plan* p, int mode, float* F, float* Mx, float* My, float*
     HIPCHK(p, hipGetLastError());
     p->have_init = true;
     p->total_iters = 0;
+    p->it_next = 0;
     p->last_res = 1.0;
     return OT_OK;
 }
@@ -760,6 +791,11 @@ void plan_problem(const ot_dyn_plan* p, int b, ot_dyn_report* rep) {
 }
 
 void plan_add_iters(ot_dyn_plan* p, int n) { p->total_iters += n; }
+
+bool plan_launch_varies(const ot_dyn_plan* p) {
+    if (p->d.refine == OT_REFINE_ADAPTIVE) return true;
+    return p->d.refine == OT_REFINE_CARRY && p->it_next < kCarryRefine;
+}
 
 int plan_copy_dual(ot_dyn_plan* p, int b, float* packed, int to_packed) {
     if (b < 0 || b >= p->g.B) return OT_ERR_PARAM;

@@ -38,7 +38,8 @@ __device__ inline Node node_of(const Geom& g) {
 // ---- the staggered work array a (Step 1 input) ---------------------------
 // a = x - tau sigma K^T b_bar on unknown faces; walls and absent faces are 0.
 // MODE 0 computes it from (x, b_bar).  MODE 1 (refinement) reads the first
-// projection x' = a + grad phi_1 from A and phi_1 = R on the fly.
+// projection x' = a + grad phi_1 from A and phi_1 = R on the fly.  MODE 2
+// adds the gradient of the carried potential Phi to the MODE 0 value.
 template <int MODE>
 struct FaceA {
     const StepArgs& s;
@@ -52,7 +53,8 @@ struct FaceA {
         const long long row = n.cb + (long long)n.y * g.X;
         const int xm = xx == 0 ? g.X - 1 : xx - 1;
         if (MODE == 1) return s.A[0][row + xx] + g.sx * (s.R[row + xx] - s.R[row + xm]);
-        return s.Mx[row + xx] - ts * (s.bb[0][row + xm] + s.bb[0][row + xx]);
+        const float v = s.Mx[row + xx] - ts * (s.bb[0][row + xm] + s.bb[0][row + xx]);
+        return MODE == 2 ? v + g.sx * (s.Phi[row + xx] - s.Phi[row + xm]) : v;
     }
     __device__ float y(int yy) const {
         const Geom& g = s.g;
@@ -62,7 +64,8 @@ struct FaceA {
         const int ym = yy == 0 ? g.Y - 1 : yy - 1;
         const long long im = n.cb + (long long)ym * g.X + n.x;
         if (MODE == 1) return s.A[1][i] + g.sy * (s.R[i] - s.R[im]);
-        return s.My[i] - ts * (s.bb[1][im] + s.bb[1][i]);
+        const float v = s.My[i] - ts * (s.bb[1][im] + s.bb[1][i]);
+        return MODE == 2 ? v + g.sy * (s.Phi[i] - s.Phi[im]) : v;
     }
     __device__ float c(int cc) const {
         const Geom& g = s.g;
@@ -72,7 +75,8 @@ struct FaceA {
         const int cm = cc == 0 ? g.C - 1 : cc - 1;
         const long long im = cidx(g, n.b, n.k, cm, n.p);
         if (MODE == 1) return s.A[2][i] + g.sc * (s.R[i] - s.R[im]);
-        return s.Mc[i] - ts * (s.bb[2][im] + s.bb[2][i]);
+        const float v = s.Mc[i] - ts * (s.bb[2][im] + s.bb[2][i]);
+        return MODE == 2 ? v + g.sc * (s.Phi[i] - s.Phi[im]) : v;
     }
     __device__ float f(int kk) const {   // time kk in [0, P]
         const Geom& g = s.g;
@@ -80,13 +84,14 @@ struct FaceA {
         const long long i = cidx(g, n.b, kk, n.c, n.p);
         const long long im = cidx(g, n.b, kk - 1, n.c, n.p);
         if (MODE == 1) return s.A[3][i] + g.st * (s.R[i] - s.R[im]);
-        return s.F[fidx(g, n.b, kk, n.c, n.p)] - ts * (s.bb[3][im] + s.bb[3][i]);
+        const float v = s.F[fidx(g, n.b, kk, n.c, n.p)] - ts * (s.bb[3][im] + s.bb[3][i]);
+        return MODE == 2 ? v + g.st * (s.Phi[i] - s.Phi[im]) : v;
     }
 };
 
 // r = A a - f_b^- (Step 1) with f_b^- folded in through F[0], F[P], and its
-// FP64 plane sums.  MODE 0 writes the own faces of a to A and r to R; MODE 1
-// writes the residual of the first projection to R2.
+// FP64 plane sums.  MODE 0 and MODE 2 write the own faces of a to A and r to
+// R; MODE 1 writes the residual of the first projection to R2.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_div(StepArgs s) {
     const Geom& g = s.g;
@@ -100,7 +105,7 @@ __global__ void __launch_bounds__(kBlock) k_div(StepArgs s) {
         const float r = g.sx * (ax1 - ax0) + g.sy * (ay1 - ay0) + g.sc * (ac1 - ac0) +
                         g.st * (af1 - af0);
         const long long i = n.cb + n.p;
-        if (MODE == 0) {
+        if (MODE != 1) {
             s.A[0][i] = ax0;
             s.A[1][i] = ay0;
             s.A[2][i] = ac0;
@@ -115,10 +120,13 @@ __global__ void __launch_bounds__(kBlock) k_div(StepArgs s) {
     if (threadIdx.x == 0) s.part_slice[(long long)blockIdx.y * s.nbx + blockIdx.x] = t;
 }
 
-// x^{r+1} = a + grad phi_1 (+ grad phi_2 when refined), z = prox(K x + c + b),
-// b and b_bar updates.
-template <int CHECK, int NPHI>
+// x^{r+1} = a + grad phi_1 (+ grad phi_2 when refined, NPHI 2 or 4),
+// z = prox(K x + c + b), b and b_bar updates.  NPHI 3 and 4: the carried
+// potential Phi takes the potentials on.
+template <int CHECK, int NPHI_>
 __global__ void __launch_bounds__(kBlock) k_update(StepArgs s) {
+    constexpr int NPHI = NPHI_ == 4 ? 2 : (NPHI_ == 3 ? 1 : NPHI_);
+    constexpr bool CARRY = NPHI_ >= 3;
     const Geom& g = s.g;
     const Node n = node_of(g);
     double db2 = 0, z2 = 0, dx2 = 0, x2 = 0, jj = 0;
@@ -192,6 +200,7 @@ __global__ void __launch_bounds__(kBlock) k_update(StepArgs s) {
         s.My[i] = my0;
         s.Mc[i] = mc0;
         if (n.k > 0) s.F[fi] = f0;
+        if (CARRY) s.Phi[i] = s.Phi[i] + (NPHI == 2 ? R[i] + R2[i] : R[i]);
     }
     if (CHECK) {
         const long long nblk = (long long)gridDim.x * gridDim.y;
@@ -253,6 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_init_state(StepArgs s, const float* 
     const long long e = (long long)n.b * g.slice + (long long)n.c * g.plane + n.p;
     if (n.k == 0) s.F[fidx(g, n.b, 0, n.c, n.p)] = f0[e];
     if (n.k == g.P - 1) s.F[fidx(g, n.b, g.P, n.c, n.p)] = f1[e];
+    if (s.Phi) s.Phi[i] = 0.f;
     if (zero) {
         s.Mx[i] = 0.f; s.My[i] = 0.f; s.Mc[i] = 0.f;
         if (n.k > 0) s.F[fidx(g, n.b, n.k, n.c, n.p)] = 0.f;
@@ -352,7 +362,8 @@ static dim3 node_grid(const Geom& g) {
 void launch_div(const StepArgs& s, int mode, hipStream_t st) {
     if (rows_ok(s.g)) { launch_div_rows(s, mode, st); return; }
     if (mode == 0) hipLaunchKernelGGL(k_div<0>, node_grid(s.g), dim3(kBlock), 0, st, s);
-    else hipLaunchKernelGGL(k_div<1>, node_grid(s.g), dim3(kBlock), 0, st, s);
+    else if (mode == 1) hipLaunchKernelGGL(k_div<1>, node_grid(s.g), dim3(kBlock), 0, st, s);
+    else hipLaunchKernelGGL(k_div<2>, node_grid(s.g), dim3(kBlock), 0, st, s);
 }
 
 void launch_update(const StepArgs& s, int check, int nphi, hipStream_t st) {
@@ -361,6 +372,12 @@ void launch_update(const StepArgs& s, int check, int nphi, hipStream_t st) {
     if (nphi == 2) {
         if (check) hipLaunchKernelGGL((k_update<1, 2>), gr, bl, 0, st, s);
         else hipLaunchKernelGGL((k_update<0, 2>), gr, bl, 0, st, s);
+    } else if (nphi == 3) {
+        if (check) hipLaunchKernelGGL((k_update<1, 3>), gr, bl, 0, st, s);
+        else hipLaunchKernelGGL((k_update<0, 3>), gr, bl, 0, st, s);
+    } else if (nphi == 4) {
+        if (check) hipLaunchKernelGGL((k_update<1, 4>), gr, bl, 0, st, s);
+        else hipLaunchKernelGGL((k_update<0, 4>), gr, bl, 0, st, s);
     } else {
         if (check) hipLaunchKernelGGL((k_update<1, 1>), gr, bl, 0, st, s);
         else hipLaunchKernelGGL((k_update<0, 1>), gr, bl, 0, st, s);

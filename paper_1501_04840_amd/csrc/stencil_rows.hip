@@ -64,8 +64,10 @@ __device__ inline Nbr neighbours(const Geom& g, int x, int y) {
 }
 
 // r = A a - f_b^- with a = x - tau sigma K^T b_bar (MODE 0: also writes a to A
-// and r to R) or a = A + grad phi_1 (MODE 1, refinement: writes r to R2), and
-// the FP64 plane sums of r (one partial per block and colour).
+// and r to R), a = A + grad phi_1 (MODE 1, refinement: writes r to R2) or
+// a = x - tau sigma K^T b_bar + grad Phi with the carried potential Phi
+// (MODE 2: writes a to A and r to R), and the FP64 plane sums of r (one
+// partial per block and colour).
 template <int MODE, int C>
 __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
     const Geom& g = s.g;
@@ -81,11 +83,12 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
         // colour faces first: own face c of every colour, into registers
         float acv[C];
         {
-            float w[C];
+            float w[C], q[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const long long i = r.i0 + (long long)c * g.plane;
-                w[c] = MODE == 0 ? s.bb[2][i] : s.R[i];
+                w[c] = MODE == 1 ? s.R[i] : s.bb[2][i];
+                q[c] = MODE == 2 ? s.Phi[i] : 0.f;
             }
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -93,8 +96,9 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
                 const long long i = r.i0 + (long long)c * g.plane;
                 const bool wall = !g.perc && c == 0;
                 float v;
-                if (MODE == 0) v = s.Mc[i] - ts * (w[cm] + w[c]);
-                else v = s.A[2][i] + g.sc * (w[c] - w[cm]);
+                if (MODE == 1) v = s.A[2][i] + g.sc * (w[c] - w[cm]);
+                else v = s.Mc[i] - ts * (w[cm] + w[c]);
+                if (MODE == 2) v += g.sc * (q[c] - q[cm]);
                 acv[c] = (wall || C == 1) ? 0.f : v;
             }
         }
@@ -103,7 +107,7 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
             const long long i = r.i0 + (long long)c * g.plane;
             const long long fi = r.f0 + (long long)c * g.plane;
             float ax0, ax1, ay0, ay1, af0, af1;
-            if (MODE == 0) {
+            if (MODE != 1) {
                 const float* bx = s.bb[0];
                 const float* by = s.bb[1];
                 const float* bt = s.bb[3];
@@ -115,6 +119,16 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
                 const float btc = bt[i];
                 af0 = k0 ? s.F[fi] : s.F[fi] - ts * (bt[i - sl] + btc);
                 af1 = k1 ? s.F[fi + sl] : s.F[fi + sl] - ts * (btc + bt[i + sl]);
+                if (MODE == 2) {           // + grad Phi on the unknown faces
+                    const float* Q = s.Phi;
+                    const float qc = Q[i];
+                    if (!nb.wx0) ax0 += g.sx * (qc - Q[i + nb.dxm]);
+                    if (!nb.wx1) ax1 += g.sx * (Q[i + nb.dxp] - qc);
+                    if (!nb.wy0) ay0 += g.sy * (qc - Q[i + nb.dym]);
+                    if (!nb.wy1) ay1 += g.sy * (Q[i + nb.dyp] - qc);
+                    if (!k0) af0 += g.st * (qc - Q[i - sl]);
+                    if (!k1) af1 += g.st * (Q[i + sl] - qc);
+                }
             } else {
                 const float* R = s.R;
                 const float pc = R[i];
@@ -129,7 +143,7 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
                               : (c + 1 < C ? acv[(c + 1) % C] : (g.perc ? acv[0] : 0.f));
             const float rr = g.sx * (ax1 - ax0) + g.sy * (ay1 - ay0) + g.sc * (ac1 - acv[c]) +
                              g.st * (af1 - af0);
-            if (MODE == 0) {
+            if (MODE != 1) {
                 s.A[0][i] = ax0;
                 s.A[1][i] = ay0;
                 s.A[2][i] = acv[c];
@@ -150,10 +164,14 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
     }
 }
 
-// x = a + grad phi_1 (+ grad phi_2), z = prox(K x + c + b), b and b_bar
-// updates, for all colours of a node; residual partials when CHECK.
-template <int CHECK, int NPHI, int C>
+// x = a + grad phi_1 (+ grad phi_2 when NPHI is 2 or 4), z = prox(K x + c +
+// b), b and b_bar updates, for all colours of a node; residual partials when
+// CHECK.  NPHI 3 and 4 (carried potential) also add the potentials into Phi
+// at the own node.
+template <int CHECK, int NPHI_, int C>
 __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
+    constexpr int NPHI = NPHI_ == 4 ? 2 : (NPHI_ == 3 ? 1 : NPHI_);
+    constexpr bool CARRY = NPHI_ >= 3;
     const Geom& g = s.g;
     const RowCtx r = row_ctx(g, nxb);
     double db2 = 0, z2 = 0, dx2 = 0, x2 = 0, jj = 0;
@@ -229,6 +247,7 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
             s.My[i] = my0;
             s.Mc[i] = mc0;
             if (!k0) s.F[fi] = f0;
+            if (CARRY) s.Phi[i] = s.Phi[i] + (NPHI == 2 ? pc + pc2 : pc);
         }
     }
     if (CHECK) {
@@ -255,7 +274,8 @@ template <int C>
 static void div_rows_c(const StepArgs& s, int mode, hipStream_t st) {
     const int bx = s.row_bx > 0 ? s.row_bx : row_block(s.g.X), nxb = (s.g.X + bx - 1) / bx;
     if (mode == 0) hipLaunchKernelGGL((k_div_rows<0, C>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
-    else hipLaunchKernelGGL((k_div_rows<1, C>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
+    else if (mode == 1) hipLaunchKernelGGL((k_div_rows<1, C>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
+    else hipLaunchKernelGGL((k_div_rows<2, C>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
 }
 
 template <int C>
@@ -265,6 +285,12 @@ static void update_rows_c(const StepArgs& s, int check, int nphi, hipStream_t st
     if (nphi == 2) {
         if (check) hipLaunchKernelGGL((k_update_rows<1, 2, C>), gr, bl, 0, st, s, nxb);
         else hipLaunchKernelGGL((k_update_rows<0, 2, C>), gr, bl, 0, st, s, nxb);
+    } else if (nphi == 3) {
+        if (check) hipLaunchKernelGGL((k_update_rows<1, 3, C>), gr, bl, 0, st, s, nxb);
+        else hipLaunchKernelGGL((k_update_rows<0, 3, C>), gr, bl, 0, st, s, nxb);
+    } else if (nphi == 4) {
+        if (check) hipLaunchKernelGGL((k_update_rows<1, 4, C>), gr, bl, 0, st, s, nxb);
+        else hipLaunchKernelGGL((k_update_rows<0, 4, C>), gr, bl, 0, st, s, nxb);
     } else {
         if (check) hipLaunchKernelGGL((k_update_rows<1, 1, C>), gr, bl, 0, st, s, nxb);
         else hipLaunchKernelGGL((k_update_rows<0, 1, C>), gr, bl, 0, st, s, nxb);

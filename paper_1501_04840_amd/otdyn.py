@@ -43,6 +43,11 @@ OT_INIT_COLD = 0
 OT_INIT_PRIMAL = 1
 OT_INIT_PRIMAL_DUAL = 2
 
+OT_REFINE_OFF = 0
+OT_REFINE_ALWAYS = 1
+OT_REFINE_ADAPTIVE = 2
+OT_REFINE_CARRY = 3
+
 
 class ot_dyn_desc(ctypes.Structure):
     _fields_ = [

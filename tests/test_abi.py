@@ -39,15 +39,15 @@ def test_default_desc_and_workspace(L):
     assert d.tau * d.sigma < 1 and d.theta == 1.0 and d.batch == 1
     n = L.ot_dyn_workspace_size(d)
     N = 256 * 256 * 3 * 32
-    assert n >= 14 * N * 4          # b, b_bar, a (4 fields each), r and r'
-    assert n < 15 * N * 4 + (1 << 24)
+    assert n >= 15 * N * 4          # b, b_bar, a (4 fields each), r, r' and Phi
+    assert n < 16 * N * 4 + (1 << 24)
     d.batch = 3
-    assert L.ot_dyn_workspace_size(d) > 3 * 14 * N * 4
+    assert L.ot_dyn_workspace_size(d) > 3 * 15 * N * 4
 
 
 @pytest.mark.parametrize("field,value,status", [
     ("P", 1, -2), ("X", 0, -2), ("C", 100, -2), ("tau", 20.0, -1), ("sigma", -1.0, -1),
-    ("theta", 1.5, -1), ("check_every", 0, -1), ("refine", 3, -1), ("batch", 0, -2),
+    ("theta", 1.5, -1), ("check_every", 0, -1), ("refine", 4, -1), ("refine", -1, -1), ("batch", 0, -2),
 ])
 def test_descriptor_validation(L, field, value, status):
     d = L.ot_dyn_default_desc(16, 16, 3, 8)

@@ -3,7 +3,9 @@
 Inputs are the seeded FP32-rounded densities of synth.inputs; the oracle gets
 the same arrays upcast to FP64.  Tolerance for floating-point results: 1e-5
 relative (L2) on the density and the transport cost, constraint residual
-below 1e-6 with the projection refinement on.
+below 1e-6.  The main cases run in both FP32 projection modes: a second
+(refinement) solve per iteration, and one solve started from the carried
+potential of the previous iteration (the library default).
 """
 import json
 import os
@@ -20,6 +22,7 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TOL = 1e-5
+MODES = [1, 3]          # OT_REFINE_ALWAYS, OT_REFINE_CARRY
 
 
 @pytest.fixture(scope="module")
@@ -35,11 +38,13 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def run_gpu(o, g, f0, f1, iters, tau=10.0, sigma=0.099, refine=1, batch=None):
+def run_gpu(o, g, f0, f1, iters, tau=10.0, sigma=0.099, refine=None, batch=None):
     import torch
     d = o.ot_dyn_default_desc(g.X, g.Y, g.C, g.P)
     d.bc[0], d.bc[1], d.bc[2] = g.bc
-    d.tau, d.sigma, d.refine = tau, sigma, refine
+    d.tau, d.sigma = tau, sigma
+    if refine is not None:
+        d.refine = refine
     B = 1 if batch is None else batch
     d.batch = B
     prob = o.Problem(d, "cuda")
@@ -84,13 +89,14 @@ SHAPES = [
 ]
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:4])))
-def test_iterates_match_oracle(otdyn, shape):
+def test_iterates_match_oracle(otdyn, shape, mode):
     X, Y, C, P, bc, iters = shape
-    _say(f"parity shape {shape}")
+    _say(f"parity shape {shape} mode {mode}")
     g = G.Grid(X, Y, C, P, bc)
     f0, f1 = inputs.random_pair(7 + X * Y + P, X, Y, C)
-    prob = run_gpu(otdyn, g, f0, f1, iters)
+    prob = run_gpu(otdyn, g, f0, f1, iters, refine=mode)
     F, Mx, My, Mc = host(prob)
     st = oracle(g, f0, f1, iters)
     gx = to_natural(g, F, Mx, My, Mc)
@@ -108,12 +114,13 @@ def test_iterates_match_oracle(otdyn, shape):
     prob.close()
 
 
-def test_cfg1_300_iterations(otdyn):
+@pytest.mark.parametrize("mode", MODES)
+def test_cfg1_300_iterations(otdyn, mode):
     """16 x 16 x 3 x 8, three anisotropic Gaussians per channel, 300 its."""
-    _say("cfg1 300 iterations")
+    _say(f"cfg1 300 iterations mode {mode}")
     g = G.Grid(16, 16, 3, 8)
     f0, f1 = inputs.cfg1_pair()
-    prob = run_gpu(otdyn, g, f0, f1, 299)
+    prob = run_gpu(otdyn, g, f0, f1, 299, refine=mode)
     st = oracle(g, f0, f1, 300)
     _, rep = prob.solve(1)       # the 300th iteration, with residuals
     F = host(prob)[0]
@@ -126,15 +133,16 @@ def test_cfg1_300_iterations(otdyn):
     prob.close()
 
 
-def test_cfg2_2000_iterations_against_stored_oracle(otdyn):
+@pytest.mark.parametrize("mode", MODES)
+def test_cfg2_2000_iterations_against_stored_oracle(otdyn, mode):
     """64 x 64 x 3 x 16 RGB bumps, 2000 its, against values written by
     tests/golden/make_golden.py (oracle only)."""
-    _say("cfg2 2000 iterations")
+    _say(f"cfg2 2000 iterations mode {mode}")
     gold = json.load(open(os.path.join(HERE, "golden", "cfg2_2000.json")))
     X, Y, C, P = gold["grid"]
     g = G.Grid(X, Y, C, P)
     f0, f1 = inputs.cfg2_pair()
-    prob = run_gpu(otdyn, g, f0, f1, gold["iters"] - 1, gold["tau"], gold["sigma"])
+    prob = run_gpu(otdyn, g, f0, f1, gold["iters"] - 1, gold["tau"], gold["sigma"], refine=mode)
     _, rep = prob.solve(1)
     F = host(prob)[0]
     f = F[1:P]
@@ -149,13 +157,14 @@ def test_cfg2_2000_iterations_against_stored_oracle(otdyn):
     prob.close()
 
 
-def test_cfg3_full_size_iterations(otdyn):
+@pytest.mark.parametrize("mode", MODES)
+def test_cfg3_full_size_iterations(otdyn, mode):
     """256 x 256 x 3 x 32 (the throughput workload, same launch shapes as the
     benchmark): three iterations compared element by element."""
-    _say("cfg3 3 iterations")
+    _say(f"cfg3 3 iterations mode {mode}")
     g = G.Grid(256, 256, 3, 32)
     f0, f1 = inputs.cfg3_pair()
-    prob = run_gpu(otdyn, g, f0, f1, 3)
+    prob = run_gpu(otdyn, g, f0, f1, 3, refine=mode)
     gx = to_natural(g, *host(prob))
     st = oracle(g, f0, f1, 3)
     assert rel(gx[3], st.x[3]) < TOL
@@ -164,11 +173,12 @@ def test_cfg3_full_size_iterations(otdyn):
     prob.close()
 
 
-def test_mass_and_divergence_invariants(otdyn):
-    _say("invariants")
+@pytest.mark.parametrize("mode", MODES)
+def test_mass_and_divergence_invariants(otdyn, mode):
+    _say(f"invariants mode {mode}")
     g = G.Grid(32, 24, 3, 10)
     f0, f1 = inputs.cfg2_pair(X=32, Y=24)
-    prob = run_gpu(otdyn, g, f0, f1, 49)
+    prob = run_gpu(otdyn, g, f0, f1, 49, refine=mode)
     _, rep = prob.solve(1)
     assert rep.r_div < 1e-6
     assert rep.e_mass < 1e-6
@@ -223,13 +233,15 @@ def test_determinism_and_resume(otdyn):
         np.testing.assert_array_equal(u, w)
 
 
-def test_solve_certifies_and_reports(otdyn):
-    _say("certified solve")
+@pytest.mark.parametrize("mode", MODES)
+def test_solve_certifies_and_reports(otdyn, mode):
+    _say(f"certified solve mode {mode}")
     import torch
     g = G.Grid(16, 16, 3, 8)
     f0, f1 = inputs.cfg1_pair()
     d = otdyn.ot_dyn_default_desc(16, 16, 3, 8)
     d.check_every = 100
+    d.refine = mode
     prob = otdyn.Problem(d, "cuda")
     prob.set_boundary(torch.from_numpy(f0), torch.from_numpy(f1))
     prob.init()
