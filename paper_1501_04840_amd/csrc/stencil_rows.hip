@@ -80,79 +80,111 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
         const Nbr nb = neighbours(g, r.x, r.y);
         const long long sl = g.slice;
         const bool k0 = r.k == 0, k1 = r.k + 1 == g.P;
-        // colour faces first: own face c of every colour, into registers
-        float acv[C];
-        {
-            float w[C], q[C];
+        if constexpr (MODE != 1) {
+            // Every operand of all colours is loaded before the first store:
+            // the stores to A and R may alias the inputs as far as the
+            // compiler knows, and interleaving would serialise the colours.
+            constexpr bool Q = MODE == 2;
+            const long long dtm = k0 ? 0 : -sl, dtp = k1 ? 0 : sl;   // clamped time steps
+            float X0[C], X1[C], Y0[C], Y1[C], MC[C], T0[C], T1[C];
+            float BXm[C], BXc[C], BXp[C], BYm[C], BYc[C], BYp[C], BC[C], BTm[C], BTc[C], BTp[C];
+            float Qc[C], Qxm[C], Qxp[C], Qym[C], Qyp[C], Qtm[C], Qtp[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const long long i = r.i0 + (long long)c * g.plane;
-                w[c] = MODE == 1 ? s.R[i] : s.bb[2][i];
-                q[c] = MODE == 2 ? s.Phi[i] : 0.f;
+                const long long fi = r.f0 + (long long)c * g.plane;
+                X0[c] = s.Mx[i]; X1[c] = s.Mx[i + nb.dxp];
+                Y0[c] = s.My[i]; Y1[c] = s.My[i + nb.dyp];
+                MC[c] = s.Mc[i];
+                T0[c] = s.F[fi]; T1[c] = s.F[fi + sl];
+                BXm[c] = s.bb[0][i + nb.dxm]; BXc[c] = s.bb[0][i]; BXp[c] = s.bb[0][i + nb.dxp];
+                BYm[c] = s.bb[1][i + nb.dym]; BYc[c] = s.bb[1][i]; BYp[c] = s.bb[1][i + nb.dyp];
+                BC[c] = s.bb[2][i];
+                BTm[c] = s.bb[3][i + dtm]; BTc[c] = s.bb[3][i]; BTp[c] = s.bb[3][i + dtp];
+                if constexpr (Q) {
+                    const float* P = s.Phi;
+                    Qc[c] = P[i];
+                    Qxm[c] = P[i + nb.dxm]; Qxp[c] = P[i + nb.dxp];
+                    Qym[c] = P[i + nb.dym]; Qyp[c] = P[i + nb.dyp];
+                    Qtm[c] = P[i + dtm]; Qtp[c] = P[i + dtp];
+                }
             }
+            float acv[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const int cm = c == 0 ? C - 1 : c - 1;
-                const long long i = r.i0 + (long long)c * g.plane;
-                const bool wall = !g.perc && c == 0;
-                float v;
-                if (MODE == 1) v = s.A[2][i] + g.sc * (w[c] - w[cm]);
-                else v = s.Mc[i] - ts * (w[cm] + w[c]);
-                if (MODE == 2) v += g.sc * (q[c] - q[cm]);
-                acv[c] = (wall || C == 1) ? 0.f : v;
+                float v = MC[c] - ts * (BC[cm] + BC[c]);
+                if constexpr (Q) v += g.sc * (Qc[c] - Qc[cm]);
+                acv[c] = ((!g.perc && c == 0) || C == 1) ? 0.f : v;
             }
-        }
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const long long i = r.i0 + (long long)c * g.plane;
-            const long long fi = r.f0 + (long long)c * g.plane;
-            float ax0, ax1, ay0, ay1, af0, af1;
-            if (MODE != 1) {
-                const float* bx = s.bb[0];
-                const float* by = s.bb[1];
-                const float* bt = s.bb[3];
-                const float bxc = bx[i], byc = by[i];
-                ax0 = nb.wx0 ? 0.f : s.Mx[i] - ts * (bx[i + nb.dxm] + bxc);
-                ax1 = nb.wx1 ? 0.f : s.Mx[i + nb.dxp] - ts * (bxc + bx[i + nb.dxp]);
-                ay0 = nb.wy0 ? 0.f : s.My[i] - ts * (by[i + nb.dym] + byc);
-                ay1 = nb.wy1 ? 0.f : s.My[i + nb.dyp] - ts * (byc + by[i + nb.dyp]);
-                const float btc = bt[i];
-                af0 = k0 ? s.F[fi] : s.F[fi] - ts * (bt[i - sl] + btc);
-                af1 = k1 ? s.F[fi + sl] : s.F[fi + sl] - ts * (btc + bt[i + sl]);
-                if (MODE == 2) {           // + grad Phi on the unknown faces
-                    const float* Q = s.Phi;
-                    const float qc = Q[i];
-                    if (!nb.wx0) ax0 += g.sx * (qc - Q[i + nb.dxm]);
-                    if (!nb.wx1) ax1 += g.sx * (Q[i + nb.dxp] - qc);
-                    if (!nb.wy0) ay0 += g.sy * (qc - Q[i + nb.dym]);
-                    if (!nb.wy1) ay1 += g.sy * (Q[i + nb.dyp] - qc);
-                    if (!k0) af0 += g.st * (qc - Q[i - sl]);
-                    if (!k1) af1 += g.st * (Q[i + sl] - qc);
+            for (int c = 0; c < C; ++c) {
+                float ax0 = X0[c] - ts * (BXm[c] + BXc[c]);
+                float ax1 = X1[c] - ts * (BXc[c] + BXp[c]);
+                float ay0 = Y0[c] - ts * (BYm[c] + BYc[c]);
+                float ay1 = Y1[c] - ts * (BYc[c] + BYp[c]);
+                float af0 = T0[c] - ts * (BTm[c] + BTc[c]);
+                float af1 = T1[c] - ts * (BTc[c] + BTp[c]);
+                if constexpr (Q) {           // + grad Phi on the unknown faces
+                    ax0 += g.sx * (Qc[c] - Qxm[c]);
+                    ax1 += g.sx * (Qxp[c] - Qc[c]);
+                    ay0 += g.sy * (Qc[c] - Qym[c]);
+                    ay1 += g.sy * (Qyp[c] - Qc[c]);
+                    af0 += g.st * (Qc[c] - Qtm[c]);
+                    af1 += g.st * (Qtp[c] - Qc[c]);
                 }
-            } else {
-                const float* R = s.R;
-                const float pc = R[i];
-                ax0 = nb.wx0 ? 0.f : s.A[0][i] + g.sx * (pc - R[i + nb.dxm]);
-                ax1 = nb.wx1 ? 0.f : s.A[0][i + nb.dxp] + g.sx * (R[i + nb.dxp] - pc);
-                ay0 = nb.wy0 ? 0.f : s.A[1][i] + g.sy * (pc - R[i + nb.dym]);
-                ay1 = nb.wy1 ? 0.f : s.A[1][i + nb.dyp] + g.sy * (R[i + nb.dyp] - pc);
-                af0 = k0 ? s.F[fi] : s.A[3][i] + g.st * (pc - R[i - sl]);
-                af1 = k1 ? s.F[fi + sl] : s.A[3][i + sl] + g.st * (R[i + sl] - pc);
-            }
-            const float ac1 = C == 1 ? 0.f
-                              : (c + 1 < C ? acv[(c + 1) % C] : (g.perc ? acv[0] : 0.f));
-            const float rr = g.sx * (ax1 - ax0) + g.sy * (ay1 - ay0) + g.sc * (ac1 - acv[c]) +
-                             g.st * (af1 - af0);
-            if (MODE != 1) {
+                ax0 = nb.wx0 ? 0.f : ax0;
+                ax1 = nb.wx1 ? 0.f : ax1;
+                ay0 = nb.wy0 ? 0.f : ay0;
+                ay1 = nb.wy1 ? 0.f : ay1;
+                af0 = k0 ? T0[c] : af0;      // boundary slices are data
+                af1 = k1 ? T1[c] : af1;
+                const float ac1 = C == 1 ? 0.f
+                                  : (c + 1 < C ? acv[(c + 1) % C] : (g.perc ? acv[0] : 0.f));
+                const float rr = g.sx * (ax1 - ax0) + g.sy * (ay1 - ay0) + g.sc * (ac1 - acv[c]) +
+                                 g.st * (af1 - af0);
+                const long long i = r.i0 + (long long)c * g.plane;
                 s.A[0][i] = ax0;
                 s.A[1][i] = ay0;
                 s.A[2][i] = acv[c];
                 s.A[3][i] = k0 ? 0.f : af0;
                 s.R[i] = rr;
-            } else {
-                s.R2[i] = rr;
+                rv[c] = rr;
             }
-            rv[c] = rr;
+        } else {
+            // colour faces first: own face c of every colour, into registers
+            float acv[C];
+            {
+                float w[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) w[c] = s.R[r.i0 + (long long)c * g.plane];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int cm = c == 0 ? C - 1 : c - 1;
+                    const long long i = r.i0 + (long long)c * g.plane;
+                    const float v = s.A[2][i] + g.sc * (w[c] - w[cm]);
+                    acv[c] = ((!g.perc && c == 0) || C == 1) ? 0.f : v;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const long long i = r.i0 + (long long)c * g.plane;
+                const long long fi = r.f0 + (long long)c * g.plane;
+                const float* R = s.R;
+                const float pc = R[i];
+                const float ax0 = nb.wx0 ? 0.f : s.A[0][i] + g.sx * (pc - R[i + nb.dxm]);
+                const float ax1 = nb.wx1 ? 0.f : s.A[0][i + nb.dxp] + g.sx * (R[i + nb.dxp] - pc);
+                const float ay0 = nb.wy0 ? 0.f : s.A[1][i] + g.sy * (pc - R[i + nb.dym]);
+                const float ay1 = nb.wy1 ? 0.f : s.A[1][i + nb.dyp] + g.sy * (R[i + nb.dyp] - pc);
+                const float af0 = k0 ? s.F[fi] : s.A[3][i] + g.st * (pc - R[i - sl]);
+                const float af1 = k1 ? s.F[fi + sl] : s.A[3][i + sl] + g.st * (R[i + sl] - pc);
+                const float ac1 = C == 1 ? 0.f
+                                  : (c + 1 < C ? acv[(c + 1) % C] : (g.perc ? acv[0] : 0.f));
+                const float rr = g.sx * (ax1 - ax0) + g.sy * (ay1 - ay0) + g.sc * (ac1 - acv[c]) +
+                                 g.st * (af1 - af0);
+                s.R2[i] = rr;
+                rv[c] = rr;
+            }
         }
     }
     const long long col = (long long)r.y * nxb + r.xb;
@@ -172,6 +204,7 @@ template <int CHECK, int NPHI_, int C>
 __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
     constexpr int NPHI = NPHI_ == 4 ? 2 : (NPHI_ == 3 ? 1 : NPHI_);
     constexpr bool CARRY = NPHI_ >= 3;
+    constexpr bool TWO = NPHI == 2;
     const Geom& g = s.g;
     const RowCtx r = row_ctx(g, nxb);
     double db2 = 0, z2 = 0, dx2 = 0, x2 = 0, jj = 0;
@@ -179,46 +212,72 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
         const Nbr nb = neighbours(g, r.x, r.y);
         const long long sl = g.slice;
         const bool k0 = r.k == 0, k1 = r.k + 1 == g.P;
-        // phi_2 (the refinement) is much smaller than phi_1: difference the
-        // two separately so that its low-order bits survive
-        float ph[C], ph2[C], mcv[C];
+        const long long dtm = k0 ? 0 : -sl, dtp = k1 ? 0 : sl;   // clamped time steps
+        // Loads of all colours first (the stores below may alias them as far
+        // as the compiler knows).  Time faces read the boundary slice of F
+        // at k = 0 and k = P, else the work array a.
+        float A0c[C], A0p[C], A1c[C], A1p[C], A2c[C], T0[C], T1[C];
+        float Rc[C], Rxm[C], Rxp[C], Rym[C], Ryp[C], Rtm[C], Rtp[C];
+        float Sc[C], Sxm[C], Sxp[C], Sym[C], Syp[C], Stm[C], Stp[C];   // phi_2
+        float B0[C], B1[C], B2[C], B3[C], Qc[C], O0[C], O1[C], O2[C], O3[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            ph[c] = s.R[r.i0 + (long long)c * g.plane];
-            ph2[c] = NPHI == 2 ? s.R2[r.i0 + (long long)c * g.plane] : 0.f;
+            const long long i = r.i0 + (long long)c * g.plane;
+            const long long fi = r.f0 + (long long)c * g.plane;
+            A0c[c] = s.A[0][i]; A0p[c] = s.A[0][i + nb.dxp];
+            A1c[c] = s.A[1][i]; A1p[c] = s.A[1][i + nb.dyp];
+            A2c[c] = s.A[2][i];
+            T0[c] = k0 ? s.F[fi] : s.A[3][i];
+            T1[c] = k1 ? s.F[fi + sl] : s.A[3][i + sl];
+            const float* R = s.R;
+            Rc[c] = R[i];
+            Rxm[c] = R[i + nb.dxm]; Rxp[c] = R[i + nb.dxp];
+            Rym[c] = R[i + nb.dym]; Ryp[c] = R[i + nb.dyp];
+            Rtm[c] = R[i + dtm]; Rtp[c] = R[i + dtp];
+            if constexpr (TWO) {
+                const float* R2 = s.R2;
+                Sc[c] = R2[i];
+                Sxm[c] = R2[i + nb.dxm]; Sxp[c] = R2[i + nb.dxp];
+                Sym[c] = R2[i + nb.dym]; Syp[c] = R2[i + nb.dyp];
+                Stm[c] = R2[i + dtm]; Stp[c] = R2[i + dtp];
+            }
+            B0[c] = s.b[0][i]; B1[c] = s.b[1][i]; B2[c] = s.b[2][i]; B3[c] = s.b[3][i];
+            if constexpr (CARRY) Qc[c] = s.Phi[i];
+            if constexpr (CHECK) {
+                O0[c] = s.Mx[i]; O1[c] = s.My[i]; O2[c] = s.Mc[i];
+                O3[c] = k0 ? 0.f : s.F[fi];
+            }
         }
-        // grad of the potential from the own node (value pair p1, p2) to j
-        auto dfrom = [&](float p1, float p2, long long j) -> float {
-            return NPHI == 2 ? (p1 - s.R[j]) + (p2 - s.R2[j]) : p1 - s.R[j];
+        // grad of the potential(s) between a cell pair (lo, hi): phi_2 (the
+        // refinement) is much smaller than phi_1, so difference the two
+        // separately and keep its low-order bits
+        auto dphi = [&](float hi, float lo, float hi2, float lo2) -> float {
+            return TWO ? (hi - lo) + (hi2 - lo2) : hi - lo;
         };
-        auto dto = [&](long long j, float p1, float p2) -> float {
-            return NPHI == 2 ? (s.R[j] - p1) + (s.R2[j] - p2) : s.R[j] - p1;
-        };
+        float mcv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int cm = c == 0 ? C - 1 : c - 1;
-            const bool wall = !g.perc && c == 0;
-            const float d = NPHI == 2 ? (ph[c] - ph[cm]) + (ph2[c] - ph2[cm]) : ph[c] - ph[cm];
-            const float v = s.A[2][r.i0 + (long long)c * g.plane] + g.sc * d;
-            mcv[c] = (wall || C == 1) ? 0.f : v;
+            const float v = A2c[c] + g.sc * dphi(Rc[c], Rc[cm], TWO ? Sc[c] : 0.f, TWO ? Sc[cm] : 0.f);
+            mcv[c] = ((!g.perc && c == 0) || C == 1) ? 0.f : v;
         }
         const float th = s.theta;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const long long i = r.i0 + (long long)c * g.plane;
             const long long fi = r.f0 + (long long)c * g.plane;
-            const float pc = ph[c], pc2 = ph2[c];
-            const float mx0 = nb.wx0 ? 0.f : s.A[0][i] + g.sx * dfrom(pc, pc2, i + nb.dxm);
-            const float mx1 = nb.wx1 ? 0.f : s.A[0][i + nb.dxp] + g.sx * dto(i + nb.dxp, pc, pc2);
-            const float my0 = nb.wy0 ? 0.f : s.A[1][i] + g.sy * dfrom(pc, pc2, i + nb.dym);
-            const float my1 = nb.wy1 ? 0.f : s.A[1][i + nb.dyp] + g.sy * dto(i + nb.dyp, pc, pc2);
-            const float f0 = k0 ? s.F[fi] : s.A[3][i] + g.st * dfrom(pc, pc2, i - sl);
-            const float f1 = k1 ? s.F[fi + sl] : s.A[3][i + sl] + g.st * dto(i + sl, pc, pc2);
+            const float s0 = TWO ? Sc[c] : 0.f;
+            const float mx0 = nb.wx0 ? 0.f : A0c[c] + g.sx * dphi(Rc[c], Rxm[c], s0, TWO ? Sxm[c] : 0.f);
+            const float mx1 = nb.wx1 ? 0.f : A0p[c] + g.sx * dphi(Rxp[c], Rc[c], TWO ? Sxp[c] : 0.f, s0);
+            const float my0 = nb.wy0 ? 0.f : A1c[c] + g.sy * dphi(Rc[c], Rym[c], s0, TWO ? Sym[c] : 0.f);
+            const float my1 = nb.wy1 ? 0.f : A1p[c] + g.sy * dphi(Ryp[c], Rc[c], TWO ? Syp[c] : 0.f, s0);
+            const float f0 = k0 ? T0[c] : T0[c] + g.st * dphi(Rc[c], Rtm[c], s0, TWO ? Stm[c] : 0.f);
+            const float f1 = k1 ? T1[c] : T1[c] + g.st * dphi(Rtp[c], Rc[c], TWO ? Stp[c] : 0.f, s0);
             const float mc0 = mcv[c];
             const float mc1 = C == 1 ? 0.f
                               : (c + 1 < C ? mcv[(c + 1) % C] : (g.perc ? mcv[0] : 0.f));
             // K x + c at the node, plus b
-            const float bx = s.b[0][i], by = s.b[1][i], bc = s.b[2][i], bf = s.b[3][i];
+            const float bx = B0[c], by = B1[c], bc = B2[c], bf = B3[c];
             const float amx = 0.5f * (mx0 + mx1) + bx, amy = 0.5f * (my0 + my1) + by;
             const float amc = 0.5f * (mc0 + mc1) + bc, amf = 0.5f * (f0 + f1) + bf;
             float ux, uy, uc, vv;
@@ -229,11 +288,9 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
             s.b[2][i] = nbc; s.bb[2][i] = nbc + th * (nbc - bc);
             s.b[3][i] = nbf; s.bb[3][i] = nbf + th * (nbf - bf);
             if (CHECK) {
-                const float ox = s.Mx[i], oy = s.My[i], oc = s.Mc[i];
-                const float of = k0 ? 0.f : s.F[fi];
                 const float nf = k0 ? 0.f : f0;
-                const double ddx = (double)mx0 - ox, ddy = (double)my0 - oy;
-                const double ddc = (double)mc0 - oc, ddf = (double)nf - of;
+                const double ddx = (double)mx0 - O0[c], ddy = (double)my0 - O1[c];
+                const double ddc = (double)mc0 - O2[c], ddf = (double)nf - O3[c];
                 dx2 += ddx * ddx + ddy * ddy + ddc * ddc + ddf * ddf;
                 x2 += (double)mx0 * mx0 + (double)my0 * my0 + (double)mc0 * mc0 + (double)nf * nf;
                 const double ex = (double)nbx - bx, ey = (double)nby - by;
@@ -247,7 +304,7 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
             s.My[i] = my0;
             s.Mc[i] = mc0;
             if (!k0) s.F[fi] = f0;
-            if (CARRY) s.Phi[i] = s.Phi[i] + (NPHI == 2 ? pc + pc2 : pc);
+            if (CARRY) s.Phi[i] = Qc[c] + (TWO ? Rc[c] + Sc[c] : Rc[c]);
         }
     }
     if (CHECK) {
