@@ -26,6 +26,37 @@ __device__ __forceinline__ float cos16(int j) {
 }
 __device__ __forceinline__ float sin16(int j) { return cos16(j - 4); }
 
+// v * e^{-2 pi i J / 16} with the trivial factors (1, -i, -1, i) and the
+// eighth roots (1 -+ i) / sqrt 2 taken apart: the general product would
+// multiply by exact zeros and ones, which IEEE arithmetic may not drop.
+template <int J>
+__device__ __forceinline__ float2 twmul(float2 v) {
+    constexpr int j = J & 15;
+    constexpr float h = 0.707106781186547524f;
+    if constexpr (j == 0) return v;
+    else if constexpr (j == 4) return make_float2(v.y, -v.x);
+    else if constexpr (j == 8) return make_float2(-v.x, -v.y);
+    else if constexpr (j == 12) return make_float2(-v.y, v.x);
+    else if constexpr (j == 2) return make_float2(h * (v.x + v.y), h * (v.y - v.x));
+    else if constexpr (j == 6) return make_float2(h * (v.y - v.x), -h * (v.x + v.y));
+    else if constexpr (j == 10) return make_float2(-h * (v.x + v.y), h * (v.x - v.y));
+    else if constexpr (j == 14) return make_float2(h * (v.x - v.y), h * (v.x + v.y));
+    else return cmul(make_float2(cos16(j), -sin16(j)), v);
+}
+
+// a[k + R/2] and a[k] of one radix-2 step, for k < K, with the twiddle of k
+// resolved at compile time.
+template <int R, int K>
+__device__ __forceinline__ void butterflies(float2* a, const float2* e, const float2* o) {
+    if constexpr (K > 0) {
+        butterflies<R, K - 1>(a, e, o);
+        constexpr int k = K - 1;
+        const float2 p = twmul<k * (16 / R)>(o[k]);
+        a[k] = cadd(e[k], p);
+        a[k + R / 2] = csub(e[k], p);
+    }
+}
+
 // In-register forward DFT of length R (radix-2 decimation in time),
 // a[k] <- sum_n a[n] e^{-2 pi i n k / R}; R in {1, 2, 4, 8, 16}.
 template <int R>
@@ -42,14 +73,7 @@ __device__ __forceinline__ void dft(float2* a) {
         for (int i = 0; i < R / 2; ++i) { e[i] = a[2 * i]; o[i] = a[2 * i + 1]; }
         dft<R / 2>(e);
         dft<R / 2>(o);
-#pragma unroll
-        for (int k = 0; k < R / 2; ++k) {
-            const int j = k * (16 / R);
-            const float2 w = make_float2(cos16(j), -sin16(j));
-            const float2 p = cmul(w, o[k]);
-            a[k] = cadd(e[k], p);
-            a[k + R / 2] = csub(e[k], p);
-        }
+        butterflies<R, R / 2>(a, e, o);
     }
 }
 

@@ -28,6 +28,30 @@ __device__ inline double block_sum(double v) {
     return t;
 }
 
+// N deterministic FP64 block sums at once (the exchanges of the N values
+// interleave); results valid in thread 0.  N <= 8.
+template <int N>
+__device__ inline void block_sums(double (&v)[N]) {
+    __shared__ double red[16][N];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int q = 0; q < N; ++q) v[q] += __shfl_down(v[q], o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < N; ++q) red[w][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            double t = 0.0;
+            for (int i = 0; i < nw; ++i) t += red[i][q];
+            v[q] = t;
+        }
+}
+
 // Pointwise prox of J / sigma (Step 2): (0, 0) if 2 a_f + sigma |a_m|^2 <= 0,
 // else v is the positive root of 2 (1 + sigma v)^2 (v - a_f) = sigma |a_m|^2,
 // reached by Newton from v0 = max(a_f, 0) + sigma |a_m|^2 / 2 (right of the

@@ -188,12 +188,14 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
         }
     }
     const long long col = (long long)r.y * nxb + r.xb;
+    double sums[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const double t = block_sum((double)rv[c]);
-        if (threadIdx.x == 0)
-            s.part_slice[(((long long)r.b * g.P + r.k) * C + c) * s.nbx + col] = t;
-    }
+    for (int c = 0; c < C; ++c) sums[c] = (double)rv[c];
+    block_sums(sums);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            s.part_slice[(((long long)r.b * g.P + r.k) * C + c) * s.nbx + col] = sums[c];
 }
 
 // x = a + grad phi_1 (+ grad phi_2 when NPHI is 2 or 4), z = prox(K x + c +
@@ -308,11 +310,10 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
         }
     }
     if (CHECK) {
-        const double vals[RS_COUNT] = {db2, z2, dx2, x2, jj};
-        for (int q = 0; q < RS_COUNT; ++q) {
-            const double t = block_sum(vals[q]);
-            if (threadIdx.x == 0) s.part_red[q * (long long)gridDim.x + r.L] = t;
-        }
+        double vals[RS_COUNT] = {db2, z2, dx2, x2, jj};
+        block_sums(vals);
+        if (threadIdx.x == 0)
+            for (int q = 0; q < RS_COUNT; ++q) s.part_red[q * (long long)gridDim.x + r.L] = vals[q];
     }
 }
 

@@ -69,6 +69,19 @@ __global__ void __launch_bounds__(kT) k_cols(float* R, long long inner, AxisTab 
     }
 }
 
+// Slots per plane of the DC-line reduction (1: one thread sums a plane) and
+// the doubles of LDS it needs for m = P C planes: the line, its transform
+// and the slot sums.
+__host__ __device__ inline int dc_slots(int m) {
+    int S = 16;
+    while (S > 1 && m * S > 2048) S >>= 1;
+    return S;
+}
+__host__ __device__ inline int dc_scratch_doubles(int m) {
+    const int S = dc_slots(m);
+    return 2 * m + (S > 1 ? m * S : 0);
+}
+
 struct TcArgs {
     Geom g;
     float* R;
@@ -156,7 +169,8 @@ __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
 // Spatial-DC line (jx, jy) = (0, 0) in FP64: S[k][c] = sum_{x,y} r from the
 // FP64 plane sums, then the (colour, time) Poisson problem with eigenvalues
 // lam_c + lam_t (zero mode dropped), scaled by 1 / sqrt(X Y); writes the
-// line at p = 0 of problem b.  Called by a whole block; d1 holds 2 P C doubles.
+// line at p = 0 of problem b.  Called by a whole block; d1 holds
+// dc_scratch_doubles(P C) doubles.
 __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1) {
     const Geom& g = a.g;
     const int P = g.P, C = g.C;
@@ -164,35 +178,44 @@ __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1) {
     float* base = a.R + (long long)b * g.nc;
     double* d2 = d1 + P * C;
     const int m = P * C;
-    // plane sums d1[k][c]: each wave takes 8 planes at a time and issues all
-    // of their coalesced partial loads before reducing (no dependent chains)
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwave = nt >> 6;
-    constexpr int kPl = 8, kLd = 2;                       // planes per chunk, loads per lane
-    for (int e0 = wv * kPl; e0 < m; e0 += nwave * kPl) {
-        double acc[kPl];
+    // plane sums d1[q], q = (k, c), of the nbx block partials of each plane:
+    // S slots per plane each sum every S-th partial (consecutive threads take
+    // consecutive slots: coalesced loads, many in flight), then one thread
+    // per plane adds its slots from LDS.  No shuffle trees: their chains of
+    // dependent exchanges made this block the tail of the whole pass.
+    const int S = dc_slots(m);
+    const double* part = a.part_slice + (long long)b * m * a.nbx;
+    if (S > 1) {
+        double* slot = d2 + m;
+        for (int e = threadIdx.x; e < m * S; e += nt) {
+            const int q = e / S, j = e - q * S;
+            const double* pp = part + (long long)q * a.nbx;
+            // 16 loads in flight per round trip
+            double v[16];
+            double acc = 0.0;
+            for (int i = j; i < a.nbx; i += 16 * S) {
 #pragma unroll
-        for (int q = 0; q < kPl; ++q) acc[q] = 0.0;
-        for (int j0 = 0; j0 < a.nbx; j0 += 64 * kLd) {
-            double v[kPl][kLd];
-#pragma unroll
-            for (int q = 0; q < kPl; ++q) {
-                const double* pp = a.part_slice + ((long long)b * m + e0 + q) * a.nbx;
-#pragma unroll
-                for (int l = 0; l < kLd; ++l) {
-                    const int j = j0 + 64 * l + lane;
-                    v[q][l] = (e0 + q < m && j < a.nbx) ? pp[j] : 0.0;
+                for (int u = 0; u < 16; ++u) {
+                    const int ii = i + u * S;
+                    v[u] = ii < a.nbx ? pp[ii] : 0.0;
                 }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) acc += v[u];
             }
-#pragma unroll
-            for (int q = 0; q < kPl; ++q)
-#pragma unroll
-                for (int l = 0; l < kLd; ++l) acc[q] += v[q][l];
+            slot[e] = acc;
         }
-#pragma unroll
-        for (int q = 0; q < kPl; ++q) {
-            double s = acc[q];
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-            if (lane == 0 && e0 + q < m) d1[e0 + q] = s;
+        __syncthreads();
+        for (int q = threadIdx.x; q < m; q += nt) {
+            double acc = 0.0;
+            for (int j = 0; j < S; ++j) acc += slot[q * S + j];
+            d1[q] = acc;
+        }
+    } else {
+        for (int q = threadIdx.x; q < m; q += nt) {
+            const double* pp = part + (long long)q * a.nbx;
+            double acc = 0.0;
+            for (int i = 0; i < a.nbx; ++i) acc += pp[i];
+            d1[q] = acc;
         }
     }
     __syncthreads();
@@ -206,6 +229,7 @@ __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1) {
     for (int e = threadIdx.x; e < m; e += nt) {      // time forward, divide
         const int jt = e / C, jc = e - jt * C;
         double acc = 0.0;
+#pragma unroll 8
         for (int k = 0; k < P; ++k) acc += a.tt64[jt * P + k] * d2[k * C + jc];
         const double lam = a.lamc64[jc] + a.lamt64[jt];
         d1[e] = lam > 0.0 ? acc / lam : 0.0;
@@ -214,6 +238,7 @@ __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1) {
     for (int e = threadIdx.x; e < m; e += nt) {      // time inverse
         const int k = e / C, jc = e - k * C;
         double acc = 0.0;
+#pragma unroll 8
         for (int jt = 0; jt < P; ++jt) acc += a.tt64[jt * P + k] * d1[jt * C + jc];
         d2[e] = acc;
     }
@@ -347,7 +372,7 @@ template <int P, int C>
 static void tc_reg_launch(const TcArgs& a, hipStream_t st) {
     const unsigned nb = (unsigned)((a.g.plane + 63) / 64) + 1;
     size_t sh = (size_t)C * P * 64 * sizeof(float);
-    const size_t sh64 = (size_t)2 * P * C * sizeof(double);
+    const size_t sh64 = (size_t)dc_scratch_doubles(P * C) * sizeof(double);
     if (sh64 > sh) sh = sh64;
     hipLaunchKernelGGL((k_tc_reg<P, C>), dim3(nb, (unsigned)a.g.B), dim3(64 * C), sh, st, a);
 }
@@ -408,7 +433,7 @@ void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty, co
     a.W = W;
     const long long nb = (g.plane + W - 1) / W;
     size_t sh = (size_t)2 * g.P * g.C * W * sizeof(float);
-    const size_t sh64 = (size_t)2 * g.P * g.C * sizeof(double);
+    const size_t sh64 = (size_t)dc_scratch_doubles(g.P * g.C) * sizeof(double);
     if (sh64 > sh) sh = sh64;
     hipLaunchKernelGGL(k_tc, dim3((unsigned)nb, (unsigned)g.B), dim3(kT), sh, st, a);
 }
