@@ -5,7 +5,9 @@ Run under rocprofv3 with one counter per pass, for example
     rocprofv3 --pmc FETCH_SIZE -d OUT --output-format csv -- python3 paper_1501_04840_amd/profile_traffic.py
     rocprofv3 --pmc WRITE_SIZE -d OUT --output-format csv -- python3 paper_1501_04840_amd/profile_traffic.py
 
-It runs a few iterations of the 256 x 256 x 3 x 32 workload and then a plain
+It runs 70 iterations of the 256 x 256 x 3 x 32 workload (past the refined
+start of the default projection mode, so the steady-state kernels are
+counted) and then a plain
 elementwise copy of known size (256 MiB read, 256 MiB written), whose
 counter values calibrate the solver kernels' readings.  ``summarise`` turns
 the two counter CSVs into bytes per launch per kernel.
@@ -25,7 +27,7 @@ sys.path.insert(0, ROOT)
 COPY_ELEMS = 64 * 1024 * 1024          # float32 elements of the calibration copy
 
 
-def run(iters: int = 3, size=(256, 256, 3, 32)):
+def run(iters: int = 70, size=(256, 256, 3, 32)):
     import torch
     from paper_1501_04840_amd import otdyn
     from synth import inputs
