@@ -146,6 +146,12 @@ def hue_batch(args):
     status, rep = bt.solve(args.hue_max_iters, chunk=args.hue_chunk)
     t_batch = time.perf_counter() - t0
     its = np.array([bt.problem(i).iterations for i in range(len(probs))])
+    open_probs = []
+    for i in range(len(probs)):
+        r = bt.problem(i)
+        if not r.converged:
+            open_probs.append({"i": i, "n": probs[i][0], "T": probs[i][1],
+                               "r_prim": r.r_prim, "r_dual": r.r_dual, "r_div": r.r_div})
     say(f"hue batch: {t_batch:.2f} s, {rep.converged} certified; looped sample next")
     bt.close()
     # plain solver, one problem at a time, on an evenly spaced sample
@@ -178,7 +184,8 @@ def hue_batch(args):
                    "chunk": args.hue_chunk, "max_iters": args.hue_max_iters,
                    "certified": int(rep.converged), "iters_max": int(its.max()),
                    "iters_median": float(np.median(its)), "autotune_s": t_tune,
-                   "cell_iters_per_s": float(cells * its.mean() / t_batch)},
+                   "cell_iters_per_s": float(cells * its.mean() / t_batch),
+                   "uncertified": open_probs},
         "looped_plain_solver": {"sample": len(idx), "certified": loop_conv,
                                 "s_per_problem": per_problem,
                                 "extrapolated_s": per_problem * len(probs),

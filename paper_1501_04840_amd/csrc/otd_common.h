@@ -45,8 +45,8 @@ struct AxisTab {
 
 struct StepArgs {
     Geom g;
-    float tau_sigma;     // tau * sigma
-    float sigma;
+    float tau_sigma;     // tau * sigma (the same for every problem)
+    const float* sig;    // sigma per problem [B] (device; residual balancing)
     float theta;
     // state
     float* F; float* Mx; float* My; float* Mc;
@@ -90,6 +90,9 @@ void launch_init_state(const StepArgs& s, const float* f0, const float* f1,
 void launch_init_dual(const StepArgs& s, const double* vfloor, hipStream_t st);
 // zero the dual fields
 void launch_zero_dual(const StepArgs& s, hipStream_t st);
+// b and b_bar of problem q times fac[q] (device [B]): keeps the unscaled dual
+// sigma b when sigma changes
+void launch_scale_dual(const StepArgs& s, const float* fac, hipStream_t st);
 // FP64 mass partials and input checks of f0, f1 ([B][C][Y][X]).
 void launch_boundary_stats(const Geom& g, const float* f0, const float* f1,
                            double* part, int nblk, hipStream_t st);

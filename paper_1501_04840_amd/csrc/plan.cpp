@@ -30,6 +30,8 @@ struct ot_dyn_plan {
     float* R;
     float* R2;
     float* Phi;              // carried potential (OT_REFINE_CARRY), else null
+    float* sig;              // sigma per problem [B] (device)
+    float* fac;              // dual rescale factors per problem [B] (device)
     float* f0;
     float* f1;
     AxisTab tab[4];          // x, y, c, t
@@ -57,6 +59,8 @@ struct ot_dyn_plan {
     std::vector<double> mass0, mass1, fbm2;
     std::vector<double> vfloor;     // per problem: 1e-3 * mean of f0 (warm-start dual)
     std::vector<double> r_prim, r_dual, r_div, cost, e_mass;
+    std::vector<float> sig_h, fac_h;     // sigma per problem and rescale factors
+    std::vector<int> n_adapt, last_adapt;   // per problem: changes, iteration of the last
     double last_res;         // max(r_prim, r_dual) of the last check
     std::string err;
     // phase timing
@@ -75,8 +79,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t off_b, off_bb, off_A, off_R, off_R2, off_Phi, off_f, off_tab[4], off_tw[4], off_tc64,
-        off_tt64;
+    size_t off_b, off_bb, off_A, off_R, off_R2, off_Phi, off_sig, off_f, off_tab[4], off_tw[4],
+        off_tc64, off_tt64;
     size_t off_pslice, off_pred, off_pdiv, off_pmass, off_pbnd, off_red;
     size_t total;
     int nbx, nbx_node, nblk_bnd;
@@ -138,8 +142,9 @@ int validate(const ot_dyn_desc* d, std::string* why) {
         return OT_ERR_PARAM;
     }
     if (d->check_every < 1 || !(d->tol_res > 0.0) || !(d->tol_div > 0.0) ||
-        !(d->tol_mass >= 0.0) || d->refine < OT_REFINE_OFF || d->refine > OT_REFINE_CARRY) {
-        if (why) *why = "need check_every >= 1, tol_res > 0, tol_div > 0, tol_mass >= 0, refine in {0,1,2,3}";
+        !(d->tol_mass >= 0.0) || d->refine < OT_REFINE_OFF || d->refine > OT_REFINE_CARRY ||
+        d->adapt < 0 || d->adapt > 1) {
+        if (why) *why = "need check_every >= 1, tol_res > 0, tol_div > 0, tol_mass >= 0, refine in {0,1,2,3}, adapt in {0,1}";
         return OT_ERR_PARAM;
     }
     return OT_OK;
@@ -157,6 +162,7 @@ Layout layout_of(const ot_dyn_desc& d) {
     L.off_R = take(ncT * sizeof(float));
     L.off_R2 = take(ncT * sizeof(float));
     L.off_Phi = take(d.refine == OT_REFINE_CARRY ? ncT * sizeof(float) : 0);
+    L.off_sig = take(2 * (size_t)g.B * sizeof(float));
     L.off_f = take(2 * (size_t)g.B * g.slice * sizeof(float));
     const int ns[4] = {d.X, d.Y, d.C, d.P};
     for (int a = 0; a < 4; ++a) {
@@ -236,7 +242,7 @@ StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     StepArgs s;
     s.g = p->g;
     s.tau_sigma = (float)(p->d.tau * p->d.sigma);
-    s.sigma = (float)p->d.sigma;
+    s.sig = p->sig;
     s.theta = (float)p->d.theta;
     s.F = F; s.Mx = Mx; s.My = My; s.Mc = Mc;
     for (int q = 0; q < 4; ++q) { s.b[q] = p->b[q]; s.bb[q] = p->bb[q]; s.A[q] = p->A[q]; }
@@ -404,6 +410,47 @@ int collect(ot_dyn_plan* p, const StepArgs& s, bool have_iter) {
     return OT_OK;
 }
 
+// Residual balancing of the step sizes (desc.adapt), per problem, after a
+// residual check: tau sigma stays fixed and sigma halves when the primal
+// iterate lags (r_dual > 4 r_prim: a larger primal step tau) or doubles when
+// the constraint residual lags (r_prim > 4 r_dual).  The unscaled dual
+// sigma b is kept, so b and b_bar are rescaled.  A problem changes at most
+// every kAdaptGap iterations and kAdaptMax times, within 64x of the given
+// sigma; certified problems keep their sigma.
+constexpr int kAdaptGap = 200;
+constexpr int kAdaptMax = 16;
+
+int adapt_steps(ot_dyn_plan* p, const StepArgs& s) {
+    if (!p->d.adapt) return OT_OK;
+    const float s0 = (float)p->d.sigma;
+    bool any = false;
+    for (int b = 0; b < p->g.B; ++b) {
+        p->fac_h[b] = 1.f;
+        const bool done = std::max(p->r_prim[b], p->r_dual[b]) < p->d.tol_res &&
+                          p->r_div[b] < p->d.tol_div;
+        if (done || p->n_adapt[b] >= kAdaptMax || p->total_iters - p->last_adapt[b] < kAdaptGap)
+            continue;
+        float f = 1.f;
+        if (p->r_dual[b] > 4.0 * p->r_prim[b] && p->sig_h[b] > s0 / 64.f) f = 2.f;
+        else if (p->r_prim[b] > 4.0 * p->r_dual[b] && p->sig_h[b] < s0 * 64.f) f = 0.5f;
+        if (f == 1.f) continue;
+        p->sig_h[b] /= f;
+        p->fac_h[b] = f;
+        p->n_adapt[b] += 1;
+        p->last_adapt[b] = p->total_iters;
+        any = true;
+    }
+    if (!any) return OT_OK;
+    const size_t B = (size_t)p->g.B;
+    HIPCHK(p, hipMemcpyAsync(p->sig, p->sig_h.data(), B * sizeof(float), hipMemcpyHostToDevice,
+                             p->stream));
+    HIPCHK(p, hipMemcpyAsync(p->fac, p->fac_h.data(), B * sizeof(float), hipMemcpyHostToDevice,
+                             p->stream));
+    launch_scale_dual(s, p->fac, p->stream);
+    HIPCHK(p, hipGetLastError());
+    return OT_OK;
+}
+
 void fill_report(const ot_dyn_plan* p, ot_dyn_report* rep) {
     if (!rep) return;
     const int B = p->g.B;
@@ -440,6 +487,7 @@ int ot_dyn_default_desc(ot_dyn_desc* d, int X, int Y, int C, int P) {
     d->tol_res = 1e-6; d->tol_div = 1e-6; d->tol_mass = 1e-5;
     d->refine = OT_REFINE_CARRY;
     d->batch = 1;
+    d->adapt = 1;
     return OT_OK;
 }
 
@@ -476,6 +524,8 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->R = (float*)(p->ws + L.off_R);
     p->R2 = (float*)(p->ws + L.off_R2);
     p->Phi = d->refine == OT_REFINE_CARRY ? (float*)(p->ws + L.off_Phi) : nullptr;
+    p->sig = (float*)(p->ws + L.off_sig);
+    p->fac = p->sig + p->g.B;
     p->f0 = (float*)(p->ws + L.off_f);
     p->f1 = p->f0 + (long long)p->g.B * p->g.slice;
     p->tc64 = (double*)(p->ws + L.off_tc64);
@@ -495,6 +545,8 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->vfloor.assign(B, 0);
     p->r_prim.assign(B, 0); p->r_dual.assign(B, 0); p->r_div.assign(B, 0);
     p->cost.assign(B, 0); p->e_mass.assign(B, 0);
+    p->sig_h.assign(B, (float)d->sigma); p->fac_h.assign(B, 1.f);
+    p->n_adapt.assign(B, 0); p->last_adapt.assign(B, 0);
     p->last_res = 1.0;
     p->total_iters = 0;
     p->it_next = 0;
@@ -608,6 +660,11 @@ int ot_dyn_init(ot_dyn_plan* p, int mode, float* F, float* Mx, float* My, float*
     if (!p->have_boundary) { p->err = "ot_dyn_set_boundary must succeed first"; return OT_ERR_STATE; }
     if (mode < OT_INIT_COLD || mode > OT_INIT_PRIMAL_DUAL) return OT_ERR_PARAM;
     const StepArgs s = step_args(p, F, Mx, My, Mc);
+    std::fill(p->sig_h.begin(), p->sig_h.end(), (float)p->d.sigma);
+    std::fill(p->n_adapt.begin(), p->n_adapt.end(), 0);
+    std::fill(p->last_adapt.begin(), p->last_adapt.end(), 0);
+    HIPCHK(p, hipMemcpyAsync(p->sig, p->sig_h.data(), p->sig_h.size() * sizeof(float),
+                             hipMemcpyHostToDevice, p->stream));
     launch_init_state(s, p->f0, p->f1, mode == OT_INIT_COLD ? 1 : 0, p->stream);
     if (mode == OT_INIT_PRIMAL_DUAL) {
         // the boundary-statistics scratch is free after set_boundary
@@ -656,6 +713,8 @@ int ot_dyn_solve(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc, int 
         }
         p->last_res = worst;
         if (worst < p->d.tol_res && worst_div < p->d.tol_div) { status = OT_OK; break; }
+        const int as = adapt_steps(p, s);
+        if (as != OT_OK) { status = as; break; }
     }
     if (rep) {
         fill_report(p, rep);
@@ -769,7 +828,8 @@ void plan_iterate(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc, boo
 
 int plan_collect(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     const StepArgs s = step_args(p, F, Mx, My, Mc);
-    const int st = collect(p, s, true);
+    int st = collect(p, s, true);
+    if (st == OT_OK) st = adapt_steps(p, s);
     double worst = 0.0;
     for (int b = 0; b < p->g.B; ++b) worst = std::max(worst, std::max(p->r_prim[b], p->r_dual[b]));
     p->last_res = worst;

@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(kBlock) k_update(StepArgs s) {
         const float bx = s.b[0][i], by = s.b[1][i], bc = s.b[2][i], bf = s.b[3][i];
         const float amx = kx + bx, amy = ky + by, amc = kc + bc, amf = kf + bf;
         float ux, uy, uc, vv;
-        prox_J(amx, amy, amc, amf, s.sigma, ux, uy, uc, vv);
+        prox_J(amx, amy, amc, amf, s.sig[n.b], ux, uy, uc, vv);
         const float nbx = amx - ux, nby = amy - uy, nbc = amc - uc, nbf = amf - vv;
         const float th = s.theta;
         s.b[0][i] = nbx; s.bb[0][i] = nbx + th * (nbx - bx);
@@ -281,6 +281,15 @@ __global__ void __launch_bounds__(kBlock) k_zero_dual(StepArgs s) {
     for (int q = 0; q < 4; ++q) { s.b[q][i] = 0.f; s.bb[q][i] = 0.f; }
 }
 
+__global__ void __launch_bounds__(kBlock) k_scale_dual(StepArgs s, const float* fac) {
+    const Geom& g = s.g;
+    const Node n = node_of(g);
+    if (!n.live) return;
+    const long long i = n.cb + n.p;
+    const float f = fac[n.b];
+    for (int q = 0; q < 4; ++q) { s.b[q][i] *= f; s.bb[q][i] *= f; }
+}
+
 // b = b_bar = grad J(K x + c) / sigma (the dual that makes a given primal a
 // fixed point of Steps 2-4 where v > 0), with v floored at vfloor[b]: at
 // nodes of (near) vacuum the fixed-point dual is not the gradient, and the
@@ -311,7 +320,7 @@ __global__ void __launch_bounds__(kBlock) k_init_dual(StepArgs s, const double* 
     const float uc = 0.5f * (fc(n.c) + fc(n.c + 1));
     float v = 0.5f * (s.F[fidx(g, n.b, n.k, n.c, n.p)] + s.F[fidx(g, n.b, n.k + 1, n.c, n.p)]);
     v = fmaxf(v, (float)vfloor[n.b]);
-    const float is = 1.f / (s.sigma * v);
+    const float is = 1.f / (s.sig[n.b] * v);
     const float bx = ux * is, by = uy * is, bc = uc * is;
     const float bf = -(ux * ux + uy * uy + uc * uc) * 0.5f * is / v;
     s.b[0][i] = bx; s.bb[0][i] = bx;
@@ -400,6 +409,10 @@ void launch_init_dual(const StepArgs& s, const double* vfloor, hipStream_t st) {
 
 void launch_zero_dual(const StepArgs& s, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_dual, node_grid(s.g), dim3(kBlock), 0, st, s);
+}
+
+void launch_scale_dual(const StepArgs& s, const float* fac, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_dual, node_grid(s.g), dim3(kBlock), 0, st, s, fac);
 }
 
 void launch_boundary_stats(const Geom& g, const float* f0, const float* f1, double* part,

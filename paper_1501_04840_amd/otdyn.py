@@ -59,6 +59,7 @@ class ot_dyn_desc(ctypes.Structure):
         ("tol_res", c_double), ("tol_div", c_double), ("tol_mass", c_double),
         ("refine", c_int),
         ("batch", c_int),
+        ("adapt", c_int),
     ]
 
 

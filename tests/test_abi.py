@@ -36,7 +36,7 @@ def test_default_desc_and_workspace(L):
     d = L.ot_dyn_default_desc(256, 256, 3, 32)
     assert (d.X, d.Y, d.C, d.P) == (256, 256, 3, 32)
     assert list(d.bc) == [L.OT_BC_NEUMANN, L.OT_BC_NEUMANN, L.OT_BC_PERIODIC]
-    assert d.tau * d.sigma < 1 and d.theta == 1.0 and d.batch == 1
+    assert d.tau * d.sigma < 1 and d.theta == 1.0 and d.batch == 1 and d.adapt == 1
     n = L.ot_dyn_workspace_size(d)
     N = 256 * 256 * 3 * 32
     assert n >= 15 * N * 4          # b, b_bar, a (4 fields each), r, r' and Phi
@@ -48,6 +48,7 @@ def test_default_desc_and_workspace(L):
 @pytest.mark.parametrize("field,value,status", [
     ("P", 1, -2), ("X", 0, -2), ("C", 100, -2), ("tau", 20.0, -1), ("sigma", -1.0, -1),
     ("theta", 1.5, -1), ("check_every", 0, -1), ("refine", 4, -1), ("refine", -1, -1), ("batch", 0, -2),
+    ("adapt", 2, -1),
 ])
 def test_descriptor_validation(L, field, value, status):
     d = L.ot_dyn_default_desc(16, 16, 3, 8)

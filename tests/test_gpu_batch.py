@@ -39,10 +39,13 @@ def hue_problems(count, seed=7, bins=(64, 180, 37, 128), steps=(8, 16)):
     return out
 
 
-def periodic_desc(o, base_refine=1):
+def periodic_desc(o, base_refine=1, adapt=0):
+    """Fixed step sizes by default: the trajectory tests compare with the
+    oracle's fixed-step Algorithm 1 iteration by iteration."""
     d = o.ot_dyn_default_desc(1, 1, 1, 2)
     d.bc[0] = o.OT_BC_PERIODIC
     d.refine = base_refine
+    d.adapt = adapt
     return d
 
 
@@ -80,6 +83,7 @@ def test_mixed_batch_equals_single_plans(otdyn):
         f0s.append(a)
         f1s.append(b)
     base = otdyn.ot_dyn_default_desc(1, 1, 1, 2)
+    base.adapt = 0
     bt = otdyn.Batch(base, shapes)
     bt.set_boundary(f0s, f1s)
     status, rep = bt.solve(120, chunk=40)
@@ -135,3 +139,37 @@ def test_batch_certifies_each_problem(otdyn):
         assert max(r.r_prim, r.r_dual) < d.tol_res and r.r_div < d.tol_div
         assert 0 < r.iterations <= r.total_iterations
     bt.close()
+
+
+def test_balanced_steps_certify_slow_hue_problems(otdyn):
+    """Hue problems of the 1024-problem workload on which the fixed step
+    sizes (tau 3, sigma 0.33) stall above the tolerance: with per-problem
+    residual balancing every problem certifies, and the certified cost agrees
+    with a fixed-step run at a step ratio that does certify (tau 100)."""
+    _say("balanced step sizes")
+    allp = inputs.cfg4_problems(1024)
+    idx = [341, 0, 682, 1023]
+    probs = [allp[i] for i in idx]
+    dims = [(n, 1, 1, T) for n, T, _, _ in probs]
+
+    def solve(tau, adapt, max_iters):
+        d = periodic_desc(otdyn, base_refine=3, adapt=adapt)
+        d.tau, d.sigma = tau, 0.99 / tau
+        bt = otdyn.Batch(d, dims)
+        bt.set_boundary([p[2].reshape(1, 1, -1) for p in probs],
+                        [p[3].reshape(1, 1, -1) for p in probs])
+        bt.solve(max_iters, chunk=200)
+        reps = [bt.problem(i) for i in range(len(probs))]
+        bt.close()
+        return reps
+
+    fixed = solve(3.0, 0, 30000)
+    assert not fixed[0].converged          # the stalled problem
+    bal = solve(3.0, 1, 30000)
+    ref = solve(100.0, 0, 40000)
+    for i in range(len(probs)):
+        assert bal[i].converged == 1, (idx[i], bal[i].as_dict())
+        assert max(bal[i].r_prim, bal[i].r_dual) < 1e-6 and bal[i].r_div < 1e-6
+        if ref[i].converged:
+            assert abs(bal[i].cost - ref[i].cost) <= 1e-5 * ref[i].cost, (idx[i], bal[i].cost, ref[i].cost)
+    assert bal[0].iterations < 20000

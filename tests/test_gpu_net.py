@@ -331,6 +331,7 @@ def test_warm_started_batch_certifies_at_once_from_a_solution(N):
     d = otdyn.ot_dyn_default_desc(X, Y, C, P)
     d.tau, d.sigma = 3.0, 0.33
     d.tol_res, d.tol_div = 1e-5, 1e-6
+    d.adapt = 0                  # compare like with like: fixed step sizes
     bt = otdyn.Batch(d, [(X, Y, C, P)] * 3, "cuda:0")
     bt.set_boundary([p[0] for p in pairs], [p[1] for p in pairs])
     st, rep = bt.solve(20000, 50)
