@@ -135,6 +135,7 @@ def hue_batch(args):
     base = otdyn.ot_dyn_default_desc(1, 1, 1, 2)
     base.bc[0] = otdyn.OT_BC_PERIODIC
     base.tau, base.sigma = args.hue_tau, args.hue_sigma
+    base.adapt = args.hue_adapt
     bt = otdyn.Batch(base, dims, "cuda:0")
     bt.set_boundary([p[2].reshape(1, 1, -1) for p in probs], [p[3].reshape(1, 1, -1) for p in probs])
     say(f"hue batch: {len(probs)} problems, {cells} cells; autotuning")
@@ -162,6 +163,7 @@ def hue_batch(args):
         d = otdyn.ot_dyn_default_desc(n, 1, 1, T)
         d.bc[0] = otdyn.OT_BC_PERIODIC
         d.tau, d.sigma = args.hue_tau, args.hue_sigma
+        d.adapt = args.hue_adapt
         d.check_every = args.hue_chunk
         pr = otdyn.Problem(d, "cuda:0")
         pr.set_boundary(torch.from_numpy(h0.reshape(1, 1, n)), torch.from_numpy(h1.reshape(1, 1, n)))
@@ -179,7 +181,7 @@ def hue_batch(args):
         "value": t_batch, "unit": "s", "higher_is_better": False,
         "n_gpus": 1, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"hue_batch_{len(probs)}", "bins": list(inputs.HUE_BINS),
-                   "tau": args.hue_tau, "sigma": args.hue_sigma,
+                   "tau": args.hue_tau, "sigma": args.hue_sigma, "adapt": args.hue_adapt,
                    "steps": list(inputs.HUE_STEPS), "cells": cells,
                    "chunk": args.hue_chunk, "max_iters": args.hue_max_iters,
                    "certified": int(rep.converged), "iters_max": int(its.max()),
@@ -194,15 +196,48 @@ def hue_batch(args):
     print(json.dumps(out))
 
 
+def warm_start(args):
+    """Learned warm start on 64 x 64 x 3 x 16 problems: certified
+    time-to-tolerance of held-out pairs from a cold start and from the
+    committed trained network (coarse solve, network correction, fine
+    solve; all of it inside the timed wall time)."""
+    import torch
+    from paper_1501_04840_amd import otnet
+    from paper_1501_04840_amd import warmstart as W
+
+    net = otnet.Net(W.net_desc(32), "cuda:0")
+    net.set_params(torch.from_numpy(W.load_weights()))
+    pairs = W.pairs_of(range(args.warm_count), held_out=True)
+    res = W.evaluate(pairs, ("cold", "warm"), net, max_iters=args.warm_max_iters,
+                     group=min(128, args.warm_count))
+    net.close()
+    summ = {m: {k: v for k, v in res[m].items() if k != "iterations"} for m in ("cold", "warm")}
+    out = {
+        "metric": "time-to-tolerance (r < 1e-6) of held-out 64x64x3x16 pairs, warm start vs cold",
+        "value": res["warm"]["wall_s"], "unit": "s", "higher_is_better": False,
+        "n_gpus": 1, "dtype": "f32 solver, bf16 network", "data": "synthetic",
+        "config": {"workload": f"warm_64x64x3x16_{args.warm_count}", "pairs": args.warm_count,
+                   "cold": summ["cold"], "warm": summ["warm"],
+                   "prediction_rel_error": res.get("prediction_rel_error"),
+                   "iterations_saved_mean": summ["cold"]["iterations_mean"] - summ["warm"]["iterations_mean"]},
+        "vs_cold": res["cold"]["wall_s"] / res["warm"]["wall_s"],
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="rgb", choices=["rgb", "hue_batch"])
+    ap.add_argument("--workload", default="rgb", choices=["rgb", "hue_batch", "warm"])
+    ap.add_argument("--warm-count", type=int, default=64)
+    ap.add_argument("--warm-max-iters", type=int, default=30000)
     ap.add_argument("--hue-count", type=int, default=1024)
     ap.add_argument("--hue-max-iters", type=int, default=30000)
     ap.add_argument("--hue-chunk", type=int, default=200)
     ap.add_argument("--hue-loop-sample", type=int, default=8)
     ap.add_argument("--hue-tau", type=float, default=3.0)
     ap.add_argument("--hue-sigma", type=float, default=0.33)
+    ap.add_argument("--hue-adapt", type=int, default=1, choices=[0, 1],
+                    help="per-problem step balancing (both the batch and the looped solver)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=64)
@@ -227,6 +262,9 @@ def main():
         build.build()
     if args.workload == "hue_batch":
         hue_batch(args)
+        return
+    if args.workload == "warm":
+        warm_start(args)
         return
     X, Y, C, P = args.size
     if (X, Y) == (256, 256):

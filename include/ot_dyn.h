@@ -96,8 +96,9 @@ typedef struct ot_dyn_desc {
     int refine;            /* FP32 accuracy of the projection: OT_REFINE_*  */
     int batch;             /* number of stacked problems of this shape (>= 1) */
     int adapt;             /* step sizes: 0 fixed (tau, sigma as given), 1
-                              balanced per problem at residual checks (see
-                              ot_dyn_solve); tau sigma stays fixed          */
+                              balanced per problem at residual checks; tau
+                              sigma stays fixed.  Helps 1D periodic (hue)
+                              problems, slows the RGB ones: off by default */
 } ot_dyn_desc;
 
 typedef struct ot_dyn_report {
@@ -119,7 +120,7 @@ typedef struct ot_dyn_plan ot_dyn_plan;
 /* Fill *d with the defaults for an X x Y x C x P grid: bc = {Neumann,
  * Neumann, periodic}, extent = 1, tau = 10, sigma = 0.099, theta = 1,
  * check_every = 50, tol_res = 1e-6, tol_div = 1e-6, tol_mass = 1e-5,
- * refine = OT_REFINE_CARRY, batch = 1, adapt = 1. */
+ * refine = OT_REFINE_CARRY, batch = 1, adapt = 0. */
 int ot_dyn_default_desc(ot_dyn_desc* d, int X, int Y, int C, int P);
 
 /* Bytes of device workspace a plan for *d needs (OT_ERR_SHAPE/PARAM if *d

@@ -487,7 +487,7 @@ int ot_dyn_default_desc(ot_dyn_desc* d, int X, int Y, int C, int P) {
     d->tol_res = 1e-6; d->tol_div = 1e-6; d->tol_mass = 1e-5;
     d->refine = OT_REFINE_CARRY;
     d->batch = 1;
-    d->adapt = 1;
+    d->adapt = 0;
     return OT_OK;
 }
 

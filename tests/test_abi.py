@@ -36,7 +36,7 @@ def test_default_desc_and_workspace(L):
     d = L.ot_dyn_default_desc(256, 256, 3, 32)
     assert (d.X, d.Y, d.C, d.P) == (256, 256, 3, 32)
     assert list(d.bc) == [L.OT_BC_NEUMANN, L.OT_BC_NEUMANN, L.OT_BC_PERIODIC]
-    assert d.tau * d.sigma < 1 and d.theta == 1.0 and d.batch == 1 and d.adapt == 1
+    assert d.tau * d.sigma < 1 and d.theta == 1.0 and d.batch == 1 and d.adapt == 0
     n = L.ot_dyn_workspace_size(d)
     N = 256 * 256 * 3 * 32
     assert n >= 15 * N * 4          # b, b_bar, a (4 fields each), r, r' and Phi

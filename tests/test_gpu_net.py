@@ -350,3 +350,31 @@ def test_warm_started_batch_certifies_at_once_from_a_solution(N):
     with pytest.raises(otdyn.OtDynError):
         bt.set_state(F, M, otdyn.OT_INIT_COLD)
     bt.close()
+
+
+def test_trained_network_gains_over_the_coarse_start(N):
+    """The committed trained network (paper_1501_04840_amd/weights) on
+    held-out 64 x 64 x 3 x 16 pairs: its correction brings the prolonged
+    coarse solution closer to the certified solution, and the warm-started
+    solves certify.  Prints the iterations to the certified tolerance from
+    the cold, coarse and network starts (the gain in iterations is small:
+    the iteration removes smooth relative errors quickly and sharp-feature
+    errors slowly, and the network's error is of the second kind)."""
+    import json
+    import torch
+    from paper_1501_04840_amd import otnet
+    from paper_1501_04840_amd import warmstart as W
+    net = otnet.Net(W.net_desc(8), "cuda:0")
+    net.set_params(torch.from_numpy(W.load_weights()))
+    pairs = W.pairs_of(range(8), held_out=True)
+    res = W.evaluate(pairs, ("cold", "coarse", "warm"), net, max_iters=30000, group=8,
+                     net_batch=8)
+    net.close()
+    err = res["prediction_rel_error"]
+    print(json.dumps({m: {k: v for k, v in r.items() if k != "iterations"}
+                      for m, r in res.items() if isinstance(r, dict) and "wall_s" in r}))
+    print(json.dumps(err))
+    for g in ("f", "mx", "my"):
+        assert err["warm_" + g] < 0.9 * err["coarse_" + g], (g, err)
+    assert res["warm"]["certified"] == len(pairs)
+    assert res["cold"]["certified"] == len(pairs)
