@@ -268,7 +268,10 @@ int ot_dyn_batch_get_state(ot_dyn_batch* bt, float* F, float* M);
 int ot_dyn_batch_get_dual(ot_dyn_batch* bt, float* Bd);
 int ot_dyn_batch_set_dual(ot_dyn_batch* bt, const float* Bd);
 
-/* Selected launch shape of the group holding problem i (row_bx, dense_xy). */
+/* Selected launch shape of the group holding problem i: row_bx is the block
+ * width of the row stencils (64, 128, 256); dense_xy the transform path (0
+ * fused three-pass Poisson solve where it applies, else five FFT passes; 1
+ * dense x/y contractions; 2 five FFT passes). */
 int ot_dyn_batch_tuning(const ot_dyn_batch* bt, int i, int* row_bx, int* dense_xy);
 
 int ot_dyn_batch_destroy(ot_dyn_batch* bt);

@@ -325,7 +325,7 @@ int ot_dyn_batch_autotune(ot_dyn_batch* bt, int trials) {
         for (int bx : {64, 128, 256})
             if (bx <= def) bxs.push_back(bx);
         std::vector<int> dens = {0};
-        if (plan_has_fast_xy(g.plan)) dens.push_back(1);
+        if (plan_has_fast_xy(g.plan)) { dens.push_back(1); dens.push_back(2); }
         float best = 1e30f;
         int bbx = def, bdn = 0;
         for (int bx : bxs)

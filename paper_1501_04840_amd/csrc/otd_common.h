@@ -109,6 +109,18 @@ void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
                const AxisTab& tc, const AxisTab& tt, const double* tc64,
                const double* tt64, const double* part_slice, int nbx, hipStream_t st);
 
+// Fused Poisson passes (transform.hip) for Neumann x and y of length 32..256,
+// P in {8, 16, 32}, C in {1, 3}: x (+ colour) pass with a transposed write to
+// Rt ([B][C][X][Y][P]; the forward pass also solves the FP64 DC line into
+// dc [B][C][P]), the y + t pass in place on Rt, and the mirrored inverse.
+bool fused_poisson_ok(const Geom& g, const AxisTab& tx, const AxisTab& ty, const AxisTab& tt);
+void launch_fused_x(const Geom& g, float* R, float* Rt, float* dc, const AxisTab& tx,
+                    const AxisTab& ty, const AxisTab& tc, const AxisTab& tt, const double* tc64,
+                    const double* tt64, const double* part_slice, int nbx, int inverse,
+                    hipStream_t st);
+void launch_fused_yt(const Geom& g, float* Rt, float* dc, const AxisTab& tx, const AxisTab& ty,
+                     const AxisTab& tc, const AxisTab& tt, hipStream_t st);
+
 // Fast power-of-two passes (fastdct.hip); kind 0 DCT-II, 1 DCT-III, 2 Hartley.
 bool fast_len(int L);
 void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st);

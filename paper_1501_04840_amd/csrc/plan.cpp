@@ -30,6 +30,9 @@ struct ot_dyn_plan {
     float* R;
     float* R2;
     float* Phi;              // carried potential (OT_REFINE_CARRY), else null
+    float* Rt;               // fused Poisson passes: transposed scratch [B][C][X][Y][P]
+    float* dcl;              // fused Poisson passes: FP64-solved DC line [B][C][P]
+    bool fused;              // the fused three-pass Poisson solve applies
     float* sig;              // sigma per problem [B] (device)
     float* fac;              // dual rescale factors per problem [B] (device)
     float* f0;
@@ -79,8 +82,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t off_b, off_bb, off_A, off_R, off_R2, off_Phi, off_sig, off_f, off_tab[4], off_tw[4],
-        off_tc64, off_tt64;
+    size_t off_b, off_bb, off_A, off_R, off_R2, off_Phi, off_Rt, off_dcl, off_sig, off_f,
+        off_tab[4], off_tw[4], off_tc64, off_tt64;
     size_t off_pslice, off_pred, off_pdiv, off_pmass, off_pbnd, off_red;
     size_t total;
     int nbx, nbx_node, nblk_bnd;
@@ -163,6 +166,8 @@ Layout layout_of(const ot_dyn_desc& d) {
     L.off_R2 = take(ncT * sizeof(float));
     L.off_Phi = take(d.refine == OT_REFINE_CARRY ? ncT * sizeof(float) : 0);
     L.off_sig = take(2 * (size_t)g.B * sizeof(float));
+    L.off_Rt = take(ncT * sizeof(float));
+    L.off_dcl = take((size_t)g.B * g.C * g.P * sizeof(float));
     L.off_f = take(2 * (size_t)g.B * g.slice * sizeof(float));
     const int ns[4] = {d.X, d.Y, d.C, d.P};
     for (int a = 0; a < 4; ++a) {
@@ -284,6 +289,18 @@ void poisson(ot_dyn_plan* p, float* R) {
     const Geom& g = p->g;
     hipStream_t st = p->stream;
     const long long B = g.B;
+    if (p->fused) {     // three passes: x (+ colour), y + t, inverse x (+ colour)
+        auto x_pass = [&](int inverse) {
+            launch_fused_x(g, R, p->Rt, p->dcl, p->tab[0], p->tab[1], p->tab[2], p->tab[3],
+                           p->tc64, p->tt64, p->part_slice, p->nbx, inverse, st);
+        };
+        timed(p, OT_PHASE_XFORM_X, [&] { x_pass(0); });
+        timed(p, OT_PHASE_TC, [&] {
+            launch_fused_yt(g, p->Rt, p->dcl, p->tab[0], p->tab[1], p->tab[2], p->tab[3], st);
+        });
+        timed(p, OT_PHASE_XFORM_X, [&] { x_pass(1); });
+        return;
+    }
     if (g.X > 1)
         timed(p, OT_PHASE_XFORM_X, [&] { launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 0, st); });
     if (g.Y > 1)
@@ -299,7 +316,8 @@ void poisson(ot_dyn_plan* p, float* R) {
 }
 
 // Launch shapes: the row-stencil block width (64, 128 or 256; 0 = default)
-// and whether the x/y transforms use the dense path instead of the FFT one.
+// and the transform path: dense_xy 0 = fused three-pass solve where it
+// applies (else five FFT passes), 1 = dense x/y passes, 2 = five FFT passes.
 void apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy) {
     const Geom& g = p->g;
     if (row_bx <= 0) row_bx = row_block(g.X);
@@ -310,7 +328,13 @@ void apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy) {
         p->nbx = g.Y * nxb;
         p->nred = (long long)g.Y * g.P * nxb;
     }
-    for (int a = 0; a < 2; ++a) p->tab[a].tw = dense_xy ? nullptr : p->tw_fast[a];
+    for (int a = 0; a < 2; ++a) p->tab[a].tw = dense_xy == 1 ? nullptr : p->tw_fast[a];
+    // the fused passes use one block per row index and problem: measured
+    // faster than the five passes at 64 x 64 and 128 x 128 (alone and
+    // batched) and 2% slower for one 256 x 256 problem (256 blocks, one fat
+    // block per CU), where the five passes are kept
+    p->fused = dense_xy == 0 && fused_poisson_ok(g, p->tab[0], p->tab[1], p->tab[3]) &&
+               ((long long)g.B * g.Y >= 512 || (long long)g.X * g.Y < 65536);
 }
 
 bool refine_now(const ot_dyn_plan* p) {
@@ -525,6 +549,9 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->R2 = (float*)(p->ws + L.off_R2);
     p->Phi = d->refine == OT_REFINE_CARRY ? (float*)(p->ws + L.off_Phi) : nullptr;
     p->sig = (float*)(p->ws + L.off_sig);
+    p->Rt = (float*)(p->ws + L.off_Rt);
+    p->dcl = (float*)(p->ws + L.off_dcl);
+    p->fused = false;
     p->fac = p->sig + p->g.B;
     p->f0 = (float*)(p->ws + L.off_f);
     p->f1 = p->f0 + (long long)p->g.B * p->g.slice;

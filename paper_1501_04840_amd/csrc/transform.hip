@@ -16,6 +16,7 @@
 // over j, so table reads are coalesced and LDS reads are broadcasts).
 #include "otd_common.h"
 #include "fft_common.h"
+#include "fft_lines.h"
 
 namespace otd {
 
@@ -72,12 +73,12 @@ __global__ void __launch_bounds__(kT) k_cols(float* R, long long inner, AxisTab 
 // Slots per plane of the DC-line reduction (1: one thread sums a plane) and
 // the doubles of LDS it needs for m = P C planes: the line, its transform
 // and the slot sums.
-__host__ __device__ inline int dc_slots(int m) {
+__host__ __device__ constexpr int dc_slots(int m) {
     int S = 16;
     while (S > 1 && m * S > 2048) S >>= 1;
     return S;
 }
-__host__ __device__ inline int dc_scratch_doubles(int m) {
+__host__ __device__ constexpr int dc_scratch_doubles(int m) {
     const int S = dc_slots(m);
     return 2 * m + (S > 1 ? m * S : 0);
 }
@@ -85,6 +86,8 @@ __host__ __device__ inline int dc_scratch_doubles(int m) {
 struct TcArgs {
     Geom g;
     float* R;
+    float* Rt;               // fused path: transposed scratch [B][C][X][Y][P]
+    float* dc;               // fused path: FP64-solved DC line [B][C][P]
     AxisTab tx, ty, tc, tt;
     const double* tc64;      // C x C forward matrix M[j][k] (FP64)
     const double* tt64;      // P x P forward matrix M[j][k] (FP64)
@@ -96,7 +99,7 @@ struct TcArgs {
     const float2* twt;       // time-axis twiddles e^{-i pi j / (2P)}, j < 4P
 };
 
-__device__ void dc_line_fp64(const TcArgs& a, int b, double* d1);
+__device__ void dc_line_fp64(const TcArgs& a, int b, double* d1, float* ct_out = nullptr);
 
 __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
     extern __shared__ float lds[];
@@ -170,8 +173,9 @@ __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
 // FP64 plane sums, then the (colour, time) Poisson problem with eigenvalues
 // lam_c + lam_t (zero mode dropped), scaled by 1 / sqrt(X Y); writes the
 // line at p = 0 of problem b.  Called by a whole block; d1 holds
-// dc_scratch_doubles(P C) doubles.
-__device__ void dc_line_fp64(const TcArgs& a, int b, double* d1) {
+// dc_scratch_doubles(P C) doubles.  With ct_out the line is left in colour
+// modes and written as ct_out[jc * P + t] (scaled) instead.
+__device__ void dc_line_fp64(const TcArgs& a, int b, double* d1, float* ct_out) {
     const Geom& g = a.g;
     const int P = g.P, C = g.C;
     const int nt = blockDim.x;
@@ -244,6 +248,13 @@ __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1) {
     }
     __syncthreads();
     const double scale = 1.0 / sqrt((double)g.plane);
+    if (ct_out) {
+        for (int e = threadIdx.x; e < m; e += nt) {
+            const int k = e / C, jc = e - k * C;
+            ct_out[jc * P + k] = (float)(d2[e] * scale);
+        }
+        return;
+    }
     for (int e = threadIdx.x; e < m; e += nt) {      // colour inverse, store
         const int k = e / C, c = e - k * C;
         double acc = 0.0;
@@ -385,6 +396,256 @@ static bool tc_reg_dispatch(const TcArgs& a, hipStream_t st) {
     OTD_TC(8, 3) OTD_TC(16, 3) OTD_TC(32, 3)
 #undef OTD_TC
     return false;
+}
+
+// ---- fused Poisson passes (Neumann x and y of power-of-two length) -------
+//
+// Three passes instead of five.  A block of the first pass owns one row
+// index y of one problem: the P C rows (t, c) of length X are staged in LDS,
+// transformed along x (DCT-II), mixed across colours, and written to a
+// transposed scratch Rt[b][jc][jx][y][t] (t fastest, so every (jc, jx) gets a
+// contiguous run of P values).  A block of the second pass owns one (jc, jx):
+// its Y x P values are contiguous in Rt; it transforms along y, then along t
+// in registers (one thread per y line), divides by the eigenvalues of A A^T,
+// inverts t and y, and writes back in place.  The third pass mirrors the
+// first.  The spatial-DC line is solved in FP64 by an extra block of the
+// first pass and substituted by the second.
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+template <int M1, int M2, int C, int P, int PS>
+__global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
+    constexpr int L = 2 * M1 * M2, T = M2, NL = PS * C, NT = NL * T, PITCH = L + 1;
+    constexpr int NV = L / (4 * T);
+    constexpr int LDSF = cmax(NL * PITCH, 2 * dc_scratch_doubles(P * C));
+    __shared__ __align__(16) float lds[LDSF];
+    const Geom& g = a.g;
+    const int b = blockIdx.y;
+    if ((int)blockIdx.x == g.Y * (P / PS)) {
+        dc_line_fp64(a, b, reinterpret_cast<double*>(lds), a.dc + (long long)b * C * P);
+        return;
+    }
+    // block: row index y, time slices t0 .. t0 + PS - 1
+    const int y = blockIdx.x / (P / PS), t0 = (blockIdx.x - y * (P / PS)) * PS;
+    const float* src = a.R + (long long)b * g.nc + (long long)t0 * g.slice + (long long)y * L;
+    float4 buf[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int e = 4 * ((int)threadIdx.x + NT * j);
+        const int line = e / L, col = e - line * L, t = line / C, c = line - t * C;
+        buf[j] = *reinterpret_cast<const float4*>(src + (long long)t * g.slice +
+                                                  (long long)c * g.plane + col);
+    }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int e = 4 * ((int)threadIdx.x + NT * j);
+        float* d = lds + (e / L) * PITCH + (e % L);
+        d[0] = buf[j].x; d[1] = buf[j].y; d[2] = buf[j].z; d[3] = buf[j].w;
+    }
+    __syncthreads();
+    const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
+    line_xform<M1, M2, 0>(lds + line * PITCH, tt, a.tx.tw);
+    if constexpr (C > 1) {
+        const float* Tc = a.tc.mat;                    // Tc[c * C + jc] = M_c[jc][c]
+        for (int q = threadIdx.x; q < PS * L; q += NT) {
+            const int t = q / L, jx = q - t * L;
+            float v[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] = lds[(t * C + c) * PITCH + jx];
+#pragma unroll
+            for (int jc = 0; jc < C; ++jc) {
+                float acc = 0.f;
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc = fmaf(Tc[c * C + jc], v[c], acc);
+                lds[(t * C + jc) * PITCH + jx] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    float* dst = a.Rt + (long long)b * g.nc + (long long)y * P + t0;
+    for (int e = threadIdx.x; e < NL * L; e += NT) {
+        const int t = e % PS, r = e / PS, jx = r % L, jc = r / L;
+        dst[(long long)(jc * L + jx) * g.Y * P + t] = lds[(t * C + jc) * PITCH + jx];
+    }
+}
+
+template <int M1, int M2, int C, int P, int PS>
+__global__ void __launch_bounds__(PS * C * M2) k_xi_tr(TcArgs a) {
+    constexpr int L = 2 * M1 * M2, T = M2, NL = PS * C, NT = NL * T, PITCH = L + 1;
+    constexpr int NV = L / (4 * T);
+    __shared__ __align__(16) float lds[NL * PITCH];
+    const Geom& g = a.g;
+    const int b = blockIdx.y;
+    const int y = blockIdx.x / (P / PS), t0 = (blockIdx.x - y * (P / PS)) * PS;
+    const float* src = a.Rt + (long long)b * g.nc + (long long)y * P + t0;
+    for (int e = threadIdx.x; e < NL * L; e += NT) {
+        const int t = e % PS, r = e / PS, jx = r % L, jc = r / L;
+        lds[(t * C + jc) * PITCH + jx] = src[(long long)(jc * L + jx) * g.Y * P + t];
+    }
+    __syncthreads();
+    if constexpr (C > 1) {
+        const float* Uc = a.tc.mat + C * C;            // Uc[jc * C + c] = M_c[jc][c]
+        for (int q = threadIdx.x; q < PS * L; q += NT) {
+            const int t = q / L, jx = q - t * L;
+            float v[C];
+#pragma unroll
+            for (int jc = 0; jc < C; ++jc) v[jc] = lds[(t * C + jc) * PITCH + jx];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                float acc = 0.f;
+#pragma unroll
+                for (int jc = 0; jc < C; ++jc) acc = fmaf(Uc[jc * C + c], v[jc], acc);
+                lds[(t * C + c) * PITCH + jx] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
+    line_xform<M1, M2, 1>(lds + line * PITCH, tt, a.tx.tw);
+    float* dstb = a.R + (long long)b * g.nc + (long long)t0 * g.slice + (long long)y * L;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int e = 4 * ((int)threadIdx.x + NT * j);
+        const int ln = e / L, col = e - ln * L, t = ln / C, c = ln - t * C;
+        const float* d = lds + ln * PITCH + col;
+        *reinterpret_cast<float4*>(dstb + (long long)t * g.slice + (long long)c * g.plane + col) =
+            make_float4(d[0], d[1], d[2], d[3]);
+    }
+}
+
+template <int M1, int M2, int P, int NT>
+__global__ void __launch_bounds__(NT) k_yt(TcArgs a) {
+    constexpr int L = 2 * M1 * M2, T = M2, PITCH = L + 1, NLINES = cmax(P, NT / T);
+    constexpr int NV = L * P / (4 * NT);
+    static_assert(NV * 4 * NT == L * P, "tile must split into float4 per thread");
+    __shared__ __align__(16) float lds[NLINES * PITCH];
+    const Geom& g = a.g;
+    const int b = blockIdx.y, jc = blockIdx.x / g.X, jx = blockIdx.x - jc * g.X;
+    float* base = a.Rt + (long long)b * g.nc + (long long)blockIdx.x * L * P;
+    float4 buf[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) buf[j] = reinterpret_cast<const float4*>(base)[threadIdx.x + NT * j];
+    for (int e = P * PITCH + threadIdx.x; e < NLINES * PITCH; e += NT) lds[e] = 0.f;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int e = 4 * ((int)threadIdx.x + NT * j);
+        const int y = e / P, t = e - y * P;
+        lds[t * PITCH + y] = buf[j].x;
+        lds[(t + 1) * PITCH + y] = buf[j].y;
+        lds[(t + 2) * PITCH + y] = buf[j].z;
+        lds[(t + 3) * PITCH + y] = buf[j].w;
+    }
+    __syncthreads();
+    const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
+    line_xform<M1, M2, 0>(lds + line * PITCH, tt, a.ty.tw);
+    const float lcx = a.tx.lam[jx] + a.tc.lam[jc];
+    for (int jy = threadIdx.x; jy < L; jy += NT) {
+        float u[P];
+        if (jx == 0 && jy == 0) {
+#pragma unroll
+            for (int t = 0; t < P; ++t) u[t] = a.dc[((long long)b * g.C + jc) * P + t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < P; ++t) u[t] = lds[t * PITCH + jy];
+            dct2_reg<P>(u, a.twt);
+            const float lc = lcx + a.ty.lam[jy];
+#pragma unroll
+            for (int jt = 0; jt < P; ++jt) {
+                const float lam = lc + a.tt.lam[jt];   // > 0 off the DC line
+                u[jt] = lam > 0.f ? u[jt] * __builtin_amdgcn_rcpf(lam) : 0.f;
+            }
+            dct3_reg<P>(u, a.twt);
+        }
+#pragma unroll
+        for (int t = 0; t < P; ++t) lds[t * PITCH + jy] = u[t];
+    }
+    __syncthreads();
+    line_xform<M1, M2, 1>(lds + line * PITCH, tt, a.ty.tw);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int e = 4 * ((int)threadIdx.x + NT * j);
+        const int y = e / P, t = e - y * P;
+        reinterpret_cast<float4*>(base)[threadIdx.x + NT * j] =
+            make_float4(lds[t * PITCH + y], lds[(t + 1) * PITCH + y], lds[(t + 2) * PITCH + y],
+                        lds[(t + 3) * PITCH + y]);
+    }
+}
+
+// Time slices per block of the x passes: all of them (blocks of half the
+// slices write 64-byte runs and measured slower at 256 x 256 x 3 x 32).
+template <int M1, int M2, int C, int P>
+static void xpair_launch(const TcArgs& a, int inverse, hipStream_t st) {
+    constexpr int PS = P, NT = PS * C * M2;
+    const unsigned nb = (unsigned)a.g.Y * (P / PS);
+    if (!inverse)
+        hipLaunchKernelGGL((k_xf_tr<M1, M2, C, P, PS>), dim3(nb + 1, (unsigned)a.g.B), dim3(NT), 0,
+                           st, a);
+    else
+        hipLaunchKernelGGL((k_xi_tr<M1, M2, C, P, PS>), dim3(nb, (unsigned)a.g.B), dim3(NT), 0, st,
+                           a);
+}
+
+template <int C, int P>
+static bool x_dispatch(const TcArgs& a, int inverse, hipStream_t st) {
+    switch (a.g.X) {
+        case 32: xpair_launch<4, 4, C, P>(a, inverse, st); return true;
+        case 64: xpair_launch<8, 4, C, P>(a, inverse, st); return true;
+        case 128: xpair_launch<8, 8, C, P>(a, inverse, st); return true;
+        case 256: xpair_launch<16, 8, C, P>(a, inverse, st); return true;
+        default: return false;
+    }
+}
+
+template <int P>
+static bool y_dispatch(const TcArgs& a, hipStream_t st) {
+    const dim3 grid((unsigned)(a.g.C * a.g.X), (unsigned)a.g.B);
+    switch (a.g.Y) {
+        case 32: hipLaunchKernelGGL((k_yt<4, 4, P, cmax(64, P * 4)>), grid, dim3(cmax(64, P * 4)), 0, st, a); return true;
+        case 64: hipLaunchKernelGGL((k_yt<8, 4, P, cmax(64, P * 4)>), grid, dim3(cmax(64, P * 4)), 0, st, a); return true;
+        case 128: hipLaunchKernelGGL((k_yt<8, 8, P, cmax(64, P * 8)>), grid, dim3(cmax(64, P * 8)), 0, st, a); return true;
+        case 256: hipLaunchKernelGGL((k_yt<16, 8, P, cmax(64, P * 8)>), grid, dim3(cmax(64, P * 8)), 0, st, a); return true;
+        default: return false;
+    }
+}
+
+bool fused_poisson_ok(const Geom& g, const AxisTab& tx, const AxisTab& ty, const AxisTab& tt) {
+    auto len_ok = [](int n) { return n == 32 || n == 64 || n == 128 || n == 256; };
+    return len_ok(g.X) && len_ok(g.Y) && !g.perx && !g.pery && tx.tw && ty.tw && tt.tw &&
+           (g.P == 8 || g.P == 16 || g.P == 32) && (g.C == 1 || g.C == 3);
+}
+
+static TcArgs fused_args(const Geom& g, float* R, float* Rt, float* dc, const AxisTab& tx,
+                         const AxisTab& ty, const AxisTab& tc, const AxisTab& tt,
+                         const double* tc64, const double* tt64, const double* part_slice,
+                         int nbx) {
+    TcArgs a{};
+    a.g = g; a.R = R; a.Rt = Rt; a.dc = dc; a.tx = tx; a.ty = ty; a.tc = tc; a.tt = tt;
+    a.tc64 = tc64;
+    a.tt64 = tt64;
+    a.lamc64 = tc64 + (long long)g.C * g.C;
+    a.lamt64 = tt64 + (long long)g.P * g.P;
+    a.part_slice = part_slice;
+    a.nbx = nbx;
+    a.twt = tt.tw;
+    return a;
+}
+
+void launch_fused_x(const Geom& g, float* R, float* Rt, float* dc, const AxisTab& tx,
+                    const AxisTab& ty, const AxisTab& tc, const AxisTab& tt, const double* tc64,
+                    const double* tt64, const double* part_slice, int nbx, int inverse,
+                    hipStream_t st) {
+    const TcArgs a = fused_args(g, R, Rt, dc, tx, ty, tc, tt, tc64, tt64, part_slice, nbx);
+#define OTD_FX(CC, PP) if (g.C == CC && g.P == PP) { x_dispatch<CC, PP>(a, inverse, st); return; }
+    OTD_FX(1, 8) OTD_FX(1, 16) OTD_FX(1, 32) OTD_FX(3, 8) OTD_FX(3, 16) OTD_FX(3, 32)
+#undef OTD_FX
+}
+
+void launch_fused_yt(const Geom& g, float* Rt, float* dc, const AxisTab& tx, const AxisTab& ty,
+                     const AxisTab& tc, const AxisTab& tt, hipStream_t st) {
+    const TcArgs a = fused_args(g, nullptr, Rt, dc, tx, ty, tc, tt, nullptr, nullptr, nullptr, 0);
+    if (g.P == 8) y_dispatch<8>(a, st);
+    else if (g.P == 16) y_dispatch<16>(a, st);
+    else y_dispatch<32>(a, st);
 }
 
 void launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStream_t st) {

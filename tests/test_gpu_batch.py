@@ -112,7 +112,7 @@ def test_autotune_keeps_results(otdyn, tmp_path, monkeypatch):
     bt.autotune(5)
     for i in range(len(probs)):
         bx, dense = otdyn.ot_dyn_batch_tuning(bt.bt, i)
-        assert bx in (64, 128, 256) and dense in (0, 1)
+        assert bx in (64, 128, 256) and dense in (0, 1, 2)
     assert (tmp_path / "tune.txt").exists()
     iters = 200
     bt.solve(iters, chunk=100)

@@ -173,6 +173,25 @@ def test_cfg3_full_size_iterations(otdyn, mode):
     prob.close()
 
 
+def test_fused_poisson_at_256_batched(otdyn):
+    """Two 256 x 256 x 3 x 8 problems in one plan take the fused three-pass
+    Poisson solve (the single 256 x 256 problem takes the five passes):
+    element-wise parity with the oracle for both problems."""
+    _say("fused poisson 256x256x3x8 batch 2")
+    g = G.Grid(256, 256, 3, 8)
+    pairs = [inputs.random_pair(900 + s, 256, 256) for s in (0, 1)]
+    f0 = np.stack([p[0] for p in pairs])
+    f1 = np.stack([p[1] for p in pairs])
+    prob = run_gpu(otdyn, g, f0, f1, 4, batch=2)
+    for b in range(2):
+        gx = to_natural(g, *host(prob, b))
+        st = oracle(g, f0[b], f1[b], 4)
+        assert rel(gx[3], st.x[3]) < TOL, b
+        for a in range(3):
+            assert rel(gx[a], st.x[a]) < TOL, (b, a)
+    prob.close()
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_mass_and_divergence_invariants(otdyn, mode):
     _say(f"invariants mode {mode}")
