@@ -58,6 +58,26 @@ def test_projection_is_kkt_solution(rng):
     assert np.abs(G.A_residual(g, p, f0, f1)).max() < 1e-11
 
 
+def test_projection_ignores_a_gradient_shift(rng):
+    """The projection of Step 1 is affine with Pi(a) = Pi(a - A^T phi) for
+    every potential phi (A^T phi lies in the range that the projection
+    removes): the identity that lets the GPU carry the previous iteration's
+    potential and solve only for the change.  Checked against the dense KKT
+    solution above through pdhg.project, on a periodic-colour and a 1D
+    periodic grid, with a random phi including a constant part."""
+    for g in (G.Grid(3, 4, 3, 3), G.Grid(6, 1, 1, 4, (G.PERIODIC, G.NEUMANN, G.NEUMANN))):
+        f0, f1 = _pair((g.C, g.Y, g.X), 11)
+        a = tuple(rng.standard_normal(s) for s in
+                  (g.m_shape(0), g.m_shape(1), g.m_shape(2), g.f_shape))
+        phi = rng.standard_normal(g.centre_shape) + 3.0
+        shift = G.AT_apply(g, phi)
+        b = tuple(ai - si for ai, si in zip(a, shift))
+        np.testing.assert_allclose(G.flat(pdhg.project(g, b, f0, f1)),
+                                   G.flat(pdhg.project(g, a, f0, f1)), atol=1e-11)
+        # and the shift is not trivial
+        assert np.linalg.norm(G.flat(shift)) > 1.0
+
+
 def test_cfg1_shape_invariants():
     """16 x 16 x 3 x 8 RGB workload: r_div at rounding level after every
     projection and exact mass in every time slice."""
