@@ -245,7 +245,7 @@ def main():
                     help="projection mode (default: the library default)")
     ap.add_argument("--size", type=int, nargs=4, default=[256, 256, 3, 32],
                     metavar=("X", "Y", "C", "P"))
-    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
