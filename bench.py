@@ -176,6 +176,9 @@ def hue_batch(args):
         say(f"looped problem {i} (n={n}, T={T}): {r.iterations} iterations, status {st}")
         pr.close()
     per_problem = t_loop / len(idx)
+    cpu = None
+    if not args.no_cpu:
+        cpu = hue_cpu_baseline(probs, idx, args)
     out = {
         "metric": "time-to-tolerance of 1024 batched hue problems",
         "value": t_batch, "unit": "s", "higher_is_better": False,
@@ -193,7 +196,28 @@ def hue_batch(args):
                                 "extrapolated_s": per_problem * len(probs),
                                 "batch_speedup": per_problem * len(probs) / t_batch},
     }
+    if cpu:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
+
+
+def hue_cpu_baseline(probs, idx, args, iters: int = 600):
+    """The FP64 oracle on the looped sample of hue problems, a fixed number
+    of iterations each (fixed step sizes, as in Algorithm 1)."""
+    import numpy as np
+    from oracle import grid as G, pdhg
+    cells, dt = 0, 0.0
+    for i in idx:
+        n, T, h0, h1 = probs[i]
+        g = G.Grid(n, 1, 1, T, (G.PERIODIC, G.NEUMANN, G.NEUMANN))
+        t0 = time.perf_counter()
+        pdhg.solve(g, h0.reshape(1, 1, -1).astype(np.float64), h1.reshape(1, 1, -1).astype(np.float64),
+                   args.hue_tau, args.hue_sigma, iters)
+        dt += time.perf_counter() - t0
+        cells += n * T * iters
+    return {"value": cells / dt, "unit": "cell-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} iterations of each of {len(idx)} hue problems "
+                      f"(the looped sample), FP64 NumPy/SciPy oracle (single-threaded), {dt:.1f} s"}
 
 
 def warm_start(args):

@@ -216,6 +216,16 @@ def ot_dyn_residuals(plan: int, F, Mx, My, Mc):
     return st, rep
 
 
+def ot_dyn_get_dual(plan: int, b) -> int:
+    """Copy the dual b of the plan into b [batch][4][P][C][Y][X] (device)."""
+    return _check(lib().ot_dyn_get_dual(plan, _ptr(b)), plan)
+
+
+def ot_dyn_set_dual(plan: int, b) -> int:
+    """Set the dual b (and b_bar = b) from b [batch][4][P][C][Y][X] (device)."""
+    return _check(lib().ot_dyn_set_dual(plan, _ptr(b)), plan)
+
+
 def ot_dyn_profile(plan: int, mask: int) -> int:
     return _check(lib().ot_dyn_profile(plan, mask), plan)
 
@@ -373,6 +383,17 @@ class Problem:
 
     def init(self, mode: int = OT_INIT_COLD):
         return ot_dyn_init(self.plan, mode, *self.state())
+
+    def get_dual(self):
+        """The dual iterate as a device tensor [B, 4, P, C, Y, X] (a copy)."""
+        import torch
+        d = self.desc
+        b = torch.empty((d.batch, 4, d.P, d.C, d.Y, d.X), dtype=torch.float32, device=self.device)
+        ot_dyn_get_dual(self.plan, b)
+        return b
+
+    def set_dual(self, b):
+        return ot_dyn_set_dual(self.plan, b)
 
     def step(self, iters: int):
         return ot_dyn_step(self.plan, *self.state(), iters)

@@ -334,3 +334,38 @@ def test_error_paths(otdyn):
     status, rep = prob.solve(3)
     assert status == otdyn.OT_NOT_CONVERGED and rep.iterations == 3
     prob.close()
+
+
+def test_restart_from_state_and_dual(otdyn):
+    """A run stopped after 100 iterations and restarted in a new plan from
+    its primal (OT_INIT_PRIMAL) and dual (ot_dyn_set_dual, which also sets
+    b_bar = b) stays close to the run that never stopped, much closer than
+    a restart from the primal alone (zero dual); the dual round-trips
+    exactly."""
+    _say("restart from state and dual")
+    import torch
+    g = G.Grid(24, 20, 3, 8)
+    f0, f1 = inputs.cfg2_pair(X=24, Y=20)
+    a = run_gpu(otdyn, g, f0, f1, 100)
+    dual = a.get_dual()
+    state = [t.clone() for t in a.state()]
+    a.step(40)
+    torch.cuda.synchronize()
+    ref = host(a)
+    errs = {}
+    for use_dual in (True, False):
+        b = run_gpu(otdyn, g, f0, f1, 0)
+        for dst, src in zip(b.state(), state):
+            dst.copy_(src)
+        b.init(otdyn.OT_INIT_PRIMAL)
+        if use_dual:
+            b.set_dual(dual)
+            np.testing.assert_array_equal(b.get_dual().cpu().numpy(), dual.cpu().numpy())
+        b.step(40)
+        torch.cuda.synchronize()
+        hb = host(b)
+        errs[use_dual] = max(rel(hb[0][1:g.P], ref[0][1:g.P]), *(rel(hb[q], ref[q]) for q in range(1, 4)))
+        b.close()
+    a.close()
+    _say(f"restart error with dual {errs[True]:.2e}, without {errs[False]:.2e}")
+    assert errs[True] < 0.2 * errs[False], errs
