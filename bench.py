@@ -255,7 +255,7 @@ def main():
     ap.add_argument("--warm-count", type=int, default=64)
     ap.add_argument("--warm-max-iters", type=int, default=30000)
     ap.add_argument("--hue-count", type=int, default=1024)
-    ap.add_argument("--hue-max-iters", type=int, default=30000)
+    ap.add_argument("--hue-max-iters", type=int, default=60000)
     ap.add_argument("--hue-chunk", type=int, default=200)
     ap.add_argument("--hue-loop-sample", type=int, default=8)
     ap.add_argument("--hue-tau", type=float, default=3.0)
