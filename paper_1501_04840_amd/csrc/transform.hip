@@ -47,6 +47,50 @@ __global__ void __launch_bounds__(kT) k_rows(float* R, long long rows, AxisTab t
     }
 }
 
+// Dense row transform on the matrix cores, for lengths without a fast path
+// (the periodic hue axes of 180 and 360 bins, image sides like 100): a block
+// owns 32 rows, staged in LDS with zero padding to Lp (a multiple of 32), and
+// its four waves compute 32 x 32 output tiles Y = X T with MFMA 32x32x2 FP32
+// steps over k (lane l supplies X[l % 32][k0 + l / 32] and
+// T[k0 + l / 32][j0 + l % 32]; the result lands at row 8 (r / 4) + 4 (l / 32)
+// + r % 4, column l % 32 of the tile).
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kMfmaRowsMaxL = 480;     // 32 rows of Lp + 1 floats stay under 64 KB
+
+__global__ void __launch_bounds__(256) k_rows_mfma(float* R, long long rows, AxisTab t, int inverse,
+                                                 int Lp) {
+    extern __shared__ float xs[];
+    const int L = t.n, pitch = Lp + 1;
+    const long long r0 = (long long)blockIdx.x * 32;
+    const int nr = (int)min((long long)32, rows - r0);
+    float* g = R + r0 * L;
+    for (int e = threadIdx.x; e < 32 * Lp; e += 256) {
+        const int r = e / Lp, k = e - r * Lp;
+        xs[r * pitch + k] = (r < nr && k < L) ? g[(long long)r * L + k] : 0.f;
+    }
+    __syncthreads();
+    const float* T = inverse ? inv_tab(t) : fwd_tab(t);      // T[k * L + j]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 31, half = lane >> 5;
+    for (int jt = w; jt * 32 < Lp; jt += 4) {
+        const int j = jt * 32 + n;
+        const bool jin = j < L;
+        f32x16 acc = {};
+#pragma unroll 8
+        for (int k0 = 0; k0 < Lp; k0 += 2) {
+            const int k = k0 + half;
+            const float a = xs[n * pitch + k];
+            const float b = (jin && k < L) ? T[(long long)k * L + j] : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+        if (!jin) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = (r >> 2) * 8 + half * 4 + (r & 3);
+            if (row < nr) g[(long long)row * L + j] = acc[r];
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kT) k_cols(float* R, long long inner, AxisTab t, int inverse,
                                             int W) {
     extern __shared__ float tile[];
@@ -654,6 +698,13 @@ void launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStr
         return;
     }
     const int L = t.n;
+    if (L <= kMfmaRowsMaxL) {
+        const int Lp = (L + 31) / 32 * 32;
+        const size_t sh = (size_t)32 * (Lp + 1) * sizeof(float);
+        hipLaunchKernelGGL(k_rows_mfma, dim3((unsigned)((rows + 31) / 32)), dim3(256), sh, st, R,
+                           rows, t, inverse, Lp);
+        return;
+    }
     int rb = kTileFloats / L;
     if (rb < 1) rb = 1;
     const long long nb = (rows + rb - 1) / rb;
