@@ -91,6 +91,46 @@ __global__ void __launch_bounds__(256) k_rows_mfma(float* R, long long rows, Axi
     }
 }
 
+// The same contraction along a strided axis (data [outer][L][inner]): a block
+// owns 32 columns i of one outer index, staged as [k][i] (rows of 32
+// consecutive floats), and computes Y[j][i] = sum_k T[k][j] X[k][i] with the
+// matrix as the MFMA A operand (lane l supplies T[k0 + l / 32][j0 + l % 32])
+// and the data as B (X[k0 + l / 32][l % 32]).
+__global__ void __launch_bounds__(256) k_cols_mfma(float* R, long long inner, AxisTab t, int inverse,
+                                                 int Lp) {
+    extern __shared__ float xs[];
+    constexpr int pitch = 33;
+    const int L = t.n;
+    const long long o = blockIdx.y;
+    const long long i0 = (long long)blockIdx.x * 32;
+    const int nw = (int)min((long long)32, inner - i0);
+    float* g = R + o * L * inner + i0;
+    for (int e = threadIdx.x; e < Lp * 32; e += 256) {
+        const int k = e >> 5, i = e & 31;
+        xs[k * pitch + i] = (k < L && i < nw) ? g[(long long)k * inner + i] : 0.f;
+    }
+    __syncthreads();
+    const float* T = inverse ? inv_tab(t) : fwd_tab(t);      // T[k * L + j]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 31, half = lane >> 5;
+    for (int jt = w; jt * 32 < Lp; jt += 4) {
+        const int jA = jt * 32 + n;          // output row supplied by this lane's A value
+        f32x16 acc = {};
+#pragma unroll 8
+        for (int k0 = 0; k0 < Lp; k0 += 2) {
+            const int k = k0 + half;
+            const float a = (jA < L && k < L) ? T[(long long)k * L + jA] : 0.f;
+            const float b = xs[k * pitch + n];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+        if (n >= nw) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int j = jt * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
+            if (j < L) g[(long long)j * inner + n] = acc[r];
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kT) k_cols(float* R, long long inner, AxisTab t, int inverse,
                                             int W) {
     extern __shared__ float tile[];
@@ -719,6 +759,13 @@ void launch_cols(float* R, long long outer, long long inner, const AxisTab& t, i
         return;
     }
     const int L = t.n;
+    if (L <= kMfmaRowsMaxL) {
+        const int Lp = (L + 31) / 32 * 32;
+        const size_t sh = (size_t)Lp * 33 * sizeof(float);
+        hipLaunchKernelGGL(k_cols_mfma, dim3((unsigned)((inner + 31) / 32), (unsigned)outer),
+                           dim3(256), sh, st, R, inner, t, inverse, Lp);
+        return;
+    }
     int W = 64;
     while (W > 1 && L * W > kTileFloats) W >>= 1;
     const long long nb = (inner + W - 1) / W;

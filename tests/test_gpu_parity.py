@@ -173,6 +173,22 @@ def test_cfg3_full_size_iterations(otdyn, mode):
     prob.close()
 
 
+def test_paper_image_size_dense_transforms(otdyn):
+    """100 x 100 x 3 x 32, the size of the paper's RGB experiments: x and y
+    have no fast path and take the dense MFMA contractions.  Element-wise
+    parity with the oracle after four iterations."""
+    _say("100x100x3x32 dense transforms")
+    g = G.Grid(100, 100, 3, 32)
+    f0, f1 = inputs.cfg3_pair(100, 100)
+    prob = run_gpu(otdyn, g, f0, f1, 4)
+    gx = to_natural(g, *host(prob))
+    st = oracle(g, f0, f1, 4)
+    assert rel(gx[3], st.x[3]) < TOL
+    for a in range(3):
+        assert rel(gx[a], st.x[a]) < TOL, a
+    prob.close()
+
+
 def test_fused_poisson_at_256_batched(otdyn):
     """Two 256 x 256 x 3 x 8 problems in one plan take the fused three-pass
     Poisson solve (the single 256 x 256 problem takes the five passes):
