@@ -50,84 +50,93 @@ __global__ void __launch_bounds__(kT) k_rows(float* R, long long rows, AxisTab t
 // Dense row transform on the matrix cores, for lengths without a fast path
 // (the periodic hue axes of 180 and 360 bins, image sides like 100): a block
 // owns 32 rows, staged in LDS with zero padding to Lp (a multiple of 32), and
-// its four waves compute 32 x 32 output tiles Y = X T with MFMA 32x32x2 FP32
-// steps over k (lane l supplies X[l % 32][k0 + l / 32] and
+// each of its Lp / 32 waves computes one 32 x 32 output tile of Y = X T with
+// MFMA 32x32x2 FP32 steps over k (lane l supplies X[l % 32][k0 + l / 32] and
 // T[k0 + l / 32][j0 + l % 32]; the result lands at row 8 (r / 4) + 4 (l / 32)
-// + r % 4, column l % 32 of the tile).
+// + r % 4, column l % 32 of the tile).  The matrix operand comes from L2 in
+// chunks of 16 steps whose loads are all in flight before the chunk's MFMAs.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kMfmaRowsMaxL = 480;     // 32 rows of Lp + 1 floats stay under 64 KB
 
-__global__ void __launch_bounds__(256) k_rows_mfma(float* R, long long rows, AxisTab t, int inverse,
-                                                 int Lp) {
+__device__ __forceinline__ int mfma_row(int r, int half) { return (r >> 2) * 8 + half * 4 + (r & 3); }
+
+__global__ void __launch_bounds__(1024) k_rows_mfma(float* R, long long rows, AxisTab t, int inverse,
+                                                  int Lp) {
     extern __shared__ float xs[];
-    const int L = t.n, pitch = Lp + 1;
+    const int L = t.n, pitch = Lp + 1, nt = blockDim.x;
     const long long r0 = (long long)blockIdx.x * 32;
     const int nr = (int)min((long long)32, rows - r0);
     float* g = R + r0 * L;
-    for (int e = threadIdx.x; e < 32 * Lp; e += 256) {
+    for (int e = threadIdx.x; e < 32 * Lp; e += nt) {
         const int r = e / Lp, k = e - r * Lp;
         xs[r * pitch + k] = (r < nr && k < L) ? g[(long long)r * L + k] : 0.f;
     }
     __syncthreads();
     const float* T = inverse ? inv_tab(t) : fwd_tab(t);      // T[k * L + j]
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 31, half = lane >> 5;
-    for (int jt = w; jt * 32 < Lp; jt += 4) {
-        const int j = jt * 32 + n;
-        const bool jin = j < L;
-        f32x16 acc = {};
-#pragma unroll 8
-        for (int k0 = 0; k0 < Lp; k0 += 2) {
-            const int k = k0 + half;
-            const float a = xs[n * pitch + k];
-            const float b = (jin && k < L) ? T[(long long)k * L + j] : 0.f;
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-        }
-        if (!jin) continue;
+    const int lane = threadIdx.x & 63, jt = threadIdx.x >> 6, n = lane & 31, half = lane >> 5;
+    const int j = jt * 32 + n;
+    const bool jin = j < L;
+    f32x16 acc = {};
+    for (int k0 = 0; k0 < Lp; k0 += 32) {
+        float bv[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = (r >> 2) * 8 + half * 4 + (r & 3);
-            if (row < nr) g[(long long)row * L + j] = acc[r];
+        for (int q = 0; q < 16; ++q) {
+            const int k = k0 + 2 * q + half;
+            bv[q] = (jin && k < L) ? T[(long long)k * L + j] : 0.f;
         }
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[n * pitch + k0 + 2 * q + half], bv[q], acc,
+                                                       0, 0, 0);
+    }
+    if (!jin) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = mfma_row(r, half);
+        if (row < nr) g[(long long)row * L + j] = acc[r];
     }
 }
 
 // The same contraction along a strided axis (data [outer][L][inner]): a block
 // owns 32 columns i of one outer index, staged as [k][i] (rows of 32
-// consecutive floats), and computes Y[j][i] = sum_k T[k][j] X[k][i] with the
-// matrix as the MFMA A operand (lane l supplies T[k0 + l / 32][j0 + l % 32])
-// and the data as B (X[k0 + l / 32][l % 32]).
-__global__ void __launch_bounds__(256) k_cols_mfma(float* R, long long inner, AxisTab t, int inverse,
-                                                 int Lp) {
+// consecutive floats), and each wave computes one 32-row tile of
+// Y[j][i] = sum_k T[k][j] X[k][i] with the matrix as the MFMA A operand (lane
+// l supplies T[k0 + l / 32][j0 + l % 32]) and the data as B (X[k0 + l / 32][l % 32]).
+__global__ void __launch_bounds__(1024) k_cols_mfma(float* R, long long inner, AxisTab t, int inverse,
+                                                  int Lp) {
     extern __shared__ float xs[];
     constexpr int pitch = 33;
-    const int L = t.n;
+    const int L = t.n, nt = blockDim.x;
     const long long o = blockIdx.y;
     const long long i0 = (long long)blockIdx.x * 32;
     const int nw = (int)min((long long)32, inner - i0);
     float* g = R + o * L * inner + i0;
-    for (int e = threadIdx.x; e < Lp * 32; e += 256) {
+    for (int e = threadIdx.x; e < Lp * 32; e += nt) {
         const int k = e >> 5, i = e & 31;
         xs[k * pitch + i] = (k < L && i < nw) ? g[(long long)k * inner + i] : 0.f;
     }
     __syncthreads();
     const float* T = inverse ? inv_tab(t) : fwd_tab(t);      // T[k * L + j]
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 31, half = lane >> 5;
-    for (int jt = w; jt * 32 < Lp; jt += 4) {
-        const int jA = jt * 32 + n;          // output row supplied by this lane's A value
-        f32x16 acc = {};
-#pragma unroll 8
-        for (int k0 = 0; k0 < Lp; k0 += 2) {
-            const int k = k0 + half;
-            const float a = (jA < L && k < L) ? T[(long long)k * L + jA] : 0.f;
-            const float b = xs[k * pitch + n];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-        }
-        if (n >= nw) continue;
+    const int lane = threadIdx.x & 63, jt = threadIdx.x >> 6, n = lane & 31, half = lane >> 5;
+    const int jA = jt * 32 + n;          // output row supplied by this lane's A value
+    f32x16 acc = {};
+    for (int k0 = 0; k0 < Lp; k0 += 32) {
+        float av[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int j = jt * 32 + (r >> 2) * 8 + half * 4 + (r & 3);
-            if (j < L) g[(long long)j * inner + n] = acc[r];
+        for (int q = 0; q < 16; ++q) {
+            const int k = k0 + 2 * q + half;
+            av[q] = (jA < L && k < L) ? T[(long long)k * L + jA] : 0.f;
         }
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], xs[(k0 + 2 * q + half) * pitch + n], acc,
+                                                       0, 0, 0);
+    }
+    if (n >= nw) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int jj = jt * 32 + mfma_row(r, half);
+        if (jj < L) g[(long long)jj * inner + n] = acc[r];
     }
 }
 
@@ -741,7 +750,7 @@ void launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStr
     if (L <= kMfmaRowsMaxL) {
         const int Lp = (L + 31) / 32 * 32;
         const size_t sh = (size_t)32 * (Lp + 1) * sizeof(float);
-        hipLaunchKernelGGL(k_rows_mfma, dim3((unsigned)((rows + 31) / 32)), dim3(256), sh, st, R,
+        hipLaunchKernelGGL(k_rows_mfma, dim3((unsigned)((rows + 31) / 32)), dim3(2 * Lp), sh, st, R,
                            rows, t, inverse, Lp);
         return;
     }
@@ -763,7 +772,7 @@ void launch_cols(float* R, long long outer, long long inner, const AxisTab& t, i
         const int Lp = (L + 31) / 32 * 32;
         const size_t sh = (size_t)Lp * 33 * sizeof(float);
         hipLaunchKernelGGL(k_cols_mfma, dim3((unsigned)((inner + 31) / 32), (unsigned)outer),
-                           dim3(256), sh, st, R, inner, t, inverse, Lp);
+                           dim3(2 * Lp), sh, st, R, inner, t, inverse, Lp);
         return;
     }
     int W = 64;
