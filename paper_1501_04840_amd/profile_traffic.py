@@ -108,5 +108,23 @@ def summarise(fetch_dir: str, write_dir: str, out_json: str, out_md: str, cmd: s
         fh.write("\n".join(lines) + "\n")
 
 
+def summarise_stats(stats_csv: str, out_md: str, title: str, cmd: str, note: str = "",
+                    top: int = 16):
+    """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv)."""
+    with open(stats_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    lines = [f"# {title}", "", "Command (repository root, one MI355X):", "", f"    {cmd}", ""]
+    if note:
+        lines += [note, ""]
+    lines += ["| kernel | calls | avg us | min us | max us | total % |", "|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     run()

@@ -47,7 +47,7 @@ SLC = CSHAPE[0] * CSHAPE[1] * C          # coarse slice
 
 
 def log(msg: str):
-    print(msg, flush=True)
+    print(msg, file=sys.stderr, flush=True)
 
 
 def solver_desc(shape=SHAPE, tau: float = 3.0, sigma: float = 0.33, tol: float = 1e-6,
