@@ -12,80 +12,118 @@
 // each do an M1-point DFT in registers, multiply by twiddles, exchange
 // through LDS once, and finish with M1 / M2 DFTs of length M2 each.
 // Twiddles come from a per-axis table tw4[j] = e^{-i pi j / (2L)}, j < 4L.
+//
+// Real-input packing relates the frequencies k and M - k: with
+// 2 ve = Z[k] + conj Z[M-k] and 2 vo = -i (Z[k] - conj Z[M-k]),
+//   V[k] = ve + w vo,  V[M-k] = conj(ve - w vo),  w = e^{-2 pi i k / L},
+// so every thread takes such pairs together (one product serves both, and
+// each packed value is read once).  LDS accesses are written as a per-thread
+// base pointer plus a compile-time offset, which the hardware encodes in the
+// instruction instead of computing an address per access.
 #pragma once
 
 #include "fft_common.h"
 
 namespace otd {
 
-// Four-step DFT of length M = M1 M2 on one line.  Stage-1 input n comes from
-// load(n); on return out[q][k2] = Z[k1 + M1 k2] with k1 = t + M2 q.  The
-// line's LDS region s (2M floats) is used for the exchange.  All threads of
-// the block must call this (it synchronises the block).
+// Four-step DFT of length M = M1 M2 on one line.  Stage-1 input n = M2 n1 + t
+// comes from load(n1) (the caller knows t); on return out[q][k2] =
+// Z[k1 + M1 k2] with k1 = t + M2 q.  The line's LDS region s (2M floats) is
+// used for the exchange.  All threads of the block must call this (it
+// synchronises the block).
 template <int M1, int M2, class Load>
 __device__ __forceinline__ void fft_core(float* s, int t, const float2* tw4, Load load,
                                          float2 (&out)[M1 / M2][M2]) {
     constexpr int M = M1 * M2, L = 2 * M;
     float2 a[M1];
 #pragma unroll
-    for (int n1 = 0; n1 < M1; ++n1) a[n1] = load(M2 * n1 + t);
+    for (int n1 = 0; n1 < M1; ++n1) a[n1] = load(n1);
     dft<M1>(a);
 #pragma unroll
     for (int k1 = 1; k1 < M1; ++k1) a[k1] = cmul(a[k1], tw4[(8 * t * k1) & (4 * L - 1)]);
     __syncthreads();
+    float* const sw = s + 2 * t;                      // Z1[k1 M2 + t]
 #pragma unroll
-    for (int k1 = 0; k1 < M1; ++k1) st2(s, k1 * M2 + t, a[k1]);
+    for (int k1 = 0; k1 < M1; ++k1) st2(sw, k1 * M2, a[k1]);
     __syncthreads();
+    const float* const sr = s + 2 * M2 * t;           // Z1[(t + M2 q) M2 + n2]
 #pragma unroll
     for (int q = 0; q < M1 / M2; ++q) {
-        const int k1 = t + M2 * q;
 #pragma unroll
-        for (int n2 = 0; n2 < M2; ++n2) out[q][n2] = ld2(s, k1 * M2 + n2);
+        for (int n2 = 0; n2 < M2; ++n2) out[q][n2] = ld2(sr, M2 * M2 * q + n2);
         dft<M2>(out[q]);
     }
 }
 
-// V[k] of the length-L real DFT from the packed Z (k = 0..M).
-template <int M>
-__device__ __forceinline__ float2 unpack(const float* s, int k, const float2* tw4) {
-    const float2 zk = ld2(s, k & (M - 1));
-    const float2 zm = ld2(s, (M - k) & (M - 1));
-    const float2 ve = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-    const float2 vo = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-    return k < M ? cadd(ve, cmul(tw4[4 * k], vo)) : csub(ve, vo);
+// Stores the stage-2 output out[q][k2] = Z[t + M2 q + M1 k2] to s[2 Z index].
+template <int M1, int M2>
+__device__ __forceinline__ void store_z(float* s, int t, const float2 (&z)[M1 / M2][M2]) {
+    float* const sw = s + 2 * t;
+#pragma unroll
+    for (int q = 0; q < M1 / M2; ++q)
+#pragma unroll
+        for (int k2 = 0; k2 < M2; ++k2) st2(sw, M2 * q + M1 * k2, z[q][k2]);
+}
+
+// Z[k] and Z[M - k] for k = t + M2 j (j compile-time) from the stored packed
+// DFT.  For k = 0 the partner is Z[0] itself.
+template <int M, int M2>
+__device__ __forceinline__ void load_pair(const float* s, int t, int j, float2& zk, float2& zm) {
+    zk = ld2(s + 2 * t, M2 * j);
+    if (j == 0) zm = ld2(s, (M - t) & (M - 1));
+    else zm = ld2(s - 2 * t, M - M2 * j);
 }
 
 // Orthonormal DCT-II of the line s[0..L) in place.
 template <int M1, int M2>
 __device__ void line_dct2(float* s, int t, const float2* tw4) {
-    constexpr int M = M1 * M2, L = 2 * M, T = M2, NK = (M + T) / T;
-    auto vidx = [](int m) { return m < M ? 2 * m : 2 * L - 1 - 2 * m; };
+    constexpr int M = M1 * M2, L = 2 * M, T = M2, NP = (M / 2 + T) / T;
+    // z[n] = v[2n] + i v[2n+1] with n = M2 n1 + t; v[2n] and v[2n+1] are
+    // x[4n], x[4n+2] in the first half (n1 < M1 / 2) and x[2L-1-4n],
+    // x[2L-3-4n] in the second.
+    const float* const sp = s + 4 * t;
+    const float* const sm = s - 4 * t;
     float2 z[M1 / M2][M2];
-    fft_core<M1, M2>(s, t, tw4, [&](int n) { return make_float2(s[vidx(2 * n)], s[vidx(2 * n + 1)]); }, z);
+    fft_core<M1, M2>(s, t, tw4, [&](int n1) {
+        return n1 < M1 / 2 ? make_float2(sp[4 * M2 * n1], sp[4 * M2 * n1 + 2])
+                           : make_float2(sm[2 * L - 1 - 4 * M2 * n1], sm[2 * L - 3 - 4 * M2 * n1]);
+    }, z);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < M1 / M2; ++q)
-#pragma unroll
-        for (int k2 = 0; k2 < M2; ++k2) st2(s, t + M2 * q + M1 * k2, z[q][k2]);
+    store_z<M1, M2>(s, t, z);
     __syncthreads();
-    float xr[NK], xi[NK];
+    // 2 V[k] = a and 2 V[M-k] = b; the factor 1/2 is folded into the scales
+    const float h = 0.5f * sqrtf(2.f / L), h0 = 0.5f * sqrtf(1.f / L);
+    float o[NP][4];
 #pragma unroll
-    for (int j = 0; j < NK; ++j) {
+    for (int j = 0; j < NP; ++j) {
         const int k = t + T * j;
-        if (k <= M) {
-            const float2 w = cmul(tw4[k], unpack<M>(s, k, tw4));
-            xr[j] = w.x;
-            xi[j] = -w.y;
+        if (k <= M / 2) {
+            float2 zk, zm;
+            load_pair<M, T>(s, t, j, zk, zm);
+            const float2 ve = make_float2(zk.x + zm.x, zk.y - zm.y);
+            const float2 vo = make_float2(zk.y + zm.y, zm.x - zk.x);
+            const float2 p = cmul(tw4[4 * k], vo);
+            const float2 xa = cmul(tw4[k], cadd(ve, p));
+            const float2 xb = cmul(tw4[M - k], make_float2(ve.x - p.x, p.y - ve.y));
+            o[j][0] = (k == 0 ? h0 : h) * xa.x;     // X[k]
+            o[j][1] = -h * xa.y;                    // X[L-k]
+            o[j][2] = h * xb.x;                     // X[M-k]
+            o[j][3] = -h * xb.y;                    // X[M+k]
         }
     }
     __syncthreads();
-    const float sc = sqrtf(2.f / L), sc0 = sqrtf(1.f / L);
+    float* const op = s + t;
+    float* const om = s - t;
 #pragma unroll
-    for (int j = 0; j < NK; ++j) {
+    for (int j = 0; j < NP; ++j) {
         const int k = t + T * j;
-        if (k <= M) {
-            s[k] = (k == 0 ? sc0 : sc) * xr[j];
-            if (k > 0 && k < M) s[L - k] = sc * xi[j];
+        if (k <= M / 2) {
+            op[T * j] = o[j][0];
+            if (k > 0) om[L - T * j] = o[j][1];
+            if (k < M / 2) {
+                om[M - T * j] = o[j][2];
+                if (k > 0) op[M + T * j] = o[j][3];
+            }
         }
     }
     __syncthreads();
@@ -94,39 +132,63 @@ __device__ void line_dct2(float* s, int t, const float2* tw4) {
 // Orthonormal DCT-III (inverse of line_dct2) in place.
 template <int M1, int M2>
 __device__ void line_dct3(float* s, int t, const float2* tw4) {
-    constexpr int M = M1 * M2, L = 2 * M, T = M2, NJ = M / T;
-    const float isc = 1.f / sqrtf(2.f / L), isc0 = 1.f / sqrtf(1.f / L);
-    auto X = [&](int k) -> float { return k >= L ? 0.f : s[k] * (k == 0 ? isc0 : isc); };
-    auto V = [&](int k) -> float2 {
-        return cmul(cconj(tw4[k]), make_float2(X(k), -X(L - k)));
-    };
-    float2 zc[NJ];
+    constexpr int M = M1 * M2, L = 2 * M, T = M2, NP = (M / 2 + T) / T;
+    // inputs scaled by sqrt(L / 2) (sqrt(L) for X[0]); with V(k) =
+    // conj(w4_k) (X[k], -X[L-k]), the packed spectrum is
+    //   conj Z[k] = conj(ve + i vo),  conj Z[M-k] = ve - i vo,
+    //   2 ve = V(k) + conj V(M-k),  2 vo = (V(k) - conj V(M-k)) conj(w_k).
+    // The factor sqrt(L / 2) / 2 is applied to the outputs instead.
+    const float* const ip = s + t;
+    const float* const im_ = s - t;
+    float2 zc[NP][2];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
+    for (int j = 0; j < NP; ++j) {
         const int k = t + T * j;
-        const float2 v = V(k), vm = cconj(V(M - k));
-        const float2 ve = make_float2(0.5f * (v.x + vm.x), 0.5f * (v.y + vm.y));
-        const float2 vo = cmul(make_float2(0.5f * (v.x - vm.x), 0.5f * (v.y - vm.y)),
-                               cconj(tw4[4 * k]));
-        const float2 zk = make_float2(ve.x - vo.y, ve.y + vo.x);
-        zc[j] = cconj(zk);
+        if (k <= M / 2) {
+            const float xk = k == 0 ? 1.41421356237309515f * s[0] : ip[T * j];
+            const float xl = j == 0 ? (k == 0 ? 0.f : s[L - t]) : im_[L - T * j];   // X[L-k]
+            const float xm = im_[M - T * j];                                         // X[M-k]
+            const float xp = ip[M + T * j];                                          // X[M+k]
+            const float2 v = cmul(cconj(tw4[k]), make_float2(xk, -xl));
+            const float2 w = cmul(cconj(tw4[M - k]), make_float2(xm, -xp));   // V(M-k)
+            const float2 ve = make_float2(v.x + w.x, v.y - w.y);
+            const float2 vo = cmul(make_float2(v.x - w.x, v.y + w.y), cconj(tw4[4 * k]));
+            zc[j][0] = make_float2(ve.x - vo.y, -(ve.y + vo.x));
+            zc[j][1] = make_float2(ve.x + vo.y, ve.y - vo.x);
+        }
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) st2(s, t + T * j, zc[j]);
+    for (int j = 0; j < NP; ++j) {
+        const int k = t + T * j;
+        if (k <= M / 2) {
+            st2(s + 2 * t, T * j, zc[j][0]);
+            if (k > 0 && k < M / 2) st2(s - 2 * t, M - T * j, zc[j][1]);
+        }
+    }
     __syncthreads();
     float2 r[M1 / M2][M2];
-    fft_core<M1, M2>(s, t, tw4, [&](int n) { return ld2(s, n); }, r);
+    const float* const sl = s + 2 * t;
+    fft_core<M1, M2>(s, t, tw4, [&](int n1) { return ld2(sl, M2 * n1); }, r);
     __syncthreads();
-    const float im = 1.f / M;
-    auto pos = [](int m) { return m < M ? 2 * m : 2 * (L - 1 - m) + 1; };
+    // output n = t + M2 q + M1 k2: x[pos(2n)] = Re r / M, x[pos(2n+1)] = -Im r / M
+    // with pos(m) = 2m (m < M), 2(L-1-m)+1 (m >= M); m < M iff the
+    // compile-time part B = 2 (M2 q + M1 k2) is below M
+    const float sc = 0.5f * sqrtf(0.5f * L) / M;
+    float* const wp = s + 4 * t;
+    float* const wm = s - 4 * t;
 #pragma unroll
     for (int q = 0; q < M1 / M2; ++q)
 #pragma unroll
         for (int k2 = 0; k2 < M2; ++k2) {
-            const int n = t + M2 * q + M1 * k2;
-            s[pos(2 * n)] = r[q][k2].x * im;
-            s[pos(2 * n + 1)] = -r[q][k2].y * im;
+            const int B = 2 * (M2 * q + M1 * k2);
+            if (B < M) {
+                wp[2 * B] = r[q][k2].x * sc;
+                wp[2 * B + 2] = -r[q][k2].y * sc;
+            } else {
+                wm[2 * L - 1 - 2 * B] = r[q][k2].x * sc;
+                wm[2 * L - 3 - 2 * B] = -r[q][k2].y * sc;
+            }
         }
     __syncthreads();
 }
@@ -134,33 +196,47 @@ __device__ void line_dct3(float* s, int t, const float2* tw4) {
 // Orthonormal discrete Hartley transform (its own inverse) in place.
 template <int M1, int M2>
 __device__ void line_dht(float* s, int t, const float2* tw4) {
-    constexpr int M = M1 * M2, L = 2 * M, T = M2, NK = (M + T) / T;
+    constexpr int M = M1 * M2, L = 2 * M, T = M2, NP = (M / 2 + T) / T;
     float2 z[M1 / M2][M2];
-    fft_core<M1, M2>(s, t, tw4, [&](int n) { return ld2(s, n); }, z);
+    const float* const sl = s + 2 * t;
+    fft_core<M1, M2>(s, t, tw4, [&](int n1) { return ld2(sl, M2 * n1); }, z);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < M1 / M2; ++q)
-#pragma unroll
-        for (int k2 = 0; k2 < M2; ++k2) st2(s, t + M2 * q + M1 * k2, z[q][k2]);
+    store_z<M1, M2>(s, t, z);
     __syncthreads();
-    float h0[NK], h1[NK];
+    // 2 F[k] = a and 2 F[M-k] = b; H[k] = (Re F - Im F) / sqrt(L) and
+    // H[L-k] = (Re F + Im F) / sqrt(L)
+    const float h = 0.5f * sqrtf(1.f / L);
+    float o[NP][4];
 #pragma unroll
-    for (int j = 0; j < NK; ++j) {
+    for (int j = 0; j < NP; ++j) {
         const int k = t + T * j;
-        if (k <= M) {
-            const float2 f = unpack<M>(s, k, tw4);
-            h0[j] = f.x - f.y;
-            h1[j] = f.x + f.y;
+        if (k <= M / 2) {
+            float2 zk, zm;
+            load_pair<M, T>(s, t, j, zk, zm);
+            const float2 ve = make_float2(zk.x + zm.x, zk.y - zm.y);
+            const float2 vo = make_float2(zk.y + zm.y, zm.x - zk.x);
+            const float2 p = cmul(tw4[4 * k], vo);
+            const float2 a = cadd(ve, p);
+            const float2 b = make_float2(ve.x - p.x, p.y - ve.y);
+            o[j][0] = h * (a.x - a.y);              // H[k]
+            o[j][1] = h * (a.x + a.y);              // H[L-k]
+            o[j][2] = h * (b.x - b.y);              // H[M-k]
+            o[j][3] = h * (b.x + b.y);              // H[M+k]
         }
     }
     __syncthreads();
-    const float sc = sqrtf(1.f / L);
+    float* const op = s + t;
+    float* const om = s - t;
 #pragma unroll
-    for (int j = 0; j < NK; ++j) {
+    for (int j = 0; j < NP; ++j) {
         const int k = t + T * j;
-        if (k <= M) {
-            s[k] = sc * h0[j];
-            if (k > 0 && k < M) s[L - k] = sc * h1[j];
+        if (k <= M / 2) {
+            op[T * j] = o[j][0];
+            if (k > 0) om[L - T * j] = o[j][1];
+            if (k < M / 2) {
+                om[M - T * j] = o[j][2];
+                if (k > 0) op[M + T * j] = o[j][3];
+            }
         }
     }
     __syncthreads();
