@@ -8,15 +8,48 @@
 
 namespace otd {
 
+// Planes reduced per block by the plane-sum blocks of k_rows_fft (32 lanes,
+// half a wave, per plane).
+constexpr int kSumPlanesPerBlock = 8;
+
 // Contiguous axis: LPB whole rows per block, row pitch L + 1 in LDS.  The
 // block's rows are one contiguous span, staged with unrolled float4 loads
-// so that every thread keeps all of its loads in flight at once.
+// so that every thread keeps all of its loads in flight at once.  The first
+// nsb blocks instead reduce the FP64 plane sums `ps` in place (the forward
+// x pass runs between the divergence kernel that writes them and the
+// colour/time pass that solves the spatial-DC line from them, so the
+// reduction costs no launch and leaves that pass a short serial part).
 template <int M1, int M2, int KIND>
-__global__ void __launch_bounds__(256) k_rows_fft(float* R, long long rows, const float2* tw4) {
+__global__ void __launch_bounds__(256) k_rows_fft(float* R, long long rows, const float2* tw4,
+                                                  PlaneSums ps, int nsb) {
     constexpr int L = 2 * M1 * M2, T = M2, LPB = 256 / T, PITCH = L + 1;
     constexpr int NV = LPB * L / 1024;            // float4 per thread
     __shared__ float lds[LPB * PITCH];
-    const long long r0 = (long long)blockIdx.x * LPB;
+    if ((int)blockIdx.x < nsb) {
+        // no block synchronisation in this role: blocks return independently
+        const int l = threadIdx.x & 31;
+        const long long q = (long long)blockIdx.x * kSumPlanesPerBlock + (threadIdx.x >> 5);
+        const bool live = q < ps.nq;
+        double* pp = ps.part + (live ? q : 0) * ps.nbx;
+        double acc = 0.0;
+        for (int i = l; i < ps.nbx; i += 32 * 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int ii = i + 32 * u;
+                v[u] = live && ii < ps.nbx ? pp[ii] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += v[u];
+        }
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 32);
+        // every lane's loads of this plane are consumed above, so slot 0
+        // can be overwritten with the total
+        if (live && l == 0) pp[0] = acc;
+        return;
+    }
+    const long long r0 = (long long)(blockIdx.x - nsb) * LPB;
     const int nr = (int)min((long long)LPB, rows - r0);
     float* g = R + r0 * L;
     float4 buf[NV];
@@ -112,12 +145,15 @@ __global__ void __launch_bounds__(256) k_cols_fft(float* R, long long inner, con
 bool fast_len(int L) { return L >= 32 && L <= 512 && (L & (L - 1)) == 0; }
 
 template <int M1, int M2>
-static void rows_dispatch(float* R, long long rows, const float2* tw, int kind, hipStream_t st) {
+static void rows_dispatch(float* R, long long rows, const float2* tw, int kind, hipStream_t st,
+                          const PlaneSums* sums) {
     constexpr int LPB = 256 / M2;
-    const dim3 grid((unsigned)((rows + LPB - 1) / LPB));
-    if (kind == 0) hipLaunchKernelGGL((k_rows_fft<M1, M2, 0>), grid, dim3(256), 0, st, R, rows, tw);
-    else if (kind == 1) hipLaunchKernelGGL((k_rows_fft<M1, M2, 1>), grid, dim3(256), 0, st, R, rows, tw);
-    else hipLaunchKernelGGL((k_rows_fft<M1, M2, 2>), grid, dim3(256), 0, st, R, rows, tw);
+    const PlaneSums ps = sums ? *sums : PlaneSums{nullptr, 0, 0};
+    const int nsb = (int)((ps.nq + kSumPlanesPerBlock - 1) / kSumPlanesPerBlock);
+    const dim3 grid((unsigned)((rows + LPB - 1) / LPB + nsb));
+    if (kind == 0) hipLaunchKernelGGL((k_rows_fft<M1, M2, 0>), grid, dim3(256), 0, st, R, rows, tw, ps, nsb);
+    else if (kind == 1) hipLaunchKernelGGL((k_rows_fft<M1, M2, 1>), grid, dim3(256), 0, st, R, rows, tw, ps, nsb);
+    else hipLaunchKernelGGL((k_rows_fft<M1, M2, 2>), grid, dim3(256), 0, st, R, rows, tw, ps, nsb);
 }
 
 template <int M1, int M2, bool VEC>
@@ -138,13 +174,14 @@ static void cols_dispatch(float* R, long long outer, long long inner, const floa
 }
 
 // kind: 0 forward DCT-II, 1 inverse (DCT-III), 2 Hartley (either direction)
-void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st) {
+void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st,
+                      const PlaneSums* sums) {
     switch (L) {
-        case 32: rows_dispatch<4, 4>(R, rows, tw, kind, st); break;
-        case 64: rows_dispatch<8, 4>(R, rows, tw, kind, st); break;
-        case 128: rows_dispatch<8, 8>(R, rows, tw, kind, st); break;
-        case 256: rows_dispatch<16, 8>(R, rows, tw, kind, st); break;
-        default: rows_dispatch<16, 16>(R, rows, tw, kind, st); break;
+        case 32: rows_dispatch<4, 4>(R, rows, tw, kind, st, sums); break;
+        case 64: rows_dispatch<8, 4>(R, rows, tw, kind, st, sums); break;
+        case 128: rows_dispatch<8, 8>(R, rows, tw, kind, st, sums); break;
+        case 256: rows_dispatch<16, 8>(R, rows, tw, kind, st, sums); break;
+        default: rows_dispatch<16, 16>(R, rows, tw, kind, st, sums); break;
     }
 }
 

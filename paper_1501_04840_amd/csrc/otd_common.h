@@ -98,16 +98,28 @@ void launch_boundary_stats(const Geom& g, const float* f0, const float* f1,
                            double* part, int nblk, hipStream_t st);
 
 // ---- transforms (transform.hip) ----------------------------------------
-// Forward or inverse orthonormal transform along x (contiguous rows).
-void launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStream_t st);
+// FP64 plane sums reduced in place: part[q nbx] = sum_i part[q nbx + i] for
+// every plane q < nq (the layout of StepArgs::part_slice).
+struct PlaneSums {
+    double* part;
+    long long nq;
+    int nbx;
+};
+// Forward or inverse orthonormal transform along x (contiguous rows).  With
+// `sums`, the fast path also reduces those plane sums (extra blocks of the
+// same launch) and returns true; otherwise it returns false and leaves them.
+bool launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStream_t st,
+                 const PlaneSums* sums = nullptr);
 // Forward or inverse transform along a strided axis: data [outer][L][inner].
 void launch_cols(float* R, long long outer, long long inner, const AxisTab& t,
                  int inverse, hipStream_t st);
 // Colour and time transforms, division by the eigenvalues of A A^T, inverse
-// transforms; the spatial-DC line is solved in FP64 from the slice sums.
+// transforms; the spatial-DC line is solved in FP64 from the slice sums
+// (already reduced to part_slice[q nbx] when `presummed`).
 void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
                const AxisTab& tc, const AxisTab& tt, const double* tc64,
-               const double* tt64, const double* part_slice, int nbx, hipStream_t st);
+               const double* tt64, const double* part_slice, int nbx, int presummed,
+               hipStream_t st);
 
 // Fused Poisson passes (transform.hip) for Neumann x and y of length 32..256,
 // P in {8, 16, 32}, C in {1, 3}: x (+ colour) pass with a transposed write to
@@ -123,7 +135,8 @@ void launch_fused_yt(const Geom& g, float* Rt, float* dc, const AxisTab& tx, con
 
 // Fast power-of-two passes (fastdct.hip); kind 0 DCT-II, 1 DCT-III, 2 Hartley.
 bool fast_len(int L);
-void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st);
+void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st,
+                      const PlaneSums* sums = nullptr);
 void launch_cols_fast(float* R, long long outer, long long inner, int L, const float2* tw, int kind,
                       hipStream_t st);
 

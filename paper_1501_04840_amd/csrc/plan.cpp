@@ -301,13 +301,19 @@ void poisson(ot_dyn_plan* p, float* R) {
         timed(p, OT_PHASE_XFORM_X, [&] { x_pass(1); });
         return;
     }
+    // the forward x pass also reduces the FP64 plane sums of r that the
+    // colour/time pass needs for the spatial-DC line (fast lengths only)
+    bool presummed = false;
     if (g.X > 1)
-        timed(p, OT_PHASE_XFORM_X, [&] { launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 0, st); });
+        timed(p, OT_PHASE_XFORM_X, [&] {
+            const PlaneSums ps{p->part_slice, B * g.P * g.C, p->nbx};
+            presummed = launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 0, st, &ps);
+        });
     if (g.Y > 1)
         timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(R, B * g.P * g.C, g.X, p->tab[1], 0, st); });
     timed(p, OT_PHASE_TC, [&] {
         launch_tc(g, R, p->tab[0], p->tab[1], p->tab[2], p->tab[3], p->tc64, p->tt64,
-                  p->part_slice, p->nbx, st);
+                  p->part_slice, p->nbx, presummed ? 1 : 0, st);
     });
     if (g.Y > 1)
         timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(R, B * g.P * g.C, g.X, p->tab[1], 1, st); });

@@ -188,6 +188,7 @@ struct TcArgs {
     const double* lamt64;
     const double* part_slice;  // [B][P][C][nbx] FP64 block partials of the plane sums
     int nbx;
+    int presummed;           // 1: part_slice[q nbx] already holds the sum of plane q
     int W;
     const float2* twt;       // time-axis twiddles e^{-i pi j / (2P)}, j < 4P
 };
@@ -282,7 +283,9 @@ __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1, float* ct_out) 
     // dependent exchanges made this block the tail of the whole pass.
     const int S = dc_slots(m);
     const double* part = a.part_slice + (long long)b * m * a.nbx;
-    if (S > 1) {
+    if (a.presummed) {
+        for (int q = threadIdx.x; q < m; q += nt) d1[q] = part[(long long)q * a.nbx];
+    } else if (S > 1) {
         double* slot = d2 + m;
         for (int e = threadIdx.x; e < m * S; e += nt) {
             const int q = e / S, j = e - q * S;
@@ -741,10 +744,11 @@ void launch_fused_yt(const Geom& g, float* Rt, float* dc, const AxisTab& tx, con
     else y_dispatch<32>(a, st);
 }
 
-void launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStream_t st) {
+bool launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStream_t st,
+                 const PlaneSums* sums) {
     if (t.tw) {
-        launch_rows_fast(R, rows, t.n, t.tw, t.periodic ? 2 : (inverse ? 1 : 0), st);
-        return;
+        launch_rows_fast(R, rows, t.n, t.tw, t.periodic ? 2 : (inverse ? 1 : 0), st, sums);
+        return sums != nullptr;
     }
     const int L = t.n;
     if (L <= kMfmaRowsMaxL) {
@@ -752,13 +756,14 @@ void launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStr
         const size_t sh = (size_t)32 * (Lp + 1) * sizeof(float);
         hipLaunchKernelGGL(k_rows_mfma, dim3((unsigned)((rows + 31) / 32)), dim3(2 * Lp), sh, st, R,
                            rows, t, inverse, Lp);
-        return;
+        return false;
     }
     int rb = kTileFloats / L;
     if (rb < 1) rb = 1;
     const long long nb = (rows + rb - 1) / rb;
     const size_t sh = (size_t)rb * L * sizeof(float);
     hipLaunchKernelGGL(k_rows, dim3((unsigned)nb), dim3(kT), sh, st, R, rows, t, inverse, rb);
+    return false;
 }
 
 void launch_cols(float* R, long long outer, long long inner, const AxisTab& t, int inverse,
@@ -785,8 +790,8 @@ void launch_cols(float* R, long long outer, long long inner, const AxisTab& t, i
 
 void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty, const AxisTab& tc,
                const AxisTab& tt, const double* tc64, const double* tt64,
-               const double* part_slice, int nbx, hipStream_t st) {
-    TcArgs a;
+               const double* part_slice, int nbx, int presummed, hipStream_t st) {
+    TcArgs a{};
     a.g = g; a.R = R; a.tx = tx; a.ty = ty; a.tc = tc; a.tt = tt;
     a.tc64 = tc64;
     a.tt64 = tt64;
@@ -794,6 +799,7 @@ void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty, co
     a.lamt64 = tt64 + (long long)g.P * g.P;
     a.part_slice = part_slice;
     a.nbx = nbx;
+    a.presummed = presummed;
     a.twt = tt.tw;
     if (tc_reg_dispatch(a, st)) return;
     int W = 64;
