@@ -375,6 +375,8 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
         }
         g.active = true;
         std::fill(g.conv_iter.begin(), g.conv_iter.end(), -1);
+        const int st = plan_freeze(g.plan, std::vector<char>(g.members.size(), 0));
+        if (st != OT_OK) return st;
     }
     bt->warm = false;
     for (auto& g : bt->P.groups) BCHK(bt, hipStreamSynchronize(g.side));
@@ -410,6 +412,14 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
             }
             if (all) { g.active = false; changed = true; }
             any_active = any_active || g.active;
+            // certified members keep their certified state: the stencil and
+            // colour/time kernels of the remaining chunks skip them
+            if (g.active) {
+                std::vector<char> frozen(g.members.size());
+                for (size_t j = 0; j < g.members.size(); ++j) frozen[j] = g.conv_iter[j] >= 0;
+                const int fst = plan_freeze(g.plan, frozen);
+                if (fst != OT_OK) { bt->err = ot_dyn_last_error(g.plan); return fst; }
+            }
         }
         if (changed) drop_graph(bt);
         if (verbose) {

@@ -21,7 +21,7 @@ constexpr int kSumPlanesPerBlock = 8;
 // reduction costs no launch and leaves that pass a short serial part).
 template <int M1, int M2, int KIND>
 __global__ void __launch_bounds__(256) k_rows_fft(float* R, long long rows, const float2* tw4,
-                                                  PlaneSums ps, int nsb) {
+                                                  PlaneSums ps, int nsb, RowSkip skip) {
     constexpr int L = 2 * M1 * M2, T = M2, LPB = 256 / T, PITCH = L + 1;
     constexpr int NV = LPB * L / 1024;            // float4 per thread
     __shared__ float lds[LPB * PITCH];
@@ -51,6 +51,7 @@ __global__ void __launch_bounds__(256) k_rows_fft(float* R, long long rows, cons
     }
     const long long r0 = (long long)(blockIdx.x - nsb) * LPB;
     const int nr = (int)min((long long)LPB, rows - r0);
+    if (rows_frozen(skip, r0, nr)) return;
     float* g = R + r0 * L;
     float4 buf[NV];
 #pragma unroll
@@ -146,14 +147,14 @@ bool fast_len(int L) { return L >= 32 && L <= 512 && (L & (L - 1)) == 0; }
 
 template <int M1, int M2>
 static void rows_dispatch(float* R, long long rows, const float2* tw, int kind, hipStream_t st,
-                          const PlaneSums* sums) {
+                          const PlaneSums* sums, RowSkip sk) {
     constexpr int LPB = 256 / M2;
     const PlaneSums ps = sums ? *sums : PlaneSums{nullptr, 0, 0};
     const int nsb = (int)((ps.nq + kSumPlanesPerBlock - 1) / kSumPlanesPerBlock);
     const dim3 grid((unsigned)((rows + LPB - 1) / LPB + nsb));
-    if (kind == 0) hipLaunchKernelGGL((k_rows_fft<M1, M2, 0>), grid, dim3(256), 0, st, R, rows, tw, ps, nsb);
-    else if (kind == 1) hipLaunchKernelGGL((k_rows_fft<M1, M2, 1>), grid, dim3(256), 0, st, R, rows, tw, ps, nsb);
-    else hipLaunchKernelGGL((k_rows_fft<M1, M2, 2>), grid, dim3(256), 0, st, R, rows, tw, ps, nsb);
+    if (kind == 0) hipLaunchKernelGGL((k_rows_fft<M1, M2, 0>), grid, dim3(256), 0, st, R, rows, tw, ps, nsb, sk);
+    else if (kind == 1) hipLaunchKernelGGL((k_rows_fft<M1, M2, 1>), grid, dim3(256), 0, st, R, rows, tw, ps, nsb, sk);
+    else hipLaunchKernelGGL((k_rows_fft<M1, M2, 2>), grid, dim3(256), 0, st, R, rows, tw, ps, nsb, sk);
 }
 
 template <int M1, int M2, bool VEC>
@@ -175,13 +176,13 @@ static void cols_dispatch(float* R, long long outer, long long inner, const floa
 
 // kind: 0 forward DCT-II, 1 inverse (DCT-III), 2 Hartley (either direction)
 void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st,
-                      const PlaneSums* sums) {
+                      const PlaneSums* sums, RowSkip sk) {
     switch (L) {
-        case 32: rows_dispatch<4, 4>(R, rows, tw, kind, st, sums); break;
-        case 64: rows_dispatch<8, 4>(R, rows, tw, kind, st, sums); break;
-        case 128: rows_dispatch<8, 8>(R, rows, tw, kind, st, sums); break;
-        case 256: rows_dispatch<16, 8>(R, rows, tw, kind, st, sums); break;
-        default: rows_dispatch<16, 16>(R, rows, tw, kind, st, sums); break;
+        case 32: rows_dispatch<4, 4>(R, rows, tw, kind, st, sums, sk); break;
+        case 64: rows_dispatch<8, 4>(R, rows, tw, kind, st, sums, sk); break;
+        case 128: rows_dispatch<8, 8>(R, rows, tw, kind, st, sums, sk); break;
+        case 256: rows_dispatch<16, 8>(R, rows, tw, kind, st, sums, sk); break;
+        default: rows_dispatch<16, 16>(R, rows, tw, kind, st, sums, sk); break;
     }
 }
 

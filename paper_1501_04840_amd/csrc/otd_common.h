@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace otd {
 
 struct Geom {
@@ -47,6 +49,8 @@ struct StepArgs {
     Geom g;
     float tau_sigma;     // tau * sigma (the same for every problem)
     const float* sig;    // sigma per problem [B] (device; residual balancing)
+    const float* frz;    // per problem [B]: nonzero = frozen (a certified member of a
+                         // batch): the stencil and colour/time kernels skip it
     float theta;
     // state
     float* F; float* Mx; float* My; float* Mc;
@@ -105,11 +109,26 @@ struct PlaneSums {
     long long nq;
     int nbx;
 };
+// Rows of a row pass that belong to frozen problems: frz[b] nonzero for
+// problem b, rpp rows per problem (null frz: none).
+struct RowSkip {
+    const float* frz;
+    long long rpp;
+};
+// True when rows [r0, r0 + n) all belong to frozen problems (block-uniform
+// when r0 and n are).
+__device__ inline bool rows_frozen(const RowSkip& k, long long r0, int n) {
+    if (!k.frz) return false;
+    for (long long b = r0 / k.rpp; b <= (r0 + n - 1) / k.rpp; ++b)
+        if (k.frz[b] == 0.f) return false;
+    return true;
+}
 // Forward or inverse orthonormal transform along x (contiguous rows).  With
 // `sums`, the fast path also reduces those plane sums (extra blocks of the
 // same launch) and returns true; otherwise it returns false and leaves them.
+// Blocks whose rows all belong to problems frozen in `skip` do nothing.
 bool launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStream_t st,
-                 const PlaneSums* sums = nullptr);
+                 const PlaneSums* sums = nullptr, RowSkip skip = RowSkip{nullptr, 1});
 // Forward or inverse transform along a strided axis: data [outer][L][inner].
 void launch_cols(float* R, long long outer, long long inner, const AxisTab& t,
                  int inverse, hipStream_t st);
@@ -119,7 +138,7 @@ void launch_cols(float* R, long long outer, long long inner, const AxisTab& t,
 void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
                const AxisTab& tc, const AxisTab& tt, const double* tc64,
                const double* tt64, const double* part_slice, int nbx, int presummed,
-               hipStream_t st);
+               const float* frz, hipStream_t st);
 
 // Fused Poisson passes (transform.hip) for Neumann x and y of length 32..256,
 // P in {8, 16, 32}, C in {1, 3}: x (+ colour) pass with a transposed write to
@@ -136,7 +155,7 @@ void launch_fused_yt(const Geom& g, float* Rt, float* dc, const AxisTab& tx, con
 // Fast power-of-two passes (fastdct.hip); kind 0 DCT-II, 1 DCT-III, 2 Hartley.
 bool fast_len(int L);
 void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st,
-                      const PlaneSums* sums = nullptr);
+                      const PlaneSums* sums = nullptr, RowSkip skip = RowSkip{nullptr, 1});
 void launch_cols_fast(float* R, long long outer, long long inner, int L, const float2* tw, int kind,
                       hipStream_t st);
 
@@ -151,6 +170,9 @@ void plan_apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy);
 bool plan_has_fast_xy(const ot_dyn_plan* p);
 void plan_problem(const ot_dyn_plan* p, int b, ot_dyn_report* rep);
 void plan_add_iters(ot_dyn_plan* p, int n);
+// Freezes problem b (frozen[b] nonzero) or releases it; uploads on the
+// plan's stream only when a flag changes.
+int plan_freeze(ot_dyn_plan* p, const std::vector<char>& frozen);
 // True while the launch sequence of the next iteration may differ from the
 // one after it (adaptive refinement; the refined start of OT_REFINE_CARRY):
 // a captured graph of iterations must then be captured again.

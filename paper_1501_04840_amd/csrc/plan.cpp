@@ -35,6 +35,7 @@ struct ot_dyn_plan {
     bool fused;              // the fused three-pass Poisson solve applies
     float* sig;              // sigma per problem [B] (device)
     float* fac;              // dual rescale factors per problem [B] (device)
+    float* frz;              // frozen flags per problem [B] (device; batches)
     float* f0;
     float* f1;
     AxisTab tab[4];          // x, y, c, t
@@ -63,6 +64,7 @@ struct ot_dyn_plan {
     std::vector<double> vfloor;     // per problem: 1e-3 * mean of f0 (warm-start dual)
     std::vector<double> r_prim, r_dual, r_div, cost, e_mass;
     std::vector<float> sig_h, fac_h;     // sigma per problem and rescale factors
+    std::vector<float> frz_h;            // frozen flags (host copy of frz)
     std::vector<int> n_adapt, last_adapt;   // per problem: changes, iteration of the last
     double last_res;         // max(r_prim, r_dual) of the last check
     std::string err;
@@ -165,7 +167,7 @@ Layout layout_of(const ot_dyn_desc& d) {
     L.off_R = take(ncT * sizeof(float));
     L.off_R2 = take(ncT * sizeof(float));
     L.off_Phi = take(d.refine == OT_REFINE_CARRY ? ncT * sizeof(float) : 0);
-    L.off_sig = take(2 * (size_t)g.B * sizeof(float));
+    L.off_sig = take(3 * (size_t)g.B * sizeof(float));   // sigma, rescale, frozen
     L.off_Rt = take(ncT * sizeof(float));
     L.off_dcl = take((size_t)g.B * g.C * g.P * sizeof(float));
     L.off_f = take(2 * (size_t)g.B * g.slice * sizeof(float));
@@ -248,6 +250,7 @@ StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     s.g = p->g;
     s.tau_sigma = (float)(p->d.tau * p->d.sigma);
     s.sig = p->sig;
+    s.frz = p->frz;
     s.theta = (float)p->d.theta;
     s.F = F; s.Mx = Mx; s.My = My; s.Mc = Mc;
     for (int q = 0; q < 4; ++q) { s.b[q] = p->b[q]; s.bb[q] = p->bb[q]; s.A[q] = p->A[q]; }
@@ -304,21 +307,25 @@ void poisson(ot_dyn_plan* p, float* R) {
     // the forward x pass also reduces the FP64 plane sums of r that the
     // colour/time pass needs for the spatial-DC line (fast lengths only)
     bool presummed = false;
+    // rows of frozen problems are skipped (rows per problem: P C Y)
+    const RowSkip skip{p->frz, (long long)g.P * g.C * g.Y};
     if (g.X > 1)
         timed(p, OT_PHASE_XFORM_X, [&] {
             const PlaneSums ps{p->part_slice, B * g.P * g.C, p->nbx};
-            presummed = launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 0, st, &ps);
+            presummed = launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 0, st, &ps, skip);
         });
     if (g.Y > 1)
         timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(R, B * g.P * g.C, g.X, p->tab[1], 0, st); });
     timed(p, OT_PHASE_TC, [&] {
         launch_tc(g, R, p->tab[0], p->tab[1], p->tab[2], p->tab[3], p->tc64, p->tt64,
-                  p->part_slice, p->nbx, presummed ? 1 : 0, st);
+                  p->part_slice, p->nbx, presummed ? 1 : 0, p->frz, st);
     });
     if (g.Y > 1)
         timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(R, B * g.P * g.C, g.X, p->tab[1], 1, st); });
     if (g.X > 1)
-        timed(p, OT_PHASE_XFORM_X, [&] { launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 1, st); });
+        timed(p, OT_PHASE_XFORM_X, [&] {
+            launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 1, st, nullptr, skip);
+        });
 }
 
 // Launch shapes: the row-stencil block width (64, 128 or 256; 0 = default)
@@ -559,6 +566,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->dcl = (float*)(p->ws + L.off_dcl);
     p->fused = false;
     p->fac = p->sig + p->g.B;
+    p->frz = p->sig + 2 * (size_t)p->g.B;
     p->f0 = (float*)(p->ws + L.off_f);
     p->f1 = p->f0 + (long long)p->g.B * p->g.slice;
     p->tc64 = (double*)(p->ws + L.off_tc64);
@@ -579,6 +587,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->r_prim.assign(B, 0); p->r_dual.assign(B, 0); p->r_div.assign(B, 0);
     p->cost.assign(B, 0); p->e_mass.assign(B, 0);
     p->sig_h.assign(B, (float)d->sigma); p->fac_h.assign(B, 1.f);
+    p->frz_h.assign(B, 0.f);
     p->n_adapt.assign(B, 0); p->last_adapt.assign(B, 0);
     p->last_res = 1.0;
     p->total_iters = 0;
@@ -643,6 +652,12 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
             if (e != hipSuccess) { delete p; return OT_ERR_HIP; }
         }
     }
+    {   // no problem starts frozen (ot_dyn_init also releases them)
+        hipError_t e = hipMemcpyAsync(p->frz, p->frz_h.data(), p->frz_h.size() * sizeof(float),
+                                      hipMemcpyHostToDevice, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) { delete p; return OT_ERR_HIP; }
+    }
     apply_tuning(p, 0, 0);
     *out = p;
     return OT_OK;
@@ -697,6 +712,9 @@ int ot_dyn_init(ot_dyn_plan* p, int mode, float* F, float* Mx, float* My, float*
     std::fill(p->n_adapt.begin(), p->n_adapt.end(), 0);
     std::fill(p->last_adapt.begin(), p->last_adapt.end(), 0);
     HIPCHK(p, hipMemcpyAsync(p->sig, p->sig_h.data(), p->sig_h.size() * sizeof(float),
+                             hipMemcpyHostToDevice, p->stream));
+    std::fill(p->frz_h.begin(), p->frz_h.end(), 0.f);
+    HIPCHK(p, hipMemcpyAsync(p->frz, p->frz_h.data(), p->frz_h.size() * sizeof(float),
                              hipMemcpyHostToDevice, p->stream));
     launch_init_state(s, p->f0, p->f1, mode == OT_INIT_COLD ? 1 : 0, p->stream);
     if (mode == OT_INIT_PRIMAL_DUAL) {
@@ -870,6 +888,19 @@ int plan_collect(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
 }
 
 void plan_apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy) { apply_tuning(p, row_bx, dense_xy); }
+
+int plan_freeze(ot_dyn_plan* p, const std::vector<char>& frozen) {
+    bool changed = false;
+    for (int b = 0; b < p->g.B; ++b) {
+        const float v = frozen[b] ? 1.f : 0.f;
+        changed = changed || v != p->frz_h[b];
+        p->frz_h[b] = v;
+    }
+    if (changed)
+        HIPCHK(p, hipMemcpyAsync(p->frz, p->frz_h.data(), p->frz_h.size() * sizeof(float),
+                                 hipMemcpyHostToDevice, p->stream));
+    return OT_OK;
+}
 
 bool plan_has_fast_xy(const ot_dyn_plan* p) { return p->tw_fast[0] || p->tw_fast[1]; }
 

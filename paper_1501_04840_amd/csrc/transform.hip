@@ -28,11 +28,12 @@ __device__ inline const float* fwd_tab(const AxisTab& t) { return t.mat; }
 __device__ inline const float* inv_tab(const AxisTab& t) { return t.mat + (long long)t.n * t.n; }
 
 __global__ void __launch_bounds__(kT) k_rows(float* R, long long rows, AxisTab t, int inverse,
-                                            int rb) {
+                                            int rb, RowSkip skip) {
     extern __shared__ float tile[];
     const int L = t.n;
     const long long r0 = (long long)blockIdx.x * rb;
     const int nr = (int)min((long long)rb, rows - r0);
+    if (rows_frozen(skip, r0, nr)) return;
     const int cnt = nr * L;
     float* g = R + r0 * L;
     for (int e = threadIdx.x; e < cnt; e += kT) tile[e] = g[e];
@@ -61,11 +62,12 @@ constexpr int kMfmaRowsMaxL = 480;     // 32 rows of Lp + 1 floats stay under 64
 __device__ __forceinline__ int mfma_row(int r, int half) { return (r >> 2) * 8 + half * 4 + (r & 3); }
 
 __global__ void __launch_bounds__(1024) k_rows_mfma(float* R, long long rows, AxisTab t, int inverse,
-                                                  int Lp) {
+                                                  int Lp, RowSkip skip) {
     extern __shared__ float xs[];
     const int L = t.n, pitch = Lp + 1, nt = blockDim.x;
     const long long r0 = (long long)blockIdx.x * 32;
     const int nr = (int)min((long long)32, rows - r0);
+    if (rows_frozen(skip, r0, nr)) return;
     float* g = R + r0 * L;
     for (int e = threadIdx.x; e < 32 * Lp; e += nt) {
         const int r = e / Lp, k = e - r * Lp;
@@ -189,6 +191,7 @@ struct TcArgs {
     const double* part_slice;  // [B][P][C][nbx] FP64 block partials of the plane sums
     int nbx;
     int presummed;           // 1: part_slice[q nbx] already holds the sum of plane q
+    const float* frz;        // per problem: nonzero = frozen, skipped (or null)
     int W;
     const float2* twt;       // time-axis twiddles e^{-i pi j / (2P)}, j < 4P
 };
@@ -203,6 +206,7 @@ __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
     float* b1 = lds;
     float* b2 = lds + n;
     const int b = blockIdx.y;
+    if (a.frz && a.frz[b] != 0.f) return;   // frozen problem (block-uniform)
     const long long i0 = (long long)blockIdx.x * W;
     const int nw = (int)min((long long)W, g.plane - i0);
     float* base = a.R + (long long)b * g.nc + i0;
@@ -423,6 +427,7 @@ __global__ void __launch_bounds__(64 * C) k_tc_reg(TcArgs a) {
     float* buf = reinterpret_cast<float*>(dsh);        // [C][P][64]
     const Geom& g = a.g;
     const int b = blockIdx.y;
+    if (a.frz && a.frz[b] != 0.f) return;   // frozen problem (block-uniform)
     if (blockIdx.x == 0) {
         dc_line_fp64(a, b, dsh);
         return;
@@ -745,9 +750,9 @@ void launch_fused_yt(const Geom& g, float* Rt, float* dc, const AxisTab& tx, con
 }
 
 bool launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStream_t st,
-                 const PlaneSums* sums) {
+                 const PlaneSums* sums, RowSkip skip) {
     if (t.tw) {
-        launch_rows_fast(R, rows, t.n, t.tw, t.periodic ? 2 : (inverse ? 1 : 0), st, sums);
+        launch_rows_fast(R, rows, t.n, t.tw, t.periodic ? 2 : (inverse ? 1 : 0), st, sums, skip);
         return sums != nullptr;
     }
     const int L = t.n;
@@ -755,14 +760,14 @@ bool launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStr
         const int Lp = (L + 31) / 32 * 32;
         const size_t sh = (size_t)32 * (Lp + 1) * sizeof(float);
         hipLaunchKernelGGL(k_rows_mfma, dim3((unsigned)((rows + 31) / 32)), dim3(2 * Lp), sh, st, R,
-                           rows, t, inverse, Lp);
+                           rows, t, inverse, Lp, skip);
         return false;
     }
     int rb = kTileFloats / L;
     if (rb < 1) rb = 1;
     const long long nb = (rows + rb - 1) / rb;
     const size_t sh = (size_t)rb * L * sizeof(float);
-    hipLaunchKernelGGL(k_rows, dim3((unsigned)nb), dim3(kT), sh, st, R, rows, t, inverse, rb);
+    hipLaunchKernelGGL(k_rows, dim3((unsigned)nb), dim3(kT), sh, st, R, rows, t, inverse, rb, skip);
     return false;
 }
 
@@ -790,7 +795,8 @@ void launch_cols(float* R, long long outer, long long inner, const AxisTab& t, i
 
 void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty, const AxisTab& tc,
                const AxisTab& tt, const double* tc64, const double* tt64,
-               const double* part_slice, int nbx, int presummed, hipStream_t st) {
+               const double* part_slice, int nbx, int presummed, const float* frz,
+               hipStream_t st) {
     TcArgs a{};
     a.g = g; a.R = R; a.tx = tx; a.ty = ty; a.tc = tc; a.tt = tt;
     a.tc64 = tc64;
@@ -800,6 +806,7 @@ void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty, co
     a.part_slice = part_slice;
     a.nbx = nbx;
     a.presummed = presummed;
+    a.frz = frz;
     a.twt = tt.tw;
     if (tc_reg_dispatch(a, st)) return;
     int W = 64;

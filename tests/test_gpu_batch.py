@@ -173,3 +173,34 @@ def test_balanced_steps_certify_slow_hue_problems(otdyn):
         if ref[i].converged:
             assert abs(bal[i].cost - ref[i].cost) <= 1e-5 * ref[i].cost, (idx[i], bal[i].cost, ref[i].cost)
     assert bal[0].iterations < 20000
+
+
+def test_certified_members_are_frozen(otdyn):
+    """Problems of one shape group certify at different checks; each keeps the
+    state of its certifying check while the others go on: its final state
+    equals, bit for bit, that of a single-problem plan stepped exactly its
+    reported iteration count."""
+    _say("frozen certified members")
+    import torch
+    probs = hue_problems(4, seed=21, bins=(64,), steps=(16,))
+    dims = [(n, 1, 1, T) for n, T, _, _ in probs]
+    d = periodic_desc(otdyn)
+    bt = otdyn.Batch(d, dims)
+    bt.set_boundary([p[2].reshape(1, 1, -1) for p in probs], [p[3].reshape(1, 1, -1) for p in probs])
+    status, rep = bt.solve(40000, chunk=100)
+    assert status == otdyn.OT_OK
+    its = [bt.problem(i).iterations for i in range(len(probs))]
+    assert len(set(its)) > 1, its              # they certify at different checks
+    for i, (n, T, h0, h1) in enumerate(probs):
+        s = periodic_desc(otdyn)
+        s.X, s.Y, s.C, s.P = n, 1, 1, T
+        prob = otdyn.Problem(s, "cuda")
+        prob.set_boundary(torch.from_numpy(h0.reshape(1, 1, -1)), torch.from_numpy(h1.reshape(1, 1, -1)))
+        prob.init()
+        prob.step(its[i])
+        torch.cuda.synchronize()
+        single = [t[0].cpu().numpy() for t in prob.state()]
+        for u, v in zip(bt.state(i), single):
+            np.testing.assert_array_equal(u, v)
+        prob.close()
+    bt.close()
