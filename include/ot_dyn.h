@@ -247,7 +247,10 @@ int ot_dyn_batch_set_state(ot_dyn_batch* bt, const float* F, const float* M, int
 /* Cold-start every problem (or start from the state of
  * ot_dyn_batch_set_state) and iterate (graph chunks of `chunk` iterations,
  * residuals checked after each chunk) until every problem is certified or
- * max_iters.  rep (may be NULL) receives the batch totals: iterations, the
+ * max_iters.  A certified problem is frozen at the check that certified it:
+ * its state (ot_dyn_batch_get_state) and report are those of that check
+ * while the rest of its shape group iterates on.  rep (may be NULL)
+ * receives the batch totals: iterations, the
  * number certified in `converged`, the worst residuals and the wall time.
  * Returns OT_OK when all are certified, OT_NOT_CONVERGED otherwise.  With
  * the environment variable OT_DYN_VERBOSE set, one progress line per chunk
