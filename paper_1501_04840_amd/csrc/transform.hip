@@ -364,7 +364,10 @@ __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1, float* ct_out) 
 }
 
 // Orthonormal DCT-II of a register line of length P (Makhoul's reordering
-// and a P/2-point packed DFT; every index is a compile-time constant).
+// and a P/2-point packed DFT; every index is a compile-time constant).  The
+// frequencies k and M - k are unpacked together: with 2 ve = Z[k] +
+// conj Z[M-k] and 2 vo = -i (Z[k] - conj Z[M-k]), V[k] = ve + w vo and
+// V[M-k] = conj(ve - w vo) for w = e^{-2 pi i k / P}.
 template <int P>
 __device__ __forceinline__ void dct2_reg(float (&x)[P], const float2* tw4) {
     constexpr int M = P / 2;
@@ -376,42 +379,52 @@ __device__ __forceinline__ void dct2_reg(float (&x)[P], const float2* tw4) {
                            x[m1 < M ? 2 * m1 : 2 * P - 1 - 2 * m1]);
     }
     dft<M>(z);
-    const float sc = sqrtf(2.f / P), sc0 = sqrtf(1.f / P);
+    // a = 2 V[k], b = 2 V[M-k]: the factor 1/2 is folded into the scales
+    const float h = 0.5f * sqrtf(2.f / P), h0 = 0.5f * sqrtf(1.f / P);
 #pragma unroll
-    for (int k = 0; k <= M; ++k) {
-        const float2 zk = z[k % M], zm = z[(M - k) % M];
-        const float2 ve = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-        const float2 vo = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-        const float2 V = k < M ? cadd(ve, cmul(tw4[4 * k], vo)) : csub(ve, vo);
-        const float2 w = cmul(tw4[k], V);
-        x[k] = w.x * (k == 0 ? sc0 : sc);
-        if (k > 0 && k < M) x[P - k] = -w.y * sc;
+    for (int k = 0; k <= M / 2; ++k) {
+        const float2 zk = z[k], zm = z[(M - k) % M];
+        const float2 ve = make_float2(zk.x + zm.x, zk.y - zm.y);
+        const float2 vo = make_float2(zk.y + zm.y, zm.x - zk.x);
+        const float2 p = cmul(tw4[4 * k], vo);
+        const float2 xa = cmul(tw4[k], cadd(ve, p));
+        const float2 xb = cmul(tw4[M - k], make_float2(ve.x - p.x, p.y - ve.y));
+        x[k] = (k == 0 ? h0 : h) * xa.x;
+        if (k > 0) x[P - k] = -h * xa.y;
+        if (k < M / 2) {
+            x[M - k] = h * xb.x;
+            if (k > 0) x[M + k] = -h * xb.y;
+        }
     }
 }
 
-// Orthonormal DCT-III (inverse of dct2_reg) of a register line.
+// Orthonormal DCT-III (inverse of dct2_reg) of a register line.  With
+// V(k) = conj(w4_k) (X[k], -X[P-k]) on inputs scaled by sqrt(P / 2)
+// (sqrt(P) for X[0]): conj Z[k] = conj(ve + i vo) and conj Z[M-k] =
+// ve - i vo, 2 ve = V(k) + conj V(M-k), 2 vo = (V(k) - conj V(M-k)) conj(w_k);
+// the factor sqrt(P / 2) / 2 is applied to the outputs.
 template <int P>
 __device__ __forceinline__ void dct3_reg(float (&x)[P], const float2* tw4) {
     constexpr int M = P / 2;
-    const float isc = 1.f / sqrtf(2.f / P), isc0 = 1.f / sqrtf(1.f / P);
-    auto X = [&](int k) -> float { return k >= P ? 0.f : x[k] * (k == 0 ? isc0 : isc); };
-    auto V = [&](int k) -> float2 { return cmul(cconj(tw4[k]), make_float2(X(k), -X(P - k))); };
     float2 zc[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-        const float2 v = V(k), vm = cconj(V(M - k));
-        const float2 ve = make_float2(0.5f * (v.x + vm.x), 0.5f * (v.y + vm.y));
-        const float2 vo = cmul(make_float2(0.5f * (v.x - vm.x), 0.5f * (v.y - vm.y)),
-                               cconj(tw4[4 * k]));
+    for (int k = 0; k <= M / 2; ++k) {
+        const float xk = k == 0 ? 1.41421356237309515f * x[0] : x[k];
+        const float xl = k == 0 ? 0.f : x[P - k];                 // X[P-k]
+        const float2 v = cmul(cconj(tw4[k]), make_float2(xk, -xl));
+        const float2 w = cmul(cconj(tw4[M - k]), make_float2(x[M - k], -x[M + k]));   // V(M-k)
+        const float2 ve = make_float2(v.x + w.x, v.y - w.y);
+        const float2 vo = cmul(make_float2(v.x - w.x, v.y + w.y), cconj(tw4[4 * k]));
         zc[k] = make_float2(ve.x - vo.y, -(ve.y + vo.x));
+        if (k > 0 && k < M / 2) zc[M - k] = make_float2(ve.x + vo.y, ve.y - vo.x);
     }
     dft<M>(zc);
-    const float im = 1.f / M;
+    const float sc = 0.5f * sqrtf(0.5f * P) / M;
 #pragma unroll
     for (int n = 0; n < M; ++n) {
         const int m0 = 2 * n, m1 = 2 * n + 1;
-        x[m0 < M ? 2 * m0 : 2 * (P - 1 - m0) + 1] = zc[n].x * im;
-        x[m1 < M ? 2 * m1 : 2 * (P - 1 - m1) + 1] = -zc[n].y * im;
+        x[m0 < M ? 2 * m0 : 2 * (P - 1 - m0) + 1] = zc[n].x * sc;
+        x[m1 < M ? 2 * m1 : 2 * (P - 1 - m1) + 1] = -zc[n].y * sc;
     }
 }
 
