@@ -63,6 +63,55 @@ def solve_v(a2: np.ndarray, af: np.ndarray, sigma: float,
     return v
 
 
+def solve_v_closed(a2: np.ndarray, af: np.ndarray, sigma: float) -> np.ndarray:
+    """Positive root of the cubic in closed form (Cardano), else 0.
+
+    With w = 1 + sigma v the cubic 2 (1 + sigma v)^2 (v - a_f) = sigma |a_m|^2
+    becomes w^3 - beta w^2 - gamma = 0, beta = 1 + sigma a_f,
+    gamma = sigma^2 |a_m|^2 / 2 >= 0.  It has exactly one positive root, and
+    that root exceeds 1 (v > 0) iff the value at w = 1,
+    -sigma (a_f + sigma |a_m|^2 / 2), is negative: the branch condition of
+    solve_v.  Two forms avoid cancellation:
+      beta > 0: w = beta / 3 + t with the depressed cubic t^3 + p t + q = 0,
+        p = -beta^2 / 3, q = -2 beta^3 / 27 - gamma; its discriminant
+        (q/2)^2 + (p/3)^3 = gamma^2 / 4 + gamma beta^3 / 27 >= 0, so
+        t = A + beta^2 / (9 A), A = cbrt(-q/2 + sqrt(disc)) > 0 (all terms
+        positive);
+      beta <= 0 (then gamma > 1 where the root is active): s = 1 / w solves
+        the depressed cubic s^3 + (beta / gamma) s - 1 / gamma = 0, whose
+        roots sum to 0 and multiply to 1 / gamma > 0, so exactly one is
+        positive.  With P = -beta / (3 gamma) >= 0 and H = 1 / (2 gamma):
+        disc = H^2 - P^3 >= 0 gives s = A + P / A, A = cbrt(H + sqrt(disc));
+        disc < 0 gives s = 2 sqrt(P) cos(acos(H / P^{3/2}) / 3), the argument
+        in (0, 1] where the largest root is well conditioned."""
+    a2 = np.asarray(a2, dtype=np.float64)
+    af = np.asarray(af, dtype=np.float64)
+    a2, af = np.broadcast_arrays(a2, af)
+    active = 2.0 * af + sigma * a2 > 0.0
+    beta = 1.0 + sigma * af
+    gamma = 0.5 * sigma * sigma * a2
+    w = np.ones(beta.shape)
+    pos = active & (beta > 0.0)
+    if np.any(pos):
+        b, g = beta[pos], gamma[pos]
+        A = np.cbrt(b ** 3 / 27.0 + 0.5 * g + np.sqrt(0.25 * g * g + g * b ** 3 / 27.0))
+        w[pos] = b / 3.0 + A + b * b / (9.0 * A)
+    neg = active & (beta <= 0.0)
+    if np.any(neg):
+        b, g = beta[neg], gamma[neg]
+        P = -b / (3.0 * g)
+        H = 0.5 / g
+        disc = H * H - P ** 3
+        sv = np.empty(b.shape)
+        one = disc >= 0.0
+        A = np.cbrt(H[one] + np.sqrt(disc[one]))
+        sv[one] = A + P[one] / A
+        thr = ~one
+        sv[thr] = 2.0 * np.sqrt(P[thr]) * np.cos(np.arccos(np.minimum(H[thr] / P[thr] ** 1.5, 1.0)) / 3.0)
+        w[neg] = 1.0 / sv
+    return np.where(active, np.maximum((w - 1.0) / sigma, 0.0), 0.0)
+
+
 def prox(am: np.ndarray, af: np.ndarray, sigma: float):
     """(u, v) = prox of J / sigma at (a_m, a_f); a_m has the axes on axis 0."""
     am = np.asarray(am, dtype=np.float64)

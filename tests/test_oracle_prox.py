@@ -100,3 +100,37 @@ def test_moreau_identity(rng):
     assert np.all(pb + 0.5 * np.sum(pa ** 2, axis=0) <= 1e-10)
     pos = v > 0
     np.testing.assert_allclose((pb + 0.5 * np.sum(pa ** 2, axis=0))[pos], 0.0, atol=1e-10)
+
+
+def test_closed_form_root_matches_newton():
+    """The closed-form (Cardano) root agrees with the Newton root, which the
+    brute-force minimisation above pins, across six decades of sigma, |a_m|
+    and a_f; the comparison is in w = 1 + sigma v, the variable the closed
+    form is exact in (v = (w - 1) / sigma loses digits when sigma v << 1)."""
+    rng = np.random.default_rng(5)
+    n = 3000
+    sig = 10.0 ** rng.uniform(-3, 3, n)
+    a2 = 10.0 ** rng.uniform(-4, 4, n) * rng.uniform(0, 1, n)
+    af = rng.standard_normal(n) * 10.0 ** rng.uniform(-3, 3, n)
+    for i in range(n):
+        vn = prox.solve_v(a2[i:i + 1], af[i:i + 1], sig[i])[0]
+        vc = prox.solve_v_closed(a2[i:i + 1], af[i:i + 1], sig[i])[0]
+        if vn == 0.0:
+            assert vc == 0.0
+        else:
+            wn, wc = 1 + sig[i] * vn, 1 + sig[i] * vc
+            assert abs(wc - wn) <= 1e-13 * wn, (a2[i], af[i], sig[i], vn, vc)
+
+
+def test_closed_form_solves_the_cubic():
+    """Residual of the cubic at the closed-form root, both forms (beta > 0
+    and beta <= 0) and both discriminant signs of the second."""
+    cases = [(4.0, 0.5, 1.0), (1e-6, 2.0, 3.0),          # beta > 0
+             (50.0, -3.0, 1.0),                          # beta < 0, one real root
+             (57.5, -1753.0, 64.0), (30.0, -11.0, 1.0)]  # beta < 0, three real roots
+    for a2, af, sig in cases:
+        beta, gamma = 1 + sig * af, 0.5 * sig * sig * a2
+        v = prox.solve_v_closed(np.array([a2]), np.array([af]), sig)[0]
+        assert v > 0
+        w = 1 + sig * v
+        assert abs(w ** 3 - beta * w ** 2 - gamma) <= 1e-12 * (w ** 3 + abs(beta) * w ** 2 + gamma)
