@@ -265,6 +265,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--prox", default="newton", choices=["newton", "closed"],
+                    help="root of the prox cubic: Newton steps or the closed form (Cardano)")
     ap.add_argument("--refine", type=int, default=None, choices=[0, 1, 3],
                     help="projection mode (default: the library default)")
     ap.add_argument("--size", type=int, nargs=4, default=[256, 256, 3, 32],
@@ -299,6 +301,7 @@ def main():
     d = otdyn.ot_dyn_default_desc(X, Y, C, P)
     if args.refine is not None:
         d.refine = args.refine
+    d.prox = {"newton": 0, "closed": 1}[args.prox]
     mode = d.refine
     prob = otdyn.Problem(d, "cuda:0")
     prob.set_boundary(torch.from_numpy(f0), torch.from_numpy(f1))
@@ -358,7 +361,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {
             "workload": f"rgb_{X}x{Y}x{C}x{P}", "X": X, "Y": Y, "C": C, "P": P,
-            "bc": "neumann x,y,t; periodic colour", "refine": mode,
+            "bc": "neumann x,y,t; periodic colour", "refine": mode, "prox": args.prox,
             "tau": d.tau, "sigma": d.sigma, "iteration_GBs_algorithmic": iter_bytes * K / dt / 1e9,
             "iteration_hbm_frac": iter_bytes * K / dt / 1e9 / HBM_PEAK_GBS,
             "phase_split_steps": n_split, "phases": split,

@@ -81,6 +81,16 @@ extern "C" {
 #define OT_REFINE_ADAPTIVE  2  /* OFF until max(r_prim, r_dual) < 1e-4, then ALWAYS */
 #define OT_REFINE_CARRY     3  /* one solve, started from the carried potential  */
 
+/* Root of the prox cubic 2 (1 + sigma v)^2 (v - a_f) = sigma |a_m|^2
+ * (ot_dyn_desc.prox).  NEWTON: monotone Newton steps from the right of the
+ * root to relative change 1e-6.  CLOSED: Cardano's formula in w = 1 + sigma v
+ * (for 1 + sigma a_f <= 0 in s = 1 / w, where the positive root is well
+ * conditioned), then one Newton step in v, which restores the digits that
+ * v = (w - 1) / sigma loses in FP32 when sigma v << 1. */
+#define OT_PROX_NEWTON      0
+#define OT_PROX_CLOSED      1
+#define OT_PROX_CLOSED_RAW  2  /* ot_dyn_prox_eval only: no Newton step */
+
 typedef struct ot_dyn_desc {
     int X, Y, C, P;        /* grid: X x Y pixels, C channels, P time steps; an
                               axis of size 1 is absent.  P >= 2.              */
@@ -99,6 +109,8 @@ typedef struct ot_dyn_desc {
                               balanced per problem at residual checks; tau
                               sigma stays fixed.  Helps 1D periodic (hue)
                               problems, slows the RGB ones: off by default */
+    int prox;              /* root of the prox cubic (Sec. 3, Step 2):
+                              OT_PROX_NEWTON or OT_PROX_CLOSED */
 } ot_dyn_desc;
 
 typedef struct ot_dyn_report {
@@ -120,7 +132,7 @@ typedef struct ot_dyn_plan ot_dyn_plan;
 /* Fill *d with the defaults for an X x Y x C x P grid: bc = {Neumann,
  * Neumann, periodic}, extent = 1, tau = 10, sigma = 0.099, theta = 1,
  * check_every = 50, tol_res = 1e-6, tol_div = 1e-6, tol_mass = 1e-5,
- * refine = OT_REFINE_CARRY, batch = 1, adapt = 0. */
+ * refine = OT_REFINE_CARRY, batch = 1, adapt = 0, prox = OT_PROX_NEWTON. */
 int ot_dyn_default_desc(ot_dyn_desc* d, int X, int Y, int C, int P);
 
 /* Bytes of device workspace a plan for *d needs (OT_ERR_SHAPE/PARAM if *d
@@ -283,6 +295,18 @@ int ot_dyn_batch_destroy(ot_dyn_batch* bt);
 const char* ot_dyn_batch_last_error(const ot_dyn_batch* bt);
 
 /* Static description of a status code. */
+/* Pointwise prox of J / sigma (Sec. 3, Step 2) on n nodes, as the update
+ * kernels compute it: (u, v) = argmin |u|^2 / (2 v) + sigma/2 |u - a_m|^2 +
+ * sigma/2 (v - a_f)^2, (0, 0) where 2 a_f + sigma |a_m|^2 <= 0.  am and u are
+ * device arrays [3][n] (the three momentum components, each contiguous), af
+ * and v device arrays [n]; the caller owns them all.  kind: OT_PROX_NEWTON,
+ * OT_PROX_CLOSED, or OT_PROX_CLOSED_RAW (the closed form without its Newton
+ * step, for accuracy comparisons).  Asynchronous on `stream` (a hipStream_t,
+ * NULL = default stream).  OT_ERR_PARAM for a null pointer, n < 0, sigma
+ * <= 0 or an unknown kind; OT_ERR_HIP if the launch fails. */
+int ot_dyn_prox_eval(int kind, long long n, const float* am, const float* af, float sigma,
+                     float* u, float* v, void* stream);
+
 const char* ot_dyn_status_str(int status);
 
 /* Last error message recorded on the plan (never NULL). */

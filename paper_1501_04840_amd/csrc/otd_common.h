@@ -48,6 +48,7 @@ struct AxisTab {
 struct StepArgs {
     Geom g;
     float tau_sigma;     // tau * sigma (the same for every problem)
+    int prox;            // root of the prox cubic: OT_PROX_NEWTON or OT_PROX_CLOSED
     const float* sig;    // sigma per problem [B] (device; residual balancing)
     const float* frz;    // per problem [B]: nonzero = frozen (a certified member of a
                          // batch): the stencil and colour/time kernels skip it
@@ -97,6 +98,10 @@ void launch_zero_dual(const StepArgs& s, hipStream_t st);
 // b and b_bar of problem q times fac[q] (device [B]): keeps the unscaled dual
 // sigma b when sigma changes
 void launch_scale_dual(const StepArgs& s, const float* fac, hipStream_t st);
+// The pointwise prox on n nodes (am, u: [3][n]; af, v: [n]), `kind` as
+// OT_PROX_* (ot_dyn_prox_eval).
+void launch_prox_eval(int kind, long long n, const float* am, const float* af, float sigma,
+                      float* u, float* v, hipStream_t st);
 // FP64 mass partials and input checks of f0, f1 ([B][C][Y][X]).
 void launch_boundary_stats(const Geom& g, const float* f0, const float* f1,
                            double* part, int nblk, hipStream_t st);

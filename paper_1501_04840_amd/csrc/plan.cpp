@@ -148,8 +148,8 @@ int validate(const ot_dyn_desc* d, std::string* why) {
     }
     if (d->check_every < 1 || !(d->tol_res > 0.0) || !(d->tol_div > 0.0) ||
         !(d->tol_mass >= 0.0) || d->refine < OT_REFINE_OFF || d->refine > OT_REFINE_CARRY ||
-        d->adapt < 0 || d->adapt > 1) {
-        if (why) *why = "need check_every >= 1, tol_res > 0, tol_div > 0, tol_mass >= 0, refine in {0,1,2,3}, adapt in {0,1}";
+        d->adapt < 0 || d->adapt > 1 || d->prox < OT_PROX_NEWTON || d->prox > OT_PROX_CLOSED) {
+        if (why) *why = "need check_every >= 1, tol_res > 0, tol_div > 0, tol_mass >= 0, refine in {0,1,2,3}, adapt in {0,1}, prox in {0,1}";
         return OT_ERR_PARAM;
     }
     return OT_OK;
@@ -249,6 +249,7 @@ StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     StepArgs s;
     s.g = p->g;
     s.tau_sigma = (float)(p->d.tau * p->d.sigma);
+    s.prox = p->d.prox;
     s.sig = p->sig;
     s.frz = p->frz;
     s.theta = (float)p->d.theta;
@@ -525,6 +526,7 @@ int ot_dyn_default_desc(ot_dyn_desc* d, int X, int Y, int C, int P) {
     d->refine = OT_REFINE_CARRY;
     d->batch = 1;
     d->adapt = 0;
+    d->prox = OT_PROX_NEWTON;
     return OT_OK;
 }
 
@@ -865,6 +867,15 @@ const char* ot_dyn_status_str(int status) {
 
 const char* ot_dyn_last_error(const ot_dyn_plan* p) {
     return p ? p->err.c_str() : "null plan";
+}
+
+int ot_dyn_prox_eval(int kind, long long n, const float* am, const float* af, float sigma,
+                     float* u, float* v, void* stream) {
+    if (!am || !af || !u || !v || n < 0 || !(sigma > 0.f) || kind < OT_PROX_NEWTON ||
+        kind > OT_PROX_CLOSED_RAW || n > (long long)0xffffffffLL * 256)
+        return OT_ERR_PARAM;
+    launch_prox_eval(kind, n, am, af, sigma, u, v, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
 }
 
 }  // extern "C"

@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_update(StepArgs s) {
         const float bx = s.b[0][i], by = s.b[1][i], bc = s.b[2][i], bf = s.b[3][i];
         const float amx = kx + bx, amy = ky + by, amc = kc + bc, amf = kf + bf;
         float ux, uy, uc, vv;
-        prox_J(amx, amy, amc, amf, s.sig[n.b], ux, uy, uc, vv);
+        prox_J(amx, amy, amc, amf, s.sig[n.b], ux, uy, uc, vv, s.prox);
         const float nbx = amx - ux, nby = amy - uy, nbc = amc - uc, nbf = amf - vv;
         const float th = s.theta;
         s.b[0][i] = nbx; s.bb[0][i] = nbx + th * (nbx - bx);
@@ -393,6 +393,26 @@ void launch_update(const StepArgs& s, int check, int nphi, hipStream_t st) {
         if (check) hipLaunchKernelGGL((k_update<1, 1>), gr, bl, 0, st, s);
         else hipLaunchKernelGGL((k_update<0, 1>), gr, bl, 0, st, s);
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_prox_eval(int kind, long long n, const float* am,
+                                                    const float* af, float sigma, float* u,
+                                                    float* v) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    float ux, uy, uc, vv;
+    prox_J(am[i], am[n + i], am[2 * n + i], af[i], sigma, ux, uy, uc, vv, kind);
+    u[i] = ux;
+    u[n + i] = uy;
+    u[2 * n + i] = uc;
+    v[i] = vv;
+}
+
+void launch_prox_eval(int kind, long long n, const float* am, const float* af, float sigma,
+                      float* u, float* v, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_prox_eval, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       kind, n, am, af, sigma, u, v);
 }
 
 void launch_resid_div(const StepArgs& s, hipStream_t st) {

@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
             const float amx = 0.5f * (mx0 + mx1) + bx, amy = 0.5f * (my0 + my1) + by;
             const float amc = 0.5f * (mc0 + mc1) + bc, amf = 0.5f * (f0 + f1) + bf;
             float ux, uy, uc, vv;
-            prox_J(amx, amy, amc, amf, sigma, ux, uy, uc, vv);
+            prox_J(amx, amy, amc, amf, sigma, ux, uy, uc, vv, s.prox);
             const float nbx = amx - ux, nby = amy - uy, nbc = amc - uc, nbf = amf - vv;
             s.b[0][i] = nbx; s.bb[0][i] = nbx + th * (nbx - bx);
             s.b[1][i] = nby; s.bb[1][i] = nby + th * (nby - by);

@@ -48,6 +48,10 @@ OT_REFINE_ALWAYS = 1
 OT_REFINE_ADAPTIVE = 2
 OT_REFINE_CARRY = 3
 
+OT_PROX_NEWTON = 0
+OT_PROX_CLOSED = 1
+OT_PROX_CLOSED_RAW = 2
+
 
 class ot_dyn_desc(ctypes.Structure):
     _fields_ = [
@@ -60,6 +64,7 @@ class ot_dyn_desc(ctypes.Structure):
         ("refine", c_int),
         ("batch", c_int),
         ("adapt", c_int),
+        ("prox", c_int),
     ]
 
 
@@ -94,6 +99,7 @@ EXPORTS = [
     "ot_dyn_batch_problem", "ot_dyn_batch_get_state", "ot_dyn_batch_set_state",
     "ot_dyn_batch_get_dual", "ot_dyn_batch_set_dual",
     "ot_dyn_batch_tuning", "ot_dyn_batch_destroy", "ot_dyn_batch_last_error",
+    "ot_dyn_prox_eval",
 ]
 
 
@@ -139,6 +145,7 @@ def lib() -> ctypes.CDLL:
     L.ot_dyn_batch_destroy.argtypes = [P]
     L.ot_dyn_batch_last_error.argtypes = [P]
     L.ot_dyn_batch_last_error.restype = c_char_p
+    L.ot_dyn_prox_eval.argtypes = [c_int, LL, P, P, ctypes.c_float, P, P, P]
     L.ot_dyn_status_str.argtypes = [c_int]
     L.ot_dyn_status_str.restype = c_char_p
     L.ot_dyn_last_error.argtypes = [P]
@@ -318,12 +325,12 @@ def ot_dyn_batch_set_dual(bt: int, Bd) -> int:
     return _checkb(lib().ot_dyn_batch_set_dual(bt, _ptr(Bd)), bt)
 
 
-def ot_dyn_get_dual(plan: int, b) -> int:
-    return _check(lib().ot_dyn_get_dual(plan, _ptr(b)), plan)
-
-
-def ot_dyn_set_dual(plan: int, b) -> int:
-    return _check(lib().ot_dyn_set_dual(plan, _ptr(b)), plan)
+def ot_dyn_prox_eval(kind: int, am, af, sigma: float, u, v, stream=None) -> int:
+    """Device prox of J / sigma on n nodes: am, u [3, n] and af, v [n]
+    float32 device tensors (see include/ot_dyn.h)."""
+    n = af.numel()
+    return _check(lib().ot_dyn_prox_eval(kind, n, _ptr(am), _ptr(af), float(sigma), _ptr(u),
+                                         _ptr(v), stream))
 
 
 def ot_dyn_batch_tuning(bt: int, i: int):

@@ -37,6 +37,7 @@ def test_default_desc_and_workspace(L):
     assert (d.X, d.Y, d.C, d.P) == (256, 256, 3, 32)
     assert list(d.bc) == [L.OT_BC_NEUMANN, L.OT_BC_NEUMANN, L.OT_BC_PERIODIC]
     assert d.tau * d.sigma < 1 and d.theta == 1.0 and d.batch == 1 and d.adapt == 0
+    assert d.prox == L.OT_PROX_NEWTON
     n = L.ot_dyn_workspace_size(d)
     N = 256 * 256 * 3 * 32
     assert n >= 15 * N * 4          # b, b_bar, a (4 fields each), r, r' and Phi
@@ -48,7 +49,7 @@ def test_default_desc_and_workspace(L):
 @pytest.mark.parametrize("field,value,status", [
     ("P", 1, -2), ("X", 0, -2), ("C", 100, -2), ("tau", 20.0, -1), ("sigma", -1.0, -1),
     ("theta", 1.5, -1), ("check_every", 0, -1), ("refine", 4, -1), ("refine", -1, -1), ("batch", 0, -2),
-    ("adapt", 2, -1),
+    ("adapt", 2, -1), ("prox", 2, -1), ("prox", -1, -1),
 ])
 def test_descriptor_validation(L, field, value, status):
     d = L.ot_dyn_default_desc(16, 16, 3, 8)
@@ -87,3 +88,16 @@ def test_status_strings(L):
     for s in (0, 1, -1, -2, -3, -4, -5, -6, -7):
         assert L.ot_dyn_status_str(s)
     assert L.ot_dyn_status_str(-99) == "unknown status"
+
+
+def test_prox_eval_rejects_bad_arguments(L):
+    """Argument errors of ot_dyn_prox_eval come back before any device call."""
+    import ctypes
+    lib = L.lib()
+    buf = (ctypes.c_float * 12)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert lib.ot_dyn_prox_eval(0, 4, None, p, 1.0, p, p, None) == L.OT_ERR_PARAM
+    assert lib.ot_dyn_prox_eval(3, 4, p, p, 1.0, p, p, None) == L.OT_ERR_PARAM     # unknown kind
+    assert lib.ot_dyn_prox_eval(-1, 4, p, p, 1.0, p, p, None) == L.OT_ERR_PARAM
+    assert lib.ot_dyn_prox_eval(0, -1, p, p, 1.0, p, p, None) == L.OT_ERR_PARAM    # n < 0
+    assert lib.ot_dyn_prox_eval(1, 4, p, p, 0.0, p, p, None) == L.OT_ERR_PARAM     # sigma <= 0
