@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
 
 # Algorithmic traffic of each phase in FP32 words per centred node and launch
-# (each array element read or written once): see the design doc.
+# (each array element read or written once).
 # Algorithmic FP32 words per centred node and launch, per projection mode
 # (refine = 0 off, 1 refinement solve, 3 carried potential Phi):
 #   div     read x (4) + b_bar (4) (+ Phi), write a (4) + r (1)

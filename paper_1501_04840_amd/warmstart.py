@@ -403,13 +403,13 @@ def main(argv=None):
     t.add_argument("--eval", type=int, default=0, help="held-out pairs to evaluate after training")
     t.add_argument("--eval-iters", type=int, default=40000)
     t.add_argument("--eval-modes", default=",".join(MODES))
-    t.add_argument("--out", default="gpurun_out/warm")
+    t.add_argument("--out", default="warm_out")
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--count", type=int, default=512)
     e.add_argument("--max-iters", type=int, default=40000)
     e.add_argument("--modes", default=",".join(MODES))
-    e.add_argument("--out", default="gpurun_out/warm")
+    e.add_argument("--out", default="warm_out")
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
     dev = "cuda:0"
