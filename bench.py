@@ -252,7 +252,7 @@ def warm_start(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="rgb", choices=["rgb", "hue_batch", "warm"])
-    ap.add_argument("--warm-count", type=int, default=64)
+    ap.add_argument("--warm-count", type=int, default=512)
     ap.add_argument("--warm-max-iters", type=int, default=30000)
     ap.add_argument("--hue-count", type=int, default=1024)
     ap.add_argument("--hue-max-iters", type=int, default=60000)
