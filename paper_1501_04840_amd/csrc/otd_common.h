@@ -157,6 +157,14 @@ void launch_fused_x(const Geom& g, float* R, float* Rt, float* dc, const AxisTab
 void launch_fused_yt(const Geom& g, float* Rt, float* dc, const AxisTab& tx, const AxisTab& ty,
                      const AxisTab& tc, const AxisTab& tt, hipStream_t st);
 
+// Whole Poisson solve of problems with one spatial axis (transform.hip):
+// Y = C = 1, X in {64, 128, 256} with its fast transform, P in {8, 16, 32};
+// one block per problem, frozen problems skipped.
+bool poisson_1d_ok(const Geom& g, const AxisTab& tx, const AxisTab& tt);
+void launch_poisson_1d(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
+                       const AxisTab& tc, const AxisTab& tt, const double* tc64,
+                       const double* tt64, const float* frz, hipStream_t st);
+
 // Fast power-of-two passes (fastdct.hip); kind 0 DCT-II, 1 DCT-III, 2 Hartley.
 bool fast_len(int L);
 void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st,

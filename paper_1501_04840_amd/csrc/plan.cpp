@@ -33,6 +33,7 @@ struct ot_dyn_plan {
     float* Rt;               // fused Poisson passes: transposed scratch [B][C][X][Y][P]
     float* dcl;              // fused Poisson passes: FP64-solved DC line [B][C][P]
     bool fused;              // the fused three-pass Poisson solve applies
+    bool p1d;                // one spatial axis: the one-block Poisson solve applies
     float* sig;              // sigma per problem [B] (device)
     float* fac;              // dual rescale factors per problem [B] (device)
     float* frz;              // frozen flags per problem [B] (device; batches)
@@ -293,6 +294,13 @@ void poisson(ot_dyn_plan* p, float* R) {
     const Geom& g = p->g;
     hipStream_t st = p->stream;
     const long long B = g.B;
+    if (p->p1d) {
+        timed(p, OT_PHASE_TC, [&] {
+            launch_poisson_1d(g, R, p->tab[0], p->tab[1], p->tab[2], p->tab[3], p->tc64, p->tt64,
+                              p->frz, st);
+        });
+        return;
+    }
     if (p->fused) {     // three passes: x (+ colour), y + t, inverse x (+ colour)
         auto x_pass = [&](int inverse) {
             launch_fused_x(g, R, p->Rt, p->dcl, p->tab[0], p->tab[1], p->tab[2], p->tab[3],
@@ -347,6 +355,8 @@ void apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy) {
     // faster than the five passes at 64 x 64 and 128 x 128 (alone and
     // batched) and 2% slower for one 256 x 256 problem (256 blocks, one fat
     // block per CU), where the five passes are kept
+    // problems with one spatial axis: the whole solve in one block per problem
+    p->p1d = dense_xy != 1 && poisson_1d_ok(g, p->tab[0], p->tab[3]);
     p->fused = dense_xy == 0 && fused_poisson_ok(g, p->tab[0], p->tab[1], p->tab[3]) &&
                ((long long)g.B * g.Y >= 512 || (long long)g.X * g.Y < 65536);
 }
@@ -567,6 +577,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->Rt = (float*)(p->ws + L.off_Rt);
     p->dcl = (float*)(p->ws + L.off_dcl);
     p->fused = false;
+    p->p1d = false;
     p->fac = p->sig + p->g.B;
     p->frz = p->sig + 2 * (size_t)p->g.B;
     p->f0 = (float*)(p->ws + L.off_f);

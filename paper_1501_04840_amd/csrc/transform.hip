@@ -267,6 +267,56 @@ __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
     dc_line_fp64(a, b, reinterpret_cast<double*>(lds));
 }
 
+// The (colour, time) problem of the spatial-DC line from the FP64 plane
+// sums d1[q], q = (k, c), visible to the whole block (d1 and d1 + P C are
+// overwritten); output as for dc_line_fp64.
+__device__ __forceinline__ void dc_solve_fp64(const TcArgs& a, int b, double* d1, float* ct_out) {
+    const Geom& g = a.g;
+    const int P = g.P, C = g.C;
+    const int nt = blockDim.x;
+    float* base = a.R + (long long)b * g.nc;
+    double* d2 = d1 + P * C;
+    const int m = P * C;
+    for (int e = threadIdx.x; e < m; e += nt) {      // colour forward
+        const int k = e / C, jc = e - k * C;
+        double acc = 0.0;
+        for (int c = 0; c < C; ++c) acc += a.tc64[jc * C + c] * d1[k * C + c];
+        d2[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m; e += nt) {      // time forward, divide
+        const int jt = e / C, jc = e - jt * C;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < P; ++k) acc += a.tt64[jt * P + k] * d2[k * C + jc];
+        const double lam = a.lamc64[jc] + a.lamt64[jt];
+        d1[e] = lam > 0.0 ? acc / lam : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m; e += nt) {      // time inverse
+        const int k = e / C, jc = e - k * C;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int jt = 0; jt < P; ++jt) acc += a.tt64[jt * P + k] * d1[jt * C + jc];
+        d2[e] = acc;
+    }
+    __syncthreads();
+    const double scale = 1.0 / sqrt((double)g.plane);
+    if (ct_out) {
+        for (int e = threadIdx.x; e < m; e += nt) {
+            const int k = e / C, jc = e - k * C;
+            ct_out[jc * P + k] = (float)(d2[e] * scale);
+        }
+        return;
+    }
+    for (int e = threadIdx.x; e < m; e += nt) {      // colour inverse, store
+        const int k = e / C, c = e - k * C;
+        double acc = 0.0;
+        for (int jc = 0; jc < C; ++jc) acc += a.tc64[jc * C + c] * d2[k * C + jc];
+        base[(long long)k * g.slice + (long long)c * g.plane] = (float)(acc * scale);
+    }
+}
+
 // Spatial-DC line (jx, jy) = (0, 0) in FP64: S[k][c] = sum_{x,y} r from the
 // FP64 plane sums, then the (colour, time) Poisson problem with eigenvalues
 // lam_c + lam_t (zero mode dropped), scaled by 1 / sqrt(X Y); writes the
@@ -277,7 +327,6 @@ __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1, float* ct_out) 
     const Geom& g = a.g;
     const int P = g.P, C = g.C;
     const int nt = blockDim.x;
-    float* base = a.R + (long long)b * g.nc;
     double* d2 = d1 + P * C;
     const int m = P * C;
     // plane sums d1[q], q = (k, c), of the nbx block partials of each plane:
@@ -323,44 +372,7 @@ __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1, float* ct_out) 
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < m; e += nt) {      // colour forward
-        const int k = e / C, jc = e - k * C;
-        double acc = 0.0;
-        for (int c = 0; c < C; ++c) acc += a.tc64[jc * C + c] * d1[k * C + c];
-        d2[e] = acc;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < m; e += nt) {      // time forward, divide
-        const int jt = e / C, jc = e - jt * C;
-        double acc = 0.0;
-#pragma unroll 8
-        for (int k = 0; k < P; ++k) acc += a.tt64[jt * P + k] * d2[k * C + jc];
-        const double lam = a.lamc64[jc] + a.lamt64[jt];
-        d1[e] = lam > 0.0 ? acc / lam : 0.0;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < m; e += nt) {      // time inverse
-        const int k = e / C, jc = e - k * C;
-        double acc = 0.0;
-#pragma unroll 8
-        for (int jt = 0; jt < P; ++jt) acc += a.tt64[jt * P + k] * d1[jt * C + jc];
-        d2[e] = acc;
-    }
-    __syncthreads();
-    const double scale = 1.0 / sqrt((double)g.plane);
-    if (ct_out) {
-        for (int e = threadIdx.x; e < m; e += nt) {
-            const int k = e / C, jc = e - k * C;
-            ct_out[jc * P + k] = (float)(d2[e] * scale);
-        }
-        return;
-    }
-    for (int e = threadIdx.x; e < m; e += nt) {      // colour inverse, store
-        const int k = e / C, c = e - k * C;
-        double acc = 0.0;
-        for (int jc = 0; jc < C; ++jc) acc += a.tc64[jc * C + c] * d2[k * C + jc];
-        base[(long long)k * g.slice + (long long)c * g.plane] = (float)(acc * scale);
-    }
+    dc_solve_fp64(a, b, d1, ct_out);
 }
 
 // Orthonormal DCT-II of a register line of length P (Makhoul's reordering
@@ -683,6 +695,125 @@ __global__ void __launch_bounds__(NT) k_yt(TcArgs a) {
             make_float4(lds[t * PITCH + y], lds[(t + 1) * PITCH + y], lds[(t + 2) * PITCH + y],
                         lds[(t + 3) * PITCH + y]);
     }
+}
+
+// Whole Poisson solve of a problem with one spatial axis (Y = C = 1, x of
+// power-of-two length 64..256, P in {8, 16, 32}) in one block: the P x X
+// tile of r stays in LDS; FP64 sums of its time rows give the spatial-DC
+// line, solved in FP64 as in the colour/time pass; the rows are transformed
+// along x (Hartley for periodic x, DCT-II for Neumann), every x-frequency
+// column along t in registers with the division by the eigenvalues, and the
+// rows back along x.  One launch instead of three for each iteration of the
+// batched 1D (hue) problems.
+template <int M1, int M2, int P, int NT, int KF, int KI>
+__global__ void __launch_bounds__(NT) k_p1d(TcArgs a) {
+    constexpr int L = 2 * M1 * M2, T = M2, PITCH = L + 1, NLINES = cmax(P, NT / T);
+    constexpr int NV = L * P / (4 * NT), S = NT / P;
+    static_assert(NV * 4 * NT == L * P, "tile must split into float4 per thread");
+    static_assert(S * P == NT && S >= 2, "row-sum slots");
+    __shared__ __align__(16) float lds[NLINES * PITCH];
+    __shared__ double dsum[NT + 2 * P];
+    __shared__ float dcl[P];
+    const Geom& g = a.g;
+    const int b = blockIdx.x;
+    if (a.frz && a.frz[b] != 0.f) return;   // frozen problem (block-uniform)
+    float* base = a.R + (long long)b * g.nc;
+    float4 buf[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) buf[j] = reinterpret_cast<const float4*>(base)[threadIdx.x + NT * j];
+    for (int e = P * PITCH + threadIdx.x; e < NLINES * PITCH; e += NT) lds[e] = 0.f;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int e = 4 * ((int)threadIdx.x + NT * j);
+        float* d = lds + (e / L) * PITCH + (e % L);
+        d[0] = buf[j].x; d[1] = buf[j].y; d[2] = buf[j].z; d[3] = buf[j].w;
+    }
+    __syncthreads();
+    {   // FP64 sums of the time rows: S slots per row, then one thread per row
+        const int t = threadIdx.x / S, q = threadIdx.x - t * S;
+        double acc = 0.0;
+        for (int x = q; x < L; x += S) acc += (double)lds[t * PITCH + x];
+        dsum[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    double* d1 = dsum + NT;
+    if (threadIdx.x < P) {
+        double acc = 0.0;
+        for (int q = 0; q < S; ++q) acc += dsum[threadIdx.x * S + q];
+        d1[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    dc_solve_fp64(a, b, d1, dcl);
+    __syncthreads();
+    const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
+    line_xform<M1, M2, KF>(lds + line * PITCH, tt, a.tx.tw);
+    for (int jx = threadIdx.x; jx < L; jx += NT) {
+        float u[P];
+        if (jx == 0) {
+#pragma unroll
+            for (int t = 0; t < P; ++t) u[t] = dcl[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < P; ++t) u[t] = lds[t * PITCH + jx];
+            dct2_reg<P>(u, a.twt);
+            const float lx = a.tx.lam[jx];
+#pragma unroll
+            for (int jt = 0; jt < P; ++jt)
+                u[jt] = u[jt] * __builtin_amdgcn_rcpf(lx + a.tt.lam[jt]);   // lx > 0 off the DC
+            dct3_reg<P>(u, a.twt);
+        }
+#pragma unroll
+        for (int t = 0; t < P; ++t) lds[t * PITCH + jx] = u[t];
+    }
+    __syncthreads();
+    line_xform<M1, M2, KI>(lds + line * PITCH, tt, a.tx.tw);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int e = 4 * ((int)threadIdx.x + NT * j);
+        const float* d = lds + (e / L) * PITCH + (e % L);
+        reinterpret_cast<float4*>(base)[threadIdx.x + NT * j] = make_float4(d[0], d[1], d[2], d[3]);
+    }
+}
+
+template <int M1, int M2, int P>
+static void p1d_launch(const TcArgs& a, hipStream_t st) {
+    constexpr int NT = cmax(64, P * M2);
+    const dim3 grid((unsigned)a.g.B);
+    if (a.g.perx)
+        hipLaunchKernelGGL((k_p1d<M1, M2, P, NT, 2, 2>), grid, dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_p1d<M1, M2, P, NT, 0, 1>), grid, dim3(NT), 0, st, a);
+}
+
+template <int P>
+static bool p1d_dispatch(const TcArgs& a, hipStream_t st) {
+    switch (a.g.X) {
+        case 64: p1d_launch<8, 4, P>(a, st); return true;
+        case 128: p1d_launch<8, 8, P>(a, st); return true;
+        case 256: p1d_launch<16, 8, P>(a, st); return true;
+        default: return false;
+    }
+}
+
+bool poisson_1d_ok(const Geom& g, const AxisTab& tx, const AxisTab& tt) {
+    return g.Y == 1 && g.C == 1 && (g.X == 64 || g.X == 128 || g.X == 256) && tx.tw && tt.tw &&
+           (g.P == 8 || g.P == 16 || g.P == 32);
+}
+
+void launch_poisson_1d(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
+                       const AxisTab& tc, const AxisTab& tt, const double* tc64,
+                       const double* tt64, const float* frz, hipStream_t st) {
+    TcArgs a{};
+    a.g = g; a.R = R; a.tx = tx; a.ty = ty; a.tc = tc; a.tt = tt;
+    a.tc64 = tc64;
+    a.tt64 = tt64;
+    a.lamc64 = tc64 + (long long)g.C * g.C;
+    a.lamt64 = tt64 + (long long)g.P * g.P;
+    a.frz = frz;
+    a.twt = tt.tw;
+    if (g.P == 8) p1d_dispatch<8>(a, st);
+    else if (g.P == 16) p1d_dispatch<16>(a, st);
+    else p1d_dispatch<32>(a, st);
 }
 
 // Time slices per block of the x passes: all of them (blocks of half the
