@@ -158,8 +158,9 @@ void launch_fused_yt(const Geom& g, float* Rt, float* dc, const AxisTab& tx, con
                      const AxisTab& tc, const AxisTab& tt, hipStream_t st);
 
 // Whole Poisson solve of problems with one spatial axis (transform.hip):
-// Y = C = 1, X in {64, 128, 256} with its fast transform, P in {8, 16, 32};
-// one block per problem, frozen problems skipped.
+// Y = C = 1, P in {8, 16, 32}, X in {64, 128, 256} with its fast transform
+// or X <= 480 with the dense transform on the matrix cores; one block per
+// problem, frozen problems skipped.
 bool poisson_1d_ok(const Geom& g, const AxisTab& tx, const AxisTab& tt);
 void launch_poisson_1d(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
                        const AxisTab& tc, const AxisTab& tt, const double* tc64,

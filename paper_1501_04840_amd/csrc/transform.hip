@@ -775,6 +775,100 @@ __global__ void __launch_bounds__(NT) k_p1d(TcArgs a) {
     }
 }
 
+// The same one-block solve for one spatial axis without a fast transform
+// (e.g. 180 or 360 periodic bins), X <= kMfmaRowsMaxL: the P time rows,
+// padded with zero rows to 32, are the A operand of the dense x contraction
+// on the matrix cores (as in k_rows_mfma: 2 Lp threads, one wave per 32
+// output columns), forward and inverse, with the time pass and the FP64 DC
+// line between them in LDS.
+// Dynamic LDS of k_p1d_dense at Lp = 416: 60.7 KB, under the 64 KB a block
+// may take (Lp = 448 would need 65.3 KB).
+constexpr int kP1dDenseMaxL = 416;
+
+template <int P>
+__global__ void __launch_bounds__(1024) k_p1d_dense(TcArgs a, int Lp) {
+    extern __shared__ double dyn[];
+    const Geom& g = a.g;
+    const int L = g.X, pitch = Lp + 1, nt = blockDim.x, S = nt / 32;
+    double* dsum = dyn;                               // [nt]
+    double* d1 = dsum + nt;                           // [2 P]
+    float* dcl = reinterpret_cast<float*>(d1 + 2 * P);   // [P]
+    float* xs = dcl + P;                              // [32][pitch]
+    const int b = blockIdx.x;
+    if (a.frz && a.frz[b] != 0.f) return;   // frozen problem (block-uniform)
+    float* base = a.R + (long long)b * g.nc;
+    for (int e = threadIdx.x; e < 32 * Lp; e += nt) {
+        const int r = e / Lp, k = e - r * Lp;
+        xs[r * pitch + k] = (r < P && k < L) ? base[(long long)r * L + k] : 0.f;
+    }
+    __syncthreads();
+    {   // FP64 sums of the time rows (S slots per row of the 32), the DC line
+        const int t = threadIdx.x / S, q = threadIdx.x - t * S;
+        double acc = 0.0;
+        for (int x = q; x < L; x += S) acc += (double)xs[t * pitch + x];
+        dsum[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < P) {
+        double acc = 0.0;
+        for (int q = 0; q < S; ++q) acc += dsum[threadIdx.x * S + q];
+        d1[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    dc_solve_fp64(a, b, d1, dcl);
+    const int lane = threadIdx.x & 63, jt = threadIdx.x >> 6, n = lane & 31, half = lane >> 5;
+    const int j = jt * 32 + n;
+    const bool jin = j < L;
+    for (int pass = 0; pass < 2; ++pass) {
+        const float* T = pass ? inv_tab(a.tx) : fwd_tab(a.tx);   // T[k * L + j]
+        f32x16 acc = {};
+        for (int k0 = 0; k0 < Lp; k0 += 32) {
+            float bv[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = k0 + 2 * q + half;
+                bv[q] = (jin && k < L) ? T[(long long)k * L + j] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[n * pitch + k0 + 2 * q + half], bv[q],
+                                                           acc, 0, 0, 0);
+        }
+        if (pass == 1) {
+            if (jin)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = mfma_row(r, half);
+                    if (row < P) base[(long long)row * L + j] = acc[r];
+                }
+            break;
+        }
+        __syncthreads();                    // every wave has read xs
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xs[mfma_row(r, half) * pitch + j] = jin ? acc[r] : 0.f;
+        __syncthreads();
+        for (int jx = threadIdx.x; jx < L; jx += nt) {
+            float u[P];
+            if (jx == 0) {
+#pragma unroll
+                for (int t = 0; t < P; ++t) u[t] = dcl[t];
+            } else {
+#pragma unroll
+                for (int t = 0; t < P; ++t) u[t] = xs[t * pitch + jx];
+                dct2_reg<P>(u, a.twt);
+                const float lx = a.tx.lam[jx];
+#pragma unroll
+                for (int jt2 = 0; jt2 < P; ++jt2)
+                    u[jt2] = u[jt2] * __builtin_amdgcn_rcpf(lx + a.tt.lam[jt2]);   // lx > 0 off the DC
+                dct3_reg<P>(u, a.twt);
+            }
+#pragma unroll
+            for (int t = 0; t < P; ++t) xs[t * pitch + jx] = u[t];
+        }
+        __syncthreads();
+    }
+}
+
 template <int M1, int M2, int P>
 static void p1d_launch(const TcArgs& a, hipStream_t st) {
     constexpr int NT = cmax(64, P * M2);
@@ -796,8 +890,17 @@ static bool p1d_dispatch(const TcArgs& a, hipStream_t st) {
 }
 
 bool poisson_1d_ok(const Geom& g, const AxisTab& tx, const AxisTab& tt) {
-    return g.Y == 1 && g.C == 1 && (g.X == 64 || g.X == 128 || g.X == 256) && tx.tw && tt.tw &&
-           (g.P == 8 || g.P == 16 || g.P == 32);
+    if (g.Y != 1 || g.C != 1 || !tt.tw || !(g.P == 8 || g.P == 16 || g.P == 32)) return false;
+    if (tx.tw) return g.X == 64 || g.X == 128 || g.X == 256;
+    return g.X >= 2 && g.X <= kP1dDenseMaxL;
+}
+
+template <int P>
+static void p1d_dense_launch(const TcArgs& a, hipStream_t st) {
+    const int Lp = (a.g.X + 31) / 32 * 32, nt = 2 * Lp;
+    const size_t sh = ((size_t)nt + 2 * P) * sizeof(double) + (size_t)P * sizeof(float) +
+                      (size_t)32 * (Lp + 1) * sizeof(float);
+    hipLaunchKernelGGL((k_p1d_dense<P>), dim3((unsigned)a.g.B), dim3(nt), sh, st, a, Lp);
 }
 
 void launch_poisson_1d(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
@@ -811,6 +914,12 @@ void launch_poisson_1d(const Geom& g, float* R, const AxisTab& tx, const AxisTab
     a.lamt64 = tt64 + (long long)g.P * g.P;
     a.frz = frz;
     a.twt = tt.tw;
+    if (!tx.tw) {
+        if (g.P == 8) p1d_dense_launch<8>(a, st);
+        else if (g.P == 16) p1d_dense_launch<16>(a, st);
+        else p1d_dense_launch<32>(a, st);
+        return;
+    }
     if (g.P == 8) p1d_dispatch<8>(a, st);
     else if (g.P == 16) p1d_dispatch<16>(a, st);
     else p1d_dispatch<32>(a, st);

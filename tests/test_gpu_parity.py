@@ -89,6 +89,8 @@ SHAPES = [
     # one spatial axis of fast length: the one-block Poisson solve
     (128, 1, 1, 16, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),   # DCT along x
     (256, 1, 1, 8, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),   # Hartley along x
+    (180, 1, 1, 16, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),  # dense Hartley (matrix cores)
+    (100, 1, 1, 32, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),   # dense DCT (matrix cores)
 ]
 
 
