@@ -781,15 +781,19 @@ __global__ void __launch_bounds__(NT) k_p1d(TcArgs a) {
 // on the matrix cores (as in k_rows_mfma: 2 Lp threads, one wave per 32
 // output columns), forward and inverse, with the time pass and the FP64 DC
 // line between them in LDS.
-// Dynamic LDS of k_p1d_dense at Lp = 416: 60.7 KB, under the 64 KB a block
-// may take (Lp = 448 would need 65.3 KB).
+// k_p1d_dense: at most 8 waves (up to 256 VGPRs; with 2 Lp threads the
+// register DCT along t spilled), each computing up to two 32-column tiles,
+// so Lp <= 512; X <= 416 keeps the dynamic LDS (32 padded rows of Lp + 1
+// floats plus the FP64 scratch) under 64 KB.
+constexpr int kP1dDenseThreads = 512;
 constexpr int kP1dDenseMaxL = 416;
 
 template <int P>
-__global__ void __launch_bounds__(1024) k_p1d_dense(TcArgs a, int Lp) {
+__global__ void __launch_bounds__(kP1dDenseThreads) k_p1d_dense(TcArgs a, int Lp) {
     extern __shared__ double dyn[];
     const Geom& g = a.g;
     const int L = g.X, pitch = Lp + 1, nt = blockDim.x, S = nt / 32;
+    const int nwave = nt >> 6, ntile = Lp / 32;       // a wave computes tiles w, w + nwave
     double* dsum = dyn;                               // [nt]
     double* d1 = dsum + nt;                           // [2 P]
     float* dcl = reinterpret_cast<float*>(d1 + 2 * P);   // [P]
@@ -816,36 +820,52 @@ __global__ void __launch_bounds__(1024) k_p1d_dense(TcArgs a, int Lp) {
     }
     __syncthreads();
     dc_solve_fp64(a, b, d1, dcl);
-    const int lane = threadIdx.x & 63, jt = threadIdx.x >> 6, n = lane & 31, half = lane >> 5;
-    const int j = jt * 32 + n;
-    const bool jin = j < L;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 31, half = lane >> 5;
     for (int pass = 0; pass < 2; ++pass) {
         const float* T = pass ? inv_tab(a.tx) : fwd_tab(a.tx);   // T[k * L + j]
-        f32x16 acc = {};
-        for (int k0 = 0; k0 < Lp; k0 += 32) {
-            float bv[16];
+        f32x16 acc[2];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int k = k0 + 2 * q + half;
-                bv[q] = (jin && k < L) ? T[(long long)k * L + j] : 0.f;
+        for (int i = 0; i < 2; ++i) {
+            acc[i] = f32x16{};
+            const int tile = wave + i * nwave;
+            if (tile >= ntile) continue;                 // wave-uniform
+            const int j = tile * 32 + n;
+            const bool jin = j < L;
+            for (int k0 = 0; k0 < Lp; k0 += 32) {
+                float bv[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int k = k0 + 2 * q + half;
+                    bv[q] = (jin && k < L) ? T[(long long)k * L + j] : 0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[n * pitch + k0 + 2 * q + half],
+                                                                  bv[q], acc[i], 0, 0, 0);
             }
-#pragma unroll
-            for (int q = 0; q < 16; ++q)
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[n * pitch + k0 + 2 * q + half], bv[q],
-                                                           acc, 0, 0, 0);
         }
         if (pass == 1) {
-            if (jin)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = mfma_row(r, half);
-                    if (row < P) base[(long long)row * L + j] = acc[r];
-                }
+            for (int i = 0; i < 2; ++i) {
+                const int j = (wave + i * nwave) * 32 + n;
+                if (wave + i * nwave < ntile && j < L)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int row = mfma_row(r, half);
+                        if (row < P) base[(long long)row * L + j] = acc[i][r];
+                    }
+            }
             break;
         }
         __syncthreads();                    // every wave has read xs
 #pragma unroll
-        for (int r = 0; r < 16; ++r) xs[mfma_row(r, half) * pitch + j] = jin ? acc[r] : 0.f;
+        for (int i = 0; i < 2; ++i) {
+            const int tile = wave + i * nwave;
+            if (tile >= ntile) continue;
+            const int j = tile * 32 + n;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) xs[mfma_row(r, half) * pitch + j] = j < L ? acc[i][r] : 0.f;
+        }
         __syncthreads();
         for (int jx = threadIdx.x; jx < L; jx += nt) {
             float u[P];
@@ -897,7 +917,7 @@ bool poisson_1d_ok(const Geom& g, const AxisTab& tx, const AxisTab& tt) {
 
 template <int P>
 static void p1d_dense_launch(const TcArgs& a, hipStream_t st) {
-    const int Lp = (a.g.X + 31) / 32 * 32, nt = 2 * Lp;
+    const int Lp = (a.g.X + 31) / 32 * 32, nt = std::min(2 * Lp, kP1dDenseThreads);
     const size_t sh = ((size_t)nt + 2 * P) * sizeof(double) + (size_t)P * sizeof(float) +
                       (size_t)32 * (Lp + 1) * sizeof(float);
     hipLaunchKernelGGL((k_p1d_dense<P>), dim3((unsigned)a.g.B), dim3(nt), sh, st, a, Lp);
