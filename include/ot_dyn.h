@@ -286,7 +286,10 @@ int ot_dyn_batch_set_dual(ot_dyn_batch* bt, const float* Bd);
 /* Selected launch shape of the group holding problem i: row_bx is the block
  * width of the row stencils (64, 128, 256); dense_xy the transform path (0
  * fused three-pass Poisson solve where it applies, else five FFT passes; 1
- * dense x/y contractions; 2 five FFT passes). */
+ * dense x/y contractions; 2 five FFT passes).  For problems with one spatial
+ * axis (Y = C = 1, P in {8, 16, 32}) paths 0 and 2 solve the whole Poisson
+ * problem in one block per problem (fast transform for X in {64, 128, 256},
+ * dense contraction on the matrix cores for other X up to 416). */
 int ot_dyn_batch_tuning(const ot_dyn_batch* bt, int i, int* row_bx, int* dense_xy);
 
 int ot_dyn_batch_destroy(ot_dyn_batch* bt);
