@@ -175,16 +175,17 @@ def test_balanced_steps_certify_slow_hue_problems(otdyn):
     assert bal[0].iterations < 20000
 
 
-def test_certified_members_are_frozen(otdyn):
+@pytest.mark.parametrize("refine", [1, 3])
+def test_certified_members_are_frozen(otdyn, refine):
     """Problems of one shape group certify at different checks; each keeps the
     state of its certifying check while the others go on: its final state
     equals, bit for bit, that of a single-problem plan stepped exactly its
-    reported iteration count."""
-    _say("frozen certified members")
+    reported iteration count (refinement and carried-potential modes)."""
+    _say(f"frozen certified members refine {refine}")
     import torch
     probs = hue_problems(4, seed=21, bins=(64,), steps=(16,))
     dims = [(n, 1, 1, T) for n, T, _, _ in probs]
-    d = periodic_desc(otdyn)
+    d = periodic_desc(otdyn, base_refine=refine)
     bt = otdyn.Batch(d, dims)
     bt.set_boundary([p[2].reshape(1, 1, -1) for p in probs], [p[3].reshape(1, 1, -1) for p in probs])
     status, rep = bt.solve(40000, chunk=100)
@@ -192,7 +193,7 @@ def test_certified_members_are_frozen(otdyn):
     its = [bt.problem(i).iterations for i in range(len(probs))]
     assert len(set(its)) > 1, its              # they certify at different checks
     for i, (n, T, h0, h1) in enumerate(probs):
-        s = periodic_desc(otdyn)
+        s = periodic_desc(otdyn, base_refine=refine)
         s.X, s.Y, s.C, s.P = n, 1, 1, T
         prob = otdyn.Problem(s, "cuda")
         prob.set_boundary(torch.from_numpy(h0.reshape(1, 1, -1)), torch.from_numpy(h1.reshape(1, 1, -1)))

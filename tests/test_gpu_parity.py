@@ -138,6 +138,31 @@ def test_cfg1_300_iterations(otdyn, mode):
     prob.close()
 
 
+@pytest.mark.parametrize("shape", [(64, 1, 1, 16, (G.PERIODIC, G.NEUMANN, G.NEUMANN)),
+                                   (180, 1, 1, 16, (G.PERIODIC, G.NEUMANN, G.NEUMANN)),
+                                   (128, 1, 1, 8, (G.NEUMANN, G.NEUMANN, G.NEUMANN))],
+                         ids=["64x1x1x16", "180x1x1x16", "128x1x1x8"])
+def test_one_axis_carried_potential_300_iterations(otdyn, shape):
+    """One spatial axis in the carried-potential mode past its refined start:
+    the solve and the update run in one launch per iteration.  f, the cost
+    and r_prim of the 300th (check) iteration against the FP64 oracle."""
+    X, Y, C, P, bc = shape
+    _say(f"one-axis carried potential {shape[:4]}")
+    g = G.Grid(X, Y, C, P, bc)
+    f0, f1 = inputs.random_pair(17 + X + P, X, Y, C)
+    prob = run_gpu(otdyn, g, f0, f1, 299, refine=otdyn.OT_REFINE_CARRY)
+    _, rep = prob.solve(1)
+    F, Mx, My, Mc = host(prob)
+    st = oracle(g, f0, f1, 300)
+    gx = to_natural(g, F, Mx, My, Mc)
+    assert rel(gx[3], st.x[3]) < TOL
+    assert rel(gx[0], st.x[0]) < TOL
+    h = st.hist[-1]
+    assert abs(rep.cost - h["cost"]) <= TOL * abs(h["cost"])
+    assert abs(rep.r_prim - h["r_prim"]) <= 1e-3 * h["r_prim"] + 1e-7
+    prob.close()
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_cfg2_2000_iterations_against_stored_oracle(otdyn, mode):
     """64 x 64 x 3 x 16 RGB bumps, 2000 its, against values written by
