@@ -28,6 +28,7 @@ __all__ = [
     "cfg3_pair",
     "cfg4_problems",
     "cfg5_pair",
+    "hue_image",
     "random_pair",
 ]
 
@@ -183,3 +184,23 @@ def random_pair(seed: int, X: int, Y: int, C: int = 3, floor: float = 0.05):
     a = rng.uniform(floor, 1.0, size=(C, Y, X))
     b = rng.uniform(floor, 1.0, size=(C, Y, X))
     return normalise_mean_one(a), normalise_mean_one(b)
+
+
+def hue_image(seed: int, H: int, W: int, sigma: float = 6.0) -> np.ndarray:
+    """Synthetic 8-bit RGB photograph stand-in, (H, W, 3) uint8, rows first.
+
+    Each channel is an independent smooth random field (white noise blurred
+    with a periodic Gaussian of width `sigma` pixels, stretched to 0..255),
+    so hues vary smoothly over the image with a few dominant families; a
+    block of grey pixels (equal channels) sits in one corner.
+    """
+    rng = _rng(seed)
+    ch = []
+    for _ in range(3):
+        z = ndimage.gaussian_filter(rng.standard_normal((H, W)), sigma, mode="wrap")
+        z = (z - z.min()) / max(z.max() - z.min(), 1e-12)
+        ch.append(np.round(255.0 * z))
+    img = np.stack(ch, axis=-1).astype(np.uint8)
+    gh, gw = max(H // 8, 1), max(W // 8, 1)
+    img[:gh, :gw, :] = img[:gh, :gw, :1]
+    return img
