@@ -1,0 +1,85 @@
+/*
+ * ot_hue.h -- hue image pipeline around the 1D periodic transport (Sec. 5).
+ *
+ * Sec. 5 transports the normalised hue histograms of two images on the
+ * circle with the periodic 1D solver of ot_dyn.h and renders the frame at
+ * time t by giving the first image's hue channel the histogram h^t, keeping
+ * saturation and value, through a periodic exact histogram specification
+ * that the paper cites without formulas.  This library is that rendering
+ * stage; the readings it takes:
+ *
+ *   hue       the HSV hexcone hue in [0, 1) of an 8-bit RGB pixel, in FP32
+ *             from the integer channel differences (grey pixels: 0);
+ *   bins      floor(hue * n) (FP32 product, at most n - 1) on n periodic bins;
+ *   counts    a target density h on the bins becomes integer counts summing
+ *             to the pixel count N: N h_k / sum(h) in FP64 (sum in bin order),
+ *             floored, the remaining pixels one each to the largest fractional
+ *             parts (equal parts: lower bin first); negative and non-finite
+ *             entries count as zero, and a density without mass keeps the
+ *             source counts;
+ *   order     pixels strictly ordered by hue, equal hues by raster index;
+ *   shift     s = lower median over the n bin edges of C_s[e] - C_t[e]
+ *             (cumulative source minus target counts before bin e), which
+ *             minimises the W1 cost on the circle of the rotated monotone map;
+ *   map       the pixel of rank r takes the target bin holding position
+ *             (r - s) mod N of the target's cumulative counts, so the output
+ *             bins have exactly the target counts;
+ *   render    hue' = hue + (k_out - k_src) / n wrapped into [0, 1) (FP32), RGB
+ *             rebuilt from the hexcone with the pixel's max and min channels
+ *             kept, rounded to 8 bits.
+ * Every FP32 step is one rounded operation in a fixed order (no fused
+ * multiply-add), so results are reproducible bit for bit.
+ *
+ * Images are device arrays of N pixels x 3 bytes (R, G, B interleaved, raster
+ * order), owned by the caller.  Work is ordered on the stream given at
+ * creation.  Status codes are those of ot_dyn.h.
+ */
+#ifndef OT_HUE_H
+#define OT_HUE_H
+
+#include "ot_dyn.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ot_hue ot_hue;
+
+/* A renderer for images of npix pixels (1 <= npix <= 2^30) on nbins periodic
+ * hue bins (2 <= nbins <= 4096).  Allocates about 20 bytes of device memory
+ * per pixel (sort keys, order, ranks) plus the sort's workspace.  stream: a
+ * hipStream_t (NULL = default stream).  OT_ERR_SHAPE for sizes out of range,
+ * OT_ERR_PARAM for a null out, OT_ERR_HIP if an allocation fails. */
+int ot_hue_create(long long npix, int nbins, void* stream, ot_hue** out);
+
+void ot_hue_destroy(ot_hue* h);
+
+/* The source image (rgb: device, npix x 3 bytes): hues, bins, bin counts, the
+ * strict order and each pixel's rank in it.  Asynchronous.  OT_ERR_PARAM for
+ * a null pointer, OT_ERR_HIP if a launch fails. */
+int ot_hue_set_source(ot_hue* h, const unsigned char* rgb);
+
+/* The source's hue histogram: counts (device int32 [nbins]) and/or density
+ * (device float [nbins], counts * nbins / npix: mean one, the solver's
+ * convention); either may be NULL.  Asynchronous.  OT_ERR_STATE before
+ * ot_hue_set_source. */
+int ot_hue_histogram(ot_hue* h, int* counts, float* density);
+
+/* One frame: the source image with its hue histogram specified to the
+ * density `target` (device float [nbins], any scale).  rgb_out: device,
+ * npix x 3 bytes (may not alias the source); bins_out: device int32 [npix],
+ * each pixel's output bin, or NULL.  Asynchronous; the source image must stay
+ * unchanged until the frame is done.  OT_ERR_STATE before ot_hue_set_source,
+ * OT_ERR_PARAM for a null target or rgb_out, OT_ERR_HIP if a launch fails. */
+int ot_hue_render(ot_hue* h, const float* target, unsigned char* rgb_out, int* bins_out);
+
+/* The last frame's target counts (host int32 [nbins], or NULL) and shift s
+ * (host, or NULL).  Synchronises the stream.  OT_ERR_STATE before the first
+ * ot_hue_render. */
+int ot_hue_plan_info(ot_hue* h, int* counts, long long* shift);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif  /* OT_HUE_H */

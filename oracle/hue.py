@@ -91,9 +91,9 @@ def target_counts(h: np.ndarray, npix: int, source: np.ndarray) -> np.ndarray:
     x = [(float(npix) * v) / S for v in h]
     c = [int(np.floor(v)) for v in x]
     rem = [x[k] - c[k] for k in range(len(h))]
-    left = npix - sum(c)
+    left = npix - sum(c)          # in [0, n) unless rounding pushed an x_k up
     order = sorted(range(len(h)), key=lambda k: (-rem[k], k))
-    for k in order[:left]:
+    for k in order[:max(left, 0)]:
         c[k] += 1
     return np.asarray(c, dtype=np.int64)
 

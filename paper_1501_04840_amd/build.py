@@ -17,7 +17,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libotdyn.so")
 
 SOURCES = ["stencil.hip", "stencil_rows.hip", "transform.hip", "fastdct.hip", "plan.cpp",
-           "batch.cpp", "otnet.hip", "net.cpp"]
+           "batch.cpp", "otnet.hip", "net.cpp", "hue.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,0 +1,130 @@
+"""Python binding of the hue image pipeline C ABI (include/ot_hue.h).
+
+Same rules as otdyn: the functions carry the C names and marshal arguments
+only; hues, histograms, the strict order and the frames are computed by the
+HIP kernels of libotdyn.so.  Device pointers are torch CUDA tensors or
+integers.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_int, c_void_p
+
+from . import otdyn
+from .otdyn import OtDynError, _ptr
+
+EXPORTS = ["ot_hue_create", "ot_hue_destroy", "ot_hue_set_source", "ot_hue_histogram",
+           "ot_hue_render", "ot_hue_plan_info"]
+
+_done = False
+
+
+def lib() -> ctypes.CDLL:
+    global _done
+    L = otdyn.lib()
+    if _done:
+        return L
+    P = c_void_p
+    LL = ctypes.c_longlong
+    L.ot_hue_create.argtypes = [LL, c_int, P, POINTER(c_void_p)]
+    L.ot_hue_destroy.argtypes = [P]
+    L.ot_hue_destroy.restype = None
+    L.ot_hue_set_source.argtypes = [P, P]
+    L.ot_hue_histogram.argtypes = [P, P, P]
+    L.ot_hue_render.argtypes = [P, P, P, P]
+    L.ot_hue_plan_info.argtypes = [P, P, POINTER(LL)]
+    for name in EXPORTS:
+        if name != "ot_hue_destroy":
+            getattr(L, name).restype = c_int
+    _done = True
+    return L
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise OtDynError(status, otdyn.lib().ot_dyn_status_str(status).decode())
+    return status
+
+
+def ot_hue_create(npix: int, nbins: int, stream=None) -> int:
+    h = c_void_p()
+    _check(lib().ot_hue_create(npix, nbins, _ptr(stream), byref(h)))
+    return h.value
+
+
+def ot_hue_destroy(h: int) -> None:
+    lib().ot_hue_destroy(h)
+
+
+def ot_hue_set_source(h: int, rgb) -> int:
+    return _check(lib().ot_hue_set_source(h, _ptr(rgb)))
+
+
+def ot_hue_histogram(h: int, counts=None, density=None) -> int:
+    return _check(lib().ot_hue_histogram(h, _ptr(counts), _ptr(density)))
+
+
+def ot_hue_render(h: int, target, rgb_out, bins_out=None) -> int:
+    return _check(lib().ot_hue_render(h, _ptr(target), _ptr(rgb_out), _ptr(bins_out)))
+
+
+def ot_hue_plan_info(h: int, counts=None):
+    """(status, shift); counts: a host int32 array (numpy) or None."""
+    s = ctypes.c_longlong()
+    cp = counts.ctypes.data if counts is not None else 0
+    st = _check(lib().ot_hue_plan_info(h, cp, byref(s)))
+    return st, s.value
+
+
+class HueRenderer:
+    """Owns one ot_hue object and the source image tensor it reads."""
+
+    def __init__(self, npix: int, nbins: int, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.npix, self.nbins = npix, nbins
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = ot_hue_create(npix, nbins, self.stream.cuda_stream)
+        self.src = None
+
+    def set_source(self, rgb):
+        """rgb: uint8 tensor on the device with npix * 3 elements."""
+        t = self.torch
+        assert rgb.dtype == t.uint8 and rgb.is_cuda and rgb.numel() == 3 * self.npix
+        self.src = rgb.contiguous()
+        ot_hue_set_source(self.h, self.src)
+
+    def histogram(self):
+        t = self.torch
+        c = t.empty(self.nbins, dtype=t.int32, device=self.device)
+        d = t.empty(self.nbins, dtype=t.float32, device=self.device)
+        ot_hue_histogram(self.h, c, d)
+        return c, d
+
+    def render(self, target, with_bins: bool = False):
+        """The frame for a device float density on the bins: uint8 (npix, 3)
+        and, with with_bins, each pixel's output bin (int32)."""
+        t = self.torch
+        assert target.dtype == t.float32 and target.is_cuda and target.numel() == self.nbins
+        out = t.empty(self.npix, 3, dtype=t.uint8, device=self.device)
+        bins = t.empty(self.npix, dtype=t.int32, device=self.device) if with_bins else None
+        ot_hue_render(self.h, target.contiguous(), out, bins)
+        return (out, bins) if with_bins else out
+
+    def plan_info(self):
+        import numpy as np
+        c = np.empty(self.nbins, dtype=np.int32)
+        _, s = ot_hue_plan_info(self.h, c)
+        return c, s
+
+    def close(self):
+        if self.h:
+            ot_hue_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -101,3 +101,18 @@ def test_prox_eval_rejects_bad_arguments(L):
     assert lib.ot_dyn_prox_eval(-1, 4, p, p, 1.0, p, p, None) == L.OT_ERR_PARAM
     assert lib.ot_dyn_prox_eval(0, -1, p, p, 1.0, p, p, None) == L.OT_ERR_PARAM    # n < 0
     assert lib.ot_dyn_prox_eval(1, 4, p, p, 0.0, p, p, None) == L.OT_ERR_PARAM     # sigma <= 0
+
+
+def test_hue_renderer_rejects_bad_sizes(L):
+    """Host-side checks of ot_hue_create (they return before any HIP call)."""
+    from paper_1501_04840_amd import othue
+    for npix, nbins in [(0, 64), (-5, 64), (10, 1), (10, 4097), ((1 << 30) + 1, 64)]:
+        with pytest.raises(L.OtDynError) as e:
+            othue.ot_hue_create(npix, nbins)
+        assert e.value.status == L.OT_ERR_SHAPE
+    lib = othue.lib()
+    assert lib.ot_hue_create(16, 8, None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_set_source(None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_render(None, None, None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_histogram(None, None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_plan_info(None, None, None) == L.OT_ERR_PARAM

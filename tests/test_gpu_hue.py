@@ -1,0 +1,146 @@
+"""GPU parity of the hue image pipeline (include/ot_hue.h) against the
+oracle: bin counts, target counts, shift, output bins and the rendered 8-bit
+frames must match bit for bit (integer and byte work; every FP32 step on both
+sides is the same single rounded operation)."""
+import numpy as np
+import pytest
+
+from oracle import hue as ref
+from synth import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def othue():
+    import torch
+    from paper_1501_04840_amd import othue as o
+    assert torch.cuda.is_available()
+    o.lib()
+    return o
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _renderer(o, img, n):
+    import torch
+    N = img.shape[0] * img.shape[1]
+    r = o.HueRenderer(N, n)
+    r.set_source(torch.from_numpy(np.ascontiguousarray(img).reshape(-1)).cuda())
+    return r
+
+
+def _frame_check(r, src, target):
+    import torch
+    out, bins = r.render(torch.from_numpy(np.asarray(target, np.float32)).cuda(), with_bins=True)
+    ct, s = r.plan_info()
+    rgb_ref, k_ref, ct_ref, s_ref = src.render(np.asarray(target, np.float32))
+    assert s == s_ref
+    assert np.array_equal(ct, ct_ref)
+    assert np.array_equal(bins.cpu().numpy(), k_ref)
+    assert np.array_equal(out.cpu().numpy(), rgb_ref)
+
+
+@pytest.mark.parametrize("H,W,n", [(96, 80, 64), (97, 83, 180), (64, 64, 360), (1, 1, 2),
+                                   (33, 7, 4096)])
+def test_source_histogram(othue, H, W, n):
+    _say(f"hue histogram {H}x{W} n={n}")
+    img = inputs.hue_image(H * 1000 + W, H, W)
+    r = _renderer(othue, img, n)
+    src = ref.Source(img, n)
+    c, d = r.histogram()
+    assert np.array_equal(c.cpu().numpy(), src.counts)
+    assert np.array_equal(d.cpu().numpy(), src.density().astype(np.float32))
+    r.close()
+
+
+@pytest.mark.parametrize("H,W,n", [(96, 80, 64), (97, 83, 180), (64, 64, 360), (1, 1, 2),
+                                   (33, 7, 4096)])
+def test_frames_match_oracle(othue, H, W, n):
+    _say(f"hue frames {H}x{W} n={n}")
+    img = inputs.hue_image(7 + H + W, H, W)
+    r = _renderer(othue, img, n)
+    src = ref.Source(img, n)
+    rng = np.random.default_rng(n)
+    targets = [
+        np.roll(src.density(), n // 3),                    # rotated own histogram
+        inputs.von_mises_hist(55 + n, n),                  # a smooth periodic density
+        src.counts.astype(np.float32),                     # own counts: identity
+        np.zeros(n, np.float32),                           # no mass: identity
+        rng.uniform(-0.2, 1.0, n),                         # negative entries count as 0
+    ]
+    t = rng.uniform(0, 1, n).astype(np.float32)
+    t[:: 5] = np.nan
+    t[1:: 7] = np.inf
+    targets.append(t)
+    for tg in targets:
+        _frame_check(r, src, tg)
+    r.close()
+
+
+def test_identity_frame_is_the_source(othue):
+    import torch
+    _say("hue identity frame")
+    img = inputs.hue_image(3, 120, 100)
+    r = _renderer(othue, img, 180)
+    c, d = r.histogram()
+    out = r.render(d)
+    assert np.array_equal(out.cpu().numpy(), img.reshape(-1, 3))
+    assert r.plan_info()[1] == 0
+    r.close()
+
+
+def test_new_source_on_one_renderer(othue):
+    import torch
+    _say("hue two sources")
+    n = 128
+    a = inputs.hue_image(11, 50, 60)
+    b = inputs.hue_image(12, 50, 60)
+    r = _renderer(othue, a, n)
+    _frame_check(r, ref.Source(a, n), inputs.von_mises_hist(5, n))
+    r.set_source(torch.from_numpy(b.reshape(-1).copy()).cuda())
+    _frame_check(r, ref.Source(b, n), inputs.von_mises_hist(6, n))
+    r.close()
+
+
+def test_pipeline_frames_along_the_geodesic(othue):
+    """Sec. 5 end to end: the two images' hue densities, the periodic 1D
+    transport between them, and the frames for time levels of f."""
+    import torch
+    from paper_1501_04840_amd import otdyn
+    _say("hue pipeline")
+    n, P = 180, 16
+    a = inputs.hue_image(21, 128, 96)
+    b = inputs.hue_image(22, 128, 96)
+    ra = _renderer(othue, a, n)
+    rb = _renderer(othue, b, n)
+    _, da = ra.histogram()
+    _, db = rb.histogram()
+    f0 = (da + 0.05) / (da + 0.05).mean()              # positive densities of mean one
+    f1 = (db + 0.05) / (db + 0.05).mean()
+    d = otdyn.ot_dyn_default_desc(n, 1, 1, P)
+    d.bc[0] = otdyn.OT_BC_PERIODIC
+    prob = otdyn.Problem(d, "cuda:0")
+    prob.set_boundary(f0.reshape(1, 1, n), f1.reshape(1, 1, n))
+    prob.init(otdyn.OT_INIT_COLD)
+    prob.step(400)
+    torch.cuda.synchronize()
+    src = ref.Source(a, n)
+    for t in (0, P // 4, P // 2, P):
+        row = prob.F[0, t, 0, 0].contiguous()
+        _frame_check(ra, src, row.cpu().numpy())
+    prob.close()
+    ra.close()
+    rb.close()
+
+
+def test_one_megapixel_frame(othue):
+    _say("hue 1024x1024 n=360")
+    img = inputs.hue_image(31, 1024, 1024, sigma=24.0)
+    n = 360
+    r = _renderer(othue, img, n)
+    src = ref.Source(img, n)
+    _frame_check(r, src, inputs.von_mises_hist(77, n))
+    r.close()
