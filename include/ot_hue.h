@@ -73,9 +73,18 @@ int ot_hue_histogram(ot_hue* h, int* counts, float* density);
  * OT_ERR_PARAM for a null target or rgb_out, OT_ERR_HIP if a launch fails. */
 int ot_hue_render(ot_hue* h, const float* target, unsigned char* rgb_out, int* bins_out);
 
+/* The two halves of ot_hue_render, for callers that time or reuse them:
+ * ot_hue_plan computes the target counts and the shift for `target` (one
+ * single-block kernel); ot_hue_apply writes the frame of the last plan (one
+ * pass over the pixels in raster order: 10 bytes of HBM traffic per pixel,
+ * 14 with bins_out).  Same arguments and status codes as ot_hue_render;
+ * ot_hue_apply before any plan for the current source is OT_ERR_STATE. */
+int ot_hue_plan(ot_hue* h, const float* target);
+int ot_hue_apply(ot_hue* h, unsigned char* rgb_out, int* bins_out);
+
 /* The last frame's target counts (host int32 [nbins], or NULL) and shift s
  * (host, or NULL).  Synchronises the stream.  OT_ERR_STATE before the first
- * ot_hue_render. */
+ * plan. */
 int ot_hue_plan_info(ot_hue* h, int* counts, long long* shift);
 
 #ifdef __cplusplus

@@ -7,10 +7,12 @@
 // inclusive cumulative target counts are int32 [n]; the shift is one int64.
 // Per frame: one single-block planning kernel (target counts, median shift)
 // and one streaming kernel over the pixels in raster order (reads 3 bytes of
-// RGB and the 4-byte rank, writes 3 bytes and optionally the 4-byte bin).
+// RGB and the 4-byte rank, writes 3 bytes and optionally the 4-byte bin),
+// four pixels per thread.
 #include <hip/hip_runtime.h>
 #include <hipcub/device/device_radix_sort.hpp>
 
+#include <cstdint>
 #include <new>
 
 #include "../../include/ot_hue.h"
@@ -22,6 +24,7 @@ constexpr long long kMaxPix = 1LL << 30;
 constexpr int kThreads = 256;
 constexpr int kPlanThreads = 1024;
 constexpr unsigned kKeyBlocks = 2048;     // 8 blocks per compute unit
+constexpr unsigned kRenderBlocks = 4096;  // 16 blocks per compute unit
 
 // Every FP32 step below is one rounded operation in the written order: no
 // contraction of a product and a sum into a fused multiply-add.
@@ -32,23 +35,19 @@ struct Hue {
 
 __device__ __forceinline__ Hue hue_of(int r, int g, int b) {
 #pragma clang fp contract(off)
+    // one division: the sector's signed difference over max - min (selects,
+    // not branches, so a wave with mixed sectors divides once)
     Hue o;
     o.hi = max(max(r, g), b);
     o.lo = min(min(r, g), b);
-    const float d = (float)(o.hi - o.lo);
-    float h6;
-    if (o.hi == o.lo) {
-        h6 = 0.f;
-    } else if (o.hi == r) {
-        h6 = (float)(g - b) / d;
-        if (h6 < 0.f) h6 = h6 + 6.f;
-    } else if (o.hi == g) {
-        h6 = (float)(b - r) / d + 2.f;
-    } else {
-        h6 = (float)(r - g) / d + 4.f;
-    }
+    const bool rs = o.hi == r, gs = !rs && o.hi == g;
+    const int num = rs ? g - b : (gs ? b - r : r - g);
+    const float d = o.hi > o.lo ? (float)(o.hi - o.lo) : 1.f;
+    const float q = (float)num / d;
+    float h6 = rs ? (q < 0.f ? q + 6.f : q) : (gs ? q + 2.f : q + 4.f);
+    h6 = o.hi > o.lo ? h6 : 0.f;
     float h = h6 / 6.f;
-    if (h >= 1.f) h = h - 1.f;
+    h = h >= 1.f ? h - 1.f : h;
     o.h = h + 0.f;        // no negative zero in the sort key
     return o;
 }
@@ -128,29 +127,61 @@ __global__ void k_hue_density(const int* __restrict__ counts, int n, long long N
     if (k < n) dens[k] = (float)((double)counts[k] * ((double)n / (double)N));
 }
 
+// Exclusive prefix sums of two integer arrays of n <= kMaxBins entries held
+// kBinsPerThread per thread (Hillis-Steele over the per-thread totals).
+constexpr int kBinsPerThread = kMaxBins / kPlanThreads;
+
+__device__ __forceinline__ void block_scan2(int& x, int& y, int* sx, int* sy) {
+    const int t = threadIdx.x;
+    sx[t] = x;
+    sy[t] = y;
+    __syncthreads();
+    for (int off = 1; off < kPlanThreads; off <<= 1) {
+        const int ax = t >= off ? sx[t - off] : 0, ay = t >= off ? sy[t - off] : 0;
+        __syncthreads();
+        sx[t] += ax;
+        sy[t] += ay;
+        __syncthreads();
+    }
+    x = t ? sx[t - 1] : 0;              // exclusive
+    y = t ? sy[t - 1] : 0;
+    __syncthreads();
+}
+
 // One block: target counts by largest remainder, the inclusive cumulative
 // target counts, and the shift (lower median of the edge differences).
+// The remainder ranks take bins strided over the block (t + 1024 i), the
+// prefix sums blocked (kBinsPerThread t + i).  The FP64 mass is summed bin by
+// bin in index order (wave 0, every lane the same chain); the integer sums
+// and prefix sums are exact in any order.
 __global__ void __launch_bounds__(kPlanThreads) k_hue_plan(const float* __restrict__ target,
                                                            const int* __restrict__ cs, int n,
                                                            long long N, int* ct_out,
                                                            int* cum_out, long long* shift) {
     __shared__ double rem[kMaxBins];
     __shared__ int ct[kMaxBins];
-    int* D = reinterpret_cast<int*>(rem);   // edge differences, once rem is consumed
+    __shared__ int sx[kPlanThreads], sy[kPlanThreads];
     __shared__ double S_sh;
-    __shared__ long long left_sh;
+    __shared__ unsigned long long fl_sh;
+    int* D = reinterpret_cast<int*>(rem);   // edge differences, once rem is consumed
     const int t = threadIdx.x;
-    if (t == 0) {                       // the density's mass, bin by bin in order
+    if (t < 64) {
         double S = 0.0;
-        for (int k = 0; k < n; ++k) {
-            const float v = target[k];
-            if (isfinite(v) && v > 0.f) S += (double)v;
+        for (int base = 0; base < n; base += 64) {
+            const float v = base + t < n ? target[base + t] : 0.f;
+            const float u = (isfinite(v) && v > 0.f) ? v : 0.f;
+            const int m = min(64, n - base);
+            for (int j = 0; j < m; ++j) S += (double)__shfl(u, j);
         }
-        S_sh = S;
+        if (t == 0) {
+            S_sh = S;
+            fl_sh = 0;
+        }
     }
     __syncthreads();
     const double S = S_sh;
     const bool keep = !(S > 0.0);
+    int fsum = 0;
     for (int k = t; k < n; k += blockDim.x) {
         if (keep) {
             ct[k] = cs[k];
@@ -163,24 +194,23 @@ __global__ void __launch_bounds__(kPlanThreads) k_hue_plan(const float* __restri
             ct[k] = (int)c;
             rem[k] = x - c;
         }
+        fsum += ct[k];
     }
+    atomicAdd(&fl_sh, (unsigned long long)fsum);
     __syncthreads();
-    if (t == 0) {
-        long long sum = 0;
-        for (int k = 0; k < n; ++k) sum += ct[k];
-        left_sh = keep ? 0 : N - sum;
-    }
-    __syncthreads();
-    const long long left = left_sh;
-    // the `left` largest remainders (ties: lower bin) get one more pixel
-    int add[kMaxBins / kPlanThreads];
+    const long long left = keep ? 0 : N - (long long)fl_sh;
+    // the `left` largest remainders (ties: lower bin) get one more pixel;
+    // bins strided over the block, the rank loop unrolled so that its LDS
+    // loads overlap
+    int add[kBinsPerThread];
 #pragma unroll
-    for (int q = 0; q < kMaxBins / kPlanThreads; ++q) {
+    for (int q = 0; q < kBinsPerThread; ++q) {
         const int k = t + q * kPlanThreads;
         add[q] = 0;
         if (k < n && left > 0) {
             const double rk = rem[k];
             int rank = 0;
+#pragma unroll 8
             for (int j = 0; j < n; ++j) {
                 const double rj = rem[j];
                 rank += (rj > rk || (rj == rk && j < k)) ? 1 : 0;
@@ -188,21 +218,33 @@ __global__ void __launch_bounds__(kPlanThreads) k_hue_plan(const float* __restri
             add[q] = rank < left ? 1 : 0;
         }
     }
-    __syncthreads();
+    __syncthreads();                    // every read of rem is done
 #pragma unroll
-    for (int q = 0; q < kMaxBins / kPlanThreads; ++q) {
+    for (int q = 0; q < kBinsPerThread; ++q) {
         const int k = t + q * kPlanThreads;
         if (k < n) ct[k] += add[q];
     }
     __syncthreads();
-    if (t == 0) {                       // edge differences and cumulative counts
-        long long es = 0, et = 0;
-        for (int k = 0; k < n; ++k) {
-            D[k] = (int)(es - et);
-            es += cs[k];
-            et += ct[k];
-            cum_out[k] = (int)et;
-            ct_out[k] = ct[k];
+    int cst[kBinsPerThread], ctt[kBinsPerThread];
+    int xs = 0, xt = 0;
+#pragma unroll
+    for (int q = 0; q < kBinsPerThread; ++q) {
+        const int k = kBinsPerThread * t + q;
+        cst[q] = k < n ? cs[k] : 0;
+        ctt[q] = k < n ? ct[k] : 0;
+        xs += cst[q];
+        xt += ctt[q];
+    }
+    block_scan2(xs, xt, sx, sy);
+#pragma unroll
+    for (int q = 0; q < kBinsPerThread; ++q) {
+        const int k = kBinsPerThread * t + q;
+        if (k < n) {
+            D[k] = xs - xt;             // before bin k
+            xs += cst[q];
+            xt += ctt[q];
+            cum_out[k] = xt;
+            ct_out[k] = ctt[q];
         }
     }
     __syncthreads();
@@ -210,6 +252,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_hue_plan(const float* __restri
     for (int e = t; e < n; e += blockDim.x) {
         const int de = D[e];
         int rank = 0;
+#pragma unroll 8
         for (int j = 0; j < n; ++j) {
             const int dj = D[j];
             rank += (dj < de || (dj == de && j < e)) ? 1 : 0;
@@ -218,39 +261,71 @@ __global__ void __launch_bounds__(kPlanThreads) k_hue_plan(const float* __restri
     }
 }
 
-// One frame: each pixel in raster order takes the target bin holding
-// position (rank - s) mod N of the cumulative target counts.
+// One pixel of a frame: the target bin of position (rank - s) mod N, the hue
+// moved by whole bins, RGB rebuilt; returns the output bin.
+__device__ __forceinline__ int render_px(const unsigned char* c, unsigned rk, long long s,
+                                         long long N, const int* cl, int n, int p2,
+                                         unsigned char* o) {
+#pragma clang fp contract(off)
+    long long q = (long long)rk - s;    // rank in [0, N), shift in (-N, N)
+    if (q < 0) q += N;
+    else if (q >= N) q -= N;
+    // first bin whose cumulative count exceeds q = the number of cumulative
+    // counts <= q (nondecreasing): fixed-trip search, p2 = 2^floor(log2 n)
+    int lo = 0;
+    for (int step = p2; step > 0; step >>= 1)
+        lo = (lo + step <= n && (long long)cl[lo + step - 1] <= q) ? lo + step : lo;
+    lo = min(lo, n - 1);
+    const Hue u = hue_of(c[0], c[1], c[2]);
+    const int ksrc = bin_of(u.h, n);
+    float h2 = u.h + (float)(lo - ksrc) / (float)n;
+    if (h2 >= 1.f) h2 = h2 - 1.f;
+    if (h2 < 0.f) h2 = h2 + 1.f;
+    if (h2 >= 1.f) h2 = h2 - 1.f;
+    rgb_of(h2, u.hi, u.lo, o);
+    return lo;
+}
+
+// One frame over the pixels in raster order, four pixels per thread in a
+// grid-stride loop.  VEC: the image pointers are 4-byte aligned (and bins_out
+// 16-byte aligned), so a group of four moves as 12 bytes of RGB, 16 bytes of
+// rank and 16 bytes of bins; the tail group and unaligned images go pixel by
+// pixel.
+template <bool VEC>
 __global__ void __launch_bounds__(kThreads) k_hue_render(const unsigned char* __restrict__ rgb,
                                                          const unsigned* __restrict__ rank,
                                                          const int* __restrict__ cum,
                                                          const long long* __restrict__ shift,
                                                          int n, long long N, unsigned char* out,
                                                          int* bins_out) {
-#pragma clang fp contract(off)
     __shared__ int cl[kMaxBins];
     for (int k = threadIdx.x; k < n; k += blockDim.x) cl[k] = cum[k];
     __syncthreads();
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N) return;
-    long long q = (long long)rank[p] - *shift;     // rank in [0, N), shift in (-N, N)
-    if (q < 0) q += N;
-    else if (q >= N) q -= N;
-    int lo = 0, hi = n - 1;            // first bin whose cumulative count exceeds q
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((long long)cl[mid] > q) hi = mid;
-        else lo = mid + 1;
+    const long long s = *shift;
+    const int p2 = 1 << (31 - __clz(n));
+    const long long groups = (N + 3) / 4;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x; gi < groups;
+         gi += stride) {
+        const long long p0 = 4 * gi;
+        if (VEC && p0 + 4 <= N) {
+            union { uint3 v; unsigned char b[12]; } in, o;
+            union { uint4 v; unsigned u[4]; } rk;
+            in.v = *reinterpret_cast<const uint3*>(rgb + 3 * p0);
+            rk.v = *reinterpret_cast<const uint4*>(rank + p0);
+            int kb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                kb[i] = render_px(in.b + 3 * i, rk.u[i], s, N, cl, n, p2, o.b + 3 * i);
+            *reinterpret_cast<uint3*>(out + 3 * p0) = o.v;
+            if (bins_out) *reinterpret_cast<int4*>(bins_out + p0) = make_int4(kb[0], kb[1], kb[2], kb[3]);
+        } else {
+            for (long long p = p0; p < p0 + 4 && p < N; ++p) {
+                const int k = render_px(rgb + 3 * p, rank[p], s, N, cl, n, p2, out + 3 * p);
+                if (bins_out) bins_out[p] = k;
+            }
+        }
     }
-    const int kout = lo;
-    const unsigned char* c = rgb + 3 * p;
-    const Hue u = hue_of(c[0], c[1], c[2]);
-    const int ksrc = bin_of(u.h, n);
-    float h2 = u.h + (float)(kout - ksrc) / (float)n;
-    if (h2 >= 1.f) h2 = h2 - 1.f;
-    if (h2 < 0.f) h2 = h2 + 1.f;
-    if (h2 >= 1.f) h2 = h2 - 1.f;
-    rgb_of(h2, u.hi, u.lo, out + 3 * p);
-    if (bins_out) bins_out[p] = kout;
 }
 
 unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -349,16 +424,36 @@ int ot_hue_histogram(ot_hue* h, int* counts, float* density) {
     return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
 }
 
-int ot_hue_render(ot_hue* h, const float* target, unsigned char* rgb_out, int* bins_out) {
-    if (!h || !target || !rgb_out) return OT_ERR_PARAM;
+int ot_hue_plan(ot_hue* h, const float* target) {
+    if (!h || !target) return OT_ERR_PARAM;
     if (!h->have_source) return OT_ERR_STATE;
     hipLaunchKernelGGL(k_hue_plan, dim3(1), dim3(kPlanThreads), 0, h->st, target, h->counts, h->n,
                        h->N, h->ct, h->cum, h->shift);
-    hipLaunchKernelGGL(k_hue_render, dim3(blocks_for(h->N, kThreads)), dim3(kThreads), 0, h->st,
-                       h->src, h->rank, h->cum, h->shift, h->n, h->N, rgb_out, bins_out);
     if (hipGetLastError() != hipSuccess) return OT_ERR_HIP;
     h->have_frame = true;
     return OT_OK;
+}
+
+int ot_hue_apply(ot_hue* h, unsigned char* rgb_out, int* bins_out) {
+    if (!h || !rgb_out) return OT_ERR_PARAM;
+    if (!h->have_frame) return OT_ERR_STATE;
+    const unsigned gb = blocks_for((h->N + 3) / 4, kThreads);
+    const dim3 grid(gb < kRenderBlocks ? gb : kRenderBlocks);
+    const bool vec = ((uintptr_t)h->src % 4 == 0) && ((uintptr_t)rgb_out % 4 == 0) &&
+                     ((uintptr_t)bins_out % 16 == 0);
+    if (vec)
+        hipLaunchKernelGGL(k_hue_render<true>, grid, dim3(kThreads), 0, h->st, h->src, h->rank,
+                           h->cum, h->shift, h->n, h->N, rgb_out, bins_out);
+    else
+        hipLaunchKernelGGL(k_hue_render<false>, grid, dim3(kThreads), 0, h->st, h->src, h->rank,
+                           h->cum, h->shift, h->n, h->N, rgb_out, bins_out);
+    return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
+}
+
+int ot_hue_render(ot_hue* h, const float* target, unsigned char* rgb_out, int* bins_out) {
+    if (!h || !target || !rgb_out) return OT_ERR_PARAM;
+    const int st = ot_hue_plan(h, target);
+    return st != OT_OK ? st : ot_hue_apply(h, rgb_out, bins_out);
 }
 
 int ot_hue_plan_info(ot_hue* h, int* counts, long long* shift) {

@@ -14,7 +14,7 @@ from . import otdyn
 from .otdyn import OtDynError, _ptr
 
 EXPORTS = ["ot_hue_create", "ot_hue_destroy", "ot_hue_set_source", "ot_hue_histogram",
-           "ot_hue_render", "ot_hue_plan_info"]
+           "ot_hue_render", "ot_hue_plan", "ot_hue_apply", "ot_hue_plan_info"]
 
 _done = False
 
@@ -32,6 +32,8 @@ def lib() -> ctypes.CDLL:
     L.ot_hue_set_source.argtypes = [P, P]
     L.ot_hue_histogram.argtypes = [P, P, P]
     L.ot_hue_render.argtypes = [P, P, P, P]
+    L.ot_hue_plan.argtypes = [P, P]
+    L.ot_hue_apply.argtypes = [P, P, P]
     L.ot_hue_plan_info.argtypes = [P, P, POINTER(LL)]
     for name in EXPORTS:
         if name != "ot_hue_destroy":
@@ -66,6 +68,14 @@ def ot_hue_histogram(h: int, counts=None, density=None) -> int:
 
 def ot_hue_render(h: int, target, rgb_out, bins_out=None) -> int:
     return _check(lib().ot_hue_render(h, _ptr(target), _ptr(rgb_out), _ptr(bins_out)))
+
+
+def ot_hue_plan(h: int, target) -> int:
+    return _check(lib().ot_hue_plan(h, _ptr(target)))
+
+
+def ot_hue_apply(h: int, rgb_out, bins_out=None) -> int:
+    return _check(lib().ot_hue_apply(h, _ptr(rgb_out), _ptr(bins_out)))
 
 
 def ot_hue_plan_info(h: int, counts=None):

@@ -116,3 +116,5 @@ def test_hue_renderer_rejects_bad_sizes(L):
     assert lib.ot_hue_render(None, None, None, None) == L.OT_ERR_PARAM
     assert lib.ot_hue_histogram(None, None, None) == L.OT_ERR_PARAM
     assert lib.ot_hue_plan_info(None, None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_plan(None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_apply(None, None, None) == L.OT_ERR_PARAM

@@ -92,6 +92,57 @@ def test_identity_frame_is_the_source(othue):
     r.close()
 
 
+def test_plan_then_apply_equals_render(othue):
+    """The frame split in its two calls: one plan serves several applies, and
+    apply before a plan for the current source is refused."""
+    import torch
+    _say("hue plan/apply")
+    n = 180
+    img = inputs.hue_image(41, 70, 90)
+    r = _renderer(othue, img, n)
+    N = 70 * 90
+    tg = torch.from_numpy(inputs.von_mises_hist(9, n)).cuda()
+    ref_out = r.render(tg)
+    othue.ot_hue_plan(r.h, tg)
+    a = torch.empty(N, 3, dtype=torch.uint8, device="cuda")
+    b = torch.empty(N, 3, dtype=torch.uint8, device="cuda")
+    othue.ot_hue_apply(r.h, a)
+    othue.ot_hue_apply(r.h, b)
+    assert torch.equal(a, ref_out) and torch.equal(b, ref_out)
+    r.set_source(torch.from_numpy(img.reshape(-1).copy()).cuda())
+    with pytest.raises(othue.OtDynError) as e:
+        othue.ot_hue_apply(r.h, a)
+    assert e.value.status == -7
+    r.close()
+
+
+def test_unaligned_images_take_the_pixel_path(othue):
+    """Source and frame at odd byte offsets and bins at a 4-byte offset: the
+    pixel-by-pixel form of the frame kernel, same results."""
+    import torch
+    _say("hue unaligned")
+    n, H, W = 180, 61, 47
+    N = H * W
+    img = inputs.hue_image(51, H, W)
+    big = torch.zeros(3 * N + 16, dtype=torch.uint8, device="cuda")
+    big[1:1 + 3 * N] = torch.from_numpy(img.reshape(-1).copy()).cuda()
+    r = othue.HueRenderer(N, n)
+    r.set_source(big[1:1 + 3 * N])
+    assert r.src.data_ptr() % 4 == 1
+    src = ref.Source(img, n)
+    tg = inputs.von_mises_hist(13, n)
+    rgb_ref, k_ref, _, _ = src.render(tg)
+    ob = torch.zeros(3 * N + 16, dtype=torch.uint8, device="cuda")
+    bb = torch.zeros(N + 8, dtype=torch.int32, device="cuda")
+    othue.ot_hue_render(r.h, torch.from_numpy(tg).cuda(), ob[3:3 + 3 * N], bb[1:1 + N])
+    torch.cuda.synchronize()
+    assert np.array_equal(ob[3:3 + 3 * N].cpu().numpy().reshape(-1, 3), rgb_ref)
+    assert np.array_equal(bb[1:1 + N].cpu().numpy(), k_ref)
+    assert int(ob[:3].sum()) == 0 and int(ob[3 + 3 * N:].sum()) == 0
+    assert int(bb[0]) == 0 and int(bb[1 + N:].sum()) == 0
+    r.close()
+
+
 def test_new_source_on_one_renderer(othue):
     import torch
     _say("hue two sources")
