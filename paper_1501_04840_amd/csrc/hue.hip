@@ -152,8 +152,8 @@ __device__ __forceinline__ void block_scan2(int& x, int& y, int* sx, int* sy) {
 // target counts, and the shift (lower median of the edge differences).
 // The remainder ranks take bins strided over the block (t + 1024 i), the
 // prefix sums blocked (kBinsPerThread t + i).  The FP64 mass is summed bin by
-// bin in index order (wave 0, every lane the same chain); the integer sums
-// and prefix sums are exact in any order.
+// bin in index order (one thread, from LDS); the integer sums and prefix sums
+// are exact in any order.
 __global__ void __launch_bounds__(kPlanThreads) k_hue_plan(const float* __restrict__ target,
                                                            const int* __restrict__ cs, int n,
                                                            long long N, int* ct_out,
@@ -165,18 +165,18 @@ __global__ void __launch_bounds__(kPlanThreads) k_hue_plan(const float* __restri
     __shared__ unsigned long long fl_sh;
     int* D = reinterpret_cast<int*>(rem);   // edge differences, once rem is consumed
     const int t = threadIdx.x;
-    if (t < 64) {
+    // the target, negative and non-finite entries as zero, staged in rem
+    for (int k = t; k < n; k += blockDim.x) {
+        const float v = target[k];
+        rem[k] = (isfinite(v) && v > 0.f) ? (double)v : 0.0;
+    }
+    if (t == 0) fl_sh = 0;
+    __syncthreads();
+    if (t == 0) {                       // the mass, bin by bin in index order
         double S = 0.0;
-        for (int base = 0; base < n; base += 64) {
-            const float v = base + t < n ? target[base + t] : 0.f;
-            const float u = (isfinite(v) && v > 0.f) ? v : 0.f;
-            const int m = min(64, n - base);
-            for (int j = 0; j < m; ++j) S += (double)__shfl(u, j);
-        }
-        if (t == 0) {
-            S_sh = S;
-            fl_sh = 0;
-        }
+#pragma unroll 8
+        for (int k = 0; k < n; ++k) S += rem[k];
+        S_sh = S;
     }
     __syncthreads();
     const double S = S_sh;
@@ -187,9 +187,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_hue_plan(const float* __restri
             ct[k] = cs[k];
             rem[k] = 0.0;
         } else {
-            const float v = target[k];
-            const double hv = (isfinite(v) && v > 0.f) ? (double)v : 0.0;
-            const double x = ((double)N * hv) / S;
+            const double x = ((double)N * rem[k]) / S;
             const double c = floor(x);
             ct[k] = (int)c;
             rem[k] = x - c;
@@ -261,29 +259,43 @@ __global__ void __launch_bounds__(kPlanThreads) k_hue_plan(const float* __restri
     }
 }
 
-// One pixel of a frame: the target bin of position (rank - s) mod N, the hue
-// moved by whole bins, RGB rebuilt; returns the output bin.
-__device__ __forceinline__ int render_px(const unsigned char* c, unsigned rk, long long s,
-                                         long long N, const int* cl, int n, int p2,
+// Output bin of a pixel of rank rk: the first bin whose cumulative count
+// exceeds q = (rk - s) mod N, i.e. the number of cumulative counts <= q
+// (nondecreasing); fixed-trip search over p2 = 2^floor(log2 n), W pixels in
+// lockstep so that their LDS loads overlap.
+template <int W>
+__device__ __forceinline__ void out_bins(const unsigned* rk, long long s, long long N,
+                                         const int* cl, int n, int p2, int* lo) {
+    long long q[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        q[i] = (long long)rk[i] - s;    // rank in [0, N), shift in (-N, N)
+        q[i] = q[i] < 0 ? q[i] + N : (q[i] >= N ? q[i] - N : q[i]);
+        lo[i] = 0;
+    }
+    for (int step = p2; step > 0; step >>= 1) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const int c = lo[i] + step;
+            const int ci = min(c, n) - 1;
+            lo[i] = (c <= n && (long long)cl[ci] <= q[i]) ? c : lo[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < W; ++i) lo[i] = min(lo[i], n - 1);
+}
+
+// One pixel of a frame: the hue moved to the output bin, RGB rebuilt.
+__device__ __forceinline__ void paint_px(const unsigned char* c, int kout, int n,
                                          unsigned char* o) {
 #pragma clang fp contract(off)
-    long long q = (long long)rk - s;    // rank in [0, N), shift in (-N, N)
-    if (q < 0) q += N;
-    else if (q >= N) q -= N;
-    // first bin whose cumulative count exceeds q = the number of cumulative
-    // counts <= q (nondecreasing): fixed-trip search, p2 = 2^floor(log2 n)
-    int lo = 0;
-    for (int step = p2; step > 0; step >>= 1)
-        lo = (lo + step <= n && (long long)cl[lo + step - 1] <= q) ? lo + step : lo;
-    lo = min(lo, n - 1);
     const Hue u = hue_of(c[0], c[1], c[2]);
     const int ksrc = bin_of(u.h, n);
-    float h2 = u.h + (float)(lo - ksrc) / (float)n;
+    float h2 = u.h + (float)(kout - ksrc) / (float)n;
     if (h2 >= 1.f) h2 = h2 - 1.f;
     if (h2 < 0.f) h2 = h2 + 1.f;
     if (h2 >= 1.f) h2 = h2 - 1.f;
     rgb_of(h2, u.hi, u.lo, o);
-    return lo;
 }
 
 // One frame over the pixels in raster order, four pixels per thread in a
@@ -314,14 +326,17 @@ __global__ void __launch_bounds__(kThreads) k_hue_render(const unsigned char* __
             in.v = *reinterpret_cast<const uint3*>(rgb + 3 * p0);
             rk.v = *reinterpret_cast<const uint4*>(rank + p0);
             int kb[4];
+            out_bins<4>(rk.u, s, N, cl, n, p2, kb);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                kb[i] = render_px(in.b + 3 * i, rk.u[i], s, N, cl, n, p2, o.b + 3 * i);
+            for (int i = 0; i < 4; ++i) paint_px(in.b + 3 * i, kb[i], n, o.b + 3 * i);
             *reinterpret_cast<uint3*>(out + 3 * p0) = o.v;
             if (bins_out) *reinterpret_cast<int4*>(bins_out + p0) = make_int4(kb[0], kb[1], kb[2], kb[3]);
         } else {
             for (long long p = p0; p < p0 + 4 && p < N; ++p) {
-                const int k = render_px(rgb + 3 * p, rank[p], s, N, cl, n, p2, out + 3 * p);
+                const unsigned r1 = rank[p];
+                int k;
+                out_bins<1>(&r1, s, N, cl, n, p2, &k);
+                paint_px(rgb + 3 * p, k, n, out + 3 * p);
                 if (bins_out) bins_out[p] = k;
             }
         }
