@@ -259,10 +259,11 @@ def warm_start(args):
 
 def hue_render(args):
     """Frames/s of the rendering stage of Sec. 5: an 8-bit RGB image whose hue
-    histogram is specified, frame by frame, to the densities of a transport
-    path (exact circular specification, saturation and value kept).  The
-    source's hues, order and ranks are prepared once (timed apart); a frame is
-    one plan (target counts and shift) and one pass over the pixels."""
+    histogram is specified to the densities of a transport path, all of its
+    time levels per call (exact circular specification, saturation and value
+    kept).  The source's hues, order and ranks are prepared once (timed
+    apart); a call is one plan kernel (target counts and shift, a block per
+    frame) and one pass over the pixels of every frame."""
     import numpy as np
     import torch
     from paper_1501_04840_amd import othue
@@ -271,13 +272,14 @@ def hue_render(args):
 
     H, W = args.hue_image
     n = args.hue_bins
+    F = args.hue_frames
     N = H * W
     img = inputs.hue_image(501, H, W, sigma=24.0)
-    dens = np.stack([inputs.von_mises_hist(600 + i, n) for i in range(33)])
+    dens = np.stack([inputs.von_mises_hist(600 + i, n) for i in range(F)]).astype(np.float32)
     r = othue.HueRenderer(N, n)
     src = torch.from_numpy(img.reshape(-1).copy()).cuda()
     tg = torch.from_numpy(dens).cuda()
-    out = torch.empty(N, 3, dtype=torch.uint8, device="cuda")
+    out = torch.empty(F, N, 3, dtype=torch.uint8, device="cuda")
     r.set_source(src)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -285,14 +287,14 @@ def hue_render(args):
     torch.cuda.synchronize()
     source_s = time.perf_counter() - t0
     for i in range(args.warmup):
-        othue.ot_hue_render(r.h, tg[i % 33], out)
+        othue.ot_hue_render(r.h, tg, F, out)
     torch.cuda.synchronize()
     K = args.steps
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(K)]
     t0 = time.perf_counter()
     for k in range(K):
-        othue.ot_hue_plan(r.h, tg[k % 33])
+        othue.ot_hue_plan(r.h, tg, F)
         ev[k][0].record()
         othue.ot_hue_apply(r.h, out)
         ev[k][1].record()
@@ -300,16 +302,17 @@ def hue_render(args):
     dt = time.perf_counter() - t0
     apply_us = 1e3 * sum(a.elapsed_time(b) for a, b in ev) / K
     r.close()
-    nbytes = 10.0 * N                 # read RGB (3) + rank (4), write RGB (3)
+    nbytes = 10.0 * N * F             # read RGB (3) + rank (4), write RGB (3), per frame
     achieved = nbytes / (apply_us * 1e-6) / 1e9
     out_json = {
-        "metric": f"frames/s, hue rendering {W}x{H}, {n} bins",
-        "value": K / dt, "unit": "frames/s",
+        "metric": f"frames/s, hue rendering {W}x{H}, {n} bins, {F} frames per call",
+        "value": K * F / dt, "unit": "frames/s",
         "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": 1e3 * dt / K,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8 image, f32 hue", "data": "synthetic",
         "config": {"workload": f"hue_render_{W}x{H}_{n}", "pixels": N, "bins": n,
-                   "targets": "33 von Mises mixtures, cycled", "source_prep_s": source_s},
+                   "frames_per_step": F, "targets": "von Mises mixtures",
+                   "source_prep_s": source_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_hue_render", "algorithmic_bytes_per_launch": nbytes,
@@ -320,7 +323,7 @@ def hue_render(args):
         src_ref = ref_hue.Source(img, n)
         t0 = time.perf_counter()
         for i in range(sample):
-            src_ref.render(dens[i].astype(np.float32))
+            src_ref.render(dens[i % F])
         cpu_dt = time.perf_counter() - t0
         out_json["cpu_baseline"] = {"value": sample / cpu_dt, "unit": "frames/s", "cores": 1,
                                     "kind": "oracle",
@@ -345,6 +348,8 @@ def main():
     ap.add_argument("--hue-image", type=int, nargs=2, default=[2160, 3840],
                     help="hue_render: image height and width")
     ap.add_argument("--hue-bins", type=int, default=360)
+    ap.add_argument("--hue-frames", type=int, default=33,
+                    help="hue_render: frames per call (time levels of a 32-step path)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=64)

@@ -65,27 +65,34 @@ int ot_hue_set_source(ot_hue* h, const unsigned char* rgb);
  * ot_hue_set_source. */
 int ot_hue_histogram(ot_hue* h, int* counts, float* density);
 
-/* One frame: the source image with its hue histogram specified to the
- * density `target` (device float [nbins], any scale).  rgb_out: device,
- * npix x 3 bytes (may not alias the source); bins_out: device int32 [npix],
- * each pixel's output bin, or NULL.  Asynchronous; the source image must stay
- * unchanged until the frame is done.  OT_ERR_STATE before ot_hue_set_source,
- * OT_ERR_PARAM for a null target or rgb_out, OT_ERR_HIP if a launch fails. */
-int ot_hue_render(ot_hue* h, const float* target, unsigned char* rgb_out, int* bins_out);
+/* Frames: the source image with its hue histogram specified to each of
+ * `frames` densities (1 <= frames <= 65535; e.g. the time levels of f along a
+ * transport path).  targets: device float [frames][nbins], any scale per
+ * frame.  rgb_out: device, frames x npix x 3 bytes, frame after frame (may
+ * not alias the source); bins_out: device int32 [frames][npix], each pixel's
+ * output bin, or NULL.  Asynchronous; the source image must stay unchanged
+ * until the frames are done.  The first call with more frames than before
+ * grows the per-frame plan arrays (synchronises the stream, allocates).
+ * OT_ERR_STATE before ot_hue_set_source, OT_ERR_PARAM for a null targets or
+ * rgb_out or frames out of range, OT_ERR_HIP if a launch or an allocation
+ * fails. */
+int ot_hue_render(ot_hue* h, const float* targets, int frames, unsigned char* rgb_out,
+                  int* bins_out);
 
 /* The two halves of ot_hue_render, for callers that time or reuse them:
- * ot_hue_plan computes the target counts and the shift for `target` (one
- * single-block kernel); ot_hue_apply writes the frame of the last plan (one
- * pass over the pixels in raster order: 10 bytes of HBM traffic per pixel,
- * 14 with bins_out).  Same arguments and status codes as ot_hue_render;
- * ot_hue_apply before any plan for the current source is OT_ERR_STATE. */
-int ot_hue_plan(ot_hue* h, const float* target);
+ * ot_hue_plan computes the target counts and the shift of every frame (one
+ * kernel, one block per frame); ot_hue_apply writes the frames of the last
+ * plan (one pass over the pixels in raster order per frame: 10 bytes of HBM
+ * traffic per pixel, 14 with bins_out).  Same arguments and status codes as
+ * ot_hue_render; ot_hue_apply before a plan for the current source is
+ * OT_ERR_STATE. */
+int ot_hue_plan(ot_hue* h, const float* targets, int frames);
 int ot_hue_apply(ot_hue* h, unsigned char* rgb_out, int* bins_out);
 
-/* The last frame's target counts (host int32 [nbins], or NULL) and shift s
- * (host, or NULL).  Synchronises the stream.  OT_ERR_STATE before the first
- * plan. */
-int ot_hue_plan_info(ot_hue* h, int* counts, long long* shift);
+/* Frame `frame` of the last plan: its target counts (host int32 [nbins], or
+ * NULL) and shift s (host, or NULL).  Synchronises the stream.  OT_ERR_STATE
+ * before a plan, OT_ERR_PARAM for a frame out of range. */
+int ot_hue_plan_info(ot_hue* h, int frame, int* counts, long long* shift);
 
 #ifdef __cplusplus
 }

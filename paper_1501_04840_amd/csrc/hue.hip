@@ -5,8 +5,9 @@
 //
 // Device layout: keys/order/rank are u32 [N]; counts, target counts and the
 // inclusive cumulative target counts are int32 [n]; the shift is one int64.
-// Per frame: one single-block planning kernel (target counts, median shift)
-// and one streaming kernel over the pixels in raster order (reads 3 bytes of
+// Per call of F frames: one planning kernel of F blocks (target counts,
+// median shift per frame) and one streaming kernel over the pixels in raster
+// order, F frames along grid y (reads 3 bytes of
 // RGB and the 4-byte rank, writes 3 bytes and optionally the 4-byte bin),
 // four pixels per thread.
 #include <hip/hip_runtime.h>
@@ -24,7 +25,8 @@ constexpr long long kMaxPix = 1LL << 30;
 constexpr int kThreads = 256;
 constexpr int kPlanThreads = 1024;
 constexpr unsigned kKeyBlocks = 2048;     // 8 blocks per compute unit
-constexpr unsigned kRenderBlocks = 4096;  // 16 blocks per compute unit
+constexpr unsigned kRenderBlocks = 4096;  // 16 blocks per compute unit, per frame
+constexpr int kMaxFrames = 65535;         // frames per call (grid y)
 
 // Every FP32 step below is one rounded operation in the written order: no
 // contraction of a product and a sum into a fused multiply-add.
@@ -158,6 +160,13 @@ __global__ void __launch_bounds__(kPlanThreads) k_hue_plan(const float* __restri
                                                            const int* __restrict__ cs, int n,
                                                            long long N, int* ct_out,
                                                            int* cum_out, long long* shift) {
+    {   // block f plans frame f
+        const long long f = blockIdx.x;
+        target += f * n;
+        ct_out += f * n;
+        cum_out += f * n;
+        shift += f;
+    }
     __shared__ double rem[kMaxBins];
     __shared__ int ct[kMaxBins];
     __shared__ int sx[kPlanThreads], sy[kPlanThreads];
@@ -310,6 +319,13 @@ __global__ void __launch_bounds__(kThreads) k_hue_render(const unsigned char* __
                                                          const long long* __restrict__ shift,
                                                          int n, long long N, unsigned char* out,
                                                          int* bins_out) {
+    {   // blockIdx.y: the frame
+        const long long f = blockIdx.y;
+        cum += f * n;
+        shift += f;
+        out += f * 3 * N;
+        if (bins_out) bins_out += f * N;
+    }
     __shared__ int cl[kMaxBins];
     for (int k = threadIdx.x; k < n; k += blockDim.x) cl[k] = cum[k];
     __syncthreads();
@@ -357,7 +373,9 @@ struct ot_hue {
     void* temp = nullptr;
     size_t temp_bytes = 0;
     const unsigned char* src = nullptr;
-    bool have_source = false, have_frame = false;
+    bool have_source = false;
+    int cap = 1;                        // frames the plan arrays hold
+    int planned = 0;                    // frames of the last plan (0: none)
 };
 
 static void hue_free(ot_hue* h) {
@@ -422,7 +440,7 @@ int ot_hue_set_source(ot_hue* h, const unsigned char* rgb) {
     if (hipGetLastError() != hipSuccess) return OT_ERR_HIP;
     h->src = rgb;
     h->have_source = true;
-    h->have_frame = false;
+    h->planned = 0;
     return OT_OK;
 }
 
@@ -439,23 +457,48 @@ int ot_hue_histogram(ot_hue* h, int* counts, float* density) {
     return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
 }
 
-int ot_hue_plan(ot_hue* h, const float* target) {
-    if (!h || !target) return OT_ERR_PARAM;
+static int reserve_frames(ot_hue* h, int frames) {
+    if (frames <= h->cap) return OT_OK;
+    if (hipStreamSynchronize(h->st) != hipSuccess) return OT_ERR_HIP;
+    (void)hipFree(h->ct);
+    (void)hipFree(h->cum);
+    (void)hipFree(h->shift);
+    h->ct = h->cum = nullptr;
+    h->shift = nullptr;
+    h->cap = 0;
+    const size_t m = (size_t)frames * h->n * sizeof(int);
+    if (hipMalloc(&h->ct, m) != hipSuccess || hipMalloc(&h->cum, m) != hipSuccess ||
+        hipMalloc(&h->shift, (size_t)frames * sizeof(long long)) != hipSuccess)
+        return OT_ERR_HIP;
+    h->cap = frames;
+    return OT_OK;
+}
+
+int ot_hue_plan(ot_hue* h, const float* targets, int frames) {
+    if (!h || !targets || frames < 1 || frames > kMaxFrames) return OT_ERR_PARAM;
     if (!h->have_source) return OT_ERR_STATE;
-    hipLaunchKernelGGL(k_hue_plan, dim3(1), dim3(kPlanThreads), 0, h->st, target, h->counts, h->n,
-                       h->N, h->ct, h->cum, h->shift);
+    const int st = reserve_frames(h, frames);
+    if (st != OT_OK) {
+        h->planned = 0;
+        return st;
+    }
+    hipLaunchKernelGGL(k_hue_plan, dim3(frames), dim3(kPlanThreads), 0, h->st, targets, h->counts,
+                       h->n, h->N, h->ct, h->cum, h->shift);
     if (hipGetLastError() != hipSuccess) return OT_ERR_HIP;
-    h->have_frame = true;
+    h->planned = frames;
     return OT_OK;
 }
 
 int ot_hue_apply(ot_hue* h, unsigned char* rgb_out, int* bins_out) {
     if (!h || !rgb_out) return OT_ERR_PARAM;
-    if (!h->have_frame) return OT_ERR_STATE;
+    if (!h->planned) return OT_ERR_STATE;
+    const int F = h->planned;
     const unsigned gb = blocks_for((h->N + 3) / 4, kThreads);
-    const dim3 grid(gb < kRenderBlocks ? gb : kRenderBlocks);
+    const dim3 grid(gb < kRenderBlocks ? gb : kRenderBlocks, (unsigned)F);
+    // every frame's image 4-byte aligned and bins 16-byte aligned
     const bool vec = ((uintptr_t)h->src % 4 == 0) && ((uintptr_t)rgb_out % 4 == 0) &&
-                     ((uintptr_t)bins_out % 16 == 0);
+                     ((uintptr_t)bins_out % 16 == 0) &&
+                     (F == 1 || ((3 * h->N) % 4 == 0 && (!bins_out || h->N % 4 == 0)));
     if (vec)
         hipLaunchKernelGGL(k_hue_render<true>, grid, dim3(kThreads), 0, h->st, h->src, h->rank,
                            h->cum, h->shift, h->n, h->N, rgb_out, bins_out);
@@ -465,20 +508,22 @@ int ot_hue_apply(ot_hue* h, unsigned char* rgb_out, int* bins_out) {
     return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
 }
 
-int ot_hue_render(ot_hue* h, const float* target, unsigned char* rgb_out, int* bins_out) {
-    if (!h || !target || !rgb_out) return OT_ERR_PARAM;
-    const int st = ot_hue_plan(h, target);
+int ot_hue_render(ot_hue* h, const float* targets, int frames, unsigned char* rgb_out,
+                  int* bins_out) {
+    if (!h || !targets || !rgb_out) return OT_ERR_PARAM;
+    const int st = ot_hue_plan(h, targets, frames);
     return st != OT_OK ? st : ot_hue_apply(h, rgb_out, bins_out);
 }
 
-int ot_hue_plan_info(ot_hue* h, int* counts, long long* shift) {
+int ot_hue_plan_info(ot_hue* h, int frame, int* counts, long long* shift) {
     if (!h) return OT_ERR_PARAM;
-    if (!h->have_frame) return OT_ERR_STATE;
-    if (counts && hipMemcpyAsync(counts, h->ct, h->n * sizeof(int), hipMemcpyDeviceToHost,
-                                 h->st) != hipSuccess)
+    if (!h->planned) return OT_ERR_STATE;
+    if (frame < 0 || frame >= h->planned) return OT_ERR_PARAM;
+    if (counts && hipMemcpyAsync(counts, h->ct + (size_t)frame * h->n, h->n * sizeof(int),
+                                 hipMemcpyDeviceToHost, h->st) != hipSuccess)
         return OT_ERR_HIP;
-    if (shift && hipMemcpyAsync(shift, h->shift, sizeof(long long), hipMemcpyDeviceToHost,
-                                h->st) != hipSuccess)
+    if (shift && hipMemcpyAsync(shift, h->shift + frame, sizeof(long long),
+                                hipMemcpyDeviceToHost, h->st) != hipSuccess)
         return OT_ERR_HIP;
     return hipStreamSynchronize(h->st) == hipSuccess ? OT_OK : OT_ERR_HIP;
 }

@@ -31,10 +31,10 @@ def lib() -> ctypes.CDLL:
     L.ot_hue_destroy.restype = None
     L.ot_hue_set_source.argtypes = [P, P]
     L.ot_hue_histogram.argtypes = [P, P, P]
-    L.ot_hue_render.argtypes = [P, P, P, P]
-    L.ot_hue_plan.argtypes = [P, P]
+    L.ot_hue_render.argtypes = [P, P, c_int, P, P]
+    L.ot_hue_plan.argtypes = [P, P, c_int]
     L.ot_hue_apply.argtypes = [P, P, P]
-    L.ot_hue_plan_info.argtypes = [P, P, POINTER(LL)]
+    L.ot_hue_plan_info.argtypes = [P, c_int, P, POINTER(LL)]
     for name in EXPORTS:
         if name != "ot_hue_destroy":
             getattr(L, name).restype = c_int
@@ -66,23 +66,24 @@ def ot_hue_histogram(h: int, counts=None, density=None) -> int:
     return _check(lib().ot_hue_histogram(h, _ptr(counts), _ptr(density)))
 
 
-def ot_hue_render(h: int, target, rgb_out, bins_out=None) -> int:
-    return _check(lib().ot_hue_render(h, _ptr(target), _ptr(rgb_out), _ptr(bins_out)))
+def ot_hue_render(h: int, targets, frames: int, rgb_out, bins_out=None) -> int:
+    return _check(lib().ot_hue_render(h, _ptr(targets), frames, _ptr(rgb_out), _ptr(bins_out)))
 
 
-def ot_hue_plan(h: int, target) -> int:
-    return _check(lib().ot_hue_plan(h, _ptr(target)))
+def ot_hue_plan(h: int, targets, frames: int = 1) -> int:
+    return _check(lib().ot_hue_plan(h, _ptr(targets), frames))
 
 
 def ot_hue_apply(h: int, rgb_out, bins_out=None) -> int:
     return _check(lib().ot_hue_apply(h, _ptr(rgb_out), _ptr(bins_out)))
 
 
-def ot_hue_plan_info(h: int, counts=None):
-    """(status, shift); counts: a host int32 array (numpy) or None."""
+def ot_hue_plan_info(h: int, frame: int = 0, counts=None):
+    """(status, shift) of one frame of the last plan; counts: a host int32
+    array (numpy) or None."""
     s = ctypes.c_longlong()
     cp = counts.ctypes.data if counts is not None else 0
-    st = _check(lib().ot_hue_plan_info(h, cp, byref(s)))
+    st = _check(lib().ot_hue_plan_info(h, frame, cp, byref(s)))
     return st, s.value
 
 
@@ -115,17 +116,24 @@ class HueRenderer:
     def render(self, target, with_bins: bool = False):
         """The frame for a device float density on the bins: uint8 (npix, 3)
         and, with with_bins, each pixel's output bin (int32)."""
+        out, bins = self.render_frames(target.reshape(1, -1), True)
+        return (out[0], bins[0]) if with_bins else out[0]
+
+    def render_frames(self, targets, with_bins: bool = False):
+        """Frames for device float densities [frames, nbins]: uint8
+        (frames, npix, 3) and, with with_bins, the output bins (frames, npix)."""
         t = self.torch
-        assert target.dtype == t.float32 and target.is_cuda and target.numel() == self.nbins
-        out = t.empty(self.npix, 3, dtype=t.uint8, device=self.device)
-        bins = t.empty(self.npix, dtype=t.int32, device=self.device) if with_bins else None
-        ot_hue_render(self.h, target.contiguous(), out, bins)
+        assert targets.dtype == t.float32 and targets.is_cuda and targets.shape[-1] == self.nbins
+        F = targets.shape[0]
+        out = t.empty(F, self.npix, 3, dtype=t.uint8, device=self.device)
+        bins = t.empty(F, self.npix, dtype=t.int32, device=self.device) if with_bins else None
+        ot_hue_render(self.h, targets.contiguous(), F, out, bins)
         return (out, bins) if with_bins else out
 
-    def plan_info(self):
+    def plan_info(self, frame: int = 0):
         import numpy as np
         c = np.empty(self.nbins, dtype=np.int32)
-        _, s = ot_hue_plan_info(self.h, c)
+        _, s = ot_hue_plan_info(self.h, frame, c)
         return c, s
 
     def close(self):

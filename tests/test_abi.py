@@ -113,8 +113,8 @@ def test_hue_renderer_rejects_bad_sizes(L):
     lib = othue.lib()
     assert lib.ot_hue_create(16, 8, None, None) == L.OT_ERR_PARAM
     assert lib.ot_hue_set_source(None, None) == L.OT_ERR_PARAM
-    assert lib.ot_hue_render(None, None, None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_render(None, None, 1, None, None) == L.OT_ERR_PARAM
     assert lib.ot_hue_histogram(None, None, None) == L.OT_ERR_PARAM
-    assert lib.ot_hue_plan_info(None, None, None) == L.OT_ERR_PARAM
-    assert lib.ot_hue_plan(None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_plan_info(None, 0, None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_plan(None, None, 1) == L.OT_ERR_PARAM
     assert lib.ot_hue_apply(None, None, None) == L.OT_ERR_PARAM

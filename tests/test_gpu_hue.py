@@ -134,12 +134,43 @@ def test_unaligned_images_take_the_pixel_path(othue):
     rgb_ref, k_ref, _, _ = src.render(tg)
     ob = torch.zeros(3 * N + 16, dtype=torch.uint8, device="cuda")
     bb = torch.zeros(N + 8, dtype=torch.int32, device="cuda")
-    othue.ot_hue_render(r.h, torch.from_numpy(tg).cuda(), ob[3:3 + 3 * N], bb[1:1 + N])
+    othue.ot_hue_render(r.h, torch.from_numpy(tg).cuda(), 1, ob[3:3 + 3 * N], bb[1:1 + N])
     torch.cuda.synchronize()
     assert np.array_equal(ob[3:3 + 3 * N].cpu().numpy().reshape(-1, 3), rgb_ref)
     assert np.array_equal(bb[1:1 + N].cpu().numpy(), k_ref)
     assert int(ob[:3].sum()) == 0 and int(ob[3 + 3 * N:].sum()) == 0
     assert int(bb[0]) == 0 and int(bb[1 + N:].sum()) == 0
+    r.close()
+
+
+@pytest.mark.parametrize("H,W,n", [(40, 36, 128), (37, 29, 180)])
+def test_frames_in_one_call(othue, H, W, n):
+    """Several frames per call (one plan block per frame, frames along the
+    grid's y): each frame as the oracle gives it, the plan arrays growing and
+    shrinking between calls; with N not a multiple of 4 the frames take the
+    pixel path."""
+    import torch
+    _say(f"hue frames per call {H}x{W} n={n}")
+    img = inputs.hue_image(61 + n, H, W)
+    N = H * W
+    r = _renderer(othue, img, n)
+    src = ref.Source(img, n)
+    rng = np.random.default_rng(n)
+    pool = [np.roll(src.density(), 5 * i) for i in range(3)] + \
+           [inputs.von_mises_hist(70 + i, n) for i in range(3)] + \
+           [src.counts.astype(np.float64), np.zeros(n), rng.uniform(-0.5, 1, n)]
+    for F in (3, 7, 2):
+        tg = np.stack([pool[(F + i) % len(pool)] for i in range(F)]).astype(np.float32)
+        out, bins = r.render_frames(torch.from_numpy(tg).cuda(), with_bins=True)
+        out, bins = out.cpu().numpy(), bins.cpu().numpy()
+        for f in range(F):
+            rgb_ref, k_ref, ct_ref, s_ref = src.render(tg[f])
+            ct, s = r.plan_info(f)
+            assert s == s_ref and np.array_equal(ct, ct_ref)
+            assert np.array_equal(bins[f], k_ref)
+            assert np.array_equal(out[f], rgb_ref)
+    with pytest.raises(othue.OtDynError):
+        othue.ot_hue_plan_info(r.h, 2)                 # the last plan had 2 frames
     r.close()
 
 
