@@ -75,16 +75,16 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prefix: str):
+def measured_traffic(prefix: str, summary: str = "traffic.json", sources=None):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) of the
-    kernels whose names start with `prefix`, from the committed counter
+    kernels whose names start with `prefix`, from a committed counter
     summary, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("sources") != kernel_sources_hash():
+    if t.get("sources") != (sources or kernel_sources_hash()):
         return None
     vals = [v["bytes_per_launch"] for k, v in t.get("kernels", {}).items() if k.startswith(prefix)]
     return sum(vals) / len(vals) if vals else None
@@ -303,6 +303,11 @@ def hue_render(args):
     apply_us = 1e3 * sum(a.elapsed_time(b) for a, b in ev) / K
     r.close()
     nbytes = 10.0 * N * F             # read RGB (3) + rank (4), write RGB (3), per frame
+    from paper_1501_04840_amd import profile_traffic
+    traffic = None
+    if (H, W, n, F) == (2160, 3840, 360, 33):      # the counted workload
+        traffic = measured_traffic("k_hue_render<true>", "traffic_hue.json",
+                                   profile_traffic.hue_sources_hash())
     achieved = nbytes / (apply_us * 1e-6) / 1e9
     out_json = {
         "metric": f"frames/s, hue rendering {W}x{H}, {n} bins, {F} frames per call",
@@ -314,7 +319,7 @@ def hue_render(args):
                    "frames_per_step": F, "targets": "von Mises mixtures",
                    "source_prep_s": source_s},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_hue_render", "algorithmic_bytes_per_launch": nbytes,
                      "avg_launch_us": apply_us, "launches": K},
     }

@@ -5,7 +5,9 @@ Run under rocprofv3 with one counter per pass, for example
     rocprofv3 --pmc FETCH_SIZE -d OUT --output-format csv -- python3 paper_1501_04840_amd/profile_traffic.py
     rocprofv3 --pmc WRITE_SIZE -d OUT --output-format csv -- python3 paper_1501_04840_amd/profile_traffic.py
 
-It runs 70 iterations of the 256 x 256 x 3 x 32 workload (past the refined
+With the argument ``hue`` it runs the hue rendering workload of bench.py
+instead (three calls of 33 frames of a 3840 x 2160 image).  By default it
+runs 70 iterations of the 256 x 256 x 3 x 32 workload (past the refined
 start of the default projection mode, so the steady-state kernels are
 counted) and then a plain
 elementwise copy of known size (256 MiB read, 256 MiB written), whose
@@ -60,6 +62,42 @@ def _sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def run_hue(H: int = 2160, W: int = 3840, n: int = 360, frames: int = 33, calls: int = 3):
+    """The hue rendering workload as bench.py times it (calls of `frames`
+    frames on one 3840 x 2160 image), then the calibration copy."""
+    import numpy as np
+    import torch
+    from paper_1501_04840_amd import othue
+    from synth import inputs
+    img = inputs.hue_image(501, H, W, sigma=24.0)
+    dens = np.stack([inputs.von_mises_hist(600 + i, n) for i in range(frames)]).astype(np.float32)
+    r = othue.HueRenderer(H * W, n)
+    r.set_source(torch.from_numpy(img.reshape(-1).copy()).cuda())
+    tg = torch.from_numpy(dens).cuda()
+    out = torch.empty(frames, H * W, 3, dtype=torch.uint8, device="cuda")
+    for _ in range(calls):
+        othue.ot_hue_render(r.h, tg, frames, out)
+    torch.cuda.synchronize()
+    src = torch.rand(COPY_ELEMS, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    r.close()
+    print("profile_traffic hue: done", flush=True)
+
+
+def hue_sources_hash() -> str:
+    """Hash of the hue image pipeline's kernel source."""
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1501_04840_amd", "csrc", "hue.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _kernel_name(raw: str) -> str:
+    return raw.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+
+
 def _read(dirname: str, counter: str):
     """{kernel name: [value per dispatch]} from a rocprofv3 counter CSV."""
     files = glob.glob(os.path.join(dirname, "**", "*counter_collection.csv"), recursive=True)
@@ -69,12 +107,15 @@ def _read(dirname: str, counter: str):
             for row in csv.DictReader(fh):
                 if row.get("Counter_Name") != counter:
                     continue
-                name = row["Kernel_Name"].split("(")[0].replace("void ", "")
+                name = _kernel_name(row["Kernel_Name"])
                 out.setdefault(name, []).append(float(row["Counter_Value"]))
     return out
 
 
-def summarise(fetch_dir: str, write_dir: str, out_json: str, out_md: str, cmd: str):
+def summarise(fetch_dir: str, write_dir: str, out_json: str, out_md: str, cmd: str,
+              workload: str = "rgb"):
+    """workload "rgb": the solver kernels of the 256 x 256 x 3 x 32 run;
+    "hue": the hue pipeline kernels of the 3840 x 2160 rendering run."""
     fetch = _read(fetch_dir, "FETCH_SIZE")
     write = _read(write_dir, "WRITE_SIZE")
     copy = [k for k in fetch if "AUnaryFunctor" in k or "MulFunctor" in k]
@@ -86,21 +127,25 @@ def summarise(fetch_dir: str, write_dir: str, out_json: str, out_md: str, cmd: s
     f_scale = nbytes / (max(fetch[ck]) * 1024.0)
     w_scale = nbytes / (max(write[ck]) * 1024.0)
     kernels = {}
+    hue = workload == "hue"
     for k in fetch:
-        if not k.startswith("otd::"):
+        if not (k.startswith("k_hue_") if hue else k.startswith("otd::")):
             continue
         fv = sum(fetch[k]) / len(fetch[k]) * 1024.0 * f_scale
         wv = sum(write.get(k, [0.0])) / max(1, len(write.get(k, []))) * 1024.0 * w_scale
         kernels[k.replace("otd::", "")] = {"fetch_bytes": fv, "write_bytes": wv,
                                            "bytes_per_launch": fv + wv,
                                            "dispatches": len(fetch[k])}
-    res = {"sources": _sources_hash(), "workload": "rgb_256x256x3x32",
+    title = ("hue rendering 3840x2160, 360 bins, 33 frames per launch" if hue
+             else "RGB transport 256x256x3x32")
+    res = {"sources": hue_sources_hash() if hue else _sources_hash(),
+           "workload": "hue_render_3840x2160_360" if hue else "rgb_256x256x3x32",
            "calibration": {"kernel": ck, "bytes_each_way": nbytes,
                            "fetch_scale": f_scale, "write_scale": w_scale},
            "kernels": kernels}
     with open(out_json, "w") as fh:
         json.dump(res, fh, indent=1)
-    lines = ["# HBM traffic per launch: RGB transport 256x256x3x32", "",
+    lines = [f"# HBM traffic per launch: {title}", "",
              "Commands (repository root, one MI355X):", "", f"    {cmd}", "",
              f"Calibration: `{ck}` copies {nbytes} B each way; FETCH_SIZE scale "
              f"{f_scale:.4f}, WRITE_SIZE scale {w_scale:.4f}.", "",
@@ -131,4 +176,7 @@ def summarise_stats(stats_csv: str, out_md: str, title: str, cmd: str, note: str
 
 
 if __name__ == "__main__":
-    run()
+    if sys.argv[1:] == ["hue"]:
+        run_hue()
+    else:
+        run()
