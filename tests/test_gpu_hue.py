@@ -92,6 +92,25 @@ def test_identity_frame_is_the_source(othue):
     r.close()
 
 
+def test_calls_before_a_source_are_refused(othue):
+    import torch
+    _say("hue state errors")
+    r = othue.HueRenderer(64, 16)
+    tg = torch.ones(16, device="cuda")
+    out = torch.empty(64, 3, dtype=torch.uint8, device="cuda")
+    for call in (lambda: othue.ot_hue_histogram(r.h, None, tg),
+                 lambda: othue.ot_hue_plan(r.h, tg, 1),
+                 lambda: othue.ot_hue_apply(r.h, out),
+                 lambda: othue.ot_hue_plan_info(r.h, 0)):
+        with pytest.raises(othue.OtDynError) as e:
+            call()
+        assert e.value.status == -7
+    with pytest.raises(othue.OtDynError) as e:
+        othue.ot_hue_render(r.h, tg, 0, out)
+    assert e.value.status == -1
+    r.close()
+
+
 def test_plan_then_apply_equals_render(othue):
     """The frame split in its two calls: one plan serves several applies, and
     apply before a plan for the current source is refused."""
