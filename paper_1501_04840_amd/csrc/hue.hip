@@ -3,13 +3,13 @@
 // density by exact circular histogram specification (the readings are listed
 // in ot_hue.h).
 //
-// Device layout: keys/order/rank are u32 [N]; counts, target counts and the
-// inclusive cumulative target counts are int32 [n]; the shift is one int64.
-// Per call of F frames: one planning kernel of F blocks (target counts,
-// median shift per frame) and one streaming kernel over the pixels in raster
-// order, F frames along grid y (reads 3 bytes of
-// RGB and the 4-byte rank, writes 3 bytes and optionally the 4-byte bin),
-// four pixels per thread.
+// Device layout: keys/order/rank are u32 [N] and the source counts int32 [n];
+// per frame, the target counts and their inclusive cumulative sums are
+// int32 [n] and the shift one int64.  Per call of F frames: one planning
+// kernel of F blocks (target counts, median shift) and one streaming kernel
+// over the pixels in raster order with the frames along grid y, four pixels
+// per thread (reads 3 bytes of RGB and the 4-byte rank, writes 3 bytes and
+// optionally the 4-byte bin).
 #include <hip/hip_runtime.h>
 #include <hipcub/device/device_radix_sort.hpp>
 
