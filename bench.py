@@ -90,17 +90,39 @@ def measured_traffic(prefix: str, summary: str = "traffic.json", sources=None):
     return sum(vals) / len(vals) if vals else None
 
 
+def host_cpu() -> str:
+    """CPU model and the cores this process may run on (the oracle uses one)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {len(os.sched_getaffinity(0))} cores available"
+
+
+def one_thread():
+    """Context that holds NumPy/SciPy's thread pools to one thread, so that the
+    oracle's timing uses exactly the one core it reports."""
+    from threadpoolctl import threadpool_limits
+    return threadpool_limits(limits=1)
+
+
 def cpu_baseline(f0, f1, X, Y, C, P, iters):
     import numpy as np
     from oracle import grid as G, pdhg
     g = G.Grid(X, Y, C, P)
     a0, a1 = f0.astype(np.float64), f1.astype(np.float64)
-    t0 = time.perf_counter()
-    pdhg.solve(g, a0, a1, 10.0, 0.099, iters)
-    dt = time.perf_counter() - t0
+    with one_thread():
+        t0 = time.perf_counter()
+        pdhg.solve(g, a0, a1, 10.0, 0.099, iters)
+        dt = time.perf_counter() - t0
     return {
         "value": X * Y * C * P * iters / dt, "unit": "cell-iters/s", "cores": 1,
-        "kind": "oracle",
+        "kind": "oracle", "host": host_cpu(),
         "sample": f"{iters} iterations of the {X}x{Y}x{C}x{P} workload, FP64 NumPy/SciPy oracle "
                   f"(single-threaded), {dt:.1f} s",
     }
@@ -218,12 +240,14 @@ def hue_cpu_baseline(probs, idx, args, iters: int = 600):
     for i in idx:
         n, T, h0, h1 = probs[i]
         g = G.Grid(n, 1, 1, T, (G.PERIODIC, G.NEUMANN, G.NEUMANN))
-        t0 = time.perf_counter()
-        pdhg.solve(g, h0.reshape(1, 1, -1).astype(np.float64), h1.reshape(1, 1, -1).astype(np.float64),
-                   args.hue_tau, args.hue_sigma, iters)
-        dt += time.perf_counter() - t0
+        with one_thread():
+            t0 = time.perf_counter()
+            pdhg.solve(g, h0.reshape(1, 1, -1).astype(np.float64),
+                       h1.reshape(1, 1, -1).astype(np.float64), args.hue_tau, args.hue_sigma, iters)
+            dt += time.perf_counter() - t0
         cells += n * T * iters
     return {"value": cells / dt, "unit": "cell-iters/s", "cores": 1, "kind": "oracle",
+            "host": host_cpu(),
             "sample": f"{iters} iterations of each of {len(idx)} hue problems "
                       f"(the looped sample), FP64 NumPy/SciPy oracle (single-threaded), {dt:.1f} s"}
 
@@ -326,12 +350,13 @@ def hue_render(args):
     if not args.no_cpu:
         sample = 8
         src_ref = ref_hue.Source(img, n)
-        t0 = time.perf_counter()
-        for i in range(sample):
-            src_ref.render(dens[i % F])
-        cpu_dt = time.perf_counter() - t0
+        with one_thread():
+            t0 = time.perf_counter()
+            for i in range(sample):
+                src_ref.render(dens[i % F])
+            cpu_dt = time.perf_counter() - t0
         out_json["cpu_baseline"] = {"value": sample / cpu_dt, "unit": "frames/s", "cores": 1,
-                                    "kind": "oracle",
+                                    "kind": "oracle", "host": host_cpu(),
                                     "sample": f"{sample} frames of the same {W}x{H} image "
                                               "(source preparation not timed)"}
     print(json.dumps(out_json))
