@@ -137,6 +137,46 @@ def rgb_of_hue(h: np.ndarray, hi: np.ndarray, lo: np.ndarray) -> np.ndarray:
     return np.clip(out, 0, 255).astype(np.uint8)
 
 
+def hsv_of_rgb(rgb: np.ndarray) -> np.ndarray:
+    """HSV (float32, (..., 3)) of u8 RGB: the hexcone hue above, saturation
+    (max - min) / max (0 for black), value max / 255."""
+    h, hi, lo = hue_of_rgb(rgb)
+    hiF = np.asarray(hi).astype(F32)
+    d = (hiF - np.asarray(lo).astype(F32)).astype(F32)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        sat = np.where(hiF > 0, (d / np.where(hiF > 0, hiF, F32(1))).astype(F32), F32(0))
+    val = (hiF / F32(255)).astype(F32)
+    return np.stack([h, sat.astype(F32), val], axis=-1).astype(F32)
+
+
+def rgb_of_hsv(hsv: np.ndarray) -> np.ndarray:
+    """u8 RGB of float HSV by the textbook hexcone: h wrapped into [0, 1),
+    sector i = floor(6h), f = 6h - i, p = v (1 - s), q = v (1 - s f),
+    t = v (1 - s (1 - f)); each channel floor(255 c + 0.5), clamped.  s and v
+    are clamped to [0, 1]; non-finite inputs give black."""
+    x = np.asarray(hsv, dtype=F32)
+    h, sat, val = x[..., 0], x[..., 1], x[..., 2]
+    bad = ~(np.isfinite(h) & np.isfinite(sat) & np.isfinite(val))
+    h = np.where(bad, F32(0), h).astype(F32)
+    sat = np.clip(np.where(bad, F32(0), sat), 0, 1).astype(F32)
+    val = np.clip(np.where(bad, F32(0), val), 0, 1).astype(F32)
+    h = (h - np.floor(h).astype(F32)).astype(F32)
+    h = np.where(h >= F32(1), h - F32(1), h).astype(F32)
+    h6 = (h * F32(6)).astype(F32)
+    i = np.clip(np.floor(h6).astype(np.int64), 0, 5)
+    f = (h6 - i.astype(F32)).astype(F32)
+    one = F32(1)
+    p = (val * (one - sat).astype(F32)).astype(F32)
+    q = (val * (one - (sat * f).astype(F32)).astype(F32)).astype(F32)
+    t = (val * (one - (sat * (one - f).astype(F32)).astype(F32)).astype(F32)).astype(F32)
+    r = np.choose(i, [val, q, p, p, t, val])
+    g = np.choose(i, [t, val, val, q, p, p])
+    b = np.choose(i, [p, p, t, val, val, q])
+    out = np.stack([r, g, b], axis=-1).astype(F32)
+    out = np.floor(((out * F32(255)).astype(F32) + F32(0.5)).astype(F32))
+    return np.clip(out, 0, 255).astype(np.uint8)
+
+
 class Source:
     """The first image's hue data: hue, bins, counts and the strict order."""
 

@@ -141,3 +141,38 @@ def test_rendered_frame_has_the_target_hue_histogram():
     sat = (src.hi - src.lo) >= 32
     assert np.all(d[sat] <= 1) and np.mean(d[sat] == 0) > 0.9
     assert np.array_equal(out[grey], img.reshape(-1, 3)[grey])
+
+
+def test_hsv_matches_colorsys_both_ways():
+    px = _pixels(9, 30000)
+    hsv = hue.hsv_of_rgb(px)
+    for i in range(0, px.shape[0], 11):
+        r, g, b = (int(v) / 255.0 for v in px[i])
+        hh, ss, vv = colorsys.rgb_to_hsv(r, g, b)
+        d = abs(float(hsv[i, 0]) - hh)
+        assert min(d, 1 - d) < 2e-6 and abs(hsv[i, 1] - ss) < 1e-6 and abs(hsv[i, 2] - vv) < 1e-6
+    rng = np.random.default_rng(10)
+    x = rng.uniform(0, 1, (5000, 3)).astype(np.float32)
+    out = hue.rgb_of_hsv(x).astype(np.int64)
+    for i in range(x.shape[0]):
+        ref = np.array(colorsys.hsv_to_rgb(*(float(v) for v in x[i]))) * 255
+        assert np.max(np.abs(out[i] - ref)) <= 0.5 + 1e-3
+
+
+def test_hsv_round_trip_is_exact_on_all_8_bit_colours():
+    v = np.arange(256, dtype=np.uint8)
+    for r0 in range(0, 256, 8):                     # 1/8 of the cube per test run
+        r = np.full(256 * 256, r0, np.uint8)
+        g, b = np.meshgrid(v, v, indexing="ij")
+        px = np.stack([r, g.ravel(), b.ravel()], axis=-1)
+        assert np.array_equal(hue.rgb_of_hsv(hue.hsv_of_rgb(px)), px)
+
+
+def test_hsv_edge_values():
+    x = np.array([[1.25, 0.5, 0.5], [-0.25, 0.5, 0.5], [0.5, 2.0, -1.0],
+                  [np.nan, 0.5, 0.5], [0.5, np.inf, 0.5], [0.999999, 1.0, 1.0]], np.float32)
+    out = hue.rgb_of_hsv(x)
+    assert np.array_equal(out[0], hue.rgb_of_hsv(np.array([[0.25, 0.5, 0.5]], np.float32))[0])
+    assert np.array_equal(out[1], hue.rgb_of_hsv(np.array([[0.75, 0.5, 0.5]], np.float32))[0])
+    assert np.array_equal(out[2], [0, 0, 0]) and np.array_equal(out[3], [0, 0, 0])
+    assert np.array_equal(out[4], [0, 0, 0]) and np.array_equal(out[5], [255, 0, 0])
