@@ -94,6 +94,18 @@ int ot_hue_apply(ot_hue* h, unsigned char* rgb_out, int* bins_out);
  * before a plan, OT_ERR_PARAM for a frame out of range. */
 int ot_hue_plan_info(ot_hue* h, int frame, int* counts, long long* shift);
 
+/* Colour-space conversions of the HSV split (stateless).  ot_hue_rgb_to_hsv:
+ * rgb device u8 [npix][3] to hsv device float [npix][3] = (the hue above,
+ * saturation (max - min) / max, 0 for black, value max / 255).
+ * ot_hue_hsv_to_rgb: the textbook hexcone inverse, h wrapped into [0, 1), s
+ * and v clamped to [0, 1], a pixel with a non-finite component black, each
+ * channel floor(255 c + 0.5); FP32 in a fixed order, so 8-bit colours round
+ * trip exactly.  npix = 0 does nothing.  Asynchronous on `stream` (a
+ * hipStream_t, NULL = default stream).  OT_ERR_PARAM for npix < 0 or a null
+ * pointer with npix > 0, OT_ERR_HIP if the launch fails. */
+int ot_hue_rgb_to_hsv(const unsigned char* rgb, long long npix, float* hsv, void* stream);
+int ot_hue_hsv_to_rgb(const float* hsv, long long npix, unsigned char* rgb, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

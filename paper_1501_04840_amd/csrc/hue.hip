@@ -27,6 +27,7 @@ constexpr int kPlanThreads = 1024;
 constexpr unsigned kKeyBlocks = 2048;     // 8 blocks per compute unit
 constexpr unsigned kRenderBlocks = 4096;  // 16 blocks per compute unit, per frame
 constexpr int kMaxFrames = 65535;         // frames per call (grid y)
+constexpr unsigned kConvBlocks = 8192;    // RGB<->HSV grid-stride launches
 
 // Every FP32 step below is one rounded operation in the written order: no
 // contraction of a product and a sum into a fused multiply-add.
@@ -90,6 +91,63 @@ __device__ __forceinline__ void rgb_of(float h, int hi, int lo, unsigned char* o
     o[0] = to_u8(r);
     o[1] = to_u8(g);
     o[2] = to_u8(b);
+}
+
+// HSV of 8-bit RGB: the hexcone hue above, saturation (max - min) / max (0
+// for black), value max / 255; float [N][3].
+__global__ void __launch_bounds__(kThreads) k_rgb_to_hsv(const unsigned char* __restrict__ rgb,
+                                                         long long N, float* hsv) {
+#pragma clang fp contract(off)
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+        const unsigned char* c = rgb + 3 * p;
+        const Hue u = hue_of(c[0], c[1], c[2]);
+        const float hf = (float)u.hi;
+        const float d = hf - (float)u.lo;
+        hsv[3 * p] = u.h;
+        hsv[3 * p + 1] = u.hi > 0 ? d / hf : 0.f;
+        hsv[3 * p + 2] = hf / 255.f;
+    }
+}
+
+// 8-bit RGB of float HSV by the textbook hexcone (h wrapped into [0, 1), s
+// and v clamped to [0, 1], non-finite input black), channels rounded to
+// nearest.
+__global__ void __launch_bounds__(kThreads) k_hsv_to_rgb(const float* __restrict__ hsv,
+                                                         long long N, unsigned char* rgb) {
+#pragma clang fp contract(off)
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+        float h = hsv[3 * p], s = hsv[3 * p + 1], v = hsv[3 * p + 2];
+        const bool bad = !(isfinite(h) && isfinite(s) && isfinite(v));
+        h = bad ? 0.f : h;
+        s = fminf(fmaxf(bad ? 0.f : s, 0.f), 1.f);
+        v = fminf(fmaxf(bad ? 0.f : v, 0.f), 1.f);
+        h = h - floorf(h);
+        h = h >= 1.f ? h - 1.f : h;
+        const float h6 = h * 6.f;
+        const int i = min(max((int)floorf(h6), 0), 5);
+        const float f = h6 - (float)i;
+        const float pp = v * (1.f - s);
+        const float sf = s * f;
+        const float qq = v * (1.f - sf);
+        const float g1 = 1.f - f;
+        const float sg = s * g1;
+        const float tt = v * (1.f - sg);
+        float r, g, b;
+        switch (i) {
+            case 0: r = v; g = tt; b = pp; break;
+            case 1: r = qq; g = v; b = pp; break;
+            case 2: r = pp; g = v; b = tt; break;
+            case 3: r = pp; g = qq; b = v; break;
+            case 4: r = tt; g = pp; b = v; break;
+            default: r = v; g = pp; b = qq; break;
+        }
+        unsigned char* o = rgb + 3 * p;
+        o[0] = to_u8(r * 255.f);
+        o[1] = to_u8(g * 255.f);
+        o[2] = to_u8(b * 255.f);
+    }
 }
 
 __global__ void k_fill_i32(int* p, int n, int v) {
@@ -526,6 +584,24 @@ int ot_hue_plan_info(ot_hue* h, int frame, int* counts, long long* shift) {
                                 hipMemcpyDeviceToHost, h->st) != hipSuccess)
         return OT_ERR_HIP;
     return hipStreamSynchronize(h->st) == hipSuccess ? OT_OK : OT_ERR_HIP;
+}
+
+int ot_hue_rgb_to_hsv(const unsigned char* rgb, long long npix, float* hsv, void* stream) {
+    if (npix < 0 || (npix > 0 && (!rgb || !hsv))) return OT_ERR_PARAM;
+    if (npix == 0) return OT_OK;
+    const unsigned gb = blocks_for(npix, kThreads);
+    hipLaunchKernelGGL(k_rgb_to_hsv, dim3(gb < kConvBlocks ? gb : kConvBlocks), dim3(kThreads), 0,
+                       (hipStream_t)stream, rgb, npix, hsv);
+    return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
+}
+
+int ot_hue_hsv_to_rgb(const float* hsv, long long npix, unsigned char* rgb, void* stream) {
+    if (npix < 0 || (npix > 0 && (!rgb || !hsv))) return OT_ERR_PARAM;
+    if (npix == 0) return OT_OK;
+    const unsigned gb = blocks_for(npix, kThreads);
+    hipLaunchKernelGGL(k_hsv_to_rgb, dim3(gb < kConvBlocks ? gb : kConvBlocks), dim3(kThreads), 0,
+                       (hipStream_t)stream, hsv, npix, rgb);
+    return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
 }
 
 }  // extern "C"

@@ -14,7 +14,8 @@ from . import otdyn
 from .otdyn import OtDynError, _ptr
 
 EXPORTS = ["ot_hue_create", "ot_hue_destroy", "ot_hue_set_source", "ot_hue_histogram",
-           "ot_hue_render", "ot_hue_plan", "ot_hue_apply", "ot_hue_plan_info"]
+           "ot_hue_render", "ot_hue_plan", "ot_hue_apply", "ot_hue_plan_info",
+           "ot_hue_rgb_to_hsv", "ot_hue_hsv_to_rgb"]
 
 _done = False
 
@@ -35,6 +36,8 @@ def lib() -> ctypes.CDLL:
     L.ot_hue_plan.argtypes = [P, P, c_int]
     L.ot_hue_apply.argtypes = [P, P, P]
     L.ot_hue_plan_info.argtypes = [P, c_int, P, POINTER(LL)]
+    L.ot_hue_rgb_to_hsv.argtypes = [P, LL, P, P]
+    L.ot_hue_hsv_to_rgb.argtypes = [P, LL, P, P]
     for name in EXPORTS:
         if name != "ot_hue_destroy":
             getattr(L, name).restype = c_int
@@ -85,6 +88,14 @@ def ot_hue_plan_info(h: int, frame: int = 0, counts=None):
     cp = counts.ctypes.data if counts is not None else 0
     st = _check(lib().ot_hue_plan_info(h, frame, cp, byref(s)))
     return st, s.value
+
+
+def ot_hue_rgb_to_hsv(rgb, npix: int, hsv, stream=None) -> int:
+    return _check(lib().ot_hue_rgb_to_hsv(_ptr(rgb), npix, _ptr(hsv), _ptr(stream)))
+
+
+def ot_hue_hsv_to_rgb(hsv, npix: int, rgb, stream=None) -> int:
+    return _check(lib().ot_hue_hsv_to_rgb(_ptr(hsv), npix, _ptr(rgb), _ptr(stream)))
 
 
 class HueRenderer:

@@ -118,3 +118,6 @@ def test_hue_renderer_rejects_bad_sizes(L):
     assert lib.ot_hue_plan_info(None, 0, None, None) == L.OT_ERR_PARAM
     assert lib.ot_hue_plan(None, None, 1) == L.OT_ERR_PARAM
     assert lib.ot_hue_apply(None, None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_rgb_to_hsv(None, 5, None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_hsv_to_rgb(None, -1, None, None) == L.OT_ERR_PARAM
+    assert lib.ot_hue_rgb_to_hsv(None, 0, None, None) == L.OT_OK
