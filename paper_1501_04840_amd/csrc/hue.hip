@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/device/device_radix_sort.hpp>
 
+#include <climits>
 #include <cstdint>
 #include <new>
 
@@ -327,29 +328,27 @@ __global__ void __launch_bounds__(kPlanThreads) k_hue_plan(const float* __restri
 }
 
 // Output bin of a pixel of rank rk: the first bin whose cumulative count
-// exceeds q = (rk - s) mod N, i.e. the number of cumulative counts <= q
-// (nondecreasing); fixed-trip search over p2 = 2^floor(log2 n), W pixels in
+// exceeds q = (rk - s) mod N, i.e. the number of cumulative counts <= q.  cl
+// holds the n nondecreasing counts padded with INT_MAX to pw = 2^ceil(log2 n)
+// entries, so the branch-free search needs no bounds test; W pixels in
 // lockstep so that their LDS loads overlap.
 template <int W>
-__device__ __forceinline__ void out_bins(const unsigned* rk, long long s, long long N,
-                                         const int* cl, int n, int p2, int* lo) {
-    long long q[W];
+__device__ __forceinline__ void out_bins(const unsigned* rk, int s, int N, const int* cl, int n,
+                                         int pw, int* lo) {
+    // N <= 2^30: rank - s lies in (-2^30, 2^31 - 1), so 32-bit arithmetic
+    int q[W];
 #pragma unroll
     for (int i = 0; i < W; ++i) {
-        q[i] = (long long)rk[i] - s;    // rank in [0, N), shift in (-N, N)
+        q[i] = (int)rk[i] - s;          // rank in [0, N), shift in (-N, N)
         q[i] = q[i] < 0 ? q[i] + N : (q[i] >= N ? q[i] - N : q[i]);
         lo[i] = 0;
     }
-    for (int step = p2; step > 0; step >>= 1) {
+    for (int half = pw >> 1; half > 0; half >>= 1) {
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-            const int c = lo[i] + step;
-            const int ci = min(c, n) - 1;
-            lo[i] = (c <= n && (long long)cl[ci] <= q[i]) ? c : lo[i];
-        }
+        for (int i = 0; i < W; ++i) lo[i] += cl[lo[i] + half - 1] <= q[i] ? half : 0;
     }
 #pragma unroll
-    for (int i = 0; i < W; ++i) lo[i] = min(lo[i], n - 1);
+    for (int i = 0; i < W; ++i) lo[i] = min(lo[i] + (cl[lo[i]] <= q[i] ? 1 : 0), n - 1);
 }
 
 // One pixel of a frame: the hue moved to the output bin, RGB rebuilt.
@@ -384,11 +383,11 @@ __global__ void __launch_bounds__(kThreads) k_hue_render(const unsigned char* __
         out += f * 3 * N;
         if (bins_out) bins_out += f * N;
     }
-    __shared__ int cl[kMaxBins];
-    for (int k = threadIdx.x; k < n; k += blockDim.x) cl[k] = cum[k];
+    extern __shared__ int cl[];        // [pw]: cumulative counts, INT_MAX padding
+    const int pw = n > 1 ? 1 << (32 - __clz(n - 1)) : 1;
+    for (int k = threadIdx.x; k < pw; k += blockDim.x) cl[k] = k < n ? cum[k] : INT_MAX;
     __syncthreads();
-    const long long s = *shift;
-    const int p2 = 1 << (31 - __clz(n));
+    const int s32 = (int)*shift, N32 = (int)N;
     const long long groups = (N + 3) / 4;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x; gi < groups;
@@ -400,7 +399,7 @@ __global__ void __launch_bounds__(kThreads) k_hue_render(const unsigned char* __
             in.v = *reinterpret_cast<const uint3*>(rgb + 3 * p0);
             rk.v = *reinterpret_cast<const uint4*>(rank + p0);
             int kb[4];
-            out_bins<4>(rk.u, s, N, cl, n, p2, kb);
+            out_bins<4>(rk.u, s32, N32, cl, n, pw, kb);
 #pragma unroll
             for (int i = 0; i < 4; ++i) paint_px(in.b + 3 * i, kb[i], n, o.b + 3 * i);
             *reinterpret_cast<uint3*>(out + 3 * p0) = o.v;
@@ -409,7 +408,7 @@ __global__ void __launch_bounds__(kThreads) k_hue_render(const unsigned char* __
             for (long long p = p0; p < p0 + 4 && p < N; ++p) {
                 const unsigned r1 = rank[p];
                 int k;
-                out_bins<1>(&r1, s, N, cl, n, p2, &k);
+                out_bins<1>(&r1, s32, N32, cl, n, pw, &k);
                 paint_px(rgb + 3 * p, k, n, out + 3 * p);
                 if (bins_out) bins_out[p] = k;
             }
@@ -557,11 +556,13 @@ int ot_hue_apply(ot_hue* h, unsigned char* rgb_out, int* bins_out) {
     const bool vec = ((uintptr_t)h->src % 4 == 0) && ((uintptr_t)rgb_out % 4 == 0) &&
                      ((uintptr_t)bins_out % 16 == 0) &&
                      (F == 1 || ((3 * h->N) % 4 == 0 && (!bins_out || h->N % 4 == 0)));
+    // LDS: the cumulative counts padded to the next power of two (<= 16 KB)
+    const size_t lds = sizeof(int) * (h->n > 1 ? (size_t)1 << (32 - __builtin_clz(h->n - 1)) : 1);
     if (vec)
-        hipLaunchKernelGGL(k_hue_render<true>, grid, dim3(kThreads), 0, h->st, h->src, h->rank,
+        hipLaunchKernelGGL(k_hue_render<true>, grid, dim3(kThreads), lds, h->st, h->src, h->rank,
                            h->cum, h->shift, h->n, h->N, rgb_out, bins_out);
     else
-        hipLaunchKernelGGL(k_hue_render<false>, grid, dim3(kThreads), 0, h->st, h->src, h->rank,
+        hipLaunchKernelGGL(k_hue_render<false>, grid, dim3(kThreads), lds, h->st, h->src, h->rank,
                            h->cum, h->shift, h->n, h->N, rgb_out, bins_out);
     return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
 }
