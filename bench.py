@@ -326,7 +326,7 @@ def hue_render(args):
     dt = time.perf_counter() - t0
     apply_us = 1e3 * sum(a.elapsed_time(b) for a, b in ev) / K
     r.close()
-    nbytes = 10.0 * N * F             # read RGB (3) + rank (4), write RGB (3), per frame
+    nbytes = 14.0 * N * F             # read RGB (3) + hue (4) + rank (4), write RGB (3), per frame
     from paper_1501_04840_amd import profile_traffic
     traffic = None
     if (H, W, n, F) == (2160, 3840, 360, 33):      # the counted workload

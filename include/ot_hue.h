@@ -82,8 +82,8 @@ int ot_hue_render(ot_hue* h, const float* targets, int frames, unsigned char* rg
 /* The two halves of ot_hue_render, for callers that time or reuse them:
  * ot_hue_plan computes the target counts and the shift of every frame (one
  * kernel, one block per frame); ot_hue_apply writes the frames of the last
- * plan (one pass over the pixels in raster order per frame: 10 bytes of HBM
- * traffic per pixel, 14 with bins_out).  Same arguments and status codes as
+ * plan (one pass over the pixels in raster order per frame: 14 bytes of HBM
+ * traffic per pixel, 18 with bins_out).  Same arguments and status codes as
  * ot_hue_render; ot_hue_apply before a plan for the current source is
  * OT_ERR_STATE. */
 int ot_hue_plan(ot_hue* h, const float* targets, int frames);

@@ -8,8 +8,9 @@
 // int32 [n] and the shift one int64.  Per call of F frames: one planning
 // kernel of F blocks (target counts, median shift) and one streaming kernel
 // over the pixels in raster order with the frames along grid y, four pixels
-// per thread (reads 3 bytes of RGB and the 4-byte rank, writes 3 bytes and
-// optionally the 4-byte bin).
+// per thread (reads 3 bytes of RGB, the 4-byte hue kept from the source's
+// sort keys and the 4-byte rank, writes 3 bytes and optionally the 4-byte
+// bin).
 #include <hip/hip_runtime.h>
 #include <hipcub/device/device_radix_sort.hpp>
 
@@ -351,17 +352,18 @@ __device__ __forceinline__ void out_bins(const unsigned* rk, int s, int N, const
     for (int i = 0; i < W; ++i) lo[i] = min(lo[i] + (cl[lo[i]] <= q[i] ? 1 : 0), n - 1);
 }
 
-// One pixel of a frame: the hue moved to the output bin, RGB rebuilt.
-__device__ __forceinline__ void paint_px(const unsigned char* c, int kout, int n,
+// One pixel of a frame: its hue h (the source's sort key, computed once per
+// source) moved to the output bin, RGB rebuilt with the max and min channels.
+__device__ __forceinline__ void paint_px(const unsigned char* c, float h, int kout, int n,
                                          unsigned char* o) {
 #pragma clang fp contract(off)
-    const Hue u = hue_of(c[0], c[1], c[2]);
-    const int ksrc = bin_of(u.h, n);
-    float h2 = u.h + (float)(kout - ksrc) / (float)n;
+    const int r = c[0], g = c[1], b = c[2];
+    const int ksrc = bin_of(h, n);
+    float h2 = h + (float)(kout - ksrc) / (float)n;
     if (h2 >= 1.f) h2 = h2 - 1.f;
     if (h2 < 0.f) h2 = h2 + 1.f;
     if (h2 >= 1.f) h2 = h2 - 1.f;
-    rgb_of(h2, u.hi, u.lo, o);
+    rgb_of(h2, max(max(r, g), b), min(min(r, g), b), o);
 }
 
 // One frame over the pixels in raster order, four pixels per thread in a
@@ -371,6 +373,7 @@ __device__ __forceinline__ void paint_px(const unsigned char* c, int kout, int n
 // pixel.
 template <bool VEC>
 __global__ void __launch_bounds__(kThreads) k_hue_render(const unsigned char* __restrict__ rgb,
+                                                         const unsigned* __restrict__ hue,
                                                          const unsigned* __restrict__ rank,
                                                          const int* __restrict__ cum,
                                                          const long long* __restrict__ shift,
@@ -395,13 +398,15 @@ __global__ void __launch_bounds__(kThreads) k_hue_render(const unsigned char* __
         const long long p0 = 4 * gi;
         if (VEC && p0 + 4 <= N) {
             union { uint3 v; unsigned char b[12]; } in, o;
-            union { uint4 v; unsigned u[4]; } rk;
+            union { uint4 v; unsigned u[4]; } rk, hu;
             in.v = *reinterpret_cast<const uint3*>(rgb + 3 * p0);
             rk.v = *reinterpret_cast<const uint4*>(rank + p0);
+            hu.v = *reinterpret_cast<const uint4*>(hue + p0);
             int kb[4];
             out_bins<4>(rk.u, s32, N32, cl, n, pw, kb);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) paint_px(in.b + 3 * i, kb[i], n, o.b + 3 * i);
+            for (int i = 0; i < 4; ++i)
+                paint_px(in.b + 3 * i, __uint_as_float(hu.u[i]), kb[i], n, o.b + 3 * i);
             *reinterpret_cast<uint3*>(out + 3 * p0) = o.v;
             if (bins_out) *reinterpret_cast<int4*>(bins_out + p0) = make_int4(kb[0], kb[1], kb[2], kb[3]);
         } else {
@@ -409,7 +414,7 @@ __global__ void __launch_bounds__(kThreads) k_hue_render(const unsigned char* __
                 const unsigned r1 = rank[p];
                 int k;
                 out_bins<1>(&r1, s32, N32, cl, n, pw, &k);
-                paint_px(rgb + 3 * p, k, n, out + 3 * p);
+                paint_px(rgb + 3 * p, __uint_as_float(hue[p]), k, n, out + 3 * p);
                 if (bins_out) bins_out[p] = k;
             }
         }
@@ -488,7 +493,9 @@ int ot_hue_set_source(ot_hue* h, const unsigned char* rgb) {
     const unsigned kb = blocks_for(h->N, kThreads);
     hipLaunchKernelGGL(k_hue_keys, dim3(kb < kKeyBlocks ? kb : kKeyBlocks), dim3(kThreads), 0, h->st,
                        rgb, h->N, h->n, h->keys, h->idx, h->counts);
-    // hues lie in [0, 1): their FP32 patterns are below 2^30
+    // hues lie in [0, 1): their FP32 patterns are below 2^30.  The sort leaves
+    // its input alone, so keys keeps each pixel's hue in raster order for the
+    // frames.
     if (hipcub::DeviceRadixSort::SortPairs(h->temp, h->temp_bytes, h->keys, h->keys2, h->idx,
                                            h->order, (int)h->N, 0, 30, h->st) != hipSuccess)
         return OT_ERR_HIP;
@@ -559,10 +566,12 @@ int ot_hue_apply(ot_hue* h, unsigned char* rgb_out, int* bins_out) {
     // LDS: the cumulative counts padded to the next power of two (<= 16 KB)
     const size_t lds = sizeof(int) * (h->n > 1 ? (size_t)1 << (32 - __builtin_clz(h->n - 1)) : 1);
     if (vec)
-        hipLaunchKernelGGL(k_hue_render<true>, grid, dim3(kThreads), lds, h->st, h->src, h->rank,
+        hipLaunchKernelGGL(k_hue_render<true>, grid, dim3(kThreads), lds, h->st, h->src, h->keys,
+                           h->rank,
                            h->cum, h->shift, h->n, h->N, rgb_out, bins_out);
     else
-        hipLaunchKernelGGL(k_hue_render<false>, grid, dim3(kThreads), lds, h->st, h->src, h->rank,
+        hipLaunchKernelGGL(k_hue_render<false>, grid, dim3(kThreads), lds, h->st, h->src, h->keys,
+                           h->rank,
                            h->cum, h->shift, h->n, h->N, rgb_out, bins_out);
     return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
 }
