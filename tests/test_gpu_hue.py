@@ -275,3 +275,29 @@ def test_rgb_hsv_conversions_match_oracle(othue):
     othue.ot_hue_hsv_to_rgb(dx, x.shape[0], out)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), ref.rgb_of_hsv(x))
+
+
+def test_bench_configuration_frames(othue):
+    """The configuration bench.py times: the 3840 x 2160 image, 360 bins, 33
+    frames in one launch; frames 0, 16 and 32 compared in full with the
+    oracle, and every frame's output bins with its target counts."""
+    import torch
+    _say("hue 3840x2160, 33 frames per call")
+    H, W, n, F = 2160, 3840, 360, 33
+    img = inputs.hue_image(501, H, W, sigma=24.0)
+    dens = np.stack([inputs.von_mises_hist(600 + i, n) for i in range(F)]).astype(np.float32)
+    r = _renderer(othue, img, n)
+    out, bins = r.render_frames(torch.from_numpy(dens).cuda(), with_bins=True)
+    torch.cuda.synchronize()
+    counts = torch.stack([torch.bincount(bins[f].long(), minlength=n) for f in range(F)]).cpu()
+    src = ref.Source(img, n)
+    for f in range(F):
+        ct, _ = r.plan_info(f)
+        assert np.array_equal(counts[f].numpy(), ct)
+        assert np.array_equal(ct, ref.target_counts(dens[f], H * W, src.counts))
+    for f in (0, F // 2, F - 1):
+        rgb_ref, k_ref, _, s_ref = src.render(dens[f])
+        assert r.plan_info(f)[1] == s_ref
+        assert np.array_equal(bins[f].cpu().numpy(), k_ref)
+        assert np.array_equal(out[f].cpu().numpy(), rgb_ref)
+    r.close()
