@@ -32,7 +32,8 @@
  *
  * Images are device arrays of N pixels x 3 bytes (R, G, B interleaved, raster
  * order), owned by the caller.  Work is ordered on the stream given at
- * creation.  Status codes are those of ot_dyn.h.
+ * creation; one renderer is not to be called from several host threads at
+ * once.  Status codes are those of ot_dyn.h.
  */
 #ifndef OT_HUE_H
 #define OT_HUE_H
@@ -55,8 +56,11 @@ int ot_hue_create(long long npix, int nbins, void* stream, ot_hue** out);
 void ot_hue_destroy(ot_hue* h);
 
 /* The source image (rgb: device, npix x 3 bytes): hues, bins, bin counts, the
- * strict order and each pixel's rank in it.  Asynchronous.  OT_ERR_PARAM for
- * a null pointer, OT_ERR_HIP if a launch fails. */
+ * strict order and each pixel's rank in it.  The renderer keeps the pointer:
+ * every later frame reads the image's max and min channels from it, so it
+ * must stay allocated and unchanged until the last frame rendered from it is
+ * done (or the next ot_hue_set_source).  Asynchronous.  OT_ERR_PARAM for a
+ * null pointer, OT_ERR_HIP if a launch fails. */
 int ot_hue_set_source(ot_hue* h, const unsigned char* rgb);
 
 /* The source's hue histogram: counts (device int32 [nbins]) and/or density
@@ -70,8 +74,7 @@ int ot_hue_histogram(ot_hue* h, int* counts, float* density);
  * transport path).  targets: device float [frames][nbins], any scale per
  * frame.  rgb_out: device, frames x npix x 3 bytes, frame after frame (may
  * not alias the source); bins_out: device int32 [frames][npix], each pixel's
- * output bin, or NULL.  Asynchronous; the source image must stay unchanged
- * until the frames are done.  The first call with more frames than before
+ * output bin, or NULL.  Asynchronous.  The first call with more frames than before
  * grows the per-frame plan arrays (synchronises the stream, allocates).
  * OT_ERR_STATE before ot_hue_set_source, OT_ERR_PARAM for a null targets or
  * rgb_out or frames out of range, OT_ERR_HIP if a launch or an allocation
