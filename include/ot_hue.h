@@ -74,11 +74,11 @@ int ot_hue_histogram(ot_hue* h, int* counts, float* density);
  * transport path).  targets: device float [frames][nbins], any scale per
  * frame.  rgb_out: device, frames x npix x 3 bytes, frame after frame (may
  * not alias the source); bins_out: device int32 [frames][npix], each pixel's
- * output bin, or NULL.  Asynchronous.  The first call with more frames than before
- * grows the per-frame plan arrays (synchronises the stream, allocates).
- * OT_ERR_STATE before ot_hue_set_source, OT_ERR_PARAM for a null targets or
- * rgb_out or frames out of range, OT_ERR_HIP if a launch or an allocation
- * fails. */
+ * output bin, or NULL.  Asynchronous.  The first call with more frames than
+ * before grows the per-frame plan arrays (synchronises the stream,
+ * allocates).  OT_ERR_STATE before ot_hue_set_source, OT_ERR_PARAM for a null
+ * targets or rgb_out or frames out of range, OT_ERR_HIP if a launch or an
+ * allocation fails. */
 int ot_hue_render(ot_hue* h, const float* targets, int frames, unsigned char* rgb_out,
                   int* bins_out);
 
