@@ -127,6 +127,7 @@ class HueRenderer:
     def render(self, target, with_bins: bool = False):
         """The frame for a device float density on the bins: uint8 (npix, 3)
         and, with with_bins, each pixel's output bin (int32)."""
+        assert target.numel() == self.nbins, "target must have nbins entries"
         out, bins = self.render_frames(target.reshape(1, -1), True)
         return (out[0], bins[0]) if with_bins else out[0]
 
@@ -134,7 +135,9 @@ class HueRenderer:
         """Frames for device float densities [frames, nbins]: uint8
         (frames, npix, 3) and, with with_bins, the output bins (frames, npix)."""
         t = self.torch
-        assert targets.dtype == t.float32 and targets.is_cuda and targets.shape[-1] == self.nbins
+        assert targets.dtype == t.float32 and targets.is_cuda
+        assert targets.dim() == 2 and targets.shape[1] == self.nbins and targets.shape[0] >= 1, \
+            "targets must be [frames, nbins]"
         F = targets.shape[0]
         out = t.empty(F, self.npix, 3, dtype=t.uint8, device=self.device)
         bins = t.empty(F, self.npix, dtype=t.int32, device=self.device) if with_bins else None
