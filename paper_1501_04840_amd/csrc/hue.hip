@@ -159,20 +159,44 @@ __global__ void k_fill_i32(int* p, int n, int v) {
 
 // Hue sort key (the FP32 bit pattern: monotone for hues >= 0), raster index,
 // and the bin histogram (per-block LDS counts over a grid-stride loop, then
-// one global add per bin and block).
+// one global add per bin and block).  Four pixels per thread; VEC: the image
+// is 4-byte aligned, so a group of four moves as one 12-byte load and two
+// 16-byte stores (the tail group and unaligned images go pixel by pixel).
+template <bool VEC>
 __global__ void __launch_bounds__(kThreads) k_hue_keys(const unsigned char* __restrict__ rgb,
                                                        long long N, int n, unsigned* keys,
                                                        unsigned* idx, int* counts) {
     __shared__ int hist[kMaxBins];
     for (int k = threadIdx.x; k < n; k += blockDim.x) hist[k] = 0;
     __syncthreads();
+    const long long groups = (N + 3) / 4;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
-        const unsigned char* c = rgb + 3 * p;
-        const Hue u = hue_of(c[0], c[1], c[2]);
-        keys[p] = __float_as_uint(u.h);
-        idx[p] = (unsigned)p;
-        atomicAdd(&hist[bin_of(u.h, n)], 1);
+    for (long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x; gi < groups;
+         gi += stride) {
+        const long long p0 = 4 * gi;
+        if (VEC && p0 + 4 <= N) {
+            union { uint3 v; unsigned char b[12]; } in;
+            in.v = *reinterpret_cast<const uint3*>(rgb + 3 * p0);
+            uint4 kv;
+            unsigned* ku = reinterpret_cast<unsigned*>(&kv);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const Hue u = hue_of(in.b[3 * i], in.b[3 * i + 1], in.b[3 * i + 2]);
+                ku[i] = __float_as_uint(u.h);
+                atomicAdd(&hist[bin_of(u.h, n)], 1);
+            }
+            *reinterpret_cast<uint4*>(keys + p0) = kv;
+            const unsigned q0 = (unsigned)p0;
+            *reinterpret_cast<uint4*>(idx + p0) = make_uint4(q0, q0 + 1, q0 + 2, q0 + 3);
+        } else {
+            for (long long p = p0; p < p0 + 4 && p < N; ++p) {
+                const unsigned char* c = rgb + 3 * p;
+                const Hue u = hue_of(c[0], c[1], c[2]);
+                keys[p] = __float_as_uint(u.h);
+                idx[p] = (unsigned)p;
+                atomicAdd(&hist[bin_of(u.h, n)], 1);
+            }
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < n; k += blockDim.x)
@@ -490,9 +514,14 @@ int ot_hue_set_source(ot_hue* h, const unsigned char* rgb) {
     if (!h || !rgb) return OT_ERR_PARAM;
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(h->n, kThreads)), dim3(kThreads), 0, h->st,
                        h->counts, h->n, 0);
-    const unsigned kb = blocks_for(h->N, kThreads);
-    hipLaunchKernelGGL(k_hue_keys, dim3(kb < kKeyBlocks ? kb : kKeyBlocks), dim3(kThreads), 0, h->st,
-                       rgb, h->N, h->n, h->keys, h->idx, h->counts);
+    const unsigned kb = blocks_for((h->N + 3) / 4, kThreads);
+    const dim3 kgrid(kb < kKeyBlocks ? kb : kKeyBlocks);
+    if ((uintptr_t)rgb % 4 == 0)
+        hipLaunchKernelGGL(k_hue_keys<true>, kgrid, dim3(kThreads), 0, h->st, rgb, h->N, h->n,
+                           h->keys, h->idx, h->counts);
+    else
+        hipLaunchKernelGGL(k_hue_keys<false>, kgrid, dim3(kThreads), 0, h->st, rgb, h->N, h->n,
+                           h->keys, h->idx, h->counts);
     // hues lie in [0, 1): their FP32 patterns are below 2^30.  The sort leaves
     // its input alone, so keys keeps each pixel's hue in raster order for the
     // frames.
