@@ -47,8 +47,8 @@ extern "C" {
 typedef struct ot_hue ot_hue;
 
 /* A renderer for images of npix pixels (1 <= npix <= 2^30) on nbins periodic
- * hue bins (2 <= nbins <= 4096).  Allocates about 20 bytes of device memory
- * per pixel (sort keys, order, ranks) plus the sort's workspace.  stream: a
+ * hue bins (2 <= nbins <= 4096).  Allocates about 24 bytes of device memory
+ * per pixel (hues, sort keys, order, ranks) plus the sort's workspace.  stream: a
  * hipStream_t (NULL = default stream).  OT_ERR_SHAPE for sizes out of range,
  * OT_ERR_PARAM for a null out, OT_ERR_HIP if an allocation fails. */
 int ot_hue_create(long long npix, int nbins, void* stream, ot_hue** out);

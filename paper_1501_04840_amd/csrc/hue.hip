@@ -162,10 +162,21 @@ __global__ void k_fill_i32(int* p, int n, int v) {
 // one global add per bin and block).  Four pixels per thread; VEC: the image
 // is 4-byte aligned, so a group of four moves as one 12-byte load and two
 // 16-byte stores (the tail group and unaligned images go pixel by pixel).
+// Sort key: floor(h 2^24), exact (a power-of-two scaling).  Distinct hues of
+// 8-bit RGB differ by at least 1 / (6 * 255^2) (differences of fractions
+// with denominators <= 255, over 6), far above 2^-24 plus the few ulps of
+// their FP32 rounding, and equal hues give equal floats, so this 24-bit key
+// orders pixels exactly as the hue does, in three radix passes instead of
+// four.
+__device__ __forceinline__ unsigned sort_key(float h) {
+    return (unsigned)(h * 16777216.f);
+}
+
 template <bool VEC>
 __global__ void __launch_bounds__(kThreads) k_hue_keys(const unsigned char* __restrict__ rgb,
                                                        long long N, int n, unsigned* keys,
-                                                       unsigned* idx, int* counts) {
+                                                       unsigned* skey, unsigned* idx,
+                                                       int* counts) {
     __shared__ int hist[kMaxBins];
     for (int k = threadIdx.x; k < n; k += blockDim.x) hist[k] = 0;
     __syncthreads();
@@ -177,15 +188,18 @@ __global__ void __launch_bounds__(kThreads) k_hue_keys(const unsigned char* __re
         if (VEC && p0 + 4 <= N) {
             union { uint3 v; unsigned char b[12]; } in;
             in.v = *reinterpret_cast<const uint3*>(rgb + 3 * p0);
-            uint4 kv;
+            uint4 kv, sv;
             unsigned* ku = reinterpret_cast<unsigned*>(&kv);
+            unsigned* su = reinterpret_cast<unsigned*>(&sv);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const Hue u = hue_of(in.b[3 * i], in.b[3 * i + 1], in.b[3 * i + 2]);
                 ku[i] = __float_as_uint(u.h);
+                su[i] = sort_key(u.h);
                 atomicAdd(&hist[bin_of(u.h, n)], 1);
             }
             *reinterpret_cast<uint4*>(keys + p0) = kv;
+            *reinterpret_cast<uint4*>(skey + p0) = sv;
             const unsigned q0 = (unsigned)p0;
             *reinterpret_cast<uint4*>(idx + p0) = make_uint4(q0, q0 + 1, q0 + 2, q0 + 3);
         } else {
@@ -193,6 +207,7 @@ __global__ void __launch_bounds__(kThreads) k_hue_keys(const unsigned char* __re
                 const unsigned char* c = rgb + 3 * p;
                 const Hue u = hue_of(c[0], c[1], c[2]);
                 keys[p] = __float_as_uint(u.h);
+                skey[p] = sort_key(u.h);
                 idx[p] = (unsigned)p;
                 atomicAdd(&hist[bin_of(u.h, n)], 1);
             }
@@ -453,7 +468,10 @@ struct ot_hue {
     long long N = 0;
     int n = 0;
     hipStream_t st = nullptr;
-    unsigned *keys = nullptr, *keys2 = nullptr, *idx = nullptr, *order = nullptr, *rank = nullptr;
+    // keys: each pixel's hue (FP32 bits, raster order, read by the frames);
+    // skey/skey2: 24-bit sort keys in and out of the radix sort
+    unsigned *keys = nullptr, *skey = nullptr, *skey2 = nullptr, *idx = nullptr, *order = nullptr,
+             *rank = nullptr;
     int *counts = nullptr, *ct = nullptr, *cum = nullptr;
     long long* shift = nullptr;
     void* temp = nullptr;
@@ -465,7 +483,7 @@ struct ot_hue {
 };
 
 static void hue_free(ot_hue* h) {
-    void* bufs[] = {h->keys, h->keys2, h->idx, h->order, h->rank, h->counts,
+    void* bufs[] = {h->keys, h->skey, h->skey2, h->idx, h->order, h->rank, h->counts,
                     h->ct, h->cum, h->shift, h->temp};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -483,7 +501,8 @@ int ot_hue_create(long long npix, int nbins, void* stream, ot_hue** out) {
     h->n = nbins;
     h->st = (hipStream_t)stream;
     const size_t w = (size_t)npix * sizeof(unsigned);
-    bool ok = hipMalloc(&h->keys, w) == hipSuccess && hipMalloc(&h->keys2, w) == hipSuccess &&
+    bool ok = hipMalloc(&h->keys, w) == hipSuccess && hipMalloc(&h->skey, w) == hipSuccess &&
+              hipMalloc(&h->skey2, w) == hipSuccess &&
               hipMalloc(&h->idx, w) == hipSuccess && hipMalloc(&h->order, w) == hipSuccess &&
               hipMalloc(&h->rank, w) == hipSuccess &&
               hipMalloc(&h->counts, nbins * sizeof(int)) == hipSuccess &&
@@ -491,8 +510,8 @@ int ot_hue_create(long long npix, int nbins, void* stream, ot_hue** out) {
               hipMalloc(&h->cum, nbins * sizeof(int)) == hipSuccess &&
               hipMalloc(&h->shift, sizeof(long long)) == hipSuccess;
     if (ok)
-        ok = hipcub::DeviceRadixSort::SortPairs(nullptr, h->temp_bytes, h->keys, h->keys2, h->idx,
-                                                h->order, (int)npix, 0, 30, h->st) == hipSuccess &&
+        ok = hipcub::DeviceRadixSort::SortPairs(nullptr, h->temp_bytes, h->skey, h->skey2, h->idx,
+                                                h->order, (int)npix, 0, 24, h->st) == hipSuccess &&
              hipMalloc(&h->temp, h->temp_bytes ? h->temp_bytes : 1) == hipSuccess;
     if (!ok) {
         hue_free(h);
@@ -518,15 +537,13 @@ int ot_hue_set_source(ot_hue* h, const unsigned char* rgb) {
     const dim3 kgrid(kb < kKeyBlocks ? kb : kKeyBlocks);
     if ((uintptr_t)rgb % 4 == 0)
         hipLaunchKernelGGL(k_hue_keys<true>, kgrid, dim3(kThreads), 0, h->st, rgb, h->N, h->n,
-                           h->keys, h->idx, h->counts);
+                           h->keys, h->skey, h->idx, h->counts);
     else
         hipLaunchKernelGGL(k_hue_keys<false>, kgrid, dim3(kThreads), 0, h->st, rgb, h->N, h->n,
-                           h->keys, h->idx, h->counts);
-    // hues lie in [0, 1): their FP32 patterns are below 2^30.  The sort leaves
-    // its input alone, so keys keeps each pixel's hue in raster order for the
-    // frames.
-    if (hipcub::DeviceRadixSort::SortPairs(h->temp, h->temp_bytes, h->keys, h->keys2, h->idx,
-                                           h->order, (int)h->N, 0, 30, h->st) != hipSuccess)
+                           h->keys, h->skey, h->idx, h->counts);
+    // 24-bit keys (sort_key): stable, so equal hues keep raster order
+    if (hipcub::DeviceRadixSort::SortPairs(h->temp, h->temp_bytes, h->skey, h->skey2, h->idx,
+                                           h->order, (int)h->N, 0, 24, h->st) != hipSuccess)
         return OT_ERR_HIP;
     hipLaunchKernelGGL(k_hue_rank, dim3(blocks_for(h->N, kThreads)), dim3(kThreads), 0, h->st,
                        h->order, h->N, h->rank);

@@ -301,3 +301,18 @@ def test_bench_configuration_frames(othue):
         assert np.array_equal(bins[f].cpu().numpy(), k_ref)
         assert np.array_equal(out[f].cpu().numpy(), rgb_ref)
     r.close()
+
+
+def test_random_pixel_image_order(othue):
+    """Uniformly random pixels: many distinct, close hues, so the output bins
+    depend on the exact strict order of the source's hues."""
+    import torch
+    _say("hue random pixels")
+    rng = np.random.default_rng(77)
+    img = rng.integers(0, 256, size=(300, 301, 3), dtype=np.uint8)
+    for n in (7, 360, 4096):
+        r = _renderer(othue, img, n)
+        src = ref.Source(img, n)
+        _frame_check(r, src, inputs.von_mises_hist(90 + n, n))
+        _frame_check(r, src, np.roll(src.density(), n // 5))
+        r.close()
