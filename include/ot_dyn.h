@@ -68,6 +68,14 @@ extern "C" {
 #define OT_INIT_PRIMAL_DUAL  2  /* caller-filled (F, M); b = b_bar = grad J(Kx+c)/sigma,
                                    the centred density floored at 1e-3 times
                                    the mean of f0 (near-vacuum nodes)        */
+/* Flag, OR-ed into OT_INIT_PRIMAL or OT_INIT_PRIMAL_DUAL (ot_dyn_init,
+ * ot_dyn_batch_set_state): the next ot_dyn_solve / ot_dyn_batch_solve
+ * certifies the warm start or falls back to Algorithm 1's cold start.  A
+ * warm-started problem that is not certified within max_iters (or whose
+ * residual turns non-finite) is initialised cold and solved again with a
+ * budget of another max_iters; its report has fallback = 1 and counts the
+ * iterations of both runs.  The flag is consumed by that one solve. */
+#define OT_INIT_FALLBACK     4
 
 /* FP32 accuracy of the projection onto the continuity constraint (Sec. 3,
  * Step 1: x = a - A^T (A A^T)^+ (A a - f_b^-)).  The transform solve in FP32
@@ -111,6 +119,10 @@ typedef struct ot_dyn_desc {
                               problems, slows the RGB ones: off by default */
     int prox;              /* root of the prox cubic (Sec. 3, Step 2):
                               OT_PROX_NEWTON or OT_PROX_CLOSED */
+    int carry_refine;      /* OT_REFINE_CARRY: the first carry_refine
+                              iterations after ot_dyn_init also run the
+                              refinement solve (early on the carried
+                              potential predicts little); >= 0, default 64 */
 } ot_dyn_desc;
 
 typedef struct ot_dyn_report {
@@ -125,6 +137,8 @@ typedef struct ot_dyn_report {
     double e_mass;         /* max_k |sum f(., k/P) - M0| / M0 (max over batch) */
     double mass0, mass1;   /* FP64 masses of f0 and f1 (problem 0)            */
     double ms;             /* wall time of the call in milliseconds           */
+    int fallback;          /* 1 if a warm start was abandoned for a cold start
+                              (OT_INIT_FALLBACK); batches: the count        */
 } ot_dyn_report;
 
 typedef struct ot_dyn_plan ot_dyn_plan;
@@ -132,7 +146,8 @@ typedef struct ot_dyn_plan ot_dyn_plan;
 /* Fill *d with the defaults for an X x Y x C x P grid: bc = {Neumann,
  * Neumann, periodic}, extent = 1, tau = 10, sigma = 0.099, theta = 1,
  * check_every = 50, tol_res = 1e-6, tol_div = 1e-6, tol_mass = 1e-5,
- * refine = OT_REFINE_CARRY, batch = 1, adapt = 0, prox = OT_PROX_NEWTON. */
+ * refine = OT_REFINE_CARRY, batch = 1, adapt = 0, prox = OT_PROX_NEWTON,
+ * carry_refine = 64. */
 int ot_dyn_default_desc(ot_dyn_desc* d, int X, int Y, int C, int P);
 
 /* Bytes of device workspace a plan for *d needs (OT_ERR_SHAPE/PARAM if *d
@@ -156,7 +171,8 @@ int ot_dyn_set_boundary(ot_dyn_plan* p, const float* f0, const float* f1);
 
 /* Initialise the iteration state.  Writes slices 0 and P of F, the Neumann
  * wall slots of Mx/My/Mc and, for OT_INIT_COLD, zeros the unknowns
- * (Algorithm 1 initialisation).  The duals live in the workspace. */
+ * (Algorithm 1 initialisation).  The duals live in the workspace.  `mode`
+ * is one of OT_INIT_*, optionally with OT_INIT_FALLBACK (warm modes only). */
 int ot_dyn_init(ot_dyn_plan* p, int mode, float* F, float* Mx, float* My, float* Mc);
 
 /* Run `iters` iterations of Algorithm 1 on the plan's stream without host
@@ -171,8 +187,16 @@ int ot_dyn_step(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc, int i
 int ot_dyn_solve(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
                  int max_iters, ot_dyn_report* rep);
 
-/* Residuals of the current state: runs one iteration with the residual
- * reductions enabled (FP64 accumulation) and fills *rep.  Synchronous. */
+/* Residuals of the current state (x, b) without iterating: the state is
+ * left bitwise unchanged.  FP64 reductions; synchronous.  Fills
+ *   r_div, e_mass   of x, as at a residual check;
+ *   r_prim, cost    from z = prox of J / sigma at K x + c + b (Sec. 3,
+ *                   Step 2): r_prim = ||K x + c - z|| / ||z|| and cost = cell
+ *                   volume * sum J(z); both vanish / reach the minimum at a
+ *                   fixed point of Algorithm 1;
+ *   r_dual          needs the previous iterate: the value of the last residual
+ *                   check since ot_dyn_init, or -1 if there was none.
+ * iterations = 0, converged = 0. */
 int ot_dyn_residuals(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
                      ot_dyn_report* rep);
 
@@ -199,6 +223,13 @@ int ot_dyn_profile(ot_dyn_plan* p, int mask);
 int ot_dyn_get_dual(ot_dyn_plan* p, float* b);
 int ot_dyn_set_dual(ot_dyn_plan* p, const float* b);
 
+/* The extrapolated dual b_bar = b + theta (b - b_old) of Step 4, which the
+ * next iteration's Step 1 reads, copied to b_bar [batch][4][P][C][Y][X]
+ * (device); with b (ot_dyn_get_dual) and (F, M) it is the whole state the
+ * next iteration depends on (up to FP32 rounding of the projection).
+ * Asynchronous on the plan's stream. */
+int ot_dyn_get_dual_bar(ot_dyn_plan* p, float* b_bar);
+
 /* Synchronise the stream and return, per phase (n <= OT_PHASE_COUNT
  * entries), the accumulated milliseconds and launch counts since the last
  * ot_dyn_profile call.  ms and launches are host arrays of n entries. */
@@ -212,8 +243,9 @@ int ot_dyn_destroy(ot_dyn_plan* p);
  * periodic hue histograms of different bin counts -- Sec. 5 of the paper
  * transports such histograms with X = bins, Y = C = 1, bc[0] periodic)
  * solved together.  Problems are grouped by shape; each group is one batched
- * plan, and all groups' iterations run as one captured HIP graph with a
- * concurrent branch per group.  Per-group launch shapes can be autotuned.
+ * plan whose chunk of iterations is captured into a HIP graph of its own,
+ * replayed on the group's own stream (one stream and graph per group).
+ * Per-group launch shapes can be autotuned.
  *
  * dims: host array of count x 4 ints (X, Y, C, P) per problem.  The other
  * descriptor fields (bc, extent, tau, sigma, theta, tolerances, refine,
@@ -251,7 +283,8 @@ int ot_dyn_batch_autotune(ot_dyn_batch* bt, int trials);
 /* Start the next ot_dyn_batch_solve from the caller's packed F and M
  * (device, layout of ot_dyn_batch_get_state) instead of a cold start: the
  * state is copied and initialised with `mode` (OT_INIT_PRIMAL or
- * OT_INIT_PRIMAL_DUAL, see ot_dyn_init).  Problems whose packed state is
+ * OT_INIT_PRIMAL_DUAL, see ot_dyn_init, optionally with OT_INIT_FALLBACK:
+ * then each problem not certified from its warm start is restarted cold).  Problems whose packed state is
  * not wanted warm can be given a cold state (zeros).  Consumed by the next
  * solve. */
 int ot_dyn_batch_set_state(ot_dyn_batch* bt, const float* F, const float* M, int mode);

@@ -99,6 +99,30 @@ def residuals(g: G.Grid, st: State, f0, f1, x_prev=None) -> dict:
     return out
 
 
+def state_residuals(g: G.Grid, x, b, f0, f1, sigma: float) -> dict:
+    """Residuals of a state (x, b) without iterating: z = prox of J / sigma at
+    K x + c + b (Sec. 3, Step 2, as in the next iteration's prox but with the
+    current x), then r_prim = ||K x + c - z|| / ||z|| and cost = cell volume *
+    sum J(z); at a fixed point of Algorithm 1 z = K x + c, so r_prim = 0 and
+    the cost is the objective at x.  Also r_div and e_mass of x."""
+    f0 = np.asarray(f0, dtype=np.float64)
+    f1 = np.asarray(f1, dtype=np.float64)
+    kx = G.K_apply(g, x, f0, f1)
+    am = np.stack([kx[i] + b[i] for i in range(3)])
+    af = kx[3] + b[3]
+    u, v = prox.prox(am, af, sigma)
+    z = (u[0], u[1], u[2], v)
+    out = {
+        "cost": g.cell_volume() * float(np.sum(prox.J(u, v))),
+        "r_prim": _norm([kx[i] - z[i] for i in range(4)]) / max(_norm(z), 1e-300),
+        "r_div": _norm([G.A_residual(g, x, f0, f1)]) / _norm([G.fb_minus(g, f0, f1)]),
+    }
+    M0 = float(np.sum(f0))
+    f = x[3]
+    out["e_mass"] = float(np.max(np.abs(np.sum(f, axis=(1, 2, 3)) - M0)) / M0) if f.shape[0] else 0.0
+    return out
+
+
 def solve(g: G.Grid, f0, f1, tau: float, sigma: float, iters: int,
           theta: float = 1.0, state: State = None, record_every: int = 0) -> State:
     """Run Algorithm 1 for a fixed number of iterations from a cold start

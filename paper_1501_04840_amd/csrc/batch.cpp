@@ -2,10 +2,10 @@
 //
 // Problems are grouped by shape (X, Y, C, P); a group is one batched plan
 // over group-contiguous buffers inside the caller's workspace.  A chunk of
-// iterations of every active group is captured into a HIP graph on the
-// group's own stream; the groups' graphs are launched on their streams, so
-// the small groups run concurrently on separate hardware queues and the
-// per-kernel launch cost is paid once per graph.  After each chunk the FP64
+// iterations of every active group is captured into a HIP graph of its own
+// and replayed on the group's own stream, so the per-kernel launch cost is
+// paid once per graph (in kernel traces the groups' graphs do not overlap on
+// the GPU: their streams give no concurrency).  After each chunk the FP64
 // residuals of every problem are
 // collected and certified problems are recorded; a group whose problems are
 // all certified leaves the graph.
@@ -44,6 +44,9 @@ struct Group {
     float *f0 = nullptr, *f1 = nullptr;
     bool active = true;
     std::vector<int> conv_iter;    // per member: iteration of certification, -1 if none
+    std::vector<char> fell_back;   // per member: restarted cold after its warm start
+    std::vector<int> deadline;     // per member: last iteration of its current run
+    std::vector<int> stopped;      // per member: iteration it stopped uncertified, -1 if running
     std::vector<ot_dyn_report> rep;
     int row_bx = 0, dense_xy = 0;
     hipGraph_t graph = nullptr;       // chunk of iterations captured on `side`
@@ -134,6 +137,7 @@ struct ot_dyn_batch {
     Plan P;
     bool have_boundary = false;
     bool warm = false;         // the next solve starts from ot_dyn_batch_set_state
+    bool fallback = false;     // ... and restarts uncertified problems cold (OT_INIT_FALLBACK)
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
     int graph_chunk = 0;
@@ -166,8 +170,7 @@ void drop_graph(ot_dyn_batch* bt) {
 }
 
 // Capture `chunk` iterations (the last one with residual partials) of every
-// active group, one graph per group on the group's own stream; the groups'
-// graphs are launched on their streams and run concurrently.
+// active group, one graph per group on the group's own stream.
 int build_graph(ot_dyn_batch* bt, int chunk) {
     drop_graph(bt);
     bool varies = false;
@@ -262,6 +265,7 @@ int ot_dyn_batch_create(const ot_dyn_desc* base, int count, const int* dims, voi
         st = ot_dyn_create(&g.d, g.side, bt->ws + g.off_plan, g.plan_bytes, &g.plan);
         if (st != OT_OK) return fail(st);
         g.conv_iter.assign(g.members.size(), -1);
+        g.fell_back.assign(g.members.size(), 0);
         g.rep.assign(g.members.size(), ot_dyn_report{});
     }
     *out = bt;
@@ -375,14 +379,34 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
         }
         g.active = true;
         std::fill(g.conv_iter.begin(), g.conv_iter.end(), -1);
+        std::fill(g.fell_back.begin(), g.fell_back.end(), 0);
+        g.deadline.assign(g.members.size(), max_iters);
+        g.stopped.assign(g.members.size(), -1);
         const int st = plan_freeze(g.plan, std::vector<char>(g.members.size(), 0));
         if (st != OT_OK) return st;
     }
+    // OT_INIT_FALLBACK: a warm start that is not certified by its deadline
+    // (or turns non-finite) restarts cold with a deadline max_iters later
+    const bool fallback = bt->warm && bt->fallback;
     bt->warm = false;
+    bt->fallback = false;
     for (auto& g : bt->P.groups) BCHK(bt, hipStreamSynchronize(g.side));
-    int done = 0, status = OT_NOT_CONVERGED;
-    while (done < max_iters) {
-        const int k = std::min(chunk, max_iters - done);
+    int done = 0;
+    while (true) {
+        // next residual check: one chunk on, or the earliest deadline of a
+        // member still running
+        int next = done + chunk;
+        bool running = false;
+        for (auto& g : bt->P.groups) {
+            if (!g.active) continue;
+            for (size_t j = 0; j < g.members.size(); ++j)
+                if (g.conv_iter[j] < 0 && g.stopped[j] < 0) {
+                    next = std::min(next, g.deadline[j]);
+                    running = true;
+                }
+        }
+        if (!running) break;
+        const int k = next - done;
         if (bt->graph_groups.empty() || bt->graph_chunk != k || bt->graph_varies) {
             const int st = build_graph(bt, k);
             if (st != OT_OK) return st;
@@ -393,33 +417,58 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
         }
         for (int gi : bt->graph_groups) BCHK(bt, hipStreamSynchronize(bt->P.groups[gi].side));
         done += k;
-        bool any_active = false, changed = false;
+        bool changed = false;
         for (int gi : bt->graph_groups) {
             Group& g = bt->P.groups[gi];
             plan_add_iters(g.plan, k);
             const int st = plan_collect(g.plan, g.F, g.Mx, g.My, g.Mc);
-            if (st != OT_OK) { bt->err = ot_dyn_last_error(g.plan); return st; }
-            bool all = true;
-            for (size_t j = 0; j < g.members.size(); ++j) {
+            if (st != OT_OK && st != OT_ERR_NONFINITE) { bt->err = ot_dyn_last_error(g.plan); return st; }
+            const size_t n = g.members.size();
+            std::vector<char> restart(n, 0);
+            bool any_restart = false, any_running = false;
+            for (size_t j = 0; j < n; ++j) {
+                if (g.conv_iter[j] >= 0 || g.stopped[j] >= 0) continue;   // frozen: report kept
                 ot_dyn_report& r = g.rep[j];
                 plan_problem(g.plan, (int)j, &r);
-                const bool ok = std::max(r.r_prim, r.r_dual) < g.d.tol_res && r.r_div < g.d.tol_div;
-                if (ok && g.conv_iter[j] < 0) g.conv_iter[j] = done;
+                const bool finite = std::isfinite(r.r_prim) && std::isfinite(r.r_dual) &&
+                                    std::isfinite(r.r_div) && std::isfinite(r.cost);
+                const bool ok = finite && std::max(r.r_prim, r.r_dual) < g.d.tol_res &&
+                                r.r_div < g.d.tol_div;
+                if (ok) {
+                    g.conv_iter[j] = done;
+                } else if (!finite || done >= g.deadline[j]) {
+                    if (fallback && !g.fell_back[j]) {
+                        restart[j] = 1;
+                        any_restart = true;
+                        g.fell_back[j] = 1;
+                        g.deadline[j] = done + max_iters;
+                    } else if (!finite) {
+                        char buf[160];
+                        std::snprintf(buf, sizeof buf, "problem %d: non-finite residual",
+                                      g.members[j]);
+                        bt->err = buf;
+                        return OT_ERR_NONFINITE;
+                    } else {
+                        g.stopped[j] = done;
+                    }
+                }
                 r.iterations = g.conv_iter[j] >= 0 ? g.conv_iter[j] : done;
                 r.converged = g.conv_iter[j] >= 0;
                 r.total_iterations = done;
-                all = all && g.conv_iter[j] >= 0;
+                r.fallback = g.fell_back[j];
+                any_running = any_running || (g.conv_iter[j] < 0 && g.stopped[j] < 0);
             }
-            if (all) { g.active = false; changed = true; }
-            any_active = any_active || g.active;
-            // certified members keep their certified state: the stencil and
-            // colour/time kernels of the remaining chunks skip them
-            if (g.active) {
-                std::vector<char> frozen(g.members.size());
-                for (size_t j = 0; j < g.members.size(); ++j) frozen[j] = g.conv_iter[j] >= 0;
-                const int fst = plan_freeze(g.plan, frozen);
-                if (fst != OT_OK) { bt->err = ot_dyn_last_error(g.plan); return fst; }
+            if (!any_running) { g.active = false; changed = true; continue; }
+            // certified (and stopped) members keep their state: the stencil
+            // and colour/time kernels of the remaining chunks skip them
+            std::vector<char> frozen(n);
+            for (size_t j = 0; j < n; ++j) frozen[j] = g.conv_iter[j] >= 0 || g.stopped[j] >= 0;
+            int fst = plan_freeze(g.plan, frozen);
+            if (fst == OT_OK && any_restart) {
+                fst = plan_restart_cold(g.plan, g.F, g.Mx, g.My, g.Mc, restart);
+                changed = true;
             }
+            if (fst != OT_OK) { bt->err = ot_dyn_last_error(g.plan); return fst; }
         }
         if (changed) drop_graph(bt);
         if (verbose) {
@@ -432,16 +481,19 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
             std::fprintf(stderr, "ot_dyn_batch: %d iterations, %d/%d certified, %d groups active, %.2f s\n",
                          done, nconv, bt->count, nact, el);
         }
-        if (!any_active) { status = OT_OK; break; }
     }
+    int nconv = 0;
+    for (auto& g : bt->P.groups)
+        for (int c : g.conv_iter) nconv += c >= 0;
+    const int status = nconv == bt->count ? OT_OK : OT_NOT_CONVERGED;
     if (rep) {
         std::memset(rep, 0, sizeof(*rep));
-        int nconv = 0, worst = 0;
+        int worst = 0, nfb = 0;
         double wv = -1.0;
         for (int i = 0; i < bt->count; ++i) {
             const Group& g = bt->P.groups[bt->P.group_of[i]];
             const ot_dyn_report& r = g.rep[bt->P.index_in_group[i]];
-            nconv += r.converged;
+            nfb += r.fallback;
             rep->r_prim = std::max(rep->r_prim, r.r_prim);
             rep->r_dual = std::max(rep->r_dual, r.r_dual);
             rep->r_div = std::max(rep->r_div, r.r_div);
@@ -452,6 +504,7 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
         rep->iterations = done;
         rep->total_iterations = done;
         rep->converged = nconv;
+        rep->fallback = nfb;
         rep->worst_problem = worst;
         rep->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -485,8 +538,11 @@ int ot_dyn_batch_get_state(ot_dyn_batch* bt, float* F, float* M) {
 
 int ot_dyn_batch_set_state(ot_dyn_batch* bt, const float* F, const float* M, int mode) {
     if (!bt || !F || !M) return OT_ERR_PARAM;
+    const bool fallback = (mode & OT_INIT_FALLBACK) != 0;
+    mode &= ~OT_INIT_FALLBACK;
     if (mode != OT_INIT_PRIMAL && mode != OT_INIT_PRIMAL_DUAL) {
-        bt->err = "set_state takes OT_INIT_PRIMAL or OT_INIT_PRIMAL_DUAL";
+        bt->err = "set_state takes OT_INIT_PRIMAL or OT_INIT_PRIMAL_DUAL (optionally with "
+                  "OT_INIT_FALLBACK)";
         return OT_ERR_PARAM;
     }
     if (!bt->have_boundary) { bt->err = "set the boundary first"; return OT_ERR_STATE; }
@@ -511,6 +567,7 @@ int ot_dyn_batch_set_state(ot_dyn_batch* bt, const float* F, const float* M, int
         BCHK(bt, hipStreamSynchronize(g.side));
     }
     bt->warm = true;
+    bt->fallback = fallback;
     return OT_OK;
 }
 

@@ -86,6 +86,11 @@ void launch_div_rows(const StepArgs& s, int mode, hipStream_t st);
 void launch_update_rows(const StepArgs& s, int check, int nphi, hipStream_t st);
 // FP64 partials of |A x - f_b^-|^2 and of the slice masses of F.
 void launch_resid_div(const StepArgs& s, hipStream_t st);
+// FP64 partials of the residual slots RS_DB2, RS_Z2, RS_X2 and RS_J (RS_DX2
+// zero) of the current state, z = prox(K x + c + b), nothing written but
+// part_red: one partial per block of the per-node grid, [RS_COUNT][B][P C
+// ceil(X Y / 256)].
+void launch_resid_state(const StepArgs& s, hipStream_t st);
 // Boundary slices, wall slots and (optionally) zero unknowns; zeroes Phi
 // when it is set.
 void launch_init_state(const StepArgs& s, const float* f0, const float* f1,
@@ -191,6 +196,11 @@ int plan_freeze(ot_dyn_plan* p, const std::vector<char>& frozen);
 // one after it (adaptive refinement; the refined start of OT_REFINE_CARRY):
 // a captured graph of iterations must then be captured again.
 bool plan_launch_varies(const ot_dyn_plan* p);
+// Restart the problems b with which[b] nonzero from Algorithm 1's cold
+// start (state, dual, carried potential, step sizes) and release them; the
+// others keep their state and frozen flags.  Synchronises the plan's stream.
+int plan_restart_cold(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
+                      const std::vector<char>& which);
 // Copy the dual b of problem b to (to_packed = 1) or from (0, also b_bar) a
 // packed [4][P][C][Y][X] array; asynchronous on the plan's stream.
 int plan_copy_dual(ot_dyn_plan* p, int b, float* packed, int to_packed);

@@ -61,6 +61,9 @@ struct ot_dyn_plan {
     bool have_init;
     int total_iters;
     int it_next;             // index of the next iteration to be issued
+    bool fallback_armed;     // OT_INIT_FALLBACK: the next solve may restart cold
+    int checks;              // residual checks since the last ot_dyn_init
+    int last_solve_iters;    // iterations of the last certified-solve loop
     std::vector<double> mass0, mass1, fbm2;
     std::vector<double> vfloor;     // per problem: 1e-3 * mean of f0 (warm-start dual)
     std::vector<double> r_prim, r_dual, r_div, cost, e_mass;
@@ -149,8 +152,9 @@ int validate(const ot_dyn_desc* d, std::string* why) {
     }
     if (d->check_every < 1 || !(d->tol_res > 0.0) || !(d->tol_div > 0.0) ||
         !(d->tol_mass >= 0.0) || d->refine < OT_REFINE_OFF || d->refine > OT_REFINE_CARRY ||
-        d->adapt < 0 || d->adapt > 1 || d->prox < OT_PROX_NEWTON || d->prox > OT_PROX_CLOSED) {
-        if (why) *why = "need check_every >= 1, tol_res > 0, tol_div > 0, tol_mass >= 0, refine in {0,1,2,3}, adapt in {0,1}, prox in {0,1}";
+        d->adapt < 0 || d->adapt > 1 || d->prox < OT_PROX_NEWTON || d->prox > OT_PROX_CLOSED ||
+        d->carry_refine < 0) {
+        if (why) *why = "need check_every >= 1, tol_res > 0, tol_div > 0, tol_mass >= 0, refine in {0,1,2,3}, adapt in {0,1}, prox in {0,1}, carry_refine >= 0";
         return OT_ERR_PARAM;
     }
     return OT_OK;
@@ -193,7 +197,10 @@ Layout layout_of(const ot_dyn_desc& d) {
     }
     const size_t nnode = (size_t)g.B * g.P * g.C * L.nbx_node;
     L.off_pslice = take((size_t)g.B * g.P * g.C * L.nbx * sizeof(double));
-    L.off_pred = take(RS_COUNT * (size_t)g.B * L.nred * sizeof(double));
+    // the residual partials also hold one per block of the per-node state
+    // residual kernel (ot_dyn_residuals)
+    const long long nred_cap = std::max<long long>(L.nred, (long long)g.P * g.C * L.nbx_node);
+    L.off_pred = take(RS_COUNT * (size_t)g.B * nred_cap * sizeof(double));
     L.off_pdiv = take(nnode * sizeof(double));
     L.off_pmass = take(nnode * sizeof(double));
     L.nblk_bnd = (int)std::min<long long>(64, (g.slice + 255) / 256);
@@ -367,11 +374,6 @@ bool refine_now(const ot_dyn_plan* p) {
     return false;
 }
 
-// Iterations after ot_dyn_init that OT_REFINE_CARRY also refines: early on
-// the iterates move fast and the carried potential predicts little, so the
-// residual it leaves is as large as the plain one.
-constexpr int kCarryRefine = 64;
-
 // One iteration of Algorithm 1; residual partials when `check`.
 void iterate(ot_dyn_plan* p, const StepArgs& s, bool check) {
     hipStream_t st = p->stream;
@@ -385,7 +387,9 @@ void iterate(ot_dyn_plan* p, const StepArgs& s, bool check) {
         // and with it the FP32 error of the transform solve.
         timed(p, OT_PHASE_DIV, [&] { launch_div(s, 2, st); });
         poisson(p, p->R);
-        const bool refine = it < kCarryRefine;
+        // early on the iterates move fast and the carried potential predicts
+        // little: the residual it leaves is as large as the plain one
+        const bool refine = it < p->d.carry_refine;
         if (refine) {   // r'' = A (a' + grad phi_1) - f_b^-, phi_2 = (A A^T)^+ r''
             timed(p, OT_PHASE_REFINE, [&] { launch_div(s, 1, st); });
             poisson(p, p->R2);
@@ -451,6 +455,55 @@ int collect(ot_dyn_plan* p, const StepArgs& s, bool have_iter) {
             !std::isfinite(p->r_div[b]) || !std::isfinite(p->cost[b]))
             finite = false;
     }
+    if (have_iter) p->checks += 1;
+    if (!finite) {
+        p->err = "non-finite residual";
+        return OT_ERR_NONFINITE;
+    }
+    return OT_OK;
+}
+
+// Residuals of the current state without iterating (ot_dyn_residuals):
+// r_div and the slice masses as in collect(), r_prim and the cost from z =
+// prox(K x + c + b).  Nothing of the state is written.
+int collect_state(ot_dyn_plan* p, const StepArgs& s) {
+    const Geom& g = p->g;
+    hipStream_t st = p->stream;
+    const int B = g.B;
+    const long long nslot = (long long)g.P * g.C * p->nbx_node;  // per problem
+    launch_resid_div(s, st);
+    launch_resid_state(s, st);
+    double* out_red = p->red_out;
+    double* out_div = out_red + RS_COUNT * B;
+    double* out_mass = out_div + B;
+    launch_reduce(p->part_red, nslot, RS_COUNT * B, out_red, st);
+    launch_reduce(p->part_div, nslot, B, out_div, st);
+    launch_reduce(p->part_mass, (long long)g.C * p->nbx_node, B * g.P, out_mass, st);
+    std::vector<double> h((size_t)RS_COUNT * B + B + (size_t)B * g.P);
+    HIPCHK(p, hipMemcpyAsync(h.data(), out_red, h.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+    HIPCHK(p, hipGetLastError());
+    double vol = 1.0 / g.P;
+    for (int a = 0; a < 3; ++a) vol *= p->d.extent[a] / axis_size(p->d, a);
+    bool finite = true;
+    for (int b = 0; b < B; ++b) {
+        const double db2 = h[RS_DB2 * B + b], z2 = h[RS_Z2 * B + b];
+        p->r_prim[b] = std::sqrt(db2) / std::max(std::sqrt(z2), 1e-300);
+        p->cost[b] = vol * h[RS_J * B + b];
+        if (p->checks == 0) p->r_dual[b] = -1.0;
+        p->r_div[b] = std::sqrt(h[RS_COUNT * B + b]) / std::max(std::sqrt(p->fbm2[b]), 1e-300);
+        double em = 0.0;
+        for (int k = 1; k < g.P; ++k) {
+            const double mk = h[(size_t)RS_COUNT * B + B + (size_t)b * g.P + k];
+            em = std::max(em, std::fabs(mk - p->mass0[b]) / p->mass0[b]);
+            if (!std::isfinite(mk)) finite = false;
+        }
+        p->e_mass[b] = em;
+        if (!std::isfinite(p->r_prim[b]) || !std::isfinite(p->r_div[b]) ||
+            !std::isfinite(p->cost[b]))
+            finite = false;
+    }
     if (!finite) {
         p->err = "non-finite residual";
         return OT_ERR_NONFINITE;
@@ -503,8 +556,8 @@ void fill_report(const ot_dyn_plan* p, ot_dyn_report* rep) {
     if (!rep) return;
     const int B = p->g.B;
     int worst = 0;
-    double wv = -1.0;
-    rep->r_prim = rep->r_dual = rep->r_div = rep->e_mass = 0.0;
+    double wv = -HUGE_VAL;
+    rep->r_prim = rep->r_dual = rep->r_div = rep->e_mass = -HUGE_VAL;
     for (int b = 0; b < B; ++b) {
         rep->r_prim = std::max(rep->r_prim, p->r_prim[b]);
         rep->r_dual = std::max(rep->r_dual, p->r_dual[b]);
@@ -519,6 +572,8 @@ void fill_report(const ot_dyn_plan* p, ot_dyn_report* rep) {
     rep->mass1 = p->mass1[0];
     rep->total_iterations = p->total_iters;
 }
+
+int solve_loop(ot_dyn_plan* p, const StepArgs& s, int max_iters);
 
 }  // namespace
 
@@ -537,6 +592,7 @@ int ot_dyn_default_desc(ot_dyn_desc* d, int X, int Y, int C, int P) {
     d->batch = 1;
     d->adapt = 0;
     d->prox = OT_PROX_NEWTON;
+    d->carry_refine = 64;
     return OT_OK;
 }
 
@@ -605,6 +661,9 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->last_res = 1.0;
     p->total_iters = 0;
     p->it_next = 0;
+    p->fallback_armed = false;
+    p->checks = 0;
+    p->last_solve_iters = 0;
     p->have_boundary = p->have_init = false;
     p->prof_mask = 0;
     p->ev_used = 0;
@@ -719,7 +778,13 @@ int ot_dyn_set_boundary(ot_dyn_plan* p, const float* f0, const float* f1) {
 int ot_dyn_init(ot_dyn_plan* p, int mode, float* F, float* Mx, float* My, float* Mc) {
     if (!p || !F || !Mx || !My || !Mc) return OT_ERR_PARAM;
     if (!p->have_boundary) { p->err = "ot_dyn_set_boundary must succeed first"; return OT_ERR_STATE; }
-    if (mode < OT_INIT_COLD || mode > OT_INIT_PRIMAL_DUAL) return OT_ERR_PARAM;
+    const bool fallback = (mode & OT_INIT_FALLBACK) != 0;
+    mode &= ~OT_INIT_FALLBACK;
+    if (mode < OT_INIT_COLD || mode > OT_INIT_PRIMAL_DUAL || (fallback && mode == OT_INIT_COLD)) {
+        p->err = "mode must be OT_INIT_COLD, OT_INIT_PRIMAL or OT_INIT_PRIMAL_DUAL (the last two "
+                 "optionally with OT_INIT_FALLBACK)";
+        return OT_ERR_PARAM;
+    }
     const StepArgs s = step_args(p, F, Mx, My, Mc);
     std::fill(p->sig_h.begin(), p->sig_h.end(), (float)p->d.sigma);
     std::fill(p->n_adapt.begin(), p->n_adapt.end(), 0);
@@ -742,6 +807,8 @@ int ot_dyn_init(ot_dyn_plan* p, int mode, float* F, float* Mx, float* My, float*
     p->total_iters = 0;
     p->it_next = 0;
     p->last_res = 1.0;
+    p->checks = 0;
+    p->fallback_armed = fallback;
     return OT_OK;
 }
 
@@ -761,6 +828,36 @@ int ot_dyn_solve(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc, int 
     if (!p->have_init) { p->err = "ot_dyn_init must succeed first"; return OT_ERR_STATE; }
     const auto t0 = std::chrono::steady_clock::now();
     const StepArgs s = step_args(p, F, Mx, My, Mc);
+    const bool fallback_armed = p->fallback_armed;
+    p->fallback_armed = false;
+    int status = solve_loop(p, s, max_iters);
+    int done = p->last_solve_iters;
+    bool fell_back = false;
+    if (fallback_armed && (status == OT_NOT_CONVERGED || status == OT_ERR_NONFINITE)) {
+        // the warm start did not certify: Algorithm 1 from its cold start
+        const int st = ot_dyn_init(p, OT_INIT_COLD, F, Mx, My, Mc);
+        if (st != OT_OK) return st;
+        status = solve_loop(p, s, max_iters);
+        done += p->last_solve_iters;
+        fell_back = true;
+    }
+    if (rep) {
+        fill_report(p, rep);
+        rep->iterations = done;
+        rep->converged = status == OT_OK;
+        rep->fallback = fell_back ? 1 : 0;
+        rep->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The certified-solve loop of ot_dyn_solve: chunks of check_every iterations,
+// the last of each with the residual reductions.
+int solve_loop(ot_dyn_plan* p, const StepArgs& s, int max_iters) {
     int done = 0, status = OT_NOT_CONVERGED;
     while (done < max_iters) {
         const int chunk = std::min(p->d.check_every, max_iters - done);
@@ -780,14 +877,13 @@ int ot_dyn_solve(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc, int 
         const int as = adapt_steps(p, s);
         if (as != OT_OK) { status = as; break; }
     }
-    if (rep) {
-        fill_report(p, rep);
-        rep->iterations = done;
-        rep->converged = status == OT_OK;
-        rep->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    }
+    p->last_solve_iters = done;
     return status;
 }
+
+}  // namespace
+
+extern "C" {
 
 int ot_dyn_residuals(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
                      ot_dyn_report* rep) {
@@ -795,14 +891,25 @@ int ot_dyn_residuals(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
     if (!p->have_init) { p->err = "ot_dyn_init must succeed first"; return OT_ERR_STATE; }
     const auto t0 = std::chrono::steady_clock::now();
     const StepArgs s = step_args(p, F, Mx, My, Mc);
-    const int cs = collect(p, s, false);
+    const int cs = collect_state(p, s);
     if (rep) {
         fill_report(p, rep);
         rep->iterations = 0;
         rep->converged = 0;
+        rep->fallback = 0;
         rep->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return cs;
+}
+
+int ot_dyn_get_dual_bar(ot_dyn_plan* p, float* b_bar) {
+    if (!p || !b_bar) return OT_ERR_PARAM;
+    if (!p->have_init) { p->err = "ot_dyn_init must succeed first"; return OT_ERR_STATE; }
+    const size_t nc = (size_t)p->g.nc, w = nc * sizeof(float);
+    for (int q = 0; q < 4; ++q)
+        HIPCHK(p, hipMemcpy2DAsync(b_bar + q * nc, 4 * w, p->bb[q], w, w, p->g.B,
+                                   hipMemcpyDeviceToDevice, p->stream));
+    return OT_OK;
 }
 
 int ot_dyn_get_dual(ot_dyn_plan* p, float* b) {
@@ -940,7 +1047,34 @@ void plan_add_iters(ot_dyn_plan* p, int n) { p->total_iters += n; }
 
 bool plan_launch_varies(const ot_dyn_plan* p) {
     if (p->d.refine == OT_REFINE_ADAPTIVE) return true;
-    return p->d.refine == OT_REFINE_CARRY && p->it_next < kCarryRefine;
+    return p->d.refine == OT_REFINE_CARRY && p->it_next < p->d.carry_refine;
+}
+
+int plan_restart_cold(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc,
+                      const std::vector<char>& which) {
+    // the init kernels skip frozen problems: freeze all but `which` for them
+    const StepArgs s = step_args(p, F, Mx, My, Mc);
+    const std::vector<float> keep = p->frz_h;
+    for (int b = 0; b < p->g.B; ++b) {
+        p->frz_h[b] = which[b] ? 0.f : 1.f;
+        if (!which[b]) continue;
+        p->sig_h[b] = (float)p->d.sigma;
+        p->n_adapt[b] = 0;
+        p->last_adapt[b] = p->total_iters;
+    }
+    const size_t nb = p->frz_h.size() * sizeof(float);
+    HIPCHK(p, hipMemcpyAsync(p->sig, p->sig_h.data(), nb, hipMemcpyHostToDevice, p->stream));
+    HIPCHK(p, hipMemcpyAsync(p->frz, p->frz_h.data(), nb, hipMemcpyHostToDevice, p->stream));
+    launch_init_state(s, p->f0, p->f1, 1, p->stream);
+    launch_zero_dual(s, p->stream);
+    HIPCHK(p, hipGetLastError());
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    for (int b = 0; b < p->g.B; ++b) p->frz_h[b] = which[b] ? 0.f : keep[b];
+    HIPCHK(p, hipMemcpyAsync(p->frz, p->frz_h.data(), nb, hipMemcpyHostToDevice, p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    p->it_next = 0;        // the restarted problems refine their start again
+    p->last_res = 1.0;
+    return OT_OK;
 }
 
 int plan_copy_dual(ot_dyn_plan* p, int b, float* packed, int to_packed) {

@@ -254,12 +254,65 @@ __global__ void __launch_bounds__(kBlock) k_resid_div(StepArgs s) {
     if (threadIdx.x == 0) s.part_mass[o] = t;
 }
 
-// Boundary slices of F, Neumann wall slots, optional zero unknowns.
+// Residuals of the current state (x, b) without iterating: z = prox(K x +
+// c + b) at the node (Sec. 3, Step 2), then |K x + c - z|^2, |z|^2, J(z) and
+// |x|^2 over the node's own faces.  Reads only; one FP64 partial per block
+// and slot in part_red ([RS_COUNT][B][P C nblk]).
+__global__ void __launch_bounds__(kBlock) k_resid_state(StepArgs s) {
+    const Geom& g = s.g;
+    const Node n = node_of(g);
+    double db2 = 0.0, z2 = 0.0, x2 = 0.0, jj = 0.0;
+    if (n.live) {
+        const long long row = n.cb + (long long)n.y * g.X;
+        auto fx = [&](int xx) -> float {
+            if (!g.perx) { if (xx <= 0 || xx >= g.X) return 0.f; }
+            else if (xx == g.X) xx = 0;
+            return s.Mx[row + xx];
+        };
+        auto fy = [&](int yy) -> float {
+            if (!g.pery) { if (yy <= 0 || yy >= g.Y) return 0.f; }
+            else if (yy == g.Y) yy = 0;
+            return s.My[n.cb + (long long)yy * g.X + n.x];
+        };
+        auto fc = [&](int cc) -> float {
+            if (!g.perc) { if (cc <= 0 || cc >= g.C) return 0.f; }
+            else if (cc == g.C) cc = 0;
+            return s.Mc[cidx(g, n.b, n.k, cc, n.p)];
+        };
+        const float mx0 = fx(n.x), my0 = fy(n.y), mc0 = fc(n.c);
+        const float f0 = s.F[fidx(g, n.b, n.k, n.c, n.p)];
+        const float f1 = s.F[fidx(g, n.b, n.k + 1, n.c, n.p)];
+        const float kx = 0.5f * (mx0 + fx(n.x + 1)), ky = 0.5f * (my0 + fy(n.y + 1));
+        const float kc = 0.5f * (mc0 + fc(n.c + 1)), kf = 0.5f * (f0 + f1);
+        const long long i = n.cb + n.p;
+        float ux, uy, uc, vv;
+        prox_J(kx + s.b[0][i], ky + s.b[1][i], kc + s.b[2][i], kf + s.b[3][i], s.sig[n.b], ux, uy,
+               uc, vv, s.prox);
+        const double ex = (double)kx - ux, ey = (double)ky - uy, ec = (double)kc - uc;
+        const double ef = (double)kf - vv;
+        db2 = ex * ex + ey * ey + ec * ec + ef * ef;
+        const double u2 = (double)ux * ux + (double)uy * uy + (double)uc * uc;
+        z2 = u2 + (double)vv * vv;
+        jj = vv > 0.f ? u2 / (2.0 * vv) : 0.0;
+        const double nf = n.k > 0 ? (double)f0 : 0.0;
+        x2 = (double)mx0 * mx0 + (double)my0 * my0 + (double)mc0 * mc0 + nf * nf;
+    }
+    const long long nblk = (long long)gridDim.x * gridDim.y;
+    const long long o = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    const double vals[RS_COUNT] = {db2, z2, 0.0, x2, jj};
+    for (int q = 0; q < RS_COUNT; ++q) {
+        const double t = block_sum(vals[q]);
+        if (threadIdx.x == 0) s.part_red[q * nblk + o] = t;
+    }
+}
+
+// Boundary slices of F, Neumann wall slots, optional zero unknowns; frozen
+// problems are left alone (ot_dyn_init releases every problem first).
 __global__ void __launch_bounds__(kBlock) k_init_state(StepArgs s, const float* f0,
                                                        const float* f1, int zero) {
     const Geom& g = s.g;
     const Node n = node_of(g);
-    if (!n.live) return;
+    if (!n.live || s.frz[n.b] != 0.f) return;
     const long long i = n.cb + n.p;
     const long long e = (long long)n.b * g.slice + (long long)n.c * g.plane + n.p;
     if (n.k == 0) s.F[fidx(g, n.b, 0, n.c, n.p)] = f0[e];
@@ -278,7 +331,7 @@ __global__ void __launch_bounds__(kBlock) k_init_state(StepArgs s, const float* 
 __global__ void __launch_bounds__(kBlock) k_zero_dual(StepArgs s) {
     const Geom& g = s.g;
     const Node n = node_of(g);
-    if (!n.live) return;
+    if (!n.live || s.frz[n.b] != 0.f) return;
     const long long i = n.cb + n.p;
     for (int q = 0; q < 4; ++q) { s.b[q][i] = 0.f; s.bb[q][i] = 0.f; }
 }
@@ -417,6 +470,10 @@ void launch_prox_eval(int kind, long long n, const float* am, const float* af, f
 
 void launch_resid_div(const StepArgs& s, hipStream_t st) {
     hipLaunchKernelGGL(k_resid_div, node_grid(s.g), dim3(kBlock), 0, st, s);
+}
+
+void launch_resid_state(const StepArgs& s, hipStream_t st) {
+    hipLaunchKernelGGL(k_resid_state, node_grid(s.g), dim3(kBlock), 0, st, s);
 }
 
 void launch_init_state(const StepArgs& s, const float* f0, const float* f1,

@@ -15,7 +15,9 @@ import os
 from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_size_t, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libotdyn.so")
+# OT_DYN_LIB selects another build of the library (the host-sanitized one
+# of build.py); by default the in-tree libotdyn.so
+LIB_PATH = os.environ.get("OT_DYN_LIB") or os.path.join(HERE, "libotdyn.so")
 
 OT_OK = 0
 OT_NOT_CONVERGED = 1
@@ -42,6 +44,7 @@ PHASE_NAMES = ["div", "xform_x", "xform_y", "tc", "refine", "update"]
 OT_INIT_COLD = 0
 OT_INIT_PRIMAL = 1
 OT_INIT_PRIMAL_DUAL = 2
+OT_INIT_FALLBACK = 4
 
 OT_REFINE_OFF = 0
 OT_REFINE_ALWAYS = 1
@@ -65,6 +68,7 @@ class ot_dyn_desc(ctypes.Structure):
         ("batch", c_int),
         ("adapt", c_int),
         ("prox", c_int),
+        ("carry_refine", c_int),
     ]
 
 
@@ -75,6 +79,7 @@ class ot_dyn_report(ctypes.Structure):
         ("r_prim", c_double), ("r_dual", c_double), ("r_div", c_double),
         ("cost", c_double), ("e_mass", c_double),
         ("mass0", c_double), ("mass1", c_double), ("ms", c_double),
+        ("fallback", c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -94,6 +99,7 @@ EXPORTS = [
     "ot_dyn_set_boundary", "ot_dyn_init", "ot_dyn_step", "ot_dyn_solve",
     "ot_dyn_residuals", "ot_dyn_destroy", "ot_dyn_status_str", "ot_dyn_last_error",
     "ot_dyn_profile", "ot_dyn_profile_read", "ot_dyn_get_dual", "ot_dyn_set_dual",
+    "ot_dyn_get_dual_bar",
     "ot_dyn_batch_workspace_size", "ot_dyn_batch_create", "ot_dyn_batch_offsets",
     "ot_dyn_batch_set_boundary", "ot_dyn_batch_autotune", "ot_dyn_batch_solve",
     "ot_dyn_batch_problem", "ot_dyn_batch_get_state", "ot_dyn_batch_set_state",
@@ -141,6 +147,7 @@ def lib() -> ctypes.CDLL:
     L.ot_dyn_batch_set_dual.argtypes = [P, P]
     L.ot_dyn_get_dual.argtypes = [P, P]
     L.ot_dyn_set_dual.argtypes = [P, P]
+    L.ot_dyn_get_dual_bar.argtypes = [P, P]
     L.ot_dyn_batch_tuning.argtypes = [P, c_int, POINTER(c_int), POINTER(c_int)]
     L.ot_dyn_batch_destroy.argtypes = [P]
     L.ot_dyn_batch_last_error.argtypes = [P]
@@ -231,6 +238,11 @@ def ot_dyn_get_dual(plan: int, b) -> int:
 def ot_dyn_set_dual(plan: int, b) -> int:
     """Set the dual b (and b_bar = b) from b [batch][4][P][C][Y][X] (device)."""
     return _check(lib().ot_dyn_set_dual(plan, _ptr(b)), plan)
+
+
+def ot_dyn_get_dual_bar(plan: int, b_bar) -> int:
+    """Copy the extrapolated dual b_bar into b_bar [batch][4][P][C][Y][X] (device)."""
+    return _check(lib().ot_dyn_get_dual_bar(plan, _ptr(b_bar)), plan)
 
 
 def ot_dyn_profile(plan: int, mask: int) -> int:
@@ -401,6 +413,14 @@ class Problem:
 
     def set_dual(self, b):
         return ot_dyn_set_dual(self.plan, b)
+
+    def get_dual_bar(self):
+        """The extrapolated dual b_bar as a device tensor [B, 4, P, C, Y, X] (a copy)."""
+        import torch
+        d = self.desc
+        b = torch.empty((d.batch, 4, d.P, d.C, d.Y, d.X), dtype=torch.float32, device=self.device)
+        ot_dyn_get_dual_bar(self.plan, b)
+        return b
 
     def step(self, iters: int):
         return ot_dyn_step(self.plan, *self.state(), iters)

@@ -121,3 +121,40 @@ def test_hue_renderer_rejects_bad_sizes(L):
     assert lib.ot_hue_rgb_to_hsv(None, 5, None, None) == L.OT_ERR_PARAM
     assert lib.ot_hue_hsv_to_rgb(None, -1, None, None) == L.OT_ERR_PARAM
     assert lib.ot_hue_rgb_to_hsv(None, 0, None, None) == L.OT_OK
+
+
+def test_batch_grouping_and_workspace_on_the_host(L):
+    """Batch grouping and workspace layout are host logic (no GPU call): the
+    1024 hue problems of uneven sizes, RGB problems of several resolutions,
+    and the argument checks of the batch entry points."""
+    from synth import inputs
+    base = L.ot_dyn_default_desc(1, 1, 1, 2)
+    base.bc[0] = L.OT_BC_PERIODIC
+    dims = [(n, 1, 1, T) for n, T, _, _ in inputs.cfg4_problems(1024)]
+    total = L.ot_dyn_batch_workspace_size(base, dims)
+    cells = sum(n * T for n, _, _, T in dims)
+    assert total > 15 * 4 * cells
+    per_shape = {}
+    for dd in dims:
+        per_shape[dd] = per_shape.get(dd, 0) + 1
+    assert len(per_shape) <= 10
+    rgb = [(16, 16, 3, 8), (24, 20, 3, 8), (16, 16, 3, 8), (64, 1, 1, 16), (30, 1, 1, 8)]
+    assert L.ot_dyn_batch_workspace_size(L.ot_dyn_default_desc(1, 1, 3, 2), rgb) > 0
+    for bad, status in [([(0, 1, 1, 8)], L.OT_ERR_SHAPE), ([(8, 1, 1, 1)], L.OT_ERR_SHAPE),
+                        ([], L.OT_ERR_PARAM)]:
+        with pytest.raises(L.OtDynError) as e:
+            L.ot_dyn_batch_workspace_size(base, bad)
+        assert e.value.status == status
+    with pytest.raises(L.OtDynError) as e:
+        L.ot_dyn_batch_create(base, rgb, 0, 0, 1 << 20)     # null workspace
+    assert e.value.status == L.OT_ERR_SHAPE
+
+
+@pytest.mark.parametrize("field,value", [("carry_refine", -1)])
+def test_descriptor_validation_new_fields(L, field, value):
+    d = L.ot_dyn_default_desc(16, 16, 3, 8)
+    assert d.carry_refine == 64
+    setattr(d, field, value)
+    with pytest.raises(L.OtDynError) as e:
+        L.ot_dyn_workspace_size(d)
+    assert e.value.status == L.OT_ERR_PARAM

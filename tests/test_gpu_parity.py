@@ -176,6 +176,9 @@ def test_cfg2_2000_iterations_against_stored_oracle(otdyn, mode):
     _, rep = prob.solve(1)
     F = host(prob)[0]
     f = F[1:P]
+    full = np.load(os.path.join(HERE, "golden", "cfg2_2000_f.npy"))
+    assert full.shape == f.shape
+    assert rel(f, full) < TOL              # every interior density value
     idx = np.asarray(gold["sample_index"])
     assert rel(f.ravel()[idx], gold["sample_f"]) < TOL
     assert abs(np.linalg.norm(f) - gold["f_norm"]) <= TOL * gold["f_norm"]
@@ -320,34 +323,52 @@ def test_solve_certifies_and_reports(otdyn, mode):
     prob.close()
 
 
-def test_balanced_solve_reaches_the_oracle_solution(otdyn):
-    """With per-problem step balancing the iterates leave the fixed-step
-    trajectory; the certified result must still be the oracle's solution:
-    the same cost (1e-5) as the fixed-step oracle run to its own
-    certification.  The certificate bounds residuals, not the distance to
-    the minimiser: two certified iterates of this problem differ by about
-    6e-4 in the density, so the density is compared at 2e-3."""
-    _say("balanced certified solve")
+def test_certified_solves_reach_the_oracle_minimiser(otdyn):
+    """Certified results against the minimiser of the discrete model (the
+    oracle's Algorithm 1 run to max(r_prim, r_dual) < 1e-12, written by
+    tests/golden/make_golden.py).  The certificate bounds residuals, not the
+    distance to the minimiser.  What it implies on this problem, measured:
+    the oracle's own fixed-step iterate at its first certified check (tol_res
+    1e-6) is `certified_f_distance` = 4.4e-5 (relative L2) from the
+    minimiser in f.  The GPU's fixed-step certified result is the same
+    iterate (within 1.5x that distance); certified at 1e-7 it is ten times
+    closer.  With the per-problem balancing of the step sizes the residuals
+    are those of different steps (r_dual is the primal change per step and
+    scales with tau), so one tolerance implies a larger distance: measured
+    6.5e-4 at 1e-6 and 8e-5 at 1e-7.  The cost is within 1e-5 of the minimal
+    cost in every case."""
+    _say("certified solves vs the converged minimiser")
     import torch
+    gold = json.load(open(os.path.join(HERE, "golden", "cfg1_converged.json")))
+    ref = np.load(os.path.join(HERE, "golden", "cfg1_converged.npz"))
     g = G.Grid(16, 16, 3, 8)
     f0, f1 = inputs.cfg1_pair()
-    res = {}
-    for adapt in (0, 1):
+    d_cert = gold["certified_f_distance"]
+    out = {}
+    for adapt, tol in ((0, 1e-6), (0, 1e-7), (1, 1e-6), (1, 1e-7)):
         d = otdyn.ot_dyn_default_desc(16, 16, 3, 8)
         d.check_every = 100
         d.adapt = adapt
+        d.tol_res = tol
         prob = otdyn.Problem(d, "cuda")
         prob.set_boundary(torch.from_numpy(f0), torch.from_numpy(f1))
         prob.init()
-        status, rep = prob.solve(40000)
-        assert status == otdyn.OT_OK, (adapt, rep.as_dict())
-        res[adapt] = (rep.iterations, rep.cost, host(prob)[0][1:8])
+        status, rep = prob.solve(60000)
+        gx = to_natural(g, *host(prob))
         prob.close()
-    st = oracle(g, f0, f1, res[0][0])
-    ref_cost = st.hist[-1]["cost"]
-    assert abs(res[1][1] - ref_cost) <= TOL * ref_cost
-    assert rel(res[1][2], st.x[3]) < 2e-3
-    _say(f"iterations fixed {res[0][0]}, balanced {res[1][0]}")
+        assert status == otdyn.OT_OK, (adapt, tol, rep.as_dict())
+        out[(adapt, tol)] = (rep.iterations, abs(rep.cost - gold["cost"]) / gold["cost"],
+                             rel(gx[3], ref["f"]), max(rel(gx[a], ref[k]) for a, k in
+                                                       enumerate(("m_x", "m_y", "m_c"))))
+    _say(f"oracle certified at {gold['certified_at']} its, f distance {d_cert:.2e}; "
+         f"gpu (iterations, cost, f, m): {out}")
+    for key, (its, ecost, ef, em) in out.items():
+        assert ecost < TOL, (key, ecost)
+    assert out[(0, 1e-6)][0] == gold["certified_at"]
+    assert out[(0, 1e-6)][2] < 1.5 * d_cert
+    assert out[(0, 1e-7)][2] < 0.2 * d_cert
+    assert out[(1, 1e-6)][2] < 1e-3
+    assert out[(1, 1e-7)][2] < 0.2 * out[(1, 1e-6)][2]
 
 
 def test_error_paths(otdyn):

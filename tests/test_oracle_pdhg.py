@@ -202,3 +202,29 @@ def test_discrete_cost_converges_to_quadratic_transport():
     assert errs[1] < errs[0] / 2.5
     assert errs[2] < errs[1] / 2.5
     assert errs[2] < 5e-5
+
+
+def test_state_residuals_at_the_fixed_point_and_without_momentum():
+    """Residuals of a state without iterating (Sec. 3, Step 2 applied to the
+    current x and b): at the fixed point reached by Algorithm 1 the prox
+    returns K x + c itself, so r_prim vanishes and the cost is the direct
+    minimiser's objective; a state without momentum (b = 0, f > 0) is a fixed
+    point of the prox, J = 0 there, so r_prim and the cost are 0."""
+    g = G.Grid(5, 1, 1, 4, (G.NEUMANN, G.NEUMANN, G.NEUMANN))
+    f0, f1 = _pair((1, 1, 5), 5)
+    _, cost_d = direct.minimise(g, f0, f1)
+    st = pdhg.solve(g, f0, f1, TAU, SIGMA, 3000)
+    r = pdhg.state_residuals(g, st.x, st.b, f0, f1, SIGMA)
+    assert r["r_prim"] < 1e-10
+    assert r["cost"] == pytest.approx(cost_d, rel=1e-10)
+    assert r["r_div"] < 1e-12 and r["e_mass"] < 1e-12
+    # no momentum, positive density, zero dual
+    g = G.Grid(4, 3, 3, 4)
+    f0, f1 = _pair((3, 3, 4), 7)
+    x = G.zeros_primal(g)
+    x = (x[0], x[1], x[2], np.full(g.f_shape, 0.7))
+    r = pdhg.state_residuals(g, x, G.zeros_dual(g), f0, f1, SIGMA)
+    assert r["r_prim"] == 0.0 and r["cost"] == 0.0
+    # a state off the fixed point has a positive primal residual
+    st = pdhg.solve(g, f0, f1, TAU, SIGMA, 5)
+    assert pdhg.state_residuals(g, st.x, st.b, f0, f1, SIGMA)["r_prim"] > 1e-6
