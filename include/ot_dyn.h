@@ -330,6 +330,28 @@ int ot_dyn_batch_destroy(ot_dyn_batch* bt);
 /* Last error message recorded on the batch (never NULL). */
 const char* ot_dyn_batch_last_error(const ot_dyn_batch* bt);
 
+/* ---- solve without device allocation -----------------------------------
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): Algorithm 1 from its cold start to the
+ * certificate, as ot_dyn_create + ot_dyn_set_boundary + ot_dyn_init
+ * (OT_INIT_COLD) + ot_dyn_solve + ot_dyn_destroy, with the plan's workspace
+ * in a device array of OT_DYN_STATIC_BYTES owned by the library (one per
+ * GPU, held until the process ends) instead of the caller's.  The caller
+ * passes inputs and outputs only: f0, f1 [batch][C][Y][X] and F, Mx, My, Mc
+ * (layouts above), device pointers on the current device; `stream` as in
+ * ot_dyn_create.  Results are those of the calls it stands for.  Calls no
+ * hipMalloc, hipFree or other allocating routine.  Synchronous.
+ * Returns OT_ERR_SHAPE when ot_dyn_workspace_size(d) exceeds
+ * OT_DYN_STATIC_BYTES (e.g. 64 x 64 x 3 x 16 needs 12.2 MiB, 128 x 128 x 3
+ * x 16 49 MiB: use ot_dyn_create with a workspace), OT_ERR_PARAM for null
+ * pointers or max_iters < 1, else the status of ot_dyn_solve.  Every call
+ * on one GPU uses the same array: calls that overlap on one GPU (several
+ * host threads or streams) race and must be serialised by the caller. */
+#define OT_DYN_STATIC_BYTES (32u << 20)
+int ot_dyn_solve_static(const ot_dyn_desc* d, void* stream, const float* f0, const float* f1,
+                        float* F, float* Mx, float* My, float* Mc, int max_iters,
+                        ot_dyn_report* rep);
+
 /* Static description of a status code. */
 /* Pointwise prox of J / sigma (Sec. 3, Step 2) on n nodes, as the update
  * kernels compute it: (u, v) = argmin |u|^2 / (2 v) + sigma/2 |u - a_m|^2 +

@@ -29,7 +29,7 @@ SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=und
              "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
 
 SOURCES = ["stencil.hip", "stencil_rows.hip", "transform.hip", "fastdct.hip", "plan.cpp",
-           "batch.cpp", "otnet.hip", "net.cpp", "hue.hip"]
+           "batch.cpp", "otnet.hip", "net.cpp", "hue.hip", "solve_static.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

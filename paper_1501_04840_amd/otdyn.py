@@ -105,7 +105,7 @@ EXPORTS = [
     "ot_dyn_batch_problem", "ot_dyn_batch_get_state", "ot_dyn_batch_set_state",
     "ot_dyn_batch_get_dual", "ot_dyn_batch_set_dual",
     "ot_dyn_batch_tuning", "ot_dyn_batch_destroy", "ot_dyn_batch_last_error",
-    "ot_dyn_prox_eval",
+    "ot_dyn_prox_eval", "ot_dyn_solve_static",
 ]
 
 
@@ -153,6 +153,8 @@ def lib() -> ctypes.CDLL:
     L.ot_dyn_batch_last_error.argtypes = [P]
     L.ot_dyn_batch_last_error.restype = c_char_p
     L.ot_dyn_prox_eval.argtypes = [c_int, LL, P, P, ctypes.c_float, P, P, P]
+    L.ot_dyn_solve_static.argtypes = [POINTER(ot_dyn_desc), P, P, P, P, P, P, P, c_int,
+                                      POINTER(ot_dyn_report)]
     L.ot_dyn_status_str.argtypes = [c_int]
     L.ot_dyn_status_str.restype = c_char_p
     L.ot_dyn_last_error.argtypes = [P]
@@ -343,6 +345,18 @@ def ot_dyn_prox_eval(kind: int, am, af, sigma: float, u, v, stream=None) -> int:
     n = af.numel()
     return _check(lib().ot_dyn_prox_eval(kind, n, _ptr(am), _ptr(af), float(sigma), _ptr(u),
                                          _ptr(v), stream))
+
+
+OT_DYN_STATIC_BYTES = 32 << 20
+
+
+def ot_dyn_solve_static(d: ot_dyn_desc, stream, f0, f1, F, Mx, My, Mc, max_iters: int):
+    """Cold-start certified solve over the library's own device workspace (no
+    device allocation; problems whose workspace fits OT_DYN_STATIC_BYTES)."""
+    rep = ot_dyn_report()
+    st = _check(lib().ot_dyn_solve_static(byref(d), _ptr(stream), _ptr(f0), _ptr(f1), _ptr(F),
+                                          _ptr(Mx), _ptr(My), _ptr(Mc), max_iters, byref(rep)))
+    return st, rep
 
 
 def ot_dyn_batch_tuning(bt: int, i: int):
