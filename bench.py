@@ -53,11 +53,14 @@ KERNEL_WORDS = {
 }
 
 
-def kernel_name(phase, mode, C):
+def kernel_name(phase, mode, C, X=0, xfold=False, xkind=0):
     """Full name of the kernel a steady-state iteration launches for `phase`
-    (row stencils and power-of-two transforms; the five-pass path)."""
+    (row stencils and power-of-two transforms; the five-pass path).  With
+    xfold the divergence kernel also does the forward x transform (DCT-II,
+    xkind 0, or Hartley, 2) of its rows of length X."""
     if phase == "div":
-        return f"k_div_rows<{ {0: 0, 1: 0, 3: 2}[mode] }, {C}>"
+        return f"k_div_rows<{ {0: 0, 1: 0, 3: 2}[mode] }, {C}, {X if xfold else 0}, " \
+               f"{xkind if xfold else 0}>"
     if phase == "update":
         return f"k_update_rows<0, { {0: 1, 1: 2, 3: 3}[mode] }, {C}>"
     if phase == "refine":
@@ -455,6 +458,8 @@ def main():
     phases = otdyn.ot_dyn_profile_read(prob.plan)
     split = {}
     iter_words = 0.0
+    # one x pass per iteration: the forward one is folded into the divergence kernel
+    xfold = phases["xform_x"][1] == n_split
     for name, (ms, n) in phases.items():
         if n == 0:
             continue
@@ -462,7 +467,7 @@ def main():
         mw = METHOD_WORDS[name]
         iter_words += kw * n / n_split
         split[name] = {"ms_per_iter": ms / n_split, "launches": n, "avg_launch_us": 1e3 * ms / n,
-                       "kernel": kernel_name(name, mode, C),
+                       "kernel": kernel_name(name, mode, C, X, xfold),
                        "method_words_per_launch": mw, "kernel_words_per_launch": kw,
                        "algorithmic_GBs": mw * 4.0 * N * n / (ms * 1e-3) / 1e9,
                        "kernel_GBs": kw * 4.0 * N * n / (ms * 1e-3) / 1e9}

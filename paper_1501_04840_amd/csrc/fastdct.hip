@@ -12,11 +12,37 @@ namespace otd {
 // half a wave, per plane).
 constexpr int kSumPlanesPerBlock = 8;
 
+// One plane-sum block: kSumPlanesPerBlock planes of `ps` (32 lanes, half a
+// wave, per plane) reduced in place into slot 0 of each plane.  No block
+// synchronisation: such blocks return independently.
+__device__ __forceinline__ void plane_sums_block(const PlaneSums& ps, long long blk) {
+    const int l = threadIdx.x & 31;
+    const long long q = blk * kSumPlanesPerBlock + (threadIdx.x >> 5);
+    const bool live = q < ps.nq;
+    double* pp = ps.part + (live ? q : 0) * ps.nbx;
+    double acc = 0.0;
+    for (int i = l; i < ps.nbx; i += 32 * 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int ii = i + 32 * u;
+            v[u] = live && ii < ps.nbx ? pp[ii] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += v[u];
+    }
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 32);
+    // every lane's loads of this plane are consumed above, so slot 0 can be
+    // overwritten with the total
+    if (live && l == 0) pp[0] = acc;
+}
+
 // Contiguous axis: LPB whole rows per block, row pitch L + 1 in LDS.  The
 // block's rows are one contiguous span, staged with unrolled float4 loads
 // so that every thread keeps all of its loads in flight at once.  The first
-// nsb blocks instead reduce the FP64 plane sums `ps` in place (the forward
-// x pass runs between the divergence kernel that writes them and the
+// nsb blocks instead reduce the FP64 plane sums `ps` in place (the first
+// forward pass runs between the divergence kernel that writes them and the
 // colour/time pass that solves the spatial-DC line from them, so the
 // reduction costs no launch and leaves that pass a short serial part).
 template <int M1, int M2, int KIND>
@@ -26,27 +52,7 @@ __global__ void __launch_bounds__(256) k_rows_fft(float* R, long long rows, cons
     constexpr int NV = LPB * L / 1024;            // float4 per thread
     __shared__ float lds[LPB * PITCH];
     if ((int)blockIdx.x < nsb) {
-        // no block synchronisation in this role: blocks return independently
-        const int l = threadIdx.x & 31;
-        const long long q = (long long)blockIdx.x * kSumPlanesPerBlock + (threadIdx.x >> 5);
-        const bool live = q < ps.nq;
-        double* pp = ps.part + (live ? q : 0) * ps.nbx;
-        double acc = 0.0;
-        for (int i = l; i < ps.nbx; i += 32 * 16) {
-            double v[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int ii = i + 32 * u;
-                v[u] = live && ii < ps.nbx ? pp[ii] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) acc += v[u];
-        }
-#pragma unroll
-        for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 32);
-        // every lane's loads of this plane are consumed above, so slot 0
-        // can be overwritten with the total
-        if (live && l == 0) pp[0] = acc;
+        plane_sums_block(ps, blockIdx.x);
         return;
     }
     const long long r0 = (long long)(blockIdx.x - nsb) * LPB;
@@ -79,13 +85,22 @@ __global__ void __launch_bounds__(256) k_rows_fft(float* R, long long rows, cons
 // Strided axis: data [outer][L][inner]; a block transforms W = LPB columns,
 // stored transposed in LDS (pitch L + 1, conflict-free transposing writes).
 // VEC: inner is a multiple of 4, so the tile rows are loaded as float4.
+// One-dimensional grid: the first nsb blocks reduce the plane sums `ps` (as
+// in k_rows_fft, when this is the first forward pass), then ntiles column
+// tiles for each of the outer slabs.
 template <int M1, int M2, int KIND, bool VEC>
-__global__ void __launch_bounds__(256) k_cols_fft(float* R, long long inner, const float2* tw4) {
+__global__ void __launch_bounds__(256) k_cols_fft(float* R, long long inner, const float2* tw4,
+                                                  PlaneSums ps, int nsb, int ntiles) {
     constexpr int L = 2 * M1 * M2, T = M2, W = 256 / T, PITCH = L + 1;
     constexpr int W4 = W / 4, NV = L * W / 1024, NS = L * W / 256;
     __shared__ float lds[W * PITCH];
-    const long long o = blockIdx.y;
-    const long long i0 = (long long)blockIdx.x * W;
+    if ((int)blockIdx.x < nsb) {
+        plane_sums_block(ps, blockIdx.x);
+        return;
+    }
+    const long long blk = (long long)blockIdx.x - nsb;
+    const long long o = blk / ntiles;
+    const long long i0 = (blk - o * ntiles) * W;
     const int nw = (int)min((long long)W, inner - i0);
     float* g = R + o * L * inner + i0;
     if constexpr (VEC) {
@@ -159,19 +174,22 @@ static void rows_dispatch(float* R, long long rows, const float2* tw, int kind, 
 
 template <int M1, int M2, bool VEC>
 static void cols_dispatch_v(float* R, long long outer, long long inner, const float2* tw, int kind,
-                            hipStream_t st) {
+                            hipStream_t st, const PlaneSums* sums) {
     constexpr int W = 256 / M2;
-    const dim3 grid((unsigned)((inner + W - 1) / W), (unsigned)outer);
-    if (kind == 0) hipLaunchKernelGGL((k_cols_fft<M1, M2, 0, VEC>), grid, dim3(256), 0, st, R, inner, tw);
-    else if (kind == 1) hipLaunchKernelGGL((k_cols_fft<M1, M2, 1, VEC>), grid, dim3(256), 0, st, R, inner, tw);
-    else hipLaunchKernelGGL((k_cols_fft<M1, M2, 2, VEC>), grid, dim3(256), 0, st, R, inner, tw);
+    const PlaneSums ps = sums ? *sums : PlaneSums{nullptr, 0, 0};
+    const int nsb = (int)((ps.nq + kSumPlanesPerBlock - 1) / kSumPlanesPerBlock);
+    const int ntiles = (int)((inner + W - 1) / W);
+    const dim3 grid((unsigned)(ntiles * outer + nsb));
+    if (kind == 0) hipLaunchKernelGGL((k_cols_fft<M1, M2, 0, VEC>), grid, dim3(256), 0, st, R, inner, tw, ps, nsb, ntiles);
+    else if (kind == 1) hipLaunchKernelGGL((k_cols_fft<M1, M2, 1, VEC>), grid, dim3(256), 0, st, R, inner, tw, ps, nsb, ntiles);
+    else hipLaunchKernelGGL((k_cols_fft<M1, M2, 2, VEC>), grid, dim3(256), 0, st, R, inner, tw, ps, nsb, ntiles);
 }
 
 template <int M1, int M2>
 static void cols_dispatch(float* R, long long outer, long long inner, const float2* tw, int kind,
-                          hipStream_t st) {
-    if (inner % 4 == 0) cols_dispatch_v<M1, M2, true>(R, outer, inner, tw, kind, st);
-    else cols_dispatch_v<M1, M2, false>(R, outer, inner, tw, kind, st);
+                          hipStream_t st, const PlaneSums* sums) {
+    if (inner % 4 == 0) cols_dispatch_v<M1, M2, true>(R, outer, inner, tw, kind, st, sums);
+    else cols_dispatch_v<M1, M2, false>(R, outer, inner, tw, kind, st, sums);
 }
 
 // kind: 0 forward DCT-II, 1 inverse (DCT-III), 2 Hartley (either direction)
@@ -187,13 +205,13 @@ void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kin
 }
 
 void launch_cols_fast(float* R, long long outer, long long inner, int L, const float2* tw, int kind,
-                      hipStream_t st) {
+                      hipStream_t st, const PlaneSums* sums) {
     switch (L) {
-        case 32: cols_dispatch<4, 4>(R, outer, inner, tw, kind, st); break;
-        case 64: cols_dispatch<8, 4>(R, outer, inner, tw, kind, st); break;
-        case 128: cols_dispatch<8, 8>(R, outer, inner, tw, kind, st); break;
-        case 256: cols_dispatch<16, 8>(R, outer, inner, tw, kind, st); break;
-        default: cols_dispatch<16, 16>(R, outer, inner, tw, kind, st); break;
+        case 32: cols_dispatch<4, 4>(R, outer, inner, tw, kind, st, sums); break;
+        case 64: cols_dispatch<8, 4>(R, outer, inner, tw, kind, st, sums); break;
+        case 128: cols_dispatch<8, 8>(R, outer, inner, tw, kind, st, sums); break;
+        case 256: cols_dispatch<16, 8>(R, outer, inner, tw, kind, st, sums); break;
+        default: cols_dispatch<16, 16>(R, outer, inner, tw, kind, st, sums); break;
     }
 }
 

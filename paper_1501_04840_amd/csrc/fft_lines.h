@@ -30,28 +30,35 @@ namespace otd {
 // comes from load(n1) (the caller knows t); on return out[q][k2] =
 // Z[k1 + M1 k2] with k1 = t + M2 q.  The line's LDS region s (2M floats) is
 // used for the exchange.  All threads of the block must call this (it
-// synchronises the block).
+// synchronises the block); threads with `act` false only take part in the
+// synchronisation (their s and out are not touched).
 template <int M1, int M2, class Load>
 __device__ __forceinline__ void fft_core(float* s, int t, const float2* tw4, Load load,
-                                         float2 (&out)[M1 / M2][M2]) {
+                                         float2 (&out)[M1 / M2][M2], bool act = true) {
     constexpr int M = M1 * M2, L = 2 * M;
     float2 a[M1];
+    if (act) {
 #pragma unroll
-    for (int n1 = 0; n1 < M1; ++n1) a[n1] = load(n1);
-    dft<M1>(a);
+        for (int n1 = 0; n1 < M1; ++n1) a[n1] = load(n1);
+        dft<M1>(a);
 #pragma unroll
-    for (int k1 = 1; k1 < M1; ++k1) a[k1] = cmul(a[k1], tw4[(8 * t * k1) & (4 * L - 1)]);
+        for (int k1 = 1; k1 < M1; ++k1) a[k1] = cmul(a[k1], tw4[(8 * t * k1) & (4 * L - 1)]);
+    }
     __syncthreads();
-    float* const sw = s + 2 * t;                      // Z1[k1 M2 + t]
+    if (act) {
+        float* const sw = s + 2 * t;                  // Z1[k1 M2 + t]
 #pragma unroll
-    for (int k1 = 0; k1 < M1; ++k1) st2(sw, k1 * M2, a[k1]);
+        for (int k1 = 0; k1 < M1; ++k1) st2(sw, k1 * M2, a[k1]);
+    }
     __syncthreads();
-    const float* const sr = s + 2 * M2 * t;           // Z1[(t + M2 q) M2 + n2]
+    if (act) {
+        const float* const sr = s + 2 * M2 * t;       // Z1[(t + M2 q) M2 + n2]
 #pragma unroll
-    for (int q = 0; q < M1 / M2; ++q) {
+        for (int q = 0; q < M1 / M2; ++q) {
 #pragma unroll
-        for (int n2 = 0; n2 < M2; ++n2) out[q][n2] = ld2(sr, M2 * M2 * q + n2);
-        dft<M2>(out[q]);
+            for (int n2 = 0; n2 < M2; ++n2) out[q][n2] = ld2(sr, M2 * M2 * q + n2);
+            dft<M2>(out[q]);
+        }
     }
 }
 
@@ -74,9 +81,14 @@ __device__ __forceinline__ void load_pair(const float* s, int t, int j, float2& 
     else zm = ld2(s - 2 * t, M - M2 * j);
 }
 
-// Orthonormal DCT-II of the line s[0..L) in place.
+// Orthonormal DCT-II of the line s[0..L) in place.  Threads with `act`
+// false only take part in the block synchronisation.  The line transforms
+// are always inlined, so that s is known to point into LDS and is accessed
+// with LDS instructions (32-bit addresses that wrap): s - 4t is below the
+// first line's start, which as a 64-bit generic (flat) address would leave
+// the LDS aperture.
 template <int M1, int M2>
-__device__ void line_dct2(float* s, int t, const float2* tw4) {
+__device__ __forceinline__ void line_dct2(float* s, int t, const float2* tw4, bool act = true) {
     constexpr int M = M1 * M2, L = 2 * M, T = M2, NP = (M / 2 + T) / T;
     // z[n] = v[2n] + i v[2n+1] with n = M2 n1 + t; v[2n] and v[2n+1] are
     // x[4n], x[4n+2] in the first half (n1 < M1 / 2) and x[2L-1-4n],
@@ -87,9 +99,9 @@ __device__ void line_dct2(float* s, int t, const float2* tw4) {
     fft_core<M1, M2>(s, t, tw4, [&](int n1) {
         return n1 < M1 / 2 ? make_float2(sp[4 * M2 * n1], sp[4 * M2 * n1 + 2])
                            : make_float2(sm[2 * L - 1 - 4 * M2 * n1], sm[2 * L - 3 - 4 * M2 * n1]);
-    }, z);
+    }, z, act);
     __syncthreads();
-    store_z<M1, M2>(s, t, z);
+    if (act) store_z<M1, M2>(s, t, z);
     __syncthreads();
     // 2 V[k] = a and 2 V[M-k] = b; the factor 1/2 is folded into the scales
     const float h = 0.5f * sqrtf(2.f / L), h0 = 0.5f * sqrtf(1.f / L);
@@ -97,7 +109,7 @@ __device__ void line_dct2(float* s, int t, const float2* tw4) {
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const int k = t + T * j;
-        if (k <= M / 2) {
+        if (act && k <= M / 2) {
             float2 zk, zm;
             load_pair<M, T>(s, t, j, zk, zm);
             const float2 ve = make_float2(zk.x + zm.x, zk.y - zm.y);
@@ -117,7 +129,7 @@ __device__ void line_dct2(float* s, int t, const float2* tw4) {
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const int k = t + T * j;
-        if (k <= M / 2) {
+        if (act && k <= M / 2) {
             op[T * j] = o[j][0];
             if (k > 0) om[L - T * j] = o[j][1];
             if (k < M / 2) {
@@ -131,7 +143,7 @@ __device__ void line_dct2(float* s, int t, const float2* tw4) {
 
 // Orthonormal DCT-III (inverse of line_dct2) in place.
 template <int M1, int M2>
-__device__ void line_dct3(float* s, int t, const float2* tw4) {
+__device__ __forceinline__ void line_dct3(float* s, int t, const float2* tw4) {
     constexpr int M = M1 * M2, L = 2 * M, T = M2, NP = (M / 2 + T) / T;
     // inputs scaled by sqrt(L / 2) (sqrt(L) for X[0]); with V(k) =
     // conj(w4_k) (X[k], -X[L-k]), the packed spectrum is
@@ -194,14 +206,15 @@ __device__ void line_dct3(float* s, int t, const float2* tw4) {
 }
 
 // Orthonormal discrete Hartley transform (its own inverse) in place.
+// Threads with `act` false only take part in the block synchronisation.
 template <int M1, int M2>
-__device__ void line_dht(float* s, int t, const float2* tw4) {
+__device__ __forceinline__ void line_dht(float* s, int t, const float2* tw4, bool act = true) {
     constexpr int M = M1 * M2, L = 2 * M, T = M2, NP = (M / 2 + T) / T;
     float2 z[M1 / M2][M2];
     const float* const sl = s + 2 * t;
-    fft_core<M1, M2>(s, t, tw4, [&](int n1) { return ld2(sl, M2 * n1); }, z);
+    fft_core<M1, M2>(s, t, tw4, [&](int n1) { return ld2(sl, M2 * n1); }, z, act);
     __syncthreads();
-    store_z<M1, M2>(s, t, z);
+    if (act) store_z<M1, M2>(s, t, z);
     __syncthreads();
     // 2 F[k] = a and 2 F[M-k] = b; H[k] = (Re F - Im F) / sqrt(L) and
     // H[L-k] = (Re F + Im F) / sqrt(L)
@@ -210,7 +223,7 @@ __device__ void line_dht(float* s, int t, const float2* tw4) {
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const int k = t + T * j;
-        if (k <= M / 2) {
+        if (act && k <= M / 2) {
             float2 zk, zm;
             load_pair<M, T>(s, t, j, zk, zm);
             const float2 ve = make_float2(zk.x + zm.x, zk.y - zm.y);
@@ -230,7 +243,7 @@ __device__ void line_dht(float* s, int t, const float2* tw4) {
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const int k = t + T * j;
-        if (k <= M / 2) {
+        if (act && k <= M / 2) {
             op[T * j] = o[j][0];
             if (k > 0) om[L - T * j] = o[j][1];
             if (k < M / 2) {

@@ -66,6 +66,11 @@ struct StepArgs {
     double* part_div;    // [B*P*C][nbx] FP64 sum of (A x - f_b^-)^2
     int nbx;             // blocks per (b, k, c) slice in the stencil kernels
     int row_bx;          // block width of the row stencil kernels (64, 128 or 256)
+    // forward transform along x folded into the divergence kernels (their
+    // block owns whole rows of every colour): x twiddles of the fast path,
+    // or null when the x pass runs on its own; kind 0 DCT-II, 2 Hartley
+    const float2* twx;
+    int xkind;
 };
 
 // ---- stencil kernels (stencil.hip) -------------------------------------
@@ -83,6 +88,9 @@ void launch_update(const StepArgs& s, int check, int nphi, hipStream_t st);
 int row_block(int X);
 bool rows_ok(const Geom& g);
 void launch_div_rows(const StepArgs& s, int mode, hipStream_t st);
+// The forward x transform can be folded into the row divergence kernels
+// (StepArgs::twx): rows of fast length 64, 128 or 256, one block per row.
+bool div_fold_ok(const Geom& g, int row_bx, const AxisTab& tx);
 void launch_update_rows(const StepArgs& s, int check, int nphi, hipStream_t st);
 // FP64 partials of |A x - f_b^-|^2 and of the slice masses of F.
 void launch_resid_div(const StepArgs& s, hipStream_t st);
@@ -140,8 +148,10 @@ __device__ inline bool rows_frozen(const RowSkip& k, long long r0, int n) {
 bool launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStream_t st,
                  const PlaneSums* sums = nullptr, RowSkip skip = RowSkip{nullptr, 1});
 // Forward or inverse transform along a strided axis: data [outer][L][inner].
-void launch_cols(float* R, long long outer, long long inner, const AxisTab& t,
-                 int inverse, hipStream_t st);
+// With `sums`, the fast path also reduces those plane sums (as launch_rows)
+// and returns true.
+bool launch_cols(float* R, long long outer, long long inner, const AxisTab& t,
+                 int inverse, hipStream_t st, const PlaneSums* sums = nullptr);
 // Colour and time transforms, division by the eigenvalues of A A^T, inverse
 // transforms; the spatial-DC line is solved in FP64 from the slice sums
 // (already reduced to part_slice[q nbx] when `presummed`).
@@ -176,7 +186,7 @@ bool fast_len(int L);
 void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st,
                       const PlaneSums* sums = nullptr, RowSkip skip = RowSkip{nullptr, 1});
 void launch_cols_fast(float* R, long long outer, long long inner, int L, const float2* tw, int kind,
-                      hipStream_t st);
+                      hipStream_t st, const PlaneSums* sums = nullptr);
 
 // ---- plan internals used by the batched solver (plan.cpp) ---------------
 }  // namespace otd

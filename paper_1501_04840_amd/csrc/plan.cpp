@@ -34,6 +34,7 @@ struct ot_dyn_plan {
     float* dcl;              // fused Poisson passes: FP64-solved DC line [B][C][P]
     bool fused;              // the fused three-pass Poisson solve applies
     bool p1d;                // one spatial axis: the one-block Poisson solve applies
+    bool xfold;              // the divergence kernels also do the forward x transform
     float* sig;              // sigma per problem [B] (device)
     float* fac;              // dual rescale factors per problem [B] (device)
     float* frz;              // frozen flags per problem [B] (device; batches)
@@ -272,6 +273,8 @@ StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     s.part_div = p->part_div;
     s.nbx = p->nbx;
     s.row_bx = p->row_bx;
+    s.twx = p->xfold ? p->tab[0].tw : nullptr;
+    s.xkind = p->tab[0].periodic ? 2 : 0;
     return s;
 }
 
@@ -320,18 +323,24 @@ void poisson(ot_dyn_plan* p, float* R) {
         timed(p, OT_PHASE_XFORM_X, [&] { x_pass(1); });
         return;
     }
-    // the forward x pass also reduces the FP64 plane sums of r that the
-    // colour/time pass needs for the spatial-DC line (fast lengths only)
+    // the first forward pass also reduces the FP64 plane sums of r that the
+    // colour/time pass needs for the spatial-DC line (fast lengths only);
+    // when the divergence kernel has done the forward x transform (xfold),
+    // the first pass is the one along y
     bool presummed = false;
+    const PlaneSums ps{p->part_slice, B * g.P * g.C, p->nbx};
     // rows of frozen problems are skipped (rows per problem: P C Y)
     const RowSkip skip{p->frz, (long long)g.P * g.C * g.Y};
-    if (g.X > 1)
+    if (g.X > 1 && !p->xfold)
         timed(p, OT_PHASE_XFORM_X, [&] {
-            const PlaneSums ps{p->part_slice, B * g.P * g.C, p->nbx};
             presummed = launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 0, st, &ps, skip);
         });
     if (g.Y > 1)
-        timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(R, B * g.P * g.C, g.X, p->tab[1], 0, st); });
+        timed(p, OT_PHASE_XFORM_Y, [&] {
+            const bool s1 = launch_cols(R, B * g.P * g.C, g.X, p->tab[1], 0, st,
+                                        presummed ? nullptr : &ps);
+            presummed = presummed || s1;
+        });
     timed(p, OT_PHASE_TC, [&] {
         launch_tc(g, R, p->tab[0], p->tab[1], p->tab[2], p->tab[3], p->tc64, p->tt64,
                   p->part_slice, p->nbx, presummed ? 1 : 0, p->frz, st);
@@ -366,6 +375,9 @@ void apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy) {
     p->p1d = dense_xy != 1 && poisson_1d_ok(g, p->tab[0], p->tab[3]);
     p->fused = dense_xy == 0 && fused_poisson_ok(g, p->tab[0], p->tab[1], p->tab[3]) &&
                ((long long)g.B * g.Y >= 512 || (long long)g.X * g.Y < 65536);
+    // the five-pass solve with rows of one block each: the divergence
+    // kernels write r already transformed along x (one pass fewer)
+    p->xfold = !p->p1d && !p->fused && g.X > 1 && div_fold_ok(g, row_bx, p->tab[0]);
 }
 
 bool refine_now(const ot_dyn_plan* p) {
@@ -634,6 +646,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->dcl = (float*)(p->ws + L.off_dcl);
     p->fused = false;
     p->p1d = false;
+    p->xfold = false;
     p->fac = p->sig + p->g.B;
     p->frz = p->sig + 2 * (size_t)p->g.B;
     p->f0 = (float*)(p->ws + L.off_f);

@@ -9,6 +9,7 @@
 // the next block and the y+1 row is P blocks later on the same XCD, so the
 // neighbour reads of the staggered stencils are L2 hits instead of refetches.
 #include "otd_common.h"
+#include "fft_lines.h"
 #include "stencil_common.h"
 
 namespace otd {
@@ -67,11 +68,16 @@ __device__ inline Nbr neighbours(const Geom& g, int x, int y) {
 // and r to R), a = A + grad phi_1 (MODE 1, refinement: writes r to R2) or
 // a = x - tau sigma K^T b_bar + grad Phi with the carried potential Phi
 // (MODE 2: writes a to A and r to R), and the FP64 plane sums of r (one
-// partial per block and colour).
-template <int MODE, int C>
+// partial per block and colour).  XL > 0: the block owns whole rows of
+// length XL (one per colour), and r is written already transformed along x
+// (the first pass of the Poisson solve of Sec. 3: DCT-II for XK = 0, discrete
+// Hartley for XK = 2) from the rows staged in LDS.
+template <int MODE, int C, int XL, int XK>
 __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
     const Geom& g = s.g;
     const RowCtx r = row_ctx(g, nxb);
+    constexpr int XP = XL + 1;                     // LDS row pitch
+    __shared__ float xl[XL > 0 ? C * XP : 1];
     if (s.frz[r.b] != 0.f) return;       // frozen problem (block-uniform)
     const float ts = 0.5f * s.tau_sigma;
     float rv[C];
@@ -149,7 +155,8 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
                 s.A[1][i] = ay0;
                 s.A[2][i] = acv[c];
                 s.A[3][i] = k0 ? 0.f : af0;
-                s.R[i] = rr;
+                if constexpr (XL > 0) xl[c * XP + r.x] = rr;
+                else s.R[i] = rr;
                 rv[c] = rr;
             }
         } else {
@@ -183,7 +190,8 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
                                   : (c + 1 < C ? acv[(c + 1) % C] : (g.perc ? acv[0] : 0.f));
                 const float rr = g.sx * (ax1 - ax0) + g.sy * (ay1 - ay0) + g.sc * (ac1 - acv[c]) +
                                  g.st * (af1 - af0);
-                s.R2[i] = rr;
+                if constexpr (XL > 0) xl[c * XP + r.x] = rr;
+                else s.R2[i] = rr;
                 rv[c] = rr;
             }
         }
@@ -197,6 +205,19 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
             s.part_slice[(((long long)r.b * g.P + r.k) * C + c) * s.nbx + col] = sums[c];
+    if constexpr (XL > 0) {
+        // the C rows of r along x, M2 threads per row (block_sums has
+        // synchronised the block since the rows were staged)
+        constexpr int M1 = XL == 256 ? 16 : 8, M2 = XL == 64 ? 4 : 8;
+        const int line = threadIdx.x / M2, t = threadIdx.x - line * M2;
+        const bool act = line < C;
+        float* const sl = xl + (act ? line : 0) * XP;
+        if constexpr (XK == 0) line_dct2<M1, M2>(sl, t, s.twx, act);
+        else line_dht<M1, M2>(sl, t, s.twx, act);
+        float* const out = MODE == 1 ? s.R2 : s.R;
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[r.i0 + (long long)c * g.plane] = xl[c * XP + r.x];
+    }
 }
 
 // x = a + grad phi_1 (+ grad phi_2 when NPHI is 2 or 4), z = prox(K x + c +
@@ -331,12 +352,33 @@ static dim3 row_grid(const Geom& g, int nxb) {
     return dim3((unsigned)((long long)g.B * g.Y * g.P * nxb));
 }
 
+template <int C, int XL, int XK>
+static void div_rows_x(const StepArgs& s, int mode, int nxb, int bx, hipStream_t st) {
+    if (mode == 0) hipLaunchKernelGGL((k_div_rows<0, C, XL, XK>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
+    else if (mode == 1) hipLaunchKernelGGL((k_div_rows<1, C, XL, XK>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
+    else hipLaunchKernelGGL((k_div_rows<2, C, XL, XK>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
+}
+
+template <int C, int XL>
+static void div_rows_k(const StepArgs& s, int mode, int nxb, int bx, hipStream_t st) {
+    if (s.xkind == 0) div_rows_x<C, XL, 0>(s, mode, nxb, bx, st);
+    else div_rows_x<C, XL, 2>(s, mode, nxb, bx, st);
+}
+
 template <int C>
 static void div_rows_c(const StepArgs& s, int mode, hipStream_t st) {
     const int bx = s.row_bx > 0 ? s.row_bx : row_block(s.g.X), nxb = (s.g.X + bx - 1) / bx;
-    if (mode == 0) hipLaunchKernelGGL((k_div_rows<0, C>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
-    else if (mode == 1) hipLaunchKernelGGL((k_div_rows<1, C>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
-    else hipLaunchKernelGGL((k_div_rows<2, C>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
+    if (!s.twx) { div_rows_x<C, 0, 0>(s, mode, nxb, bx, st); return; }
+    switch (s.g.X) {     // div_fold_ok: X == bx in {64, 128, 256}
+        case 64: div_rows_k<C, 64>(s, mode, nxb, bx, st); break;
+        case 128: div_rows_k<C, 128>(s, mode, nxb, bx, st); break;
+        default: div_rows_k<C, 256>(s, mode, nxb, bx, st); break;
+    }
+}
+
+bool div_fold_ok(const Geom& g, int row_bx, const AxisTab& tx) {
+    const int bx = row_bx > 0 ? row_bx : row_block(g.X);
+    return rows_ok(g) && tx.tw != nullptr && bx == g.X && (g.X == 64 || g.X == 128 || g.X == 256);
 }
 
 template <int C>

@@ -1044,11 +1044,11 @@ bool launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStr
     return false;
 }
 
-void launch_cols(float* R, long long outer, long long inner, const AxisTab& t, int inverse,
-                 hipStream_t st) {
+bool launch_cols(float* R, long long outer, long long inner, const AxisTab& t, int inverse,
+                 hipStream_t st, const PlaneSums* sums) {
     if (t.tw) {
-        launch_cols_fast(R, outer, inner, t.n, t.tw, t.periodic ? 2 : (inverse ? 1 : 0), st);
-        return;
+        launch_cols_fast(R, outer, inner, t.n, t.tw, t.periodic ? 2 : (inverse ? 1 : 0), st, sums);
+        return sums != nullptr;
     }
     const int L = t.n;
     if (L <= kMfmaRowsMaxL) {
@@ -1056,7 +1056,7 @@ void launch_cols(float* R, long long outer, long long inner, const AxisTab& t, i
         const size_t sh = (size_t)Lp * 33 * sizeof(float);
         hipLaunchKernelGGL(k_cols_mfma, dim3((unsigned)((inner + 31) / 32), (unsigned)outer),
                            dim3(2 * Lp), sh, st, R, inner, t, inverse, Lp);
-        return;
+        return false;
     }
     int W = 64;
     while (W > 1 && L * W > kTileFloats) W >>= 1;
@@ -1064,6 +1064,7 @@ void launch_cols(float* R, long long outer, long long inner, const AxisTab& t, i
     const size_t sh = (size_t)L * W * sizeof(float);
     hipLaunchKernelGGL(k_cols, dim3((unsigned)nb, (unsigned)outer), dim3(kT), sh, st, R, inner,
                        t, inverse, W);
+    return false;
 }
 
 void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty, const AxisTab& tc,
