@@ -46,17 +46,27 @@ extern "C" {
 
 typedef struct ot_hue ot_hue;
 
-/* A renderer for images of npix pixels (1 <= npix <= 2^30) on nbins periodic
- * hue bins (2 <= nbins <= 4096).  Allocates about 24 bytes of device memory
- * per pixel (hues, sort keys, order, ranks) plus the sort's workspace.  stream: a
- * hipStream_t (NULL = default stream).  OT_ERR_SHAPE for sizes out of range,
- * OT_ERR_PARAM for a null out, OT_ERR_HIP if an allocation fails. */
-int ot_hue_create(long long npix, int nbins, void* stream, ot_hue** out);
+/* Bytes of device workspace a renderer for images of npix pixels (1 <= npix
+ * <= 2^30) on nbins periodic hue bins (2 <= nbins <= 4096) that plans up to
+ * max_frames frames per call (1 <= max_frames <= 65535) needs: about 20
+ * bytes per pixel (hues, sort keys and indices, ranks), the radix sort's
+ * histograms (1 KB per 8192 pixels) and 8 n + 8 bytes per frame.
+ * OT_ERR_SHAPE for sizes out of range, OT_ERR_PARAM for a null bytes. */
+int ot_hue_workspace_size(long long npix, int nbins, int max_frames, size_t* bytes);
+
+/* A renderer over the caller's device workspace of ws_bytes bytes (256-byte
+ * aligned; ot_hue_workspace_size): the library allocates no device memory.
+ * stream: a hipStream_t (NULL = default stream).  The workspace must stay
+ * allocated until ot_hue_destroy.  OT_ERR_SHAPE for sizes out of range or a
+ * missing, small or misaligned workspace, OT_ERR_PARAM for a null out. */
+int ot_hue_create(long long npix, int nbins, int max_frames, void* stream, void* workspace,
+                  size_t ws_bytes, ot_hue** out);
 
 void ot_hue_destroy(ot_hue* h);
 
 /* The source image (rgb: device, npix x 3 bytes): hues, bins, bin counts, the
- * strict order and each pixel's rank in it.  The renderer keeps the pointer:
+ * strict order (a stable radix sort of 24-bit hue keys, three 8-bit passes)
+ * and each pixel's rank in it.  The renderer keeps the pointer:
  * every later frame reads the image's max and min channels from it, so it
  * must stay allocated and unchanged until the last frame rendered from it is
  * done (or the next ot_hue_set_source).  Asynchronous.  OT_ERR_PARAM for a
@@ -70,15 +80,13 @@ int ot_hue_set_source(ot_hue* h, const unsigned char* rgb);
 int ot_hue_histogram(ot_hue* h, int* counts, float* density);
 
 /* Frames: the source image with its hue histogram specified to each of
- * `frames` densities (1 <= frames <= 65535; e.g. the time levels of f along a
- * transport path).  targets: device float [frames][nbins], any scale per
+ * `frames` densities (1 <= frames <= max_frames; e.g. the time levels of f
+ * along a transport path).  targets: device float [frames][nbins], any scale per
  * frame.  rgb_out: device, frames x npix x 3 bytes, frame after frame (may
  * not alias the source); bins_out: device int32 [frames][npix], each pixel's
- * output bin, or NULL.  Asynchronous.  The first call with more frames than
- * before grows the per-frame plan arrays (synchronises the stream,
- * allocates).  OT_ERR_STATE before ot_hue_set_source, OT_ERR_PARAM for a null
- * targets or rgb_out or frames out of range, OT_ERR_HIP if a launch or an
- * allocation fails. */
+ * output bin, or NULL.  Asynchronous.  OT_ERR_STATE before ot_hue_set_source,
+ * OT_ERR_PARAM for a null targets or rgb_out or frames < 1, OT_ERR_SHAPE for
+ * frames > max_frames, OT_ERR_HIP if a launch fails. */
 int ot_hue_render(ot_hue* h, const float* targets, int frames, unsigned char* rgb_out,
                   int* bins_out);
 

@@ -3,16 +3,22 @@
 // density by exact circular histogram specification (the readings are listed
 // in ot_hue.h).
 //
-// Device layout: keys/order/rank are u32 [N] and the source counts int32 [n];
-// per frame, the target counts and their inclusive cumulative sums are
-// int32 [n] and the shift one int64.  Per call of F frames: one planning
+// Device layout (one caller-owned workspace, carved by ot_hue_create): the
+// hue bits, two sort-key buffers, two index buffers (the first also holds the
+// ranks) u32 [N], the radix histograms int32 [256][tiles] and their digit
+// totals, the source counts int32 [n]; per frame, the target counts and their
+// inclusive cumulative sums int32 [n] and the shift one int64.  The strict
+// order is a stable LSD radix sort of 24-bit keys written here: three passes
+// of 8 bits, each a histogram kernel, a scan kernel and a scatter kernel
+// whose blocks rank their tile stably in LDS (wave ballots per round) and
+// write every digit's run contiguously; the last pass writes each pixel's
+// rank instead of the order.  Per call of F frames: one planning
 // kernel of F blocks (target counts, median shift) and one streaming kernel
 // over the pixels in raster order with the frames along grid y, four pixels
 // per thread (reads 3 bytes of RGB, the 4-byte hue kept from the source's
 // sort keys and the 4-byte rank, writes 3 bytes and optionally the 4-byte
 // bin).
 #include <hip/hip_runtime.h>
-#include <hipcub/device/device_radix_sort.hpp>
 
 #include <climits>
 #include <cstdint>
@@ -30,6 +36,14 @@ constexpr unsigned kKeyBlocks = 2048;     // 8 blocks per compute unit
 constexpr unsigned kRenderBlocks = 4096;  // 16 blocks per compute unit, per frame
 constexpr int kMaxFrames = 65535;         // frames per call (grid y)
 constexpr unsigned kConvBlocks = 8192;    // RGB<->HSV grid-stride launches
+// radix sort of the 24-bit hue keys: 3 passes of 8-bit digits over tiles of
+// kSortThreads x kSortItems keys
+constexpr int kSortThreads = 512;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kRadix = 256;
+constexpr int kKeyBits = 24;
 
 // Every FP32 step below is one rounded operation in the written order: no
 // contraction of a product and a sum into a fused multiply-add.
@@ -175,8 +189,7 @@ __device__ __forceinline__ unsigned sort_key(float h) {
 template <bool VEC>
 __global__ void __launch_bounds__(kThreads) k_hue_keys(const unsigned char* __restrict__ rgb,
                                                        long long N, int n, unsigned* keys,
-                                                       unsigned* skey, unsigned* idx,
-                                                       int* counts) {
+                                                       unsigned* skey, int* counts) {
     __shared__ int hist[kMaxBins];
     for (int k = threadIdx.x; k < n; k += blockDim.x) hist[k] = 0;
     __syncthreads();
@@ -200,15 +213,12 @@ __global__ void __launch_bounds__(kThreads) k_hue_keys(const unsigned char* __re
             }
             *reinterpret_cast<uint4*>(keys + p0) = kv;
             *reinterpret_cast<uint4*>(skey + p0) = sv;
-            const unsigned q0 = (unsigned)p0;
-            *reinterpret_cast<uint4*>(idx + p0) = make_uint4(q0, q0 + 1, q0 + 2, q0 + 3);
         } else {
             for (long long p = p0; p < p0 + 4 && p < N; ++p) {
                 const unsigned char* c = rgb + 3 * p;
                 const Hue u = hue_of(c[0], c[1], c[2]);
                 keys[p] = __float_as_uint(u.h);
                 skey[p] = sort_key(u.h);
-                idx[p] = (unsigned)p;
                 atomicAdd(&hist[bin_of(u.h, n)], 1);
             }
         }
@@ -218,9 +228,165 @@ __global__ void __launch_bounds__(kThreads) k_hue_keys(const unsigned char* __re
         if (hist[k]) atomicAdd(&counts[k], hist[k]);
 }
 
-__global__ void k_hue_rank(const unsigned* __restrict__ order, long long N, unsigned* rank) {
-    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < N) rank[order[j]] = (unsigned)j;
+// ---- stable LSD radix sort of the 24-bit keys ------------------------------
+// Tile i holds keys [i T, (i + 1) T) of the current order, T = kSortTile;
+// thread t takes element r kSortThreads + t of its tile in round r, so the
+// order (round, wave, lane) is the tile's element order.
+
+// hist[d][tile] = number of keys of digit d in the tile.
+__global__ void __launch_bounds__(kSortThreads) k_sort_hist(const unsigned* __restrict__ keys,
+                                                            long long N, int shift, int ntiles,
+                                                            int* hist) {
+    __shared__ int cnt[kRadix];
+    const int t = threadIdx.x;
+    if (t < kRadix) cnt[t] = 0;
+    __syncthreads();
+    const long long base = (long long)blockIdx.x * kSortTile;
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const long long e = base + r * kSortThreads + t;
+        if (e < N) atomicAdd(&cnt[(keys[e] >> shift) & (kRadix - 1)], 1);
+    }
+    __syncthreads();
+    if (t < kRadix) hist[(long long)t * ntiles + blockIdx.x] = cnt[t];
+}
+
+// Block d: exclusive prefix sums of hist[d][0..ntiles) in place (the start of
+// each tile's run of digit d among all keys of digit d) and totals[d].
+__global__ void __launch_bounds__(kRadix) k_sort_scan(int* hist, int ntiles, int* totals) {
+    __shared__ int part[kRadix];
+    const int t = threadIdx.x;
+    int* h = hist + (long long)blockIdx.x * ntiles;
+    const int per = (ntiles + kRadix - 1) / kRadix;
+    const int i0 = t * per, i1 = min(i0 + per, ntiles);
+    int sum = 0;
+    for (int i = i0; i < i1; ++i) sum += h[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < kRadix; off <<= 1) {       // inclusive scan of the parts
+        const int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+    for (int i = i0; i < i1; ++i) {
+        const int v = h[i];
+        h[i] = run;
+        run += v;
+    }
+    if (t == kRadix - 1) totals[blockIdx.x] = part[t];
+}
+
+// Exclusive scan of v over the kRadix threads t < kRadix of the block (all
+// threads of the block call it); returns the value for t < kRadix.
+__device__ __forceinline__ int radix_scan(int v, int* sh) {
+    const int t = threadIdx.x;
+    if (t < kRadix) sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kRadix; off <<= 1) {
+        const int a = (t < kRadix && t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        if (t < kRadix) sh[t] += a;
+        __syncthreads();
+    }
+    const int r = t < kRadix ? sh[t] - v : 0;
+    __syncthreads();
+    return r;
+}
+
+// One radix pass: every key goes to position off[d] + pre[d][tile] + (its
+// stable rank among the tile's keys of digit d), off[d] the number of keys of
+// smaller digits.  FIRST: the input index is the element's own position (the
+// raster index); LAST: writes rank_out[index] = position instead of the
+// sorted keys and indices.
+template <bool FIRST, bool LAST>
+__global__ void __launch_bounds__(kSortThreads) k_sort_scatter(
+    const unsigned* __restrict__ kin, const unsigned* __restrict__ iin, unsigned* kout,
+    unsigned* iout, unsigned* rank_out, long long N, int shift, int ntiles,
+    const int* __restrict__ pre, const int* __restrict__ totals) {
+    __shared__ int cnt[kSortWaves][kRadix];
+    __shared__ int run[kRadix], dbase[kRadix], dstart[kRadix], sh[kRadix];
+    __shared__ unsigned sk[kSortTile], si[kSortTile];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const long long tile = blockIdx.x, base = tile * kSortTile;
+    // global start of this tile's run of each digit
+    {
+        const int tot = t < kRadix ? totals[t] : 0;
+        const int off = radix_scan(tot, sh);
+        if (t < kRadix) {
+            dbase[t] = off + pre[(long long)t * ntiles + tile];
+            run[t] = 0;
+        }
+    }
+    unsigned key[kSortItems], idx[kSortItems];
+    int rk[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const long long e = base + r * kSortThreads + t;
+        const bool valid = e < N;
+        key[r] = valid ? kin[e] : 0u;
+        idx[r] = valid ? (FIRST ? (unsigned)e : iin[e]) : 0u;
+    }
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int r = 0; r < kSortItems; ++r) {
+        for (int i = t; i < kSortWaves * kRadix; i += kSortThreads) (&cnt[0][0])[i] = 0;
+        __syncthreads();
+        const bool valid = base + r * kSortThreads + t < N;
+        const int d = (int)((key[r] >> shift) & (kRadix - 1));
+        // lanes of this wave with the same digit
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const unsigned long long m = __ballot(valid && bit);
+            peers &= bit ? m : ~m;
+        }
+        const int lr = __popcll(peers & lt);
+        if (valid && lr == 0) cnt[w][d] = __popcll(peers);
+        __syncthreads();
+        if (t < kRadix) {          // digit t: start of each wave's keys in this round
+            int s0 = run[t];
+#pragma unroll
+            for (int q = 0; q < kSortWaves; ++q) {
+                const int c = cnt[q][t];
+                cnt[q][t] = s0;
+                s0 += c;
+            }
+            run[t] = s0;
+        }
+        __syncthreads();
+        rk[r] = valid ? cnt[w][d] + lr : 0;
+        __syncthreads();
+    }
+    // the tile sorted by digit in LDS: digit runs in order, each stable
+    {
+        const int st = radix_scan(t < kRadix ? run[t] : 0, sh);
+        if (t < kRadix) dstart[t] = st;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        if (base + r * kSortThreads + t < N) {
+            const int d = (int)((key[r] >> shift) & (kRadix - 1));
+            const int p = dstart[d] + rk[r];
+            sk[p] = key[r];
+            si[p] = idx[r];
+        }
+    }
+    __syncthreads();
+    const int nh = (int)min((long long)kSortTile, N - base);
+    for (int j = t; j < nh; j += kSortThreads) {
+        const unsigned k = sk[j];
+        const int d = (int)((k >> shift) & (kRadix - 1));
+        const long long pos = (long long)dbase[d] + (j - dstart[d]);
+        if (LAST) {
+            rank_out[si[j]] = (unsigned)pos;
+        } else {
+            kout[pos] = k;
+            iout[pos] = si[j];
+        }
+    }
 }
 
 __global__ void k_hue_density(const int* __restrict__ counts, int n, long long N, float* dens) {
@@ -462,62 +628,99 @@ __global__ void __launch_bounds__(kThreads) k_hue_render(const unsigned char* __
 
 unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Workspace carve of a renderer (256-byte aligned pieces).
+struct HueLayout {
+    size_t keys, skey, skey2, idxa, idxb, hist, totals, counts, ct, cum, shift, total;
+    int ntiles;
+};
+
+HueLayout hue_layout(long long N, int n, int frames) {
+    HueLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = (o + bytes + 255) / 256 * 256; return r; };
+    const size_t w = (size_t)N * sizeof(unsigned);
+    L.ntiles = (int)((N + kSortTile - 1) / kSortTile);
+    L.keys = take(w);
+    L.skey = take(w);
+    L.skey2 = take(w);
+    L.idxa = take(w);
+    L.idxb = take(w);
+    L.hist = take((size_t)kRadix * L.ntiles * sizeof(int));
+    L.totals = take(kRadix * sizeof(int));
+    L.counts = take((size_t)n * sizeof(int));
+    L.ct = take((size_t)frames * n * sizeof(int));
+    L.cum = take((size_t)frames * n * sizeof(int));
+    L.shift = take((size_t)frames * sizeof(long long));
+    L.total = o;
+    return L;
+}
+
+int hue_check(long long npix, int nbins, int frames) {
+    if (npix < 1 || npix > kMaxPix || nbins < 2 || nbins > kMaxBins || frames < 1 ||
+        frames > kMaxFrames)
+        return OT_ERR_SHAPE;
+    return OT_OK;
+}
+
 }  // namespace
 
 struct ot_hue {
     long long N = 0;
     int n = 0;
+    int cap = 0;                        // frames the plan arrays hold
+    int ntiles = 0;
     hipStream_t st = nullptr;
     // keys: each pixel's hue (FP32 bits, raster order, read by the frames);
-    // skey/skey2: 24-bit sort keys in and out of the radix sort
-    unsigned *keys = nullptr, *skey = nullptr, *skey2 = nullptr, *idx = nullptr, *order = nullptr,
-             *rank = nullptr;
+    // skey/skey2: 24-bit sort keys, idxa/idxb: the sort's raster indices
+    // (idxb holds the ranks once the sort is done)
+    unsigned *keys = nullptr, *skey = nullptr, *skey2 = nullptr, *idxa = nullptr, *idxb = nullptr;
+    unsigned* rank = nullptr;
+    int *hist = nullptr, *totals = nullptr;
     int *counts = nullptr, *ct = nullptr, *cum = nullptr;
     long long* shift = nullptr;
-    void* temp = nullptr;
-    size_t temp_bytes = 0;
     const unsigned char* src = nullptr;
     bool have_source = false;
-    int cap = 1;                        // frames the plan arrays hold
     int planned = 0;                    // frames of the last plan (0: none)
 };
 
-static void hue_free(ot_hue* h) {
-    void* bufs[] = {h->keys, h->skey, h->skey2, h->idx, h->order, h->rank, h->counts,
-                    h->ct, h->cum, h->shift, h->temp};
-    for (void* b : bufs)
-        if (b) (void)hipFree(b);
-}
-
 extern "C" {
 
-int ot_hue_create(long long npix, int nbins, void* stream, ot_hue** out) {
+int ot_hue_workspace_size(long long npix, int nbins, int max_frames, size_t* bytes) {
+    if (!bytes) return OT_ERR_PARAM;
+    const int st = hue_check(npix, nbins, max_frames);
+    if (st != OT_OK) return st;
+    *bytes = hue_layout(npix, nbins, max_frames).total;
+    return OT_OK;
+}
+
+int ot_hue_create(long long npix, int nbins, int max_frames, void* stream, void* workspace,
+                  size_t ws_bytes, ot_hue** out) {
     if (!out) return OT_ERR_PARAM;
     *out = nullptr;
-    if (npix < 1 || npix > kMaxPix || nbins < 2 || nbins > kMaxBins) return OT_ERR_SHAPE;
+    const int st = hue_check(npix, nbins, max_frames);
+    if (st != OT_OK) return st;
+    const HueLayout L = hue_layout(npix, nbins, max_frames);
+    if (!workspace || ws_bytes < L.total || (uintptr_t)workspace % 256 != 0) return OT_ERR_SHAPE;
     ot_hue* h = new (std::nothrow) ot_hue;
-    if (!h) return OT_ERR_HIP;
+    if (!h) return OT_ERR_PARAM;
+    char* ws = (char*)workspace;
     h->N = npix;
     h->n = nbins;
+    h->cap = max_frames;
+    h->ntiles = L.ntiles;
     h->st = (hipStream_t)stream;
-    const size_t w = (size_t)npix * sizeof(unsigned);
-    bool ok = hipMalloc(&h->keys, w) == hipSuccess && hipMalloc(&h->skey, w) == hipSuccess &&
-              hipMalloc(&h->skey2, w) == hipSuccess &&
-              hipMalloc(&h->idx, w) == hipSuccess && hipMalloc(&h->order, w) == hipSuccess &&
-              hipMalloc(&h->rank, w) == hipSuccess &&
-              hipMalloc(&h->counts, nbins * sizeof(int)) == hipSuccess &&
-              hipMalloc(&h->ct, nbins * sizeof(int)) == hipSuccess &&
-              hipMalloc(&h->cum, nbins * sizeof(int)) == hipSuccess &&
-              hipMalloc(&h->shift, sizeof(long long)) == hipSuccess;
-    if (ok)
-        ok = hipcub::DeviceRadixSort::SortPairs(nullptr, h->temp_bytes, h->skey, h->skey2, h->idx,
-                                                h->order, (int)npix, 0, 24, h->st) == hipSuccess &&
-             hipMalloc(&h->temp, h->temp_bytes ? h->temp_bytes : 1) == hipSuccess;
-    if (!ok) {
-        hue_free(h);
-        delete h;
-        return OT_ERR_HIP;
-    }
+    h->keys = (unsigned*)(ws + L.keys);
+    h->skey = (unsigned*)(ws + L.skey);
+    h->skey2 = (unsigned*)(ws + L.skey2);
+    h->idxa = (unsigned*)(ws + L.idxa);
+    h->idxb = (unsigned*)(ws + L.idxb);
+    h->rank = h->idxb;
+    h->hist = (int*)(ws + L.hist);
+    h->totals = (int*)(ws + L.totals);
+    h->counts = (int*)(ws + L.counts);
+    h->ct = (int*)(ws + L.ct);
+    h->cum = (int*)(ws + L.cum);
+    h->shift = (long long*)(ws + L.shift);
     *out = h;
     return OT_OK;
 }
@@ -525,7 +728,6 @@ int ot_hue_create(long long npix, int nbins, void* stream, ot_hue** out) {
 void ot_hue_destroy(ot_hue* h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->st);
-    hue_free(h);
     delete h;
 }
 
@@ -537,17 +739,39 @@ int ot_hue_set_source(ot_hue* h, const unsigned char* rgb) {
     const dim3 kgrid(kb < kKeyBlocks ? kb : kKeyBlocks);
     if ((uintptr_t)rgb % 4 == 0)
         hipLaunchKernelGGL(k_hue_keys<true>, kgrid, dim3(kThreads), 0, h->st, rgb, h->N, h->n,
-                           h->keys, h->skey, h->idx, h->counts);
+                           h->keys, h->skey, h->counts);
     else
         hipLaunchKernelGGL(k_hue_keys<false>, kgrid, dim3(kThreads), 0, h->st, rgb, h->N, h->n,
-                           h->keys, h->skey, h->idx, h->counts);
-    // 24-bit keys (sort_key): stable, so equal hues keep raster order
-    if (hipcub::DeviceRadixSort::SortPairs(h->temp, h->temp_bytes, h->skey, h->skey2, h->idx,
-                                           h->order, (int)h->N, 0, 24, h->st) != hipSuccess)
-        return OT_ERR_HIP;
-    hipLaunchKernelGGL(k_hue_rank, dim3(blocks_for(h->N, kThreads)), dim3(kThreads), 0, h->st,
-                       h->order, h->N, h->rank);
+                           h->keys, h->skey, h->counts);
+    // stable radix sort of the 24-bit keys (sort_key): equal hues keep raster
+    // order.  Pass 0: keys skey -> skey2, raster indices (implicit) -> idxb;
+    // pass 1: skey2 -> skey, idxb -> idxa; pass 2 reads skey and idxa and
+    // writes each pixel's rank into idxb.
+    const unsigned* kin[3] = {h->skey, h->skey2, h->skey};
+    unsigned* kout[3] = {h->skey2, h->skey, nullptr};
+    const unsigned* iin[3] = {nullptr, h->idxb, h->idxa};
+    unsigned* iout[3] = {h->idxb, h->idxa, nullptr};
+    for (int pass = 0; pass < kKeyBits / 8; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_sort_hist, dim3(h->ntiles), dim3(kSortThreads), 0, h->st, kin[pass],
+                           h->N, shift, h->ntiles, h->hist);
+        hipLaunchKernelGGL(k_sort_scan, dim3(kRadix), dim3(kRadix), 0, h->st, h->hist, h->ntiles,
+                           h->totals);
+        if (pass == 0)
+            hipLaunchKernelGGL((k_sort_scatter<true, false>), dim3(h->ntiles), dim3(kSortThreads), 0,
+                               h->st, kin[0], nullptr, kout[0], iout[0], nullptr, h->N, shift,
+                               h->ntiles, h->hist, h->totals);
+        else if (pass == 1)
+            hipLaunchKernelGGL((k_sort_scatter<false, false>), dim3(h->ntiles), dim3(kSortThreads),
+                               0, h->st, kin[1], iin[1], kout[1], iout[1], nullptr, h->N, shift,
+                               h->ntiles, h->hist, h->totals);
+        else
+            hipLaunchKernelGGL((k_sort_scatter<false, true>), dim3(h->ntiles), dim3(kSortThreads),
+                               0, h->st, kin[2], iin[2], nullptr, nullptr, h->idxb, h->N, shift,
+                               h->ntiles, h->hist, h->totals);
+    }
     if (hipGetLastError() != hipSuccess) return OT_ERR_HIP;
+    h->rank = h->idxb;
     h->src = rgb;
     h->have_source = true;
     h->planned = 0;
@@ -567,30 +791,12 @@ int ot_hue_histogram(ot_hue* h, int* counts, float* density) {
     return hipGetLastError() == hipSuccess ? OT_OK : OT_ERR_HIP;
 }
 
-static int reserve_frames(ot_hue* h, int frames) {
-    if (frames <= h->cap) return OT_OK;
-    if (hipStreamSynchronize(h->st) != hipSuccess) return OT_ERR_HIP;
-    (void)hipFree(h->ct);
-    (void)hipFree(h->cum);
-    (void)hipFree(h->shift);
-    h->ct = h->cum = nullptr;
-    h->shift = nullptr;
-    h->cap = 0;
-    const size_t m = (size_t)frames * h->n * sizeof(int);
-    if (hipMalloc(&h->ct, m) != hipSuccess || hipMalloc(&h->cum, m) != hipSuccess ||
-        hipMalloc(&h->shift, (size_t)frames * sizeof(long long)) != hipSuccess)
-        return OT_ERR_HIP;
-    h->cap = frames;
-    return OT_OK;
-}
-
 int ot_hue_plan(ot_hue* h, const float* targets, int frames) {
     if (!h || !targets || frames < 1 || frames > kMaxFrames) return OT_ERR_PARAM;
     if (!h->have_source) return OT_ERR_STATE;
-    const int st = reserve_frames(h, frames);
-    if (st != OT_OK) {
+    if (frames > h->cap) {
         h->planned = 0;
-        return st;
+        return OT_ERR_SHAPE;
     }
     hipLaunchKernelGGL(k_hue_plan, dim3(frames), dim3(kPlanThreads), 0, h->st, targets, h->counts,
                        h->n, h->N, h->ct, h->cum, h->shift);

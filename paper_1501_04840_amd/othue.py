@@ -13,7 +13,7 @@ from ctypes import POINTER, byref, c_int, c_void_p
 from . import otdyn
 from .otdyn import OtDynError, _ptr
 
-EXPORTS = ["ot_hue_create", "ot_hue_destroy", "ot_hue_set_source", "ot_hue_histogram",
+EXPORTS = ["ot_hue_workspace_size", "ot_hue_create", "ot_hue_destroy", "ot_hue_set_source", "ot_hue_histogram",
            "ot_hue_render", "ot_hue_plan", "ot_hue_apply", "ot_hue_plan_info",
            "ot_hue_rgb_to_hsv", "ot_hue_hsv_to_rgb"]
 
@@ -27,7 +27,8 @@ def lib() -> ctypes.CDLL:
         return L
     P = c_void_p
     LL = ctypes.c_longlong
-    L.ot_hue_create.argtypes = [LL, c_int, P, POINTER(c_void_p)]
+    L.ot_hue_workspace_size.argtypes = [LL, c_int, c_int, POINTER(ctypes.c_size_t)]
+    L.ot_hue_create.argtypes = [LL, c_int, c_int, P, P, ctypes.c_size_t, POINTER(c_void_p)]
     L.ot_hue_destroy.argtypes = [P]
     L.ot_hue_destroy.restype = None
     L.ot_hue_set_source.argtypes = [P, P]
@@ -51,9 +52,16 @@ def _check(status: int) -> int:
     return status
 
 
-def ot_hue_create(npix: int, nbins: int, stream=None) -> int:
+def ot_hue_workspace_size(npix: int, nbins: int, max_frames: int = 1) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().ot_hue_workspace_size(npix, nbins, max_frames, byref(n)))
+    return int(n.value)
+
+
+def ot_hue_create(npix: int, nbins: int, max_frames: int, stream, workspace, ws_bytes: int) -> int:
     h = c_void_p()
-    _check(lib().ot_hue_create(npix, nbins, _ptr(stream), byref(h)))
+    _check(lib().ot_hue_create(npix, nbins, max_frames, _ptr(stream), _ptr(workspace), ws_bytes,
+                               byref(h)))
     return h.value
 
 
@@ -99,16 +107,33 @@ def ot_hue_hsv_to_rgb(hsv, npix: int, rgb, stream=None) -> int:
 
 
 class HueRenderer:
-    """Owns one ot_hue object and the source image tensor it reads."""
+    """Owns one ot_hue object, its device workspace (torch memory) and the
+    source image tensor it reads.  A call with more frames than the workspace
+    plans for makes a renderer with room for them (and prepares the source
+    again)."""
 
-    def __init__(self, npix: int, nbins: int, device="cuda:0"):
+    def __init__(self, npix: int, nbins: int, device="cuda:0", max_frames: int = 64):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.npix, self.nbins = npix, nbins
         self.stream = torch.cuda.current_stream(self.device)
-        self.h = ot_hue_create(npix, nbins, self.stream.cuda_stream)
+        self.h = None
         self.src = None
+        self._make(max_frames)
+
+    def _make(self, max_frames: int):
+        t = self.torch
+        if self.h:
+            ot_hue_destroy(self.h)
+            self.h = None
+        self.max_frames = max_frames
+        n = ot_hue_workspace_size(self.npix, self.nbins, max_frames)
+        self.ws = t.empty(n + 256, dtype=t.uint8, device=self.device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.h = ot_hue_create(self.npix, self.nbins, max_frames, self.stream.cuda_stream, ptr, n)
+        if self.src is not None:
+            ot_hue_set_source(self.h, self.src)
 
     def set_source(self, rgb):
         """rgb: uint8 tensor on the device with npix * 3 elements."""
@@ -116,6 +141,11 @@ class HueRenderer:
         assert rgb.dtype == t.uint8 and rgb.is_cuda and rgb.numel() == 3 * self.npix
         self.src = rgb.contiguous()
         ot_hue_set_source(self.h, self.src)
+
+    def reserve(self, frames: int):
+        """Room for calls of `frames` frames."""
+        if frames > self.max_frames:
+            self._make(frames)
 
     def histogram(self):
         t = self.torch
@@ -139,6 +169,7 @@ class HueRenderer:
         assert targets.dim() == 2 and targets.shape[1] == self.nbins and targets.shape[0] >= 1, \
             "targets must be [frames, nbins]"
         F = targets.shape[0]
+        self.reserve(F)
         out = t.empty(F, self.npix, 3, dtype=t.uint8, device=self.device)
         bins = t.empty(F, self.npix, dtype=t.int32, device=self.device) if with_bins else None
         ot_hue_render(self.h, targets.contiguous(), F, out, bins)

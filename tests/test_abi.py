@@ -104,14 +104,24 @@ def test_prox_eval_rejects_bad_arguments(L):
 
 
 def test_hue_renderer_rejects_bad_sizes(L):
-    """Host-side checks of ot_hue_create (they return before any HIP call)."""
+    """Host-side checks of ot_hue_workspace_size / ot_hue_create and of the
+    other hue entry points (they return before any HIP call)."""
+    import ctypes
     from paper_1501_04840_amd import othue
-    for npix, nbins in [(0, 64), (-5, 64), (10, 1), (10, 4097), ((1 << 30) + 1, 64)]:
+    for npix, nbins, frames in [(0, 64, 1), (-5, 64, 1), (10, 1, 1), (10, 4097, 1),
+                                ((1 << 30) + 1, 64, 1), (10, 64, 0), (10, 64, 65536)]:
         with pytest.raises(L.OtDynError) as e:
-            othue.ot_hue_create(npix, nbins)
+            othue.ot_hue_workspace_size(npix, nbins, frames)
         assert e.value.status == L.OT_ERR_SHAPE
+    n = othue.ot_hue_workspace_size(3840 * 2160, 360, 33)
+    assert 20 * 3840 * 2160 <= n < 21 * 3840 * 2160 + (1 << 20)
     lib = othue.lib()
-    assert lib.ot_hue_create(16, 8, None, None) == L.OT_ERR_PARAM
+    out = ctypes.c_void_p()
+    assert lib.ot_hue_create(16, 8, 1, None, None, 0, None) == L.OT_ERR_PARAM
+    n = othue.ot_hue_workspace_size(16, 8, 1)
+    assert lib.ot_hue_create(16, 8, 1, None, None, n, ctypes.byref(out)) == L.OT_ERR_SHAPE
+    assert lib.ot_hue_create(16, 8, 1, None, 1 << 20, n - 1, ctypes.byref(out)) == L.OT_ERR_SHAPE
+    assert lib.ot_hue_create(16, 8, 1, None, (1 << 20) + 4, n, ctypes.byref(out)) == L.OT_ERR_SHAPE
     assert lib.ot_hue_set_source(None, None) == L.OT_ERR_PARAM
     assert lib.ot_hue_render(None, None, 1, None, None) == L.OT_ERR_PARAM
     assert lib.ot_hue_histogram(None, None, None) == L.OT_ERR_PARAM

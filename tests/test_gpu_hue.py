@@ -316,3 +316,33 @@ def test_random_pixel_image_order(othue):
         _frame_check(r, src, inputs.von_mises_hist(90 + n, n))
         _frame_check(r, src, np.roll(src.density(), n // 5))
         r.close()
+
+
+def test_frames_beyond_the_workspace_capacity(othue):
+    """The renderer's workspace plans for max_frames frames per call: a plan
+    for more is refused (OT_ERR_SHAPE) before any launch, and the binding's
+    renderer makes room for them (a new renderer over a larger workspace,
+    the source prepared again), with frames equal to those of a renderer
+    that had the room from the start."""
+    import torch
+    from paper_1501_04840_amd import otdyn
+    _say("hue frames beyond the workspace capacity")
+    H, W, n, F = 37, 53, 90, 5
+    img = inputs.hue_image(77, H, W)
+    src = torch.from_numpy(img.reshape(-1).copy()).cuda()
+    tg = torch.from_numpy(np.stack([inputs.von_mises_hist(800 + i, n) for i in range(F)])
+                          .astype(np.float32)).cuda()
+    small = othue.HueRenderer(H * W, n, max_frames=2)
+    small.set_source(src)
+    with pytest.raises(otdyn.OtDynError) as e:
+        othue.ot_hue_plan(small.h, tg, F)
+    assert e.value.status == otdyn.OT_ERR_SHAPE
+    a = small.render_frames(tg)
+    assert small.max_frames == F
+    big = othue.HueRenderer(H * W, n, max_frames=F)
+    big.set_source(src)
+    b = big.render_frames(tg)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    small.close()
+    big.close()
