@@ -175,6 +175,37 @@ def summarise_stats(stats_csv: str, out_md: str, title: str, cmd: str, note: str
         fh.write("\n".join(lines) + "\n")
 
 
+def summarise_counters(dirname: str, counters, out_md: str, title: str, cmd: str,
+                       prefix: str = "otd::", note: str = ""):
+    """Markdown table of instruction / wait counters (rocprofv3 --pmc, one run)
+    per kernel: the average per dispatch of each counter, and per wave where
+    SQ_WAVES was collected."""
+    vals = {c: _read(dirname, c) for c in counters}
+    names = sorted({k for c in counters for k in vals[c] if k.startswith(prefix)})
+    lines = [f"# {title}", "", "Command (repository root, one MI355X):", "", f"    {cmd}", ""]
+    if note:
+        lines += [note, ""]
+    per_wave = "SQ_WAVES" in counters
+    head = ["kernel", "dispatches"] + [c + (" / wave" if per_wave and c != "SQ_WAVES" else "")
+                                       for c in counters]
+    lines += ["| " + " | ".join(head) + " |", "|" + "---|" * len(head)]
+    for k in names:
+        row = [f"`{k.replace(prefix, '')}`", str(len(vals[counters[0]].get(k, [])))]
+        waves = (sum(vals["SQ_WAVES"][k]) / len(vals["SQ_WAVES"][k])) if per_wave and k in vals["SQ_WAVES"] else None
+        for c in counters:
+            v = vals[c].get(k)
+            if not v:
+                row.append("-")
+                continue
+            m = sum(v) / len(v)
+            if per_wave and c != "SQ_WAVES" and waves:
+                m /= waves
+            row.append(f"{m:.1f}")
+        lines.append("| " + " | ".join(row) + " |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1:] == ["hue"]:
         run_hue()
