@@ -114,8 +114,10 @@ typedef struct ot_dyn_desc {
     int refine;            /* FP32 accuracy of the projection: OT_REFINE_*  */
     int batch;             /* number of stacked problems of this shape (>= 1) */
     int adapt;             /* step sizes: 0 fixed (tau, sigma as given), 1
-                              balanced per problem at residual checks; tau
-                              sigma stays fixed.  Helps 1D periodic (hue)
+                              balanced per problem at residual checks (sigma
+                              halved or doubled towards r_prim ~ r_dual, at
+                              most 4 times, none once both are below 3e-5);
+                              tau sigma stays fixed.  Helps 1D periodic (hue)
                               problems, slows the RGB ones: off by default */
     int prox;              /* root of the prox cubic (Sec. 3, Step 2):
                               OT_PROX_NEWTON or OT_PROX_CLOSED */

@@ -529,9 +529,15 @@ int collect_state(ot_dyn_plan* p, const StepArgs& s) {
 // the constraint residual lags (r_prim > 4 r_dual).  The unscaled dual
 // sigma b is kept, so b and b_bar are rescaled.  A problem changes at most
 // every kAdaptGap iterations and kAdaptMax times, within 64x of the given
-// sigma; certified problems keep their sigma.
+// sigma, and no more once max(r_prim, r_dual) < kAdaptStop: near the fixed
+// point a change of steps perturbs the iteration, and problems whose steps
+// kept changing there stalled just above the tolerance (measured on the
+// 1024 hue problems: 4 changes at most and no change below 3e-5 certify 1023
+// of them in 4.6 s, 16 changes without that bound 1019 in 5.4 s).  Certified
+// problems keep their sigma.
 constexpr int kAdaptGap = 200;
-constexpr int kAdaptMax = 16;
+constexpr int kAdaptMax = 4;
+constexpr double kAdaptStop = 3e-5;
 
 int adapt_steps(ot_dyn_plan* p, const StepArgs& s) {
     if (!p->d.adapt) return OT_OK;
@@ -541,7 +547,8 @@ int adapt_steps(ot_dyn_plan* p, const StepArgs& s) {
         p->fac_h[b] = 1.f;
         const bool done = std::max(p->r_prim[b], p->r_dual[b]) < p->d.tol_res &&
                           p->r_div[b] < p->d.tol_div;
-        if (done || p->n_adapt[b] >= kAdaptMax || p->total_iters - p->last_adapt[b] < kAdaptGap)
+        if (done || p->n_adapt[b] >= kAdaptMax || p->total_iters - p->last_adapt[b] < kAdaptGap ||
+            std::max(p->r_prim[b], p->r_dual[b]) < kAdaptStop)
             continue;
         float f = 1.f;
         if (p->r_dual[b] > 4.0 * p->r_prim[b] && p->sig_h[b] > s0 / 64.f) f = 2.f;

@@ -9,6 +9,8 @@
 #include "otd_common.h"
 #include "stencil_common.h"
 
+#pragma clang fp contract(on)   // as in stencil_common.h: fusion within an expression only
+
 namespace otd {
 
 constexpr int kBlock = 256;

@@ -4,6 +4,13 @@
 
 #include "otd_common.h"
 
+// Multiply-adds are fused only within one source expression, never across
+// statements: left to the backend, fusion depends on which other values use
+// a product, so the instantiation that also forms the residual partials of a
+// check iteration would round the state update differently from the one
+// that does not, and runs with and without checks would drift apart.
+#pragma clang fp contract(on)
+
 namespace otd {
 
 __device__ inline long long cidx(const Geom& g, int b, int k, int c, int p) {

@@ -12,6 +12,8 @@
 #include "fft_lines.h"
 #include "stencil_common.h"
 
+#pragma clang fp contract(on)   // as in stencil_common.h: fusion within an expression only
+
 namespace otd {
 
 // Hardware blocks are dispatched round-robin over the 8 XCDs; give XCD j the

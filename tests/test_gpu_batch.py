@@ -143,12 +143,14 @@ def test_batch_certifies_each_problem(otdyn):
 
 def test_balanced_steps_certify_slow_hue_problems(otdyn):
     """Hue problems of the 1024-problem workload on which the fixed step
-    sizes (tau 3, sigma 0.33) stall above the tolerance: with per-problem
-    residual balancing every problem certifies, and the certified cost agrees
-    with a fixed-step run at a step ratio that does certify (tau 100)."""
+    sizes (tau 3, sigma 0.33) stall above the tolerance (341) or certify
+    late (386, 493, 629; with balancing that kept changing the steps near the
+    fixed point they did not certify at all): with per-problem residual
+    balancing every problem certifies, and the certified cost agrees with a
+    fixed-step run at a step ratio that does certify (tau 100)."""
     _say("balanced step sizes")
     allp = inputs.cfg4_problems(1024)
-    idx = [341, 0, 682, 1023]
+    idx = [341, 0, 682, 1023, 386, 493, 629]
     probs = [allp[i] for i in idx]
     dims = [(n, 1, 1, T) for n, T, _, _ in probs]
 
@@ -165,7 +167,7 @@ def test_balanced_steps_certify_slow_hue_problems(otdyn):
 
     fixed = solve(3.0, 0, 30000)
     assert not fixed[0].converged          # the stalled problem
-    bal = solve(3.0, 1, 30000)
+    bal = solve(3.0, 1, 60000)
     ref = solve(100.0, 0, 40000)
     for i in range(len(probs)):
         assert bal[i].converged == 1, (idx[i], bal[i].as_dict())
