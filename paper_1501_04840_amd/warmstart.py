@@ -17,8 +17,12 @@ layout maps, restriction and prolongation); this module sequences the calls,
 keeps the data in device memory (torch tensors as buffers) and writes logs.
 
 Usage (one GPU):
-  python -m paper_1501_04840_amd.warmstart train --pairs 3072 --out DIR
+  python -m paper_1501_04840_amd.warmstart train --out DIR [--eval 64]
   python -m paper_1501_04840_amd.warmstart eval --weights FILE --count 512
+
+`train` with its defaults is the run that produced weights/warm64.npy; its
+record (command, pairs, certified count, loss per epoch, evaluation) is
+weights/warm64_train.json.
 """
 from __future__ import annotations
 
@@ -56,7 +60,6 @@ def solver_desc(shape=SHAPE, tau: float = 3.0, sigma: float = 0.33, tol: float =
     d.tau, d.sigma = tau, sigma
     d.tol_res, d.tol_div = tol, tol
     d.check_every = check_every
-    d.refine = 1
     return d
 
 
@@ -381,15 +384,15 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
-    t.add_argument("--pairs", type=int, default=3072)
-    t.add_argument("--iters", type=int, default=12000)
+    t.add_argument("--pairs", type=int, default=2048)
+    t.add_argument("--iters", type=int, default=30000)
     t.add_argument("--group", type=int, default=256)
     t.add_argument("--coarse-iters", type=int, default=8000)
     t.add_argument("--epochs", type=int, default=150)
     t.add_argument("--batch", type=int, default=32)
     t.add_argument("--lr", type=float, default=1e-3)
-    t.add_argument("--eval", type=int, default=0, help="held-out pairs to evaluate after training")
-    t.add_argument("--eval-iters", type=int, default=40000)
+    t.add_argument("--eval", type=int, default=64, help="held-out pairs to evaluate after training")
+    t.add_argument("--eval-iters", type=int, default=30000)
     t.add_argument("--eval-modes", default=",".join(MODES))
     t.add_argument("--out", default="warm_out")
     e = sub.add_parser("eval")
@@ -403,16 +406,26 @@ def main(argv=None):
     dev = "cuda:0"
     if a.cmd == "train":
         pairs = pairs_of(range(a.pairs), held_out=False)
+        t0 = time.time()
         xs, ts, its, cert = datagen(pairs, a.iters, a.group, 250, a.coarse_iters, dev)
-        # every pair is a training pair: the uncertified ones are the solver's
-        # iterate after the iteration cap, far closer to the solution than
-        # the network's own error
+        t_data = time.time() - t0
+        # the targets are certified solutions only (r < 1e-6)
+        keep = torch.from_numpy(np.flatnonzero(cert)).to(dev)
+        xs, ts = xs.index_select(0, keep), ts.index_select(0, keep)
+        t0 = time.time()
         net, hist, cw = train(xs, ts, a.epochs, a.batch, a.lr, 0, dev)
+        t_train = time.time() - t0
         flat = net.get_params().cpu().numpy()
         save_weights(os.path.join(a.out, "warm64.npy"), flat)
-        rep = {"pairs": a.pairs, "datagen_iters": a.iters, "certified": int(cert.sum()),
-               "datagen_iterations_median": float(np.median(its)), "epochs": a.epochs,
-               "batch": a.batch, "lr": a.lr, "loss": hist}
+        rep = {"command": "python -m paper_1501_04840_amd.warmstart " + " ".join(
+                   argv if argv is not None else sys.argv[1:]),
+               "pairs": a.pairs, "pair_seeds": "synth.inputs.cfg5_pair(i), i < pairs",
+               "datagen_iters": a.iters, "certified": int(cert.sum()),
+               "trained_on": int(keep.numel()),
+               "datagen_iterations_median": float(np.median(its)),
+               "datagen_s": t_data, "train_s": t_train, "coarse_iters": a.coarse_iters,
+               "epochs": a.epochs, "batch": a.batch, "lr": a.lr,
+               "loss_per_epoch": hist}
         log(json.dumps(rep))
         if a.eval:
             del xs, ts
