@@ -77,6 +77,95 @@ __device__ __forceinline__ void dft(float2* a) {
     }
 }
 
+// ---- in-register DFTs of lengths with factors 2, 3 and 5 --------------------
+// Length 3: X1,2 = a - (b + c) / 2 -+ i (sqrt 3 / 2)(b - c).
+__device__ __forceinline__ void dft3(float2* x) {
+    constexpr float h = 0.866025403784438647f;   // sqrt(3) / 2
+    const float2 t1 = cadd(x[1], x[2]), d = csub(x[1], x[2]);
+    const float2 t2 = make_float2(x[0].x - 0.5f * t1.x, x[0].y - 0.5f * t1.y);
+    const float2 r = make_float2(h * d.y, -h * d.x);    // -i (sqrt 3 / 2) d
+    x[0] = cadd(x[0], t1);
+    x[1] = cadd(t2, r);
+    x[2] = csub(t2, r);
+}
+
+// Length 5 with the symmetric sums t1 = x1 + x4, t2 = x2 + x3 and the
+// differences d1 = x1 - x4, d2 = x2 - x3: with c_j = cos(2 pi j / 5) and
+// s_j = sin(2 pi j / 5),
+//   X1,4 = x0 + c1 t1 + c2 t2 -+ i (s1 d1 + s2 d2),
+//   X2,3 = x0 + c2 t1 + c1 t2 -+ i (s2 d1 - s1 d2).
+__device__ __forceinline__ void dft5(float2* x) {
+    constexpr float c1 = 0.309016994374947424f, c2 = -0.809016994374947424f;
+    constexpr float s1 = 0.951056516295153572f, s2 = 0.587785252292473129f;
+    const float2 t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
+    const float2 d1 = csub(x[1], x[4]), d2 = csub(x[2], x[3]);
+    const float2 a1 = make_float2(x[0].x + c1 * t1.x + c2 * t2.x, x[0].y + c1 * t1.y + c2 * t2.y);
+    const float2 a2 = make_float2(x[0].x + c2 * t1.x + c1 * t2.x, x[0].y + c2 * t1.y + c1 * t2.y);
+    const float2 b1 = make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+    const float2 b2 = make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+    x[0] = cadd(x[0], cadd(t1, t2));
+    x[1] = make_float2(a1.x + b1.y, a1.y - b1.x);       // a1 - i b1
+    x[4] = make_float2(a1.x - b1.y, a1.y + b1.x);       // a1 + i b1
+    x[2] = make_float2(a2.x + b2.y, a2.y - b2.x);
+    x[3] = make_float2(a2.x - b2.y, a2.y + b2.x);
+}
+
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+constexpr int cmodinv(int a, int m) {   // a^-1 mod m (gcd(a, m) = 1, m > 1)
+    int r = 1;
+    while ((a * r) % m != 1) ++r;
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ void dftm(float2* a);
+
+// Prime-factor (Good-Thomas) DFT of length N = R S with gcd(R, S) = 1: with
+// n = (S n1 + R n2) mod N and k = (S e1 k1 + R e2 k2) mod N, e1 = S^-1 mod R,
+// e2 = R^-1 mod S, the exponent n k is S e1 n1 k1 + R e2 n2 k2 mod N, so the
+// DFT is R-point DFTs over n1 followed by S-point DFTs over n2, without
+// twiddle factors.  All indices are compile-time constants once unrolled.
+template <int R, int S>
+__device__ __forceinline__ void pfa(float2* a) {
+    static_assert(cgcd(R, S) == 1, "prime-factor DFT needs coprime factors");
+    constexpr int N = R * S;
+    constexpr int e1 = R == 1 ? 0 : cmodinv(S % R, R), e2 = S == 1 ? 0 : cmodinv(R % S, S);
+    float2 u[S][R];
+#pragma unroll
+    for (int n2 = 0; n2 < S; ++n2)
+#pragma unroll
+        for (int n1 = 0; n1 < R; ++n1) u[n2][n1] = a[(S * n1 + R * n2) % N];
+#pragma unroll
+    for (int n2 = 0; n2 < S; ++n2) dftm<R>(u[n2]);
+    float2 v[R][S];
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1)
+#pragma unroll
+        for (int n2 = 0; n2 < S; ++n2) v[k1][n2] = u[n2][k1];
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) dftm<S>(v[k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < S; ++k2) a[(S * e1 * k1 + R * e2 * k2) % N] = v[k1][k2];
+}
+
+// In-register forward DFT a[k] <- sum_n a[n] e^{-2 pi i n k / N} for the
+// lengths of the mixed-radix line transforms: powers of two up to 16, 3, 5,
+// and coprime products of these (6, 10, 12, 15, 20, 30, 60).
+template <int N>
+__device__ __forceinline__ void dftm(float2* a) {
+    if constexpr (N == 1 || N == 2 || N == 4 || N == 8 || N == 16) dft<N>(a);
+    else if constexpr (N == 3) dft3(a);
+    else if constexpr (N == 5) dft5(a);
+    else if constexpr (N % 16 == 0 && cgcd(16, N / 16) == 1) pfa<16, N / 16>(a);
+    else if constexpr (N % 8 == 0 && cgcd(8, N / 8) == 1) pfa<8, N / 8>(a);
+    else if constexpr (N % 4 == 0 && cgcd(4, N / 4) == 1) pfa<4, N / 4>(a);
+    else if constexpr (N % 2 == 0 && cgcd(2, N / 2) == 1) pfa<2, N / 2>(a);
+    else if constexpr (N % 3 == 0 && cgcd(3, N / 3) == 1) pfa<3, N / 3>(a);
+    else static_assert(N == 1, "dftm: unsupported length");
+}
+
 __device__ __forceinline__ float2 ld2(const float* s, int c) { return make_float2(s[2 * c], s[2 * c + 1]); }
 __device__ __forceinline__ void st2(float* s, int c, float2 v) { s[2 * c] = v.x; s[2 * c + 1] = v.y; }
 

@@ -255,6 +255,83 @@ __device__ __forceinline__ void line_dht(float* s, int t, const float2* tw4, boo
     __syncthreads();
 }
 
+// Orthonormal discrete Hartley transform of a line of length L = 2 M with M =
+// M1 M2 not a power of two (e.g. the periodic hue axes of 180 and 360 bins:
+// M = 6 x 15 and 12 x 15), in place.  The packed complex DFT of length M is a
+// four-step M1 x M2 decomposition (M1 <= M2): thread t < M2 does the M1-point
+// DFT of z[M2 n1 + t] in registers and multiplies by e^{-2 pi i t k1 / M};
+// after one exchange through LDS thread t < M1 does the M2-point DFT of row
+// k1 = t, giving Z[t + M1 k2].  The unpacking to the real DFT and the
+// Hartley combination are those of line_dht.  tw4[j] = e^{-i pi j / (2L)},
+// j < 4L, as for the power-of-two lengths.  M2 threads per line; threads
+// with `act` false only take part in the block synchronisation.
+template <int M1, int M2>
+__device__ __forceinline__ void line_dht_mix(float* s, int t, const float2* tw4, bool act = true) {
+    static_assert(M1 <= M2, "one stage-2 DFT per thread");
+    constexpr int M = M1 * M2, L = 2 * M, NP = (M / 2 + M2) / M2;
+    static_assert(M % 2 == 0, "pairs k, M - k");
+    float2 a[M1];
+    if (act) {
+#pragma unroll
+        for (int n1 = 0; n1 < M1; ++n1) a[n1] = ld2(s, M2 * n1 + t);
+        dftm<M1>(a);
+#pragma unroll
+        for (int k1 = 1; k1 < M1; ++k1) a[k1] = cmul(a[k1], tw4[8 * t * k1]);   // 8 t k1 < 4L
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int k1 = 0; k1 < M1; ++k1) st2(s, k1 * M2 + t, a[k1]);
+    }
+    __syncthreads();
+    const bool act2 = act && t < M1;
+    float2 b[M2];
+    if (act2) {
+#pragma unroll
+        for (int n2 = 0; n2 < M2; ++n2) b[n2] = ld2(s, t * M2 + n2);
+        dftm<M2>(b);
+    }
+    __syncthreads();
+    if (act2) {
+#pragma unroll
+        for (int k2 = 0; k2 < M2; ++k2) st2(s, t + M1 * k2, b[k2]);
+    }
+    __syncthreads();
+    // 2 F[k] = a and 2 F[M-k] = b for the pairs k <= M / 2 (k = t + M2 j)
+    const float h = 0.5f * sqrtf(1.f / L);
+    float o[NP][4];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int k = t + M2 * j;
+        if (act && k <= M / 2) {
+            const float2 zk = ld2(s, k), zm = ld2(s, k == 0 ? 0 : M - k);
+            const float2 ve = make_float2(zk.x + zm.x, zk.y - zm.y);
+            const float2 vo = make_float2(zk.y + zm.y, zm.x - zk.x);
+            const float2 p = cmul(tw4[4 * k], vo);
+            const float2 fa = cadd(ve, p);
+            const float2 fb = make_float2(ve.x - p.x, p.y - ve.y);
+            o[j][0] = h * (fa.x - fa.y);            // H[k]
+            o[j][1] = h * (fa.x + fa.y);            // H[L-k]
+            o[j][2] = h * (fb.x - fb.y);            // H[M-k]
+            o[j][3] = h * (fb.x + fb.y);            // H[M+k]
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int k = t + M2 * j;
+        if (act && k <= M / 2) {
+            s[k] = o[j][0];
+            if (k > 0) s[L - k] = o[j][1];
+            if (k < M / 2) {
+                s[M - k] = o[j][2];
+                if (k > 0) s[M + k] = o[j][3];
+            }
+        }
+    }
+    __syncthreads();
+}
+
 template <int M1, int M2, int KIND>
 __device__ __forceinline__ void line_xform(float* s, int t, const float2* tw4) {
     if constexpr (KIND == 0) line_dct2<M1, M2>(s, t, tw4);

@@ -717,8 +717,11 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
         p->tab[a].lam = dst + 2 * (size_t)n * n;
         // twiddles e^{-i pi j / (2n)}, j < 4n, for the power-of-two fast paths
         const bool fast = (a < 2 && fast_len(n)) || (a == 3 && (n == 8 || n == 16 || n == 32));
+        // the same table for the mixed-radix Hartley transform of periodic x
+        const bool mixed = a == 0 && per[a] && !fast && mix_len(n);
         p->tab[a].tw = nullptr;
-        if (fast) {
+        p->tab[a].twm = nullptr;
+        if (fast || mixed) {
             std::vector<float> tw(8 * (size_t)n);
             const double pi = 3.14159265358979323846;
             for (int j = 0; j < 4 * n; ++j) {
@@ -730,7 +733,8 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
                                p->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
             if (e != hipSuccess) { delete p; return OT_ERR_HIP; }
-            p->tab[a].tw = (const float2*)tdst;
+            if (fast) p->tab[a].tw = (const float2*)tdst;
+            else p->tab[a].twm = (const float2*)tdst;
         }
         if (a < 2) p->tw_fast[a] = p->tab[a].tw;
         if (a == 2 || a == 3) {

@@ -775,6 +775,78 @@ __global__ void __launch_bounds__(NT) k_p1d(TcArgs a) {
     }
 }
 
+// The one-block solve for a periodic axis whose length 2 M1 M2 is not a
+// power of two but has only the factors 2, 3 and 5 (the hue axes of 180 and
+// 360 bins): as k_p1d, with the mixed-radix Hartley transform of
+// line_dht_mix (its own inverse) along x instead of the dense contraction
+// on the matrix cores.  NT threads, a multiple of P and of 64, at least
+// P M2; the rows are staged with float4 loads (L is a multiple of 4).
+template <int M1, int M2, int P, int NT>
+__global__ void __launch_bounds__(NT) k_p1d_mix(TcArgs a) {
+    constexpr int L = 2 * M1 * M2, T = M2, PITCH = L + 1, S = NT / P;
+    static_assert(L % 4 == 0 && S * P == NT && S >= 2 && P * T <= NT, "block shape");
+    __shared__ __align__(16) float lds[P * PITCH];
+    __shared__ double dsum[NT + 2 * P];
+    __shared__ float dcl[P];
+    const Geom& g = a.g;
+    const int b = blockIdx.x;
+    if (a.frz && a.frz[b] != 0.f) return;   // frozen problem (block-uniform)
+    float* base = a.R + (long long)b * g.nc;
+    constexpr int NV4 = L * P / 4;
+    for (int v = threadIdx.x; v < NV4; v += NT) {
+        const float4 q = reinterpret_cast<const float4*>(base)[v];
+        const int e = 4 * v;
+        float* d = lds + (e / L) * PITCH + (e % L);
+        d[0] = q.x; d[1] = q.y; d[2] = q.z; d[3] = q.w;
+    }
+    __syncthreads();
+    {   // FP64 sums of the time rows: S slots per row, then one thread per row
+        const int t = threadIdx.x / S, q = threadIdx.x - t * S;
+        double acc = 0.0;
+        for (int x = q; x < L; x += S) acc += (double)lds[t * PITCH + x];
+        dsum[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    double* d1 = dsum + NT;
+    if (threadIdx.x < P) {
+        double acc = 0.0;
+        for (int q = 0; q < S; ++q) acc += dsum[threadIdx.x * S + q];
+        d1[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    dc_solve_fp64(a, b, d1, dcl);
+    __syncthreads();
+    const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
+    const bool act = line < P;
+    float* const sl = lds + (act ? line : 0) * PITCH;
+    line_dht_mix<M1, M2>(sl, tt, a.tx.twm, act);
+    for (int jx = threadIdx.x; jx < L; jx += NT) {
+        float u[P];
+        if (jx == 0) {
+#pragma unroll
+            for (int t = 0; t < P; ++t) u[t] = dcl[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < P; ++t) u[t] = lds[t * PITCH + jx];
+            dct2_reg<P>(u, a.twt);
+            const float lx = a.tx.lam[jx];
+#pragma unroll
+            for (int jt = 0; jt < P; ++jt)
+                u[jt] = u[jt] * __builtin_amdgcn_rcpf(lx + a.tt.lam[jt]);   // lx > 0 off the DC
+            dct3_reg<P>(u, a.twt);
+        }
+#pragma unroll
+        for (int t = 0; t < P; ++t) lds[t * PITCH + jx] = u[t];
+    }
+    __syncthreads();
+    line_dht_mix<M1, M2>(sl, tt, a.tx.twm, act);
+    for (int v = threadIdx.x; v < NV4; v += NT) {
+        const int e = 4 * v;
+        const float* d = lds + (e / L) * PITCH + (e % L);
+        reinterpret_cast<float4*>(base)[v] = make_float4(d[0], d[1], d[2], d[3]);
+    }
+}
+
 // The same one-block solve for one spatial axis without a fast transform
 // (e.g. 180 or 360 periodic bins), X <= kMfmaRowsMaxL: the P time rows,
 // padded with zero rows to 32, are the A operand of the dense x contraction
@@ -909,6 +981,23 @@ static bool p1d_dispatch(const TcArgs& a, hipStream_t st) {
     }
 }
 
+// Periodic lengths with a mixed-radix Hartley transform (k_p1d_mix), as
+// 2 M1 M2: 180 = 2 x 6 x 15, 360 = 2 x 12 x 15.
+bool mix_len(int n) { return n == 180 || n == 360; }
+
+template <int M1, int M2, int P>
+static void p1d_mix_launch(const TcArgs& a, hipStream_t st) {
+    constexpr int NT0 = P * M2, NT = (NT0 + 63) / 64 * 64;
+    static_assert(NT % P == 0, "row-sum slots");
+    hipLaunchKernelGGL((k_p1d_mix<M1, M2, P, NT>), dim3((unsigned)a.g.B), dim3(NT), 0, st, a);
+}
+
+template <int P>
+static void p1d_mix_dispatch(const TcArgs& a, hipStream_t st) {
+    if (a.g.X == 180) p1d_mix_launch<6, 15, P>(a, st);
+    else p1d_mix_launch<12, 15, P>(a, st);
+}
+
 bool poisson_1d_ok(const Geom& g, const AxisTab& tx, const AxisTab& tt) {
     if (g.Y != 1 || g.C != 1 || !tt.tw || !(g.P == 8 || g.P == 16 || g.P == 32)) return false;
     if (tx.tw) return g.X == 64 || g.X == 128 || g.X == 256;
@@ -934,6 +1023,12 @@ void launch_poisson_1d(const Geom& g, float* R, const AxisTab& tx, const AxisTab
     a.lamt64 = tt64 + (long long)g.P * g.P;
     a.frz = frz;
     a.twt = tt.tw;
+    if (!tx.tw && tx.twm) {
+        if (g.P == 8) p1d_mix_dispatch<8>(a, st);
+        else if (g.P == 16) p1d_mix_dispatch<16>(a, st);
+        else p1d_mix_dispatch<32>(a, st);
+        return;
+    }
     if (!tx.tw) {
         if (g.P == 8) p1d_dense_launch<8>(a, st);
         else if (g.P == 16) p1d_dense_launch<16>(a, st);

@@ -167,7 +167,7 @@ def summarise_stats(stats_csv: str, out_md: str, title: str, cmd: str, note: str
         lines += [note, ""]
     lines += ["| kernel | calls | avg us | min us | max us | total % |", "|---|---|---|---|---|---|"]
     for r in rows[:top]:
-        name = r["Name"].split("(")[0].replace("void ", "")
+        name = r["Name"].replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['Percentage']):.2f} |")

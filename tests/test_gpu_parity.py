@@ -89,7 +89,10 @@ SHAPES = [
     # one spatial axis of fast length: the one-block Poisson solve
     (128, 1, 1, 16, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),   # DCT along x
     (256, 1, 1, 8, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),   # Hartley along x
-    (180, 1, 1, 16, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),  # dense Hartley (matrix cores)
+    (180, 1, 1, 16, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),  # mixed-radix Hartley, 6 x 15
+    (360, 1, 1, 32, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),  # mixed-radix Hartley, 12 x 15
+    (180, 1, 1, 8, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),   # mixed-radix Hartley, P = 8
+    (150, 1, 1, 16, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),  # dense Hartley (matrix cores)
     (100, 1, 1, 32, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),   # dense DCT (matrix cores)
 ]
 
@@ -140,8 +143,9 @@ def test_cfg1_300_iterations(otdyn, mode):
 
 @pytest.mark.parametrize("shape", [(64, 1, 1, 16, (G.PERIODIC, G.NEUMANN, G.NEUMANN)),
                                    (180, 1, 1, 16, (G.PERIODIC, G.NEUMANN, G.NEUMANN)),
+                                   (360, 1, 1, 32, (G.PERIODIC, G.NEUMANN, G.NEUMANN)),
                                    (128, 1, 1, 8, (G.NEUMANN, G.NEUMANN, G.NEUMANN))],
-                         ids=["64x1x1x16", "180x1x1x16", "128x1x1x8"])
+                         ids=["64x1x1x16", "180x1x1x16", "360x1x1x32", "128x1x1x8"])
 def test_one_axis_carried_potential_300_iterations(otdyn, shape):
     """One spatial axis in the carried-potential mode past its refined start:
     the solve and the update run in one launch per iteration.  f, the cost
