@@ -129,7 +129,7 @@ def summarise(fetch_dir: str, write_dir: str, out_json: str, out_md: str, cmd: s
     kernels = {}
     hue = workload == "hue"
     for k in fetch:
-        if not (k.startswith("k_hue_") if hue else k.startswith("otd::")):
+        if not (k.startswith(("k_hue_", "k_sort_")) if hue else k.startswith("otd::")):
             continue
         fv = sum(fetch[k]) / len(fetch[k]) * 1024.0 * f_scale
         wv = sum(write.get(k, [0.0])) / max(1, len(write.get(k, []))) * 1024.0 * w_scale
