@@ -196,6 +196,7 @@ struct TcArgs {
     const float2* twt;       // time-axis twiddles e^{-i pi j / (2P)}, j < 4P
 };
 
+template <int PT = 0>
 __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1, float* ct_out = nullptr);
 
 __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
@@ -269,10 +270,14 @@ __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
 
 // The (colour, time) problem of the spatial-DC line from the FP64 plane
 // sums d1[q], q = (k, c), visible to the whole block (d1 and d1 + P C are
-// overwritten); output as for dc_line_fp64.
+// overwritten); output as for dc_line_fp64.  PT > 0: P is the compile-time
+// PT, and each thread issues the P loads of its row or column of the FP64
+// time matrix at once (one round trip to the cache instead of one per eight
+// terms: the time products were the serial part of the one-block solves).
+template <int PT>
 __device__ __forceinline__ void dc_solve_fp64(const TcArgs& a, int b, double* d1, float* ct_out) {
     const Geom& g = a.g;
-    const int P = g.P, C = g.C;
+    const int P = PT > 0 ? PT : g.P, C = g.C;
     const int nt = blockDim.x;
     float* base = a.R + (long long)b * g.nc;
     double* d2 = d1 + P * C;
@@ -287,8 +292,16 @@ __device__ __forceinline__ void dc_solve_fp64(const TcArgs& a, int b, double* d1
     for (int e = threadIdx.x; e < m; e += nt) {      // time forward, divide
         const int jt = e / C, jc = e - jt * C;
         double acc = 0.0;
+        if constexpr (PT > 0) {
+            double w[PT];
+#pragma unroll
+            for (int k = 0; k < PT; ++k) w[k] = a.tt64[jt * PT + k];
+#pragma unroll
+            for (int k = 0; k < PT; ++k) acc += w[k] * d2[k * C + jc];
+        } else {
 #pragma unroll 8
-        for (int k = 0; k < P; ++k) acc += a.tt64[jt * P + k] * d2[k * C + jc];
+            for (int k = 0; k < P; ++k) acc += a.tt64[jt * P + k] * d2[k * C + jc];
+        }
         const double lam = a.lamc64[jc] + a.lamt64[jt];
         d1[e] = lam > 0.0 ? acc / lam : 0.0;
     }
@@ -296,8 +309,16 @@ __device__ __forceinline__ void dc_solve_fp64(const TcArgs& a, int b, double* d1
     for (int e = threadIdx.x; e < m; e += nt) {      // time inverse
         const int k = e / C, jc = e - k * C;
         double acc = 0.0;
+        if constexpr (PT > 0) {
+            double w[PT];
+#pragma unroll
+            for (int jt = 0; jt < PT; ++jt) w[jt] = a.tt64[jt * PT + k];
+#pragma unroll
+            for (int jt = 0; jt < PT; ++jt) acc += w[jt] * d1[jt * C + jc];
+        } else {
 #pragma unroll 8
-        for (int jt = 0; jt < P; ++jt) acc += a.tt64[jt * P + k] * d1[jt * C + jc];
+            for (int jt = 0; jt < P; ++jt) acc += a.tt64[jt * P + k] * d1[jt * C + jc];
+        }
         d2[e] = acc;
     }
     __syncthreads();
@@ -323,6 +344,7 @@ __device__ __forceinline__ void dc_solve_fp64(const TcArgs& a, int b, double* d1
 // line at p = 0 of problem b.  Called by a whole block; d1 holds
 // dc_scratch_doubles(P C) doubles.  With ct_out the line is left in colour
 // modes and written as ct_out[jc * P + t] (scaled) instead.
+template <int PT>
 __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1, float* ct_out) {
     const Geom& g = a.g;
     const int P = g.P, C = g.C;
@@ -372,7 +394,7 @@ __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1, float* ct_out) 
         }
     }
     __syncthreads();
-    dc_solve_fp64(a, b, d1, ct_out);
+    dc_solve_fp64<PT>(a, b, d1, ct_out);
 }
 
 // Orthonormal DCT-II of a register line of length P (Makhoul's reordering
@@ -454,7 +476,7 @@ __global__ void __launch_bounds__(64 * C) k_tc_reg(TcArgs a) {
     const int b = blockIdx.y;
     if (a.frz && a.frz[b] != 0.f) return;   // frozen problem (block-uniform)
     if (blockIdx.x == 0) {
-        dc_line_fp64(a, b, dsh);
+        dc_line_fp64<P>(a, b, dsh);
         return;
     }
     const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
@@ -548,7 +570,7 @@ __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
     const Geom& g = a.g;
     const int b = blockIdx.y;
     if ((int)blockIdx.x == g.Y * (P / PS)) {
-        dc_line_fp64(a, b, reinterpret_cast<double*>(lds), a.dc + (long long)b * C * P);
+        dc_line_fp64<P>(a, b, reinterpret_cast<double*>(lds), a.dc + (long long)b * C * P);
         return;
     }
     // block: row index y, time slices t0 .. t0 + PS - 1
@@ -743,7 +765,7 @@ __global__ void __launch_bounds__(NT) k_p1d(TcArgs a) {
         d1[threadIdx.x] = acc;
     }
     __syncthreads();
-    dc_solve_fp64(a, b, d1, dcl);
+    dc_solve_fp64<P>(a, b, d1, dcl);
     __syncthreads();
     const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
     line_xform<M1, M2, KF>(lds + line * PITCH, tt, a.tx.tw);
@@ -814,7 +836,7 @@ __global__ void __launch_bounds__(NT) k_p1d_mix(TcArgs a) {
         d1[threadIdx.x] = acc;
     }
     __syncthreads();
-    dc_solve_fp64(a, b, d1, dcl);
+    dc_solve_fp64<P>(a, b, d1, dcl);
     __syncthreads();
     const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
     const bool act = line < P;
@@ -891,7 +913,7 @@ __global__ void __launch_bounds__(kP1dDenseThreads) k_p1d_dense(TcArgs a, int Lp
         d1[threadIdx.x] = acc;
     }
     __syncthreads();
-    dc_solve_fp64(a, b, d1, dcl);
+    dc_solve_fp64<P>(a, b, d1, dcl);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 31, half = lane >> 5;
     for (int pass = 0; pass < 2; ++pass) {
         const float* T = pass ? inv_tab(a.tx) : fwd_tab(a.tx);   // T[k * L + j]
