@@ -187,7 +187,12 @@ def hue_batch(args):
     t0 = time.perf_counter()
     bt.autotune(10)
     t_tune = time.perf_counter() - t0
-    say(f"hue batch: autotune {t_tune:.2f} s; solving")
+    tuned = {}
+    for i, (n, T, _, _) in enumerate(probs):
+        if f"{n}x{T}" not in tuned:
+            bx, dense = otdyn.ot_dyn_batch_tuning(bt.bt, i)
+            tuned[f"{n}x{T}"] = {"row_bx": bx, "dense_xy": dense}
+    say(f"hue batch: autotune {t_tune:.2f} s ({tuned}); solving")
     t0 = time.perf_counter()
     status, rep = bt.solve(args.hue_max_iters, chunk=args.hue_chunk)
     t_batch = time.perf_counter() - t0
@@ -234,6 +239,7 @@ def hue_batch(args):
                    "chunk": args.hue_chunk, "max_iters": args.hue_max_iters,
                    "certified": int(rep.converged), "iters_max": int(its.max()),
                    "iters_median": float(np.median(its)), "autotune_s": t_tune,
+                   "tuning": tuned,
                    "cell_iters_per_s": float(cells * its.mean() / t_batch),
                    "uncertified": open_probs},
         "looped_plain_solver": {"sample": len(idx), "certified": loop_conv,

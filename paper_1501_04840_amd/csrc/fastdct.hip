@@ -158,6 +158,113 @@ __global__ void __launch_bounds__(256) k_cols_fft(float* R, long long inner, con
     }
 }
 
+// ---- lengths L = 2 M1 M2 with factors 2, 3 and 5 (line_xform_mix) ------------
+// 32 lines per block and M2 threads per line (NT = 32 M2 >= 256 threads);
+// otherwise as k_rows_fft / k_cols_fft, including the plane-sum blocks
+// (their first 256 threads, as there).
+constexpr int kMixLines = 32;
+
+template <int M1, int M2, int KIND>
+__global__ void __launch_bounds__(kMixLines * M2) k_rows_mix(float* R, long long rows, const float2* tw4,
+                                                             PlaneSums ps, int nsb, RowSkip skip) {
+    constexpr int L = 2 * M1 * M2, NT = kMixLines * M2, PITCH = L + 1;
+    static_assert(NT >= 256 && L % 4 == 0, "block shape");
+    __shared__ float lds[kMixLines * PITCH];
+    if ((int)blockIdx.x < nsb) {
+        if (threadIdx.x < 256) plane_sums_block(ps, blockIdx.x);
+        return;
+    }
+    const long long r0 = (long long)(blockIdx.x - nsb) * kMixLines;
+    const int nr = (int)min((long long)kMixLines, rows - r0);
+    if (rows_frozen(skip, r0, nr)) return;
+    float* g = R + r0 * L;
+    const int n4 = nr * L / 4;
+    for (int v = threadIdx.x; v < n4; v += NT) {
+        const float4 q = reinterpret_cast<const float4*>(g)[v];
+        const int e = 4 * v;
+        float* d = lds + (e / L) * PITCH + (e % L);
+        d[0] = q.x; d[1] = q.y; d[2] = q.z; d[3] = q.w;
+    }
+    __syncthreads();
+    const int line = threadIdx.x / M2, t = threadIdx.x - line * M2;
+    line_xform_mix<M1, M2, KIND>(lds + line * PITCH, t, tw4, line < nr);
+    for (int v = threadIdx.x; v < n4; v += NT) {
+        const int e = 4 * v;
+        const float* d = lds + (e / L) * PITCH + (e % L);
+        reinterpret_cast<float4*>(g)[v] = make_float4(d[0], d[1], d[2], d[3]);
+    }
+}
+
+// Strided axis: data [outer][L][inner]; a block transforms 32 columns
+// (128 contiguous bytes per row of the tile), stored transposed in LDS.
+template <int M1, int M2, int KIND>
+__global__ void __launch_bounds__(kMixLines * M2) k_cols_mix(float* R, long long inner, const float2* tw4,
+                                                             PlaneSums ps, int nsb, int ntiles) {
+    constexpr int L = 2 * M1 * M2, NT = kMixLines * M2, W = kMixLines, PITCH = L + 1;
+    static_assert(NT >= 256, "block shape");
+    __shared__ float lds[W * PITCH];
+    if ((int)blockIdx.x < nsb) {
+        if (threadIdx.x < 256) plane_sums_block(ps, blockIdx.x);
+        return;
+    }
+    const long long blk = (long long)blockIdx.x - nsb;
+    const long long o = blk / ntiles;
+    const long long i0 = (blk - o * ntiles) * W;
+    const int nw = (int)min((long long)W, inner - i0);
+    float* g = R + o * L * inner + i0;
+    for (int e = threadIdx.x; e < L * W; e += NT) {
+        const int k = e / W, i = e - k * W;
+        if (i < nw) lds[i * PITCH + k] = g[(long long)k * inner + i];
+    }
+    __syncthreads();
+    const int line = threadIdx.x / M2, t = threadIdx.x - line * M2;
+    line_xform_mix<M1, M2, KIND>(lds + line * PITCH, t, tw4, line < nw);
+    for (int e = threadIdx.x; e < L * W; e += NT) {
+        const int k = e / W, i = e - k * W;
+        if (i < nw) g[(long long)k * inner + i] = lds[i * PITCH + k];
+    }
+}
+
+// The (M1, M2) split of each mixed length L = 2 M1 M2.
+bool mix_len(int L) { return L == 100 || L == 180 || L == 360; }
+
+template <int M1, int M2>
+static void rows_mix_dispatch(float* R, long long rows, const float2* tw, int kind, hipStream_t st,
+                              const PlaneSums* sums, RowSkip sk) {
+    const PlaneSums ps = sums ? *sums : PlaneSums{nullptr, 0, 0};
+    const int nsb = (int)((ps.nq + kSumPlanesPerBlock - 1) / kSumPlanesPerBlock);
+    const dim3 grid((unsigned)((rows + kMixLines - 1) / kMixLines + nsb)), block(kMixLines * M2);
+    if (kind == 0) hipLaunchKernelGGL((k_rows_mix<M1, M2, 0>), grid, block, 0, st, R, rows, tw, ps, nsb, sk);
+    else if (kind == 1) hipLaunchKernelGGL((k_rows_mix<M1, M2, 1>), grid, block, 0, st, R, rows, tw, ps, nsb, sk);
+    else hipLaunchKernelGGL((k_rows_mix<M1, M2, 2>), grid, block, 0, st, R, rows, tw, ps, nsb, sk);
+}
+
+template <int M1, int M2>
+static void cols_mix_dispatch(float* R, long long outer, long long inner, const float2* tw, int kind,
+                              hipStream_t st, const PlaneSums* sums) {
+    const PlaneSums ps = sums ? *sums : PlaneSums{nullptr, 0, 0};
+    const int nsb = (int)((ps.nq + kSumPlanesPerBlock - 1) / kSumPlanesPerBlock);
+    const int ntiles = (int)((inner + kMixLines - 1) / kMixLines);
+    const dim3 grid((unsigned)(ntiles * outer + nsb)), block(kMixLines * M2);
+    if (kind == 0) hipLaunchKernelGGL((k_cols_mix<M1, M2, 0>), grid, block, 0, st, R, inner, tw, ps, nsb, ntiles);
+    else if (kind == 1) hipLaunchKernelGGL((k_cols_mix<M1, M2, 1>), grid, block, 0, st, R, inner, tw, ps, nsb, ntiles);
+    else hipLaunchKernelGGL((k_cols_mix<M1, M2, 2>), grid, block, 0, st, R, inner, tw, ps, nsb, ntiles);
+}
+
+void launch_rows_mix(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st,
+                     const PlaneSums* sums, RowSkip sk) {
+    if (L == 100) rows_mix_dispatch<5, 10>(R, rows, tw, kind, st, sums, sk);
+    else if (L == 180) rows_mix_dispatch<6, 15>(R, rows, tw, kind, st, sums, sk);
+    else rows_mix_dispatch<12, 15>(R, rows, tw, kind, st, sums, sk);
+}
+
+void launch_cols_mix(float* R, long long outer, long long inner, int L, const float2* tw, int kind,
+                     hipStream_t st, const PlaneSums* sums) {
+    if (L == 100) cols_mix_dispatch<5, 10>(R, outer, inner, tw, kind, st, sums);
+    else if (L == 180) cols_mix_dispatch<6, 15>(R, outer, inner, tw, kind, st, sums);
+    else cols_mix_dispatch<12, 15>(R, outer, inner, tw, kind, st, sums);
+}
+
 bool fast_len(int L) { return L >= 32 && L <= 512 && (L & (L - 1)) == 0; }
 
 template <int M1, int M2>

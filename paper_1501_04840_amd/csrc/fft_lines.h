@@ -255,25 +255,29 @@ __device__ __forceinline__ void line_dht(float* s, int t, const float2* tw4, boo
     __syncthreads();
 }
 
-// Orthonormal discrete Hartley transform of a line of length L = 2 M with M =
-// M1 M2 not a power of two (e.g. the periodic hue axes of 180 and 360 bins:
-// M = 6 x 15 and 12 x 15), in place.  The packed complex DFT of length M is a
-// four-step M1 x M2 decomposition (M1 <= M2): thread t < M2 does the M1-point
-// DFT of z[M2 n1 + t] in registers and multiplies by e^{-2 pi i t k1 / M};
-// after one exchange through LDS thread t < M1 does the M2-point DFT of row
-// k1 = t, giving Z[t + M1 k2].  The unpacking to the real DFT and the
-// Hartley combination are those of line_dht.  tw4[j] = e^{-i pi j / (2L)},
-// j < 4L, as for the power-of-two lengths.  M2 threads per line; threads
-// with `act` false only take part in the block synchronisation.
-template <int M1, int M2>
-__device__ __forceinline__ void line_dht_mix(float* s, int t, const float2* tw4, bool act = true) {
+// ---- lines of length L = 2 M with M = M1 M2 not a power of two -----------
+// (e.g. the paper's 100-pixel image sides, M = 5 x 10, and the periodic hue
+// axes of 180 and 360 bins, M = 6 x 15 and 12 x 15).  The packed complex DFT
+// of length M is a four-step M1 x M2 decomposition with M1 <= M2 and M2
+// threads per line: thread t does the M1-point DFT of z[M2 n1 + t] in
+// registers (the prime-factor DFTs of fft_common.h) and multiplies by
+// e^{-2 pi i t k1 / M}; after one exchange through LDS thread t < M1 does the
+// M2-point DFT of row k1 = t.  The packing and unpacking steps are those of
+// the power-of-two transforms above, with every LDS index formed from the
+// line start (no offsets below it).  tw4[j] = e^{-i pi j / (2L)}, j < 4L, as
+// for the power-of-two lengths.  Threads with `act` false only take part in
+// the block synchronisation.
+
+// On return, threads t < M1 hold out[k2] = Z[t + M1 k2]; load(n1) must give
+// z[M2 n1 + t].  The line's LDS region s (2M floats) is used for the exchange.
+template <int M1, int M2, class Load>
+__device__ __forceinline__ void fft_core_mix(float* s, int t, const float2* tw4, Load load,
+                                             float2 (&out)[M2], bool act) {
     static_assert(M1 <= M2, "one stage-2 DFT per thread");
-    constexpr int M = M1 * M2, L = 2 * M, NP = (M / 2 + M2) / M2;
-    static_assert(M % 2 == 0, "pairs k, M - k");
     float2 a[M1];
     if (act) {
 #pragma unroll
-        for (int n1 = 0; n1 < M1; ++n1) a[n1] = ld2(s, M2 * n1 + t);
+        for (int n1 = 0; n1 < M1; ++n1) a[n1] = load(n1);
         dftm<M1>(a);
 #pragma unroll
         for (int k1 = 1; k1 < M1; ++k1) a[k1] = cmul(a[k1], tw4[8 * t * k1]);   // 8 t k1 < 4L
@@ -284,15 +288,128 @@ __device__ __forceinline__ void line_dht_mix(float* s, int t, const float2* tw4,
         for (int k1 = 0; k1 < M1; ++k1) st2(s, k1 * M2 + t, a[k1]);
     }
     __syncthreads();
-    const bool act2 = act && t < M1;
-    float2 b[M2];
-    if (act2) {
+    if (act && t < M1) {
 #pragma unroll
-        for (int n2 = 0; n2 < M2; ++n2) b[n2] = ld2(s, t * M2 + n2);
-        dftm<M2>(b);
+        for (int n2 = 0; n2 < M2; ++n2) out[n2] = ld2(s, t * M2 + n2);
+        dftm<M2>(out);
+    }
+}
+
+// Orthonormal DCT-II in place (Makhoul's reordering as in line_dct2).
+template <int M1, int M2>
+__device__ __forceinline__ void line_dct2_mix(float* s, int t, const float2* tw4, bool act = true) {
+    constexpr int M = M1 * M2, L = 2 * M, NP = (M / 2 + M2) / M2;
+    static_assert(M % 2 == 0, "pairs k, M - k");
+    float2 z[M2];
+    fft_core_mix<M1, M2>(s, t, tw4, [&](int n1) {
+        const int n = M2 * n1 + t;         // v[2n], v[2n+1]
+        return n < M / 2 ? make_float2(s[4 * n], s[4 * n + 2])
+                         : make_float2(s[2 * L - 1 - 4 * n], s[2 * L - 3 - 4 * n]);
+    }, z, act);
+    __syncthreads();
+    if (act && t < M1) {
+#pragma unroll
+        for (int k2 = 0; k2 < M2; ++k2) st2(s, t + M1 * k2, z[k2]);
     }
     __syncthreads();
-    if (act2) {
+    const float h = 0.5f * sqrtf(2.f / L), h0 = 0.5f * sqrtf(1.f / L);
+    float o[NP][4];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int k = t + M2 * j;
+        if (act && k <= M / 2) {
+            const float2 zk = ld2(s, k), zm = ld2(s, k == 0 ? 0 : M - k);
+            const float2 ve = make_float2(zk.x + zm.x, zk.y - zm.y);
+            const float2 vo = make_float2(zk.y + zm.y, zm.x - zk.x);
+            const float2 p = cmul(tw4[4 * k], vo);
+            const float2 xa = cmul(tw4[k], cadd(ve, p));
+            const float2 xb = cmul(tw4[M - k], make_float2(ve.x - p.x, p.y - ve.y));
+            o[j][0] = (k == 0 ? h0 : h) * xa.x;     // X[k]
+            o[j][1] = -h * xa.y;                    // X[L-k]
+            o[j][2] = h * xb.x;                     // X[M-k]
+            o[j][3] = -h * xb.y;                    // X[M+k]
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int k = t + M2 * j;
+        if (act && k <= M / 2) {
+            s[k] = o[j][0];
+            if (k > 0) s[L - k] = o[j][1];
+            if (k < M / 2) {
+                s[M - k] = o[j][2];
+                if (k > 0) s[M + k] = o[j][3];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Orthonormal DCT-III (inverse of line_dct2_mix) in place, as line_dct3.
+template <int M1, int M2>
+__device__ __forceinline__ void line_dct3_mix(float* s, int t, const float2* tw4, bool act = true) {
+    constexpr int M = M1 * M2, L = 2 * M, NP = (M / 2 + M2) / M2;
+    static_assert(M % 2 == 0, "pairs k, M - k");
+    float2 zc[NP][2];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int k = t + M2 * j;
+        if (act && k <= M / 2) {
+            const float xk = k == 0 ? 1.41421356237309515f * s[0] : s[k];
+            const float xl = k == 0 ? 0.f : s[L - k];                         // X[L-k]
+            const float xm = s[M - k];                                        // X[M-k]
+            const float xp = s[M + k];                                        // X[M+k]
+            const float2 v = cmul(cconj(tw4[k]), make_float2(xk, -xl));
+            const float2 w = cmul(cconj(tw4[M - k]), make_float2(xm, -xp));   // V(M-k)
+            const float2 ve = make_float2(v.x + w.x, v.y - w.y);
+            const float2 vo = cmul(make_float2(v.x - w.x, v.y + w.y), cconj(tw4[4 * k]));
+            zc[j][0] = make_float2(ve.x - vo.y, -(ve.y + vo.x));
+            zc[j][1] = make_float2(ve.x + vo.y, ve.y - vo.x);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int k = t + M2 * j;
+        if (act && k <= M / 2) {
+            st2(s, k, zc[j][0]);
+            if (k > 0 && k < M / 2) st2(s, M - k, zc[j][1]);
+        }
+    }
+    __syncthreads();
+    float2 r[M2];
+    fft_core_mix<M1, M2>(s, t, tw4, [&](int n1) { return ld2(s, M2 * n1 + t); }, r, act);
+    __syncthreads();
+    // output n = t + M1 k2: x[pos(2n)] = Re r / M, x[pos(2n+1)] = -Im r / M with
+    // pos(m) = 2m (m < M), 2(L-1-m)+1 (m >= M)
+    const float sc = 0.5f * sqrtf(0.5f * L) / M;
+    if (act && t < M1) {
+#pragma unroll
+        for (int k2 = 0; k2 < M2; ++k2) {
+            const int n = t + M1 * k2;
+            if (n < M / 2) {
+                s[4 * n] = r[k2].x * sc;
+                s[4 * n + 2] = -r[k2].y * sc;
+            } else {
+                s[2 * L - 1 - 4 * n] = r[k2].x * sc;
+                s[2 * L - 3 - 4 * n] = -r[k2].y * sc;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Orthonormal discrete Hartley transform (its own inverse) in place, as
+// line_dht.
+template <int M1, int M2>
+__device__ __forceinline__ void line_dht_mix(float* s, int t, const float2* tw4, bool act = true) {
+    constexpr int M = M1 * M2, L = 2 * M, NP = (M / 2 + M2) / M2;
+    static_assert(M % 2 == 0, "pairs k, M - k");
+    float2 b[M2];
+    fft_core_mix<M1, M2>(s, t, tw4, [&](int n1) { return ld2(s, M2 * n1 + t); }, b, act);
+    __syncthreads();
+    if (act && t < M1) {
 #pragma unroll
         for (int k2 = 0; k2 < M2; ++k2) st2(s, t + M1 * k2, b[k2]);
     }
@@ -330,6 +447,13 @@ __device__ __forceinline__ void line_dht_mix(float* s, int t, const float2* tw4,
         }
     }
     __syncthreads();
+}
+
+template <int M1, int M2, int KIND>
+__device__ __forceinline__ void line_xform_mix(float* s, int t, const float2* tw4, bool act) {
+    if constexpr (KIND == 0) line_dct2_mix<M1, M2>(s, t, tw4, act);
+    else if constexpr (KIND == 1) line_dct3_mix<M1, M2>(s, t, tw4, act);
+    else line_dht_mix<M1, M2>(s, t, tw4, act);
 }
 
 template <int M1, int M2, int KIND>

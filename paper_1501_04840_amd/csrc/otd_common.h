@@ -43,8 +43,7 @@ struct AxisTab {
     const float* mat;    // n x n forward matrix M[j][k] (row j = frequency)
     const float* lam;    // n eigenvalues of A A^T along this axis
     const float2* tw;    // fast path: tw[j] = e^{-i pi j / (2n)}, j < 4n; else null
-    const float2* twm;   // mixed-radix Hartley path (periodic, mix_len(n)): the same
-                         // table; else null
+    const float2* twm;   // mixed-radix path (mix_len(n)): the same table; else null
 };
 
 struct StepArgs {
@@ -178,9 +177,14 @@ void launch_fused_yt(const Geom& g, float* Rt, float* dc, const AxisTab& tx, con
 // Y = C = 1, P in {8, 16, 32}, X in {64, 128, 256} with its fast transform
 // or X <= 480 with the dense transform on the matrix cores; one block per
 // problem, frozen problems skipped.
-// Periodic lengths that the one-block 1D solve transforms by a mixed-radix
-// Hartley transform (factors 2, 3 and 5) instead of a dense contraction.
+// Lengths L = 2 M1 M2 (factors 2, 3 and 5) with mixed-radix line transforms
+// (x and y passes, one-block 1D solve) instead of dense contractions: 100,
+// 180 and 360.
 bool mix_len(int n);
+void launch_rows_mix(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st,
+                     const PlaneSums* sums, RowSkip sk);
+void launch_cols_mix(float* R, long long outer, long long inner, int L, const float2* tw, int kind,
+                     hipStream_t st, const PlaneSums* sums);
 bool poisson_1d_ok(const Geom& g, const AxisTab& tx, const AxisTab& tt);
 void launch_poisson_1d(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
                        const AxisTab& tc, const AxisTab& tt, const double* tc64,

@@ -57,6 +57,7 @@ struct ot_dyn_plan {
     int row_bx;
     int dense_xy;
     const float2* tw_fast[2];    // fast-path twiddles of x and y (null if absent)
+    const float2* tw_mix[2];     // mixed-radix twiddles of x and y (null if absent)
     // host state
     bool have_boundary;
     bool have_init;
@@ -366,7 +367,10 @@ void apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy) {
         p->nbx = g.Y * nxb;
         p->nred = (long long)g.Y * g.P * nxb;
     }
-    for (int a = 0; a < 2; ++a) p->tab[a].tw = dense_xy == 1 ? nullptr : p->tw_fast[a];
+    for (int a = 0; a < 2; ++a) {
+        p->tab[a].tw = dense_xy == 1 ? nullptr : p->tw_fast[a];
+        p->tab[a].twm = dense_xy == 1 ? nullptr : p->tw_mix[a];
+    }
     // the fused passes use one block per row index and problem: measured
     // faster than the five passes at 64 x 64 and 128 x 128 (alone and
     // batched) and 2% slower for one 256 x 256 problem (256 blocks, one fat
@@ -717,8 +721,8 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
         p->tab[a].lam = dst + 2 * (size_t)n * n;
         // twiddles e^{-i pi j / (2n)}, j < 4n, for the power-of-two fast paths
         const bool fast = (a < 2 && fast_len(n)) || (a == 3 && (n == 8 || n == 16 || n == 32));
-        // the same table for the mixed-radix Hartley transform of periodic x
-        const bool mixed = a == 0 && per[a] && !fast && mix_len(n);
+        // the same table for the mixed-radix transforms of x and y
+        const bool mixed = a < 2 && !fast && mix_len(n);
         p->tab[a].tw = nullptr;
         p->tab[a].twm = nullptr;
         if (fast || mixed) {
@@ -736,7 +740,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
             if (fast) p->tab[a].tw = (const float2*)tdst;
             else p->tab[a].twm = (const float2*)tdst;
         }
-        if (a < 2) p->tw_fast[a] = p->tab[a].tw;
+        if (a < 2) { p->tw_fast[a] = p->tab[a].tw; p->tw_mix[a] = p->tab[a].twm; }
         if (a == 2 || a == 3) {
             std::vector<double> h64((size_t)n * n + n);
             std::copy(M.begin(), M.end(), h64.begin());
@@ -1055,7 +1059,9 @@ int plan_freeze(ot_dyn_plan* p, const std::vector<char>& frozen) {
     return OT_OK;
 }
 
-bool plan_has_fast_xy(const ot_dyn_plan* p) { return p->tw_fast[0] || p->tw_fast[1]; }
+bool plan_has_fast_xy(const ot_dyn_plan* p) {
+    return p->tw_fast[0] || p->tw_fast[1] || p->tw_mix[0] || p->tw_mix[1];
+}
 
 void plan_problem(const ot_dyn_plan* p, int b, ot_dyn_report* rep) {
     rep->r_prim = p->r_prim[b];

@@ -797,13 +797,13 @@ __global__ void __launch_bounds__(NT) k_p1d(TcArgs a) {
     }
 }
 
-// The one-block solve for a periodic axis whose length 2 M1 M2 is not a
-// power of two but has only the factors 2, 3 and 5 (the hue axes of 180 and
-// 360 bins): as k_p1d, with the mixed-radix Hartley transform of
-// line_dht_mix (its own inverse) along x instead of the dense contraction
-// on the matrix cores.  NT threads, a multiple of P and of 64, at least
+// The one-block solve for an axis whose length 2 M1 M2 is not a power of
+// two but has only the factors 2, 3 and 5 (the hue axes of 180 and 360
+// bins): as k_p1d, with the mixed-radix transforms of fft_lines.h along x
+// (Hartley for periodic x, KF = KI = 2; DCT-II / DCT-III for Neumann x)
+// instead of the dense contraction on the matrix cores.  NT threads, a multiple of P and of 64, at least
 // P M2; the rows are staged with float4 loads (L is a multiple of 4).
-template <int M1, int M2, int P, int NT>
+template <int M1, int M2, int P, int NT, int KF, int KI>
 __global__ void __launch_bounds__(NT) k_p1d_mix(TcArgs a) {
     constexpr int L = 2 * M1 * M2, T = M2, PITCH = L + 1, S = NT / P;
     static_assert(L % 4 == 0 && S * P == NT && S >= 2 && P * T <= NT, "block shape");
@@ -841,7 +841,7 @@ __global__ void __launch_bounds__(NT) k_p1d_mix(TcArgs a) {
     const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
     const bool act = line < P;
     float* const sl = lds + (act ? line : 0) * PITCH;
-    line_dht_mix<M1, M2>(sl, tt, a.tx.twm, act);
+    line_xform_mix<M1, M2, KF>(sl, tt, a.tx.twm, act);
     for (int jx = threadIdx.x; jx < L; jx += NT) {
         float u[P];
         if (jx == 0) {
@@ -861,7 +861,7 @@ __global__ void __launch_bounds__(NT) k_p1d_mix(TcArgs a) {
         for (int t = 0; t < P; ++t) lds[t * PITCH + jx] = u[t];
     }
     __syncthreads();
-    line_dht_mix<M1, M2>(sl, tt, a.tx.twm, act);
+    line_xform_mix<M1, M2, KI>(sl, tt, a.tx.twm, act);
     for (int v = threadIdx.x; v < NV4; v += NT) {
         const int e = 4 * v;
         const float* d = lds + (e / L) * PITCH + (e % L);
@@ -1003,20 +1003,20 @@ static bool p1d_dispatch(const TcArgs& a, hipStream_t st) {
     }
 }
 
-// Periodic lengths with a mixed-radix Hartley transform (k_p1d_mix), as
-// 2 M1 M2: 180 = 2 x 6 x 15, 360 = 2 x 12 x 15.
-bool mix_len(int n) { return n == 180 || n == 360; }
-
 template <int M1, int M2, int P>
 static void p1d_mix_launch(const TcArgs& a, hipStream_t st) {
     constexpr int NT0 = P * M2, NT = (NT0 + 63) / 64 * 64;
     static_assert(NT % P == 0, "row-sum slots");
-    hipLaunchKernelGGL((k_p1d_mix<M1, M2, P, NT>), dim3((unsigned)a.g.B), dim3(NT), 0, st, a);
+    if (a.g.perx)
+        hipLaunchKernelGGL((k_p1d_mix<M1, M2, P, NT, 2, 2>), dim3((unsigned)a.g.B), dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_p1d_mix<M1, M2, P, NT, 0, 1>), dim3((unsigned)a.g.B), dim3(NT), 0, st, a);
 }
 
 template <int P>
 static void p1d_mix_dispatch(const TcArgs& a, hipStream_t st) {
-    if (a.g.X == 180) p1d_mix_launch<6, 15, P>(a, st);
+    if (a.g.X == 100) p1d_mix_launch<5, 10, P>(a, st);
+    else if (a.g.X == 180) p1d_mix_launch<6, 15, P>(a, st);
     else p1d_mix_launch<12, 15, P>(a, st);
 }
 
@@ -1145,6 +1145,10 @@ bool launch_rows(float* R, long long rows, const AxisTab& t, int inverse, hipStr
         launch_rows_fast(R, rows, t.n, t.tw, t.periodic ? 2 : (inverse ? 1 : 0), st, sums, skip);
         return sums != nullptr;
     }
+    if (t.twm) {
+        launch_rows_mix(R, rows, t.n, t.twm, t.periodic ? 2 : (inverse ? 1 : 0), st, sums, skip);
+        return sums != nullptr;
+    }
     const int L = t.n;
     if (L <= kMfmaRowsMaxL) {
         const int Lp = (L + 31) / 32 * 32;
@@ -1165,6 +1169,10 @@ bool launch_cols(float* R, long long outer, long long inner, const AxisTab& t, i
                  hipStream_t st, const PlaneSums* sums) {
     if (t.tw) {
         launch_cols_fast(R, outer, inner, t.n, t.tw, t.periodic ? 2 : (inverse ? 1 : 0), st, sums);
+        return sums != nullptr;
+    }
+    if (t.twm) {
+        launch_cols_mix(R, outer, inner, t.n, t.twm, t.periodic ? 2 : (inverse ? 1 : 0), st, sums);
         return sums != nullptr;
     }
     const int L = t.n;
