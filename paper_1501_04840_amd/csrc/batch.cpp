@@ -264,6 +264,7 @@ int ot_dyn_batch_create(const ot_dyn_desc* base, int count, const int* dims, voi
         g.f1 = g.f0 + B * g.slice();
         st = ot_dyn_create(&g.d, g.side, bt->ws + g.off_plan, g.plan_bytes, &g.plan);
         if (st != OT_OK) return fail(st);
+        plan_enable_freeze(g.plan);
         g.conv_iter.assign(g.members.size(), -1);
         g.fell_back.assign(g.members.size(), 0);
         g.rep.assign(g.members.size(), ot_dyn_report{});

@@ -52,7 +52,10 @@ struct StepArgs {
     int prox;            // root of the prox cubic: OT_PROX_NEWTON or OT_PROX_CLOSED
     const float* sig;    // sigma per problem [B] (device; residual balancing)
     const float* frz;    // per problem [B]: nonzero = frozen (a certified member of a
-                         // batch): the stencil and colour/time kernels skip it
+                         // batch): the initialisation kernels skip it
+    const float* frz_run;  // the same flags for the iteration kernels, or null for a
+                           // plan outside a batch (no frozen problems; the kernels
+                           // then start without waiting for a flag load)
     float theta;
     // state
     float* F; float* Mx; float* My; float* Mc;
@@ -206,6 +209,9 @@ void plan_iterate(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc, boo
 int plan_collect(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc);
 void plan_apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy);
 bool plan_has_fast_xy(const ot_dyn_plan* p);
+// Marks a batch group's plan: its iteration kernels read the frozen flags
+// (call before the first launch or capture).
+void plan_enable_freeze(ot_dyn_plan* p);
 void plan_problem(const ot_dyn_plan* p, int b, ot_dyn_report* rep);
 void plan_add_iters(ot_dyn_plan* p, int n);
 // Freezes problem b (frozen[b] nonzero) or releases it; uploads on the

@@ -33,6 +33,7 @@ struct ot_dyn_plan {
     float* Rt;               // fused Poisson passes: transposed scratch [B][C][X][Y][P]
     float* dcl;              // fused Poisson passes: FP64-solved DC line [B][C][P]
     bool fused;              // the fused three-pass Poisson solve applies
+    bool freezable;          // a batch group's plan: its problems can be frozen
     bool p1d;                // one spatial axis: the one-block Poisson solve applies
     bool xfold;              // the divergence kernels also do the forward x transform
     float* sig;              // sigma per problem [B] (device)
@@ -262,6 +263,7 @@ StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     s.prox = p->d.prox;
     s.sig = p->sig;
     s.frz = p->frz;
+    s.frz_run = p->freezable ? p->frz : nullptr;
     s.theta = (float)p->d.theta;
     s.F = F; s.Mx = Mx; s.My = My; s.Mc = Mc;
     for (int q = 0; q < 4; ++q) { s.b[q] = p->b[q]; s.bb[q] = p->bb[q]; s.A[q] = p->A[q]; }
@@ -308,7 +310,7 @@ void poisson(ot_dyn_plan* p, float* R) {
     if (p->p1d) {
         timed(p, OT_PHASE_TC, [&] {
             launch_poisson_1d(g, R, p->tab[0], p->tab[1], p->tab[2], p->tab[3], p->tc64, p->tt64,
-                              p->frz, st);
+                              p->freezable ? p->frz : nullptr, st);
         });
         return;
     }
@@ -331,7 +333,7 @@ void poisson(ot_dyn_plan* p, float* R) {
     bool presummed = false;
     const PlaneSums ps{p->part_slice, B * g.P * g.C, p->nbx};
     // rows of frozen problems are skipped (rows per problem: P C Y)
-    const RowSkip skip{p->frz, (long long)g.P * g.C * g.Y};
+    const RowSkip skip{p->freezable ? p->frz : nullptr, (long long)g.P * g.C * g.Y};
     if (g.X > 1 && !p->xfold)
         timed(p, OT_PHASE_XFORM_X, [&] {
             presummed = launch_rows(R, B * g.P * g.C * g.Y, p->tab[0], 0, st, &ps, skip);
@@ -344,7 +346,7 @@ void poisson(ot_dyn_plan* p, float* R) {
         });
     timed(p, OT_PHASE_TC, [&] {
         launch_tc(g, R, p->tab[0], p->tab[1], p->tab[2], p->tab[3], p->tc64, p->tt64,
-                  p->part_slice, p->nbx, presummed ? 1 : 0, p->frz, st);
+                  p->part_slice, p->nbx, presummed ? 1 : 0, p->freezable ? p->frz : nullptr, st);
     });
     if (g.Y > 1)
         timed(p, OT_PHASE_XFORM_Y, [&] { launch_cols(R, B * g.P * g.C, g.X, p->tab[1], 1, st); });
@@ -658,6 +660,7 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->fused = false;
     p->p1d = false;
     p->xfold = false;
+    p->freezable = false;
     p->fac = p->sig + p->g.B;
     p->frz = p->sig + 2 * (size_t)p->g.B;
     p->f0 = (float*)(p->ws + L.off_f);
@@ -1058,6 +1061,8 @@ int plan_freeze(ot_dyn_plan* p, const std::vector<char>& frozen) {
                                  hipMemcpyHostToDevice, p->stream));
     return OT_OK;
 }
+
+void plan_enable_freeze(ot_dyn_plan* p) { p->freezable = true; }
 
 bool plan_has_fast_xy(const ot_dyn_plan* p) {
     return p->tw_fast[0] || p->tw_fast[1] || p->tw_mix[0] || p->tw_mix[1];

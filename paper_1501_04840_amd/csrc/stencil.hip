@@ -98,7 +98,7 @@ template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_div(StepArgs s) {
     const Geom& g = s.g;
     const Node n = node_of(g);
-    if (s.frz[n.b] != 0.f) return;       // frozen problem (block-uniform)
+    if (s.frz_run && s.frz_run[n.b] != 0.f) return;   // frozen problem (block-uniform)
     double acc = 0.0;
     if (n.live) {
         FaceA<MODE> a{s, n, 0.5f * s.tau_sigma};
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kBlock) k_update(StepArgs s) {
     constexpr bool CARRY = NPHI_ >= 3;
     const Geom& g = s.g;
     const Node n = node_of(g);
-    if (s.frz[n.b] != 0.f) return;       // frozen problem (block-uniform)
+    if (s.frz_run && s.frz_run[n.b] != 0.f) return;   // frozen problem (block-uniform)
     double db2 = 0, z2 = 0, dx2 = 0, x2 = 0, jj = 0;
     if (n.live) {
         const long long i = n.cb + n.p;

@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
     const RowCtx r = row_ctx(g, nxb);
     constexpr int XP = XL + 1;                     // LDS row pitch
     __shared__ float xl[XL > 0 ? C * XP : 1];
-    if (s.frz[r.b] != 0.f) return;       // frozen problem (block-uniform)
+    if (s.frz_run && s.frz_run[r.b] != 0.f) return;   // frozen problem (block-uniform)
     const float ts = 0.5f * s.tau_sigma;
     float rv[C];
 #pragma unroll
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
     constexpr bool TWO = NPHI == 2;
     const Geom& g = s.g;
     const RowCtx r = row_ctx(g, nxb);
-    if (s.frz[r.b] != 0.f) return;       // frozen problem (block-uniform)
+    if (s.frz_run && s.frz_run[r.b] != 0.f) return;   // frozen problem (block-uniform)
     double db2 = 0, z2 = 0, dx2 = 0, x2 = 0, jj = 0;
     if (r.live) {
         const Nbr nb = neighbours(g, r.x, r.y);
