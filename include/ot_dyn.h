@@ -245,8 +245,8 @@ int ot_dyn_destroy(ot_dyn_plan* p);
  * periodic hue histograms of different bin counts -- Sec. 5 of the paper
  * transports such histograms with X = bins, Y = C = 1, bc[0] periodic)
  * solved together.  Problems are grouped by shape; each group is one batched
- * plan whose chunk of iterations is captured into a HIP graph of its own,
- * replayed on the group's own stream (one stream and graph per group).
+ * plan, and a chunk of iterations of every active group is captured into
+ * one HIP graph with a branch per group (each on the group's own stream).
  * Per-group launch shapes can be autotuned.
  *
  * dims: host array of count x 4 ints (X, Y, C, P) per problem.  The other

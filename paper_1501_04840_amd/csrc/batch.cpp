@@ -2,13 +2,14 @@
 //
 // Problems are grouped by shape (X, Y, C, P); a group is one batched plan
 // over group-contiguous buffers inside the caller's workspace.  A chunk of
-// iterations of every active group is captured into a HIP graph of its own
-// and replayed on the group's own stream, so the per-kernel launch cost is
-// paid once per graph (in kernel traces the groups' graphs do not overlap on
-// the GPU: their streams give no concurrency).  After each chunk the FP64
-// residuals of every problem are
-// collected and certified problems are recorded; a group whose problems are
-// all certified leaves the graph.
+// iterations of every active group is captured into one HIP graph with a
+// branch per group (the batch's stream forks into the groups' streams and
+// joins them), so the per-kernel launch cost is paid once per graph.  The
+// branches overlap little on the GPU: the tail of a batch, where a few
+// problems of several groups remain, costs about the sum of the groups'
+// launch latencies per iteration.  After each chunk the FP64 residuals of
+// every problem are collected and certified problems are recorded; a group
+// whose problems are all certified leaves the graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,8 +50,6 @@ struct Group {
     std::vector<int> stopped;      // per member: iteration it stopped uncertified, -1 if running
     std::vector<ot_dyn_report> rep;
     int row_bx = 0, dense_xy = 0;
-    hipGraph_t graph = nullptr;       // chunk of iterations captured on `side`
-    hipGraphExec_t exec = nullptr;
     long long slice() const { return (long long)d.X * d.Y * d.C; }
     long long nc() const { return slice() * d.P; }
     long long nf() const { return slice() * (d.P + 1); }
@@ -143,6 +142,8 @@ struct ot_dyn_batch {
     int graph_chunk = 0;
     bool graph_varies = false;     // launch sequence changes after this graph
     std::vector<int> graph_groups;
+    hipGraph_t graph = nullptr;    // one chunk of every active group, a branch each
+    hipGraphExec_t exec = nullptr;
     std::string err;
 };
 
@@ -159,34 +160,48 @@ int hipfail(ot_dyn_batch* bt, hipError_t e, const char* what) {
     } while (0)
 
 void drop_graph(ot_dyn_batch* bt) {
-    for (auto& g : bt->P.groups) {
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        if (g.graph) (void)hipGraphDestroy(g.graph);
-        g.exec = nullptr;
-        g.graph = nullptr;
-    }
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    bt->exec = nullptr;
+    bt->graph = nullptr;
     bt->graph_groups.clear();
     bt->graph_chunk = 0;
 }
 
 // Capture `chunk` iterations (the last one with residual partials) of every
-// active group, one graph per group on the group's own stream.
+// active group into one graph: the batch's stream forks into the groups'
+// streams (event record / wait), each group's chunk is a branch, and the
+// branches join back, so the graph holds independent chains that the
+// runtime can run concurrently.
 int build_graph(ot_dyn_batch* bt, int chunk) {
     drop_graph(bt);
     bool varies = false;
-    for (size_t gi = 0; gi < bt->P.groups.size(); ++gi) {
-        Group& g = bt->P.groups[gi];
-        if (!g.active) continue;
+    std::vector<int> act;
+    for (size_t gi = 0; gi < bt->P.groups.size(); ++gi)
+        if (bt->P.groups[gi].active) act.push_back((int)gi);
+    if (act.empty()) return OT_OK;
+    BCHK(bt, hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipEventRecord(bt->ev_fork, bt->stream);
+    for (size_t i = 0; e == hipSuccess && i < act.size(); ++i) {
+        Group& g = bt->P.groups[act[i]];
         varies = varies || plan_launch_varies(g.plan);
-        BCHK(bt, hipStreamBeginCapture(g.side, hipStreamCaptureModeThreadLocal));
+        e = hipStreamWaitEvent(g.side, bt->ev_fork, 0);
+        if (e != hipSuccess) break;
         for (int it = 0; it < chunk; ++it)
             plan_iterate(g.plan, g.F, g.Mx, g.My, g.Mc, it + 1 == chunk);
-        hipGraph_t graph = nullptr;
-        BCHK(bt, hipStreamEndCapture(g.side, &graph));
-        g.graph = graph;
-        BCHK(bt, hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
-        bt->graph_groups.push_back((int)gi);
+        e = hipEventRecord(bt->ev_join[act[i]], g.side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(bt->stream, bt->ev_join[act[i]], 0);
     }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(bt->stream, &graph);
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hipfail(bt, e, "capture of the groups' chunk");
+    }
+    if (e2 != hipSuccess) return hipfail(bt, e2, "hipStreamEndCapture");
+    bt->graph = graph;
+    BCHK(bt, hipGraphInstantiate(&bt->exec, graph, nullptr, nullptr, 0));
+    bt->graph_groups = act;
     bt->graph_chunk = chunk;
     bt->graph_varies = varies;
     return OT_OK;
@@ -412,11 +427,11 @@ int ot_dyn_batch_solve(ot_dyn_batch* bt, int max_iters, int chunk, ot_dyn_report
             const int st = build_graph(bt, k);
             if (st != OT_OK) return st;
         }
-        for (int gi : bt->graph_groups) {
-            Group& g = bt->P.groups[gi];
-            BCHK(bt, hipGraphLaunch(g.exec, g.side));
-        }
+        // work the last check left on the groups' streams (step rescaling,
+        // frozen flags) precedes the graph
         for (int gi : bt->graph_groups) BCHK(bt, hipStreamSynchronize(bt->P.groups[gi].side));
+        BCHK(bt, hipGraphLaunch(bt->exec, bt->stream));
+        BCHK(bt, hipStreamSynchronize(bt->stream));
         done += k;
         bool changed = false;
         for (int gi : bt->graph_groups) {
