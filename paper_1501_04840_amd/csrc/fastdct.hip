@@ -6,6 +6,8 @@
 #include "otd_common.h"
 #include "fft_lines.h"
 
+#pragma clang fp contract(on)   // as in fft_common.h
+
 namespace otd {
 
 // Planes reduced per block by the plane-sum blocks of k_rows_fft (32 lanes,

@@ -3,6 +3,12 @@
 
 #include <hip/hip_runtime.h>
 
+// Multiply-adds are fused only within one source expression (as in the
+// stencil kernels): left to the backend, fusion depends on the surrounding
+// code, and the same line transform would round differently in different
+// kernels.
+#pragma clang fp contract(on)
+
 namespace otd {
 
 // ---- complex helpers --------------------------------------------------------

@@ -18,6 +18,8 @@
 #include "fft_common.h"
 #include "fft_lines.h"
 
+#pragma clang fp contract(on)   // as in fft_common.h
+
 namespace otd {
 
 constexpr int kT = 256;
