@@ -41,8 +41,11 @@ __device__ __forceinline__ void plane_sums_block(const PlaneSums& ps, long long 
 }
 
 // Contiguous axis: LPB whole rows per block, row pitch L + 1 in LDS.  The
-// block's rows are one contiguous span, staged with unrolled float4 loads
-// so that every thread keeps all of its loads in flight at once.  The first
+// block's rows are one contiguous span, staged with unrolled loads so that
+// every thread keeps all of its loads in flight at once; single floats,
+// consecutive over the threads, so that the LDS writes of a wave fall in
+// distinct banks (float4 loads written as four floats hit each bank four
+// times).  The first
 // nsb blocks instead reduce the FP64 plane sums `ps` in place (the first
 // forward pass runs between the divergence kernel that writes them and the
 // colour/time pass that solves the spatial-DC line from them, so the
@@ -51,7 +54,7 @@ template <int M1, int M2, int KIND>
 __global__ void __launch_bounds__(256) k_rows_fft(float* R, long long rows, const float2* tw4,
                                                   PlaneSums ps, int nsb, RowSkip skip) {
     constexpr int L = 2 * M1 * M2, T = M2, LPB = 256 / T, PITCH = L + 1;
-    constexpr int NV = LPB * L / 1024;            // float4 per thread
+    constexpr int NS = LPB * L / 256;             // floats per thread
     __shared__ float lds[LPB * PITCH];
     if ((int)blockIdx.x < nsb) {
         plane_sums_block(ps, blockIdx.x);
@@ -61,26 +64,24 @@ __global__ void __launch_bounds__(256) k_rows_fft(float* R, long long rows, cons
     const int nr = (int)min((long long)LPB, rows - r0);
     if (rows_frozen(skip, r0, nr)) return;
     float* g = R + r0 * L;
-    float4 buf[NV];
+    float buf[NS];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int e = 4 * (threadIdx.x + 256 * j);
-        buf[j] = e / L < nr ? *reinterpret_cast<const float4*>(g + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int j = 0; j < NS; ++j) {
+        const int e = threadIdx.x + 256 * j;
+        buf[j] = e / L < nr ? g[e] : 0.f;
     }
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int e = 4 * (threadIdx.x + 256 * j);
-        float* d = lds + (e / L) * PITCH + (e % L);
-        d[0] = buf[j].x; d[1] = buf[j].y; d[2] = buf[j].z; d[3] = buf[j].w;
+    for (int j = 0; j < NS; ++j) {
+        const int e = threadIdx.x + 256 * j;
+        lds[(e / L) * PITCH + (e % L)] = buf[j];
     }
     __syncthreads();
     const int line = threadIdx.x / T, t = threadIdx.x - line * T;
     line_xform<M1, M2, KIND>(lds + line * PITCH, t, tw4);
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int e = 4 * (threadIdx.x + 256 * j);
-        const float* d = lds + (e / L) * PITCH + (e % L);
-        if (e / L < nr) *reinterpret_cast<float4*>(g + e) = make_float4(d[0], d[1], d[2], d[3]);
+    for (int j = 0; j < NS; ++j) {
+        const int e = threadIdx.x + 256 * j;
+        if (e / L < nr) g[e] = lds[(e / L) * PITCH + (e % L)];
     }
 }
 

@@ -732,8 +732,8 @@ __global__ void __launch_bounds__(NT) k_yt(TcArgs a) {
 template <int M1, int M2, int P, int NT, int KF, int KI>
 __global__ void __launch_bounds__(NT) k_p1d(TcArgs a) {
     constexpr int L = 2 * M1 * M2, T = M2, PITCH = L + 1, NLINES = cmax(P, NT / T);
-    constexpr int NV = L * P / (4 * NT), S = NT / P;
-    static_assert(NV * 4 * NT == L * P, "tile must split into float4 per thread");
+    constexpr int NS = L * P / NT, S = NT / P;
+    static_assert(NS * NT == L * P, "tile must split into floats per thread");
     static_assert(S * P == NT && S >= 2, "row-sum slots");
     __shared__ __align__(16) float lds[NLINES * PITCH];
     __shared__ double dsum[NT + 2 * P];
@@ -742,15 +742,15 @@ __global__ void __launch_bounds__(NT) k_p1d(TcArgs a) {
     const int b = blockIdx.x;
     if (a.frz && a.frz[b] != 0.f) return;   // frozen problem (block-uniform)
     float* base = a.R + (long long)b * g.nc;
-    float4 buf[NV];
+    // single floats, consecutive over the threads (conflict-free LDS writes)
+    float buf[NS];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) buf[j] = reinterpret_cast<const float4*>(base)[threadIdx.x + NT * j];
+    for (int j = 0; j < NS; ++j) buf[j] = base[threadIdx.x + NT * j];
     for (int e = P * PITCH + threadIdx.x; e < NLINES * PITCH; e += NT) lds[e] = 0.f;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int e = 4 * ((int)threadIdx.x + NT * j);
-        float* d = lds + (e / L) * PITCH + (e % L);
-        d[0] = buf[j].x; d[1] = buf[j].y; d[2] = buf[j].z; d[3] = buf[j].w;
+    for (int j = 0; j < NS; ++j) {
+        const int e = (int)threadIdx.x + NT * j;
+        lds[(e / L) * PITCH + (e % L)] = buf[j];
     }
     __syncthreads();
     {   // FP64 sums of the time rows: S slots per row, then one thread per row
@@ -792,10 +792,9 @@ __global__ void __launch_bounds__(NT) k_p1d(TcArgs a) {
     __syncthreads();
     line_xform<M1, M2, KI>(lds + line * PITCH, tt, a.tx.tw);
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int e = 4 * ((int)threadIdx.x + NT * j);
-        const float* d = lds + (e / L) * PITCH + (e % L);
-        reinterpret_cast<float4*>(base)[threadIdx.x + NT * j] = make_float4(d[0], d[1], d[2], d[3]);
+    for (int j = 0; j < NS; ++j) {
+        const int e = (int)threadIdx.x + NT * j;
+        base[e] = lds[(e / L) * PITCH + (e % L)];
     }
 }
 
@@ -804,7 +803,7 @@ __global__ void __launch_bounds__(NT) k_p1d(TcArgs a) {
 // bins): as k_p1d, with the mixed-radix transforms of fft_lines.h along x
 // (Hartley for periodic x, KF = KI = 2; DCT-II / DCT-III for Neumann x)
 // instead of the dense contraction on the matrix cores.  NT threads, a multiple of P and of 64, at least
-// P M2; the rows are staged with float4 loads (L is a multiple of 4).
+// P M2; the rows are staged as in k_p1d.
 template <int M1, int M2, int P, int NT, int KF, int KI>
 __global__ void __launch_bounds__(NT) k_p1d_mix(TcArgs a) {
     constexpr int L = 2 * M1 * M2, T = M2, PITCH = L + 1, S = NT / P;
@@ -816,12 +815,19 @@ __global__ void __launch_bounds__(NT) k_p1d_mix(TcArgs a) {
     const int b = blockIdx.x;
     if (a.frz && a.frz[b] != 0.f) return;   // frozen problem (block-uniform)
     float* base = a.R + (long long)b * g.nc;
-    constexpr int NV4 = L * P / 4;
-    for (int v = threadIdx.x; v < NV4; v += NT) {
-        const float4 q = reinterpret_cast<const float4*>(base)[v];
-        const int e = 4 * v;
-        float* d = lds + (e / L) * PITCH + (e % L);
-        d[0] = q.x; d[1] = q.y; d[2] = q.z; d[3] = q.w;
+    // single floats, consecutive over the threads (conflict-free LDS writes),
+    // all of a thread's loads in flight at once
+    constexpr int NS = (L * P + NT - 1) / NT;
+    float buf[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const int e = (int)threadIdx.x + NT * j;
+        buf[j] = e < L * P ? base[e] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const int e = (int)threadIdx.x + NT * j;
+        if (e < L * P) lds[(e / L) * PITCH + (e % L)] = buf[j];
     }
     __syncthreads();
     {   // FP64 sums of the time rows: S slots per row, then one thread per row
@@ -864,10 +870,10 @@ __global__ void __launch_bounds__(NT) k_p1d_mix(TcArgs a) {
     }
     __syncthreads();
     line_xform_mix<M1, M2, KI>(sl, tt, a.tx.twm, act);
-    for (int v = threadIdx.x; v < NV4; v += NT) {
-        const int e = 4 * v;
-        const float* d = lds + (e / L) * PITCH + (e % L);
-        reinterpret_cast<float4*>(base)[v] = make_float4(d[0], d[1], d[2], d[3]);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const int e = (int)threadIdx.x + NT * j;
+        if (e < L * P) base[e] = lds[(e / L) * PITCH + (e % L)];
     }
 }
 
