@@ -101,6 +101,8 @@ SHAPES = [
     (180, 12, 1, 8, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),   # Hartley rows, 6 x 15
     (24, 360, 1, 4, (G.NEUMANN, G.PERIODIC, G.NEUMANN), 12),   # Hartley cols, 12 x 15
     (36, 180, 2, 4, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),   # DCT cols, 6 x 15
+    (360, 6, 1, 4, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),     # DCT rows, 12 x 15
+    (180, 1, 1, 16, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),    # one-block solve, DCT 6 x 15
 ]
 
 
