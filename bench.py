@@ -53,11 +53,13 @@ KERNEL_WORDS = {
 }
 
 
-def kernel_name(phase, mode, C, X=0, xfold=False, xkind=0):
+def kernel_name(phase, mode, C, X=0, xfold=False, xkind=0, fused=False):
     """Full name of the kernel a steady-state iteration launches for `phase`
-    (row stencils and power-of-two transforms; the five-pass path).  With
-    xfold the divergence kernel also does the forward x transform (DCT-II,
-    xkind 0, or Hartley, 2) of its rows of length X."""
+    (row stencils and power-of-two transforms).  With xfold the divergence
+    kernel also does the forward x transform (DCT-II, xkind 0, or Hartley, 2)
+    of its rows of length X; with fused the Poisson solve is the three-pass
+    one (x pass with the colour transform into a transposed scratch, the y
+    and time pass, the inverse x pass)."""
     if phase == "div":
         return f"k_div_rows<{ {0: 0, 1: 0, 3: 2}[mode] }, {C}, {X if xfold else 0}, " \
                f"{xkind if xfold else 0}>"
@@ -65,6 +67,8 @@ def kernel_name(phase, mode, C, X=0, xfold=False, xkind=0):
         return f"k_update_rows<0, { {0: 1, 1: 2, 3: 3}[mode] }, {C}>"
     if phase == "refine":
         return f"k_div_rows<1, {C}>"
+    if fused:
+        return {"xform_x": "k_xf_tr + k_xi_tr", "tc": "k_yt"}[phase]
     return {"xform_x": "k_rows_fft", "xform_y": "k_cols_fft", "tc": "k_tc_reg"}[phase]
 
 
@@ -464,8 +468,10 @@ def main():
     phases = otdyn.ot_dyn_profile_read(prob.plan)
     split = {}
     iter_words = 0.0
-    # one x pass per iteration: the forward one is folded into the divergence kernel
+    # one x pass per iteration: the forward one is folded into the divergence
+    # kernel; no y pass: the three-pass solve (y and time in one pass)
     xfold = phases["xform_x"][1] == n_split
+    fused = Y > 1 and phases["xform_y"][1] == 0
     for name, (ms, n) in phases.items():
         if n == 0:
             continue
@@ -473,7 +479,7 @@ def main():
         mw = METHOD_WORDS[name]
         iter_words += kw * n / n_split
         split[name] = {"ms_per_iter": ms / n_split, "launches": n, "avg_launch_us": 1e3 * ms / n,
-                       "kernel": kernel_name(name, mode, C, X, xfold),
+                       "kernel": kernel_name(name, mode, C, X, xfold, fused=fused),
                        "method_words_per_launch": mw, "kernel_words_per_launch": kw,
                        "algorithmic_GBs": mw * 4.0 * N * n / (ms * 1e-3) / 1e9,
                        "kernel_GBs": kw * 4.0 * N * n / (ms * 1e-3) / 1e9}

@@ -375,12 +375,12 @@ void apply_tuning(ot_dyn_plan* p, int row_bx, int dense_xy) {
     }
     // the fused passes use one block per row index and problem: measured
     // faster than the five passes at 64 x 64 and 128 x 128 (alone and
-    // batched) and 2% slower for one 256 x 256 problem (256 blocks, one fat
-    // block per CU), where the five passes are kept
+    // batched) and, since the FP64 DC line's loads are all in flight, for one
+    // 256 x 256 problem as well (1.3% per iteration against the five passes
+    // with the forward x transform folded into the divergence kernel)
     // problems with one spatial axis: the whole solve in one block per problem
     p->p1d = dense_xy != 1 && poisson_1d_ok(g, p->tab[0], p->tab[3]);
-    p->fused = dense_xy == 0 && fused_poisson_ok(g, p->tab[0], p->tab[1], p->tab[3]) &&
-               ((long long)g.B * g.Y >= 512 || (long long)g.X * g.Y < 65536);
+    p->fused = dense_xy == 0 && fused_poisson_ok(g, p->tab[0], p->tab[1], p->tab[3]);
     // the five-pass solve with rows of one block each: the divergence
     // kernels write r already transformed along x (one pass fewer)
     p->xfold = !p->p1d && !p->fused && g.X > 1 && div_fold_ok(g, row_bx, p->tab[0]);
