@@ -566,7 +566,8 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <int M1, int M2, int C, int P, int PS>
 __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
     constexpr int L = 2 * M1 * M2, T = M2, NL = PS * C, NT = NL * T, PITCH = L + 1;
-    constexpr int NV = L / (4 * T);
+    constexpr int NE = L / T;                      // tile floats per thread
+    static_assert(NE * NT == NL * L && NT % PS == 0, "tile split");
     constexpr int LDSF = cmax(NL * PITCH, 2 * dc_scratch_doubles(P * C));
     __shared__ __align__(16) float lds[LDSF];
     const Geom& g = a.g;
@@ -578,19 +579,22 @@ __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
     // block: row index y, time slices t0 .. t0 + PS - 1
     const int y = blockIdx.x / (P / PS), t0 = (blockIdx.x - y * (P / PS)) * PS;
     const float* src = a.R + (long long)b * g.nc + (long long)t0 * g.slice + (long long)y * L;
-    float4 buf[NV];
+    // single floats, consecutive over the threads (coalesced loads, all in
+    // flight; conflict-free LDS writes).  Offsets within a problem fit in 32
+    // bits (at most 256 x 256 x 3 x 32 values), so the loads take a uniform
+    // base and a 32-bit offset.
+    const unsigned slice = (unsigned)g.slice, plane = (unsigned)g.plane;
+    float buf[NE];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int e = 4 * ((int)threadIdx.x + NT * j);
-        const int line = e / L, col = e - line * L, t = line / C, c = line - t * C;
-        buf[j] = *reinterpret_cast<const float4*>(src + (long long)t * g.slice +
-                                                  (long long)c * g.plane + col);
+    for (int j = 0; j < NE; ++j) {
+        const unsigned e = threadIdx.x + NT * j;
+        const unsigned line = e / L, col = e % L, t = line / C, c = line % C;
+        buf[j] = src[t * slice + c * plane + col];
     }
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int e = 4 * ((int)threadIdx.x + NT * j);
-        float* d = lds + (e / L) * PITCH + (e % L);
-        d[0] = buf[j].x; d[1] = buf[j].y; d[2] = buf[j].z; d[3] = buf[j].w;
+    for (int j = 0; j < NE; ++j) {
+        const int e = (int)threadIdx.x + NT * j;
+        lds[(e / L) * PITCH + (e % L)] = buf[j];
     }
     __syncthreads();
     const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
@@ -612,25 +616,42 @@ __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
         }
         __syncthreads();
     }
+    // transposed store: a thread keeps its slice tq (NT is a multiple of PS)
+    // and steps r = jc L + jx by NT / PS; every LDS read before the stores
+    const unsigned tq = threadIdx.x % PS, r0 = threadIdx.x / PS, ys = (unsigned)(g.Y * P);
     float* dst = a.Rt + (long long)b * g.nc + (long long)y * P + t0;
-    for (int e = threadIdx.x; e < NL * L; e += NT) {
-        const int t = e % PS, r = e / PS, jx = r % L, jc = r / L;
-        dst[(long long)(jc * L + jx) * g.Y * P + t] = lds[(t * C + jc) * PITCH + jx];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        const unsigned r = r0 + (NT / PS) * j, jx = r % L, jc = r / L;
+        buf[j] = lds[(tq * C + jc) * PITCH + jx];
     }
+    const unsigned o0 = r0 * ys + tq, step = (NT / PS) * ys;
+#pragma unroll
+    for (int j = 0; j < NE; ++j) dst[o0 + j * step] = buf[j];
 }
 
 template <int M1, int M2, int C, int P, int PS>
 __global__ void __launch_bounds__(PS * C * M2) k_xi_tr(TcArgs a) {
     constexpr int L = 2 * M1 * M2, T = M2, NL = PS * C, NT = NL * T, PITCH = L + 1;
-    constexpr int NV = L / (4 * T);
+    constexpr int NE = L / T;                      // tile floats per thread
+    static_assert(NE * NT == NL * L && NT % PS == 0, "tile split");
     __shared__ __align__(16) float lds[NL * PITCH];
     const Geom& g = a.g;
     const int b = blockIdx.y;
     const int y = blockIdx.x / (P / PS), t0 = (blockIdx.x - y * (P / PS)) * PS;
+    // transposed load, the mirror of the forward pass's store: all loads in
+    // flight before the first LDS write
+    // (32-bit offsets from a uniform base, as in the forward pass)
+    const unsigned tq = threadIdx.x % PS, r0 = threadIdx.x / PS, ys = (unsigned)(g.Y * P);
     const float* src = a.Rt + (long long)b * g.nc + (long long)y * P + t0;
-    for (int e = threadIdx.x; e < NL * L; e += NT) {
-        const int t = e % PS, r = e / PS, jx = r % L, jc = r / L;
-        lds[(t * C + jc) * PITCH + jx] = src[(long long)(jc * L + jx) * g.Y * P + t];
+    const unsigned o0 = r0 * ys + tq, step = (NT / PS) * ys;
+    float buf[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) buf[j] = src[o0 + j * step];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        const unsigned r = r0 + (NT / PS) * j, jx = r % L, jc = r / L;
+        lds[(tq * C + jc) * PITCH + jx] = buf[j];
     }
     __syncthreads();
     if constexpr (C > 1) {
@@ -654,12 +675,15 @@ __global__ void __launch_bounds__(PS * C * M2) k_xi_tr(TcArgs a) {
     line_xform<M1, M2, 1>(lds + line * PITCH, tt, a.tx.tw);
     float* dstb = a.R + (long long)b * g.nc + (long long)t0 * g.slice + (long long)y * L;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int e = 4 * ((int)threadIdx.x + NT * j);
-        const int ln = e / L, col = e - ln * L, t = ln / C, c = ln - t * C;
-        const float* d = lds + ln * PITCH + col;
-        *reinterpret_cast<float4*>(dstb + (long long)t * g.slice + (long long)c * g.plane + col) =
-            make_float4(d[0], d[1], d[2], d[3]);
+    for (int j = 0; j < NE; ++j) {
+        const int e = (int)threadIdx.x + NT * j;
+        buf[j] = lds[(e / L) * PITCH + (e % L)];
+    }
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        const int e = (int)threadIdx.x + NT * j;
+        const unsigned ln = (unsigned)e / L, col = (unsigned)e % L, ts = ln / C, c = ln % C;
+        dstb[ts * (unsigned)g.slice + c * (unsigned)g.plane + col] = buf[j];
     }
 }
 
