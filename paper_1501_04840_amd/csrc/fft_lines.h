@@ -28,14 +28,16 @@ namespace otd {
 
 // Four-step DFT of length M = M1 M2 on one line.  Stage-1 input n = M2 n1 + t
 // comes from load(n1) (the caller knows t); on return out[q][k2] =
-// Z[k1 + M1 k2] with k1 = t + M2 q.  The line's LDS region s (2M floats) is
-// used for the exchange.  All threads of the block must call this (it
-// synchronises the block); threads with `act` false only take part in the
-// synchronisation (their s and out are not touched).
-template <int M1, int M2, class Load>
+// Z[k1 + M1 k2] with k1 = t + M2 q.  The line's LDS region s is used for the
+// exchange: M1 rows of M2 complex values, each row followed by XP padding
+// floats (M1 (2 M2 + XP) floats; XP even).  All threads of the block must
+// call this (it synchronises the block); threads with `act` false only take
+// part in the synchronisation (their s and out are not touched).
+template <int M1, int M2, int XP = 0, class Load>
 __device__ __forceinline__ void fft_core(float* s, int t, const float2* tw4, Load load,
                                          float2 (&out)[M1 / M2][M2], bool act = true) {
-    constexpr int M = M1 * M2, L = 2 * M;
+    constexpr int M = M1 * M2, L = 2 * M, RW = M2 + XP / 2;   // exchange row, complex units
+    static_assert(XP % 2 == 0, "exchange padding in whole complex values");
     float2 a[M1];
     if (act) {
 #pragma unroll
@@ -46,17 +48,17 @@ __device__ __forceinline__ void fft_core(float* s, int t, const float2* tw4, Loa
     }
     __syncthreads();
     if (act) {
-        float* const sw = s + 2 * t;                  // Z1[k1 M2 + t]
+        float* const sw = s + 2 * t;                  // Z1[k1][t]
 #pragma unroll
-        for (int k1 = 0; k1 < M1; ++k1) st2(sw, k1 * M2, a[k1]);
+        for (int k1 = 0; k1 < M1; ++k1) st2(sw, k1 * RW, a[k1]);
     }
     __syncthreads();
     if (act) {
-        const float* const sr = s + 2 * M2 * t;       // Z1[(t + M2 q) M2 + n2]
+        const float* const sr = s + 2 * RW * t;       // Z1[t + M2 q][n2]
 #pragma unroll
         for (int q = 0; q < M1 / M2; ++q) {
 #pragma unroll
-            for (int n2 = 0; n2 < M2; ++n2) out[q][n2] = ld2(sr, M2 * M2 * q + n2);
+            for (int n2 = 0; n2 < M2; ++n2) out[q][n2] = ld2(sr, RW * M2 * q + n2);
             dft<M2>(out[q]);
         }
     }
@@ -87,7 +89,7 @@ __device__ __forceinline__ void load_pair(const float* s, int t, int j, float2& 
 // with LDS instructions (32-bit addresses that wrap): s - 4t is below the
 // first line's start, which as a 64-bit generic (flat) address would leave
 // the LDS aperture.
-template <int M1, int M2>
+template <int M1, int M2, int XP = 0>
 __device__ __forceinline__ void line_dct2(float* s, int t, const float2* tw4, bool act = true) {
     constexpr int M = M1 * M2, L = 2 * M, T = M2, NP = (M / 2 + T) / T;
     // z[n] = v[2n] + i v[2n+1] with n = M2 n1 + t; v[2n] and v[2n+1] are
@@ -96,7 +98,7 @@ __device__ __forceinline__ void line_dct2(float* s, int t, const float2* tw4, bo
     const float* const sp = s + 4 * t;
     const float* const sm = s - 4 * t;
     float2 z[M1 / M2][M2];
-    fft_core<M1, M2>(s, t, tw4, [&](int n1) {
+    fft_core<M1, M2, XP>(s, t, tw4, [&](int n1) {
         return n1 < M1 / 2 ? make_float2(sp[4 * M2 * n1], sp[4 * M2 * n1 + 2])
                            : make_float2(sm[2 * L - 1 - 4 * M2 * n1], sm[2 * L - 3 - 4 * M2 * n1]);
     }, z, act);
@@ -142,7 +144,7 @@ __device__ __forceinline__ void line_dct2(float* s, int t, const float2* tw4, bo
 }
 
 // Orthonormal DCT-III (inverse of line_dct2) in place.
-template <int M1, int M2>
+template <int M1, int M2, int XP = 0>
 __device__ __forceinline__ void line_dct3(float* s, int t, const float2* tw4) {
     constexpr int M = M1 * M2, L = 2 * M, T = M2, NP = (M / 2 + T) / T;
     // inputs scaled by sqrt(L / 2) (sqrt(L) for X[0]); with V(k) =
@@ -181,7 +183,7 @@ __device__ __forceinline__ void line_dct3(float* s, int t, const float2* tw4) {
     __syncthreads();
     float2 r[M1 / M2][M2];
     const float* const sl = s + 2 * t;
-    fft_core<M1, M2>(s, t, tw4, [&](int n1) { return ld2(sl, M2 * n1); }, r);
+    fft_core<M1, M2, XP>(s, t, tw4, [&](int n1) { return ld2(sl, M2 * n1); }, r);
     __syncthreads();
     // output n = t + M2 q + M1 k2: x[pos(2n)] = Re r / M, x[pos(2n+1)] = -Im r / M
     // with pos(m) = 2m (m < M), 2(L-1-m)+1 (m >= M); m < M iff the
@@ -456,10 +458,13 @@ __device__ __forceinline__ void line_xform_mix(float* s, int t, const float2* tw
     else line_dht_mix<M1, M2>(s, t, tw4, act);
 }
 
-template <int M1, int M2, int KIND>
+// XP: exchange padding of the DCTs (fft_core); the line's LDS region then
+// needs max(2 M, M1 (2 M2 + XP)) floats.
+template <int M1, int M2, int KIND, int XP = 0>
 __device__ __forceinline__ void line_xform(float* s, int t, const float2* tw4) {
-    if constexpr (KIND == 0) line_dct2<M1, M2>(s, t, tw4);
-    else if constexpr (KIND == 1) line_dct3<M1, M2>(s, t, tw4);
+    static_assert(KIND != 2 || XP == 0, "no padded exchange for the Hartley transform");
+    if constexpr (KIND == 0) line_dct2<M1, M2, XP>(s, t, tw4);
+    else if constexpr (KIND == 1) line_dct3<M1, M2, XP>(s, t, tw4);
     else line_dht<M1, M2>(s, t, tw4);
 }
 

@@ -563,9 +563,19 @@ static bool tc_reg_dispatch(const TcArgs& a, hipStream_t st) {
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
+// LDS layout of the lines of length 256 in the fused passes: a row pitch of
+// 325 floats and 4 floats of padding after each row of the four-step
+// exchange, which takes the line transforms' bank conflicts (8 lines of 8
+// threads per wave) to about half of those of the pitch L + 1; other
+// lengths keep L + 1 and no padding.
+template <int L> constexpr int fused_xp() { return L == 256 ? 4 : 0; }
+template <int L> constexpr int fused_pitch() { return L == 256 ? 325 : L + 1; }
+
 template <int M1, int M2, int C, int P, int PS>
 __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
-    constexpr int L = 2 * M1 * M2, T = M2, NL = PS * C, NT = NL * T, PITCH = L + 1;
+    constexpr int L = 2 * M1 * M2, T = M2, NL = PS * C, NT = NL * T, PITCH = fused_pitch<L>();
+    constexpr int XP = fused_xp<L>();
+    static_assert(PITCH >= M1 * (2 * M2 + XP), "exchange fits the line");
     constexpr int NE = L / T;                      // tile floats per thread
     static_assert(NE * NT == NL * L && NT % PS == 0, "tile split");
     constexpr int LDSF = cmax(NL * PITCH, 2 * dc_scratch_doubles(P * C));
@@ -598,7 +608,7 @@ __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
     }
     __syncthreads();
     const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
-    line_xform<M1, M2, 0>(lds + line * PITCH, tt, a.tx.tw);
+    line_xform<M1, M2, 0, XP>(lds + line * PITCH, tt, a.tx.tw);
     if constexpr (C > 1) {
         const float* Tc = a.tc.mat;                    // Tc[c * C + jc] = M_c[jc][c]
         for (int q = threadIdx.x; q < PS * L; q += NT) {
@@ -632,7 +642,9 @@ __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
 
 template <int M1, int M2, int C, int P, int PS>
 __global__ void __launch_bounds__(PS * C * M2) k_xi_tr(TcArgs a) {
-    constexpr int L = 2 * M1 * M2, T = M2, NL = PS * C, NT = NL * T, PITCH = L + 1;
+    constexpr int L = 2 * M1 * M2, T = M2, NL = PS * C, NT = NL * T, PITCH = fused_pitch<L>();
+    constexpr int XP = fused_xp<L>();
+    static_assert(PITCH >= M1 * (2 * M2 + XP), "exchange fits the line");
     constexpr int NE = L / T;                      // tile floats per thread
     static_assert(NE * NT == NL * L && NT % PS == 0, "tile split");
     __shared__ __align__(16) float lds[NL * PITCH];
@@ -672,7 +684,7 @@ __global__ void __launch_bounds__(PS * C * M2) k_xi_tr(TcArgs a) {
         __syncthreads();
     }
     const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
-    line_xform<M1, M2, 1>(lds + line * PITCH, tt, a.tx.tw);
+    line_xform<M1, M2, 1, XP>(lds + line * PITCH, tt, a.tx.tw);
     float* dstb = a.R + (long long)b * g.nc + (long long)t0 * g.slice + (long long)y * L;
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
@@ -689,7 +701,9 @@ __global__ void __launch_bounds__(PS * C * M2) k_xi_tr(TcArgs a) {
 
 template <int M1, int M2, int P, int NT>
 __global__ void __launch_bounds__(NT) k_yt(TcArgs a) {
-    constexpr int L = 2 * M1 * M2, T = M2, PITCH = L + 1, NLINES = cmax(P, NT / T);
+    constexpr int L = 2 * M1 * M2, T = M2, PITCH = fused_pitch<L>(), NLINES = cmax(P, NT / T);
+    constexpr int XP = fused_xp<L>();
+    static_assert(PITCH >= M1 * (2 * M2 + XP), "exchange fits the line");
     constexpr int NV = L * P / (4 * NT);
     static_assert(NV * 4 * NT == L * P, "tile must split into float4 per thread");
     __shared__ __align__(16) float lds[NLINES * PITCH];
@@ -711,7 +725,7 @@ __global__ void __launch_bounds__(NT) k_yt(TcArgs a) {
     }
     __syncthreads();
     const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
-    line_xform<M1, M2, 0>(lds + line * PITCH, tt, a.ty.tw);
+    line_xform<M1, M2, 0, XP>(lds + line * PITCH, tt, a.ty.tw);
     const float lcx = a.tx.lam[jx] + a.tc.lam[jc];
     for (int jy = threadIdx.x; jy < L; jy += NT) {
         float u[P];
@@ -734,7 +748,7 @@ __global__ void __launch_bounds__(NT) k_yt(TcArgs a) {
         for (int t = 0; t < P; ++t) lds[t * PITCH + jy] = u[t];
     }
     __syncthreads();
-    line_xform<M1, M2, 1>(lds + line * PITCH, tt, a.ty.tw);
+    line_xform<M1, M2, 1, XP>(lds + line * PITCH, tt, a.ty.tw);
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
         const int e = 4 * ((int)threadIdx.x + NT * j);
