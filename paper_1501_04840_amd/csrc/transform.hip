@@ -571,6 +571,16 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <int L> constexpr int fused_xp() { return L == 256 ? 4 : 0; }
 template <int L> constexpr int fused_pitch() { return L == 256 ? 325 : L + 1; }
 
+// Row block of the x passes for hardware block hw of n: blocks are dispatched
+// round-robin over the 8 XCDs (one L2 each), and XCD j gets the j-th
+// contiguous eighth of the rows, so that the pieces of the transposed scratch
+// one L2 holds (P values per (jc, jx) and row) are contiguous runs in memory
+// rather than 128-byte pieces a kilobyte apart.
+__device__ __forceinline__ int x_row_block(int hw, int n) {
+    const int q = n >> 3, r = n & 7, xcd = hw & 7, slot = hw >> 3;
+    return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
 template <int M1, int M2, int C, int P, int PS>
 __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
     constexpr int L = 2 * M1 * M2, T = M2, NL = PS * C, NT = NL * T, PITCH = fused_pitch<L>();
@@ -587,7 +597,8 @@ __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
         return;
     }
     // block: row index y, time slices t0 .. t0 + PS - 1
-    const int y = blockIdx.x / (P / PS), t0 = (blockIdx.x - y * (P / PS)) * PS;
+    const int lb = x_row_block(blockIdx.x, g.Y * (P / PS));
+    const int y = lb / (P / PS), t0 = (lb - y * (P / PS)) * PS;
     const float* src = a.R + (long long)b * g.nc + (long long)t0 * g.slice + (long long)y * L;
     // single floats, consecutive over the threads (coalesced loads, all in
     // flight; conflict-free LDS writes).  Offsets within a problem fit in 32
@@ -650,7 +661,8 @@ __global__ void __launch_bounds__(PS * C * M2) k_xi_tr(TcArgs a) {
     __shared__ __align__(16) float lds[NL * PITCH];
     const Geom& g = a.g;
     const int b = blockIdx.y;
-    const int y = blockIdx.x / (P / PS), t0 = (blockIdx.x - y * (P / PS)) * PS;
+    const int lb = x_row_block(blockIdx.x, g.Y * (P / PS));
+    const int y = lb / (P / PS), t0 = (lb - y * (P / PS)) * PS;
     // transposed load, the mirror of the forward pass's store: all loads in
     // flight before the first LDS write
     // (32-bit offsets from a uniform base, as in the forward pass)
