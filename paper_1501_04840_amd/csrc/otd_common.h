@@ -161,19 +161,20 @@ bool launch_cols(float* R, long long outer, long long inner, const AxisTab& t,
 // (already reduced to part_slice[q nbx] when `presummed`).
 void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
                const AxisTab& tc, const AxisTab& tt, const double* tc64,
-               const double* tt64, const double* part_slice, int nbx, int presummed,
+               const double* tt64, double* part_slice, int nbx, int presummed,
                const float* frz, hipStream_t st);
 
 // Fused Poisson passes (transform.hip) for Neumann x and y of length 32..256,
 // P in {8, 16, 32}, C in {1, 3}: x (+ colour) pass with a transposed write to
-// Rt ([B][C][X][Y][P]; the forward pass also solves the FP64 DC line into
-// dc [B][C][P]), the y + t pass in place on Rt, and the mirrored inverse.
+// Rt ([B][C][X][Y][P]; the forward pass also reduces the plane sums of r in
+// part_slice in place), the y + t pass in place on Rt, and the mirrored
+// inverse, which also solves the spatial-DC line in FP64 and adds it.
 bool fused_poisson_ok(const Geom& g, const AxisTab& tx, const AxisTab& ty, const AxisTab& tt);
-void launch_fused_x(const Geom& g, float* R, float* Rt, float* dc, const AxisTab& tx,
+void launch_fused_x(const Geom& g, float* R, float* Rt, const AxisTab& tx,
                     const AxisTab& ty, const AxisTab& tc, const AxisTab& tt, const double* tc64,
-                    const double* tt64, const double* part_slice, int nbx, int inverse,
+                    const double* tt64, double* part_slice, int nbx, int inverse,
                     hipStream_t st);
-void launch_fused_yt(const Geom& g, float* Rt, float* dc, const AxisTab& tx, const AxisTab& ty,
+void launch_fused_yt(const Geom& g, float* Rt, const AxisTab& tx, const AxisTab& ty,
                      const AxisTab& tc, const AxisTab& tt, hipStream_t st);
 
 // Whole Poisson solve of problems with one spatial axis (transform.hip):

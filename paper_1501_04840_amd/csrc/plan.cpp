@@ -31,7 +31,6 @@ struct ot_dyn_plan {
     float* R2;
     float* Phi;              // carried potential (OT_REFINE_CARRY), else null
     float* Rt;               // fused Poisson passes: transposed scratch [B][C][X][Y][P]
-    float* dcl;              // fused Poisson passes: FP64-solved DC line [B][C][P]
     bool fused;              // the fused three-pass Poisson solve applies
     bool freezable;          // a batch group's plan: its problems can be frozen
     bool p1d;                // one spatial axis: the one-block Poisson solve applies
@@ -91,7 +90,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t off_b, off_bb, off_A, off_R, off_R2, off_Phi, off_Rt, off_dcl, off_sig, off_f,
+    size_t off_b, off_bb, off_A, off_R, off_R2, off_Phi, off_Rt, off_sig, off_f,
         off_tab[4], off_tw[4], off_tc64, off_tt64;
     size_t off_pslice, off_pred, off_pdiv, off_pmass, off_pbnd, off_red;
     size_t total;
@@ -177,7 +176,6 @@ Layout layout_of(const ot_dyn_desc& d) {
     L.off_Phi = take(d.refine == OT_REFINE_CARRY ? ncT * sizeof(float) : 0);
     L.off_sig = take(3 * (size_t)g.B * sizeof(float));   // sigma, rescale, frozen
     L.off_Rt = take(ncT * sizeof(float));
-    L.off_dcl = take((size_t)g.B * g.C * g.P * sizeof(float));
     L.off_f = take(2 * (size_t)g.B * g.slice * sizeof(float));
     const int ns[4] = {d.X, d.Y, d.C, d.P};
     for (int a = 0; a < 4; ++a) {
@@ -316,12 +314,12 @@ void poisson(ot_dyn_plan* p, float* R) {
     }
     if (p->fused) {     // three passes: x (+ colour), y + t, inverse x (+ colour)
         auto x_pass = [&](int inverse) {
-            launch_fused_x(g, R, p->Rt, p->dcl, p->tab[0], p->tab[1], p->tab[2], p->tab[3],
+            launch_fused_x(g, R, p->Rt, p->tab[0], p->tab[1], p->tab[2], p->tab[3],
                            p->tc64, p->tt64, p->part_slice, p->nbx, inverse, st);
         };
         timed(p, OT_PHASE_XFORM_X, [&] { x_pass(0); });
         timed(p, OT_PHASE_TC, [&] {
-            launch_fused_yt(g, p->Rt, p->dcl, p->tab[0], p->tab[1], p->tab[2], p->tab[3], st);
+            launch_fused_yt(g, p->Rt, p->tab[0], p->tab[1], p->tab[2], p->tab[3], st);
         });
         timed(p, OT_PHASE_XFORM_X, [&] { x_pass(1); });
         return;
@@ -656,7 +654,6 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
     p->Phi = d->refine == OT_REFINE_CARRY ? (float*)(p->ws + L.off_Phi) : nullptr;
     p->sig = (float*)(p->ws + L.off_sig);
     p->Rt = (float*)(p->ws + L.off_Rt);
-    p->dcl = (float*)(p->ws + L.off_dcl);
     p->fused = false;
     p->p1d = false;
     p->xfold = false;

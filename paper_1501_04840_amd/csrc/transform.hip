@@ -184,13 +184,10 @@ struct TcArgs {
     Geom g;
     float* R;
     float* Rt;               // fused path: transposed scratch [B][C][X][Y][P]
-    float* dc;               // fused path: FP64-solved DC line [B][C][P]
     AxisTab tx, ty, tc, tt;
-    const double* tc64;      // C x C forward matrix M[j][k] (FP64)
-    const double* tt64;      // P x P forward matrix M[j][k] (FP64)
-    const double* lamc64;
-    const double* lamt64;
-    const double* part_slice;  // [B][P][C][nbx] FP64 block partials of the plane sums
+    const double* tc64;      // C x C forward matrix M[j][k] (FP64), then the C eigenvalues
+    const double* tt64;      // P x P forward matrix M[j][k] (FP64), then the P eigenvalues
+    double* part_slice;        // [B][P][C][nbx] FP64 block partials of the plane sums
     int nbx;
     int presummed;           // 1: part_slice[q nbx] already holds the sum of plane q
     const float* frz;        // per problem: nonzero = frozen, skipped (or null)
@@ -276,10 +273,20 @@ __global__ void __launch_bounds__(kT) k_tc(TcArgs a) {
 // PT, and each thread issues the P loads of its row or column of the FP64
 // time matrix at once (one round trip to the cache instead of one per eight
 // terms: the time products were the serial part of the one-block solves).
-template <int PT>
-__device__ __forceinline__ void dc_solve_fp64(const TcArgs& a, int b, double* d1, float* ct_out) {
+// With TAB the time and colour matrices, each followed by its eigenvalues,
+// come from tab (copies in LDS: P P + P doubles, then C C + C), else from
+// a.tt64 and a.tc64.  The choice is made at compile time, so that LDS
+// copies are read with LDS instructions (a pointer that may be either is a
+// flat one, and a flat load waits behind every global load issued before it).
+template <int PT, bool TAB = false>
+__device__ __forceinline__ void dc_solve_fp64(const TcArgs& a, int b, double* d1, float* ct_out,
+                                              const double* tab = nullptr) {
     const Geom& g = a.g;
     const int P = PT > 0 ? PT : g.P, C = g.C;
+    const double* Tt = TAB ? tab : a.tt64;
+    const double* Tc = TAB ? tab + P * P + P : a.tc64;
+    const double* lamt = Tt + P * P;
+    const double* lamc = Tc + C * C;
     const int nt = blockDim.x;
     float* base = a.R + (long long)b * g.nc;
     double* d2 = d1 + P * C;
@@ -287,7 +294,7 @@ __device__ __forceinline__ void dc_solve_fp64(const TcArgs& a, int b, double* d1
     for (int e = threadIdx.x; e < m; e += nt) {      // colour forward
         const int k = e / C, jc = e - k * C;
         double acc = 0.0;
-        for (int c = 0; c < C; ++c) acc += a.tc64[jc * C + c] * d1[k * C + c];
+        for (int c = 0; c < C; ++c) acc += Tc[jc * C + c] * d1[k * C + c];
         d2[e] = acc;
     }
     __syncthreads();
@@ -297,14 +304,14 @@ __device__ __forceinline__ void dc_solve_fp64(const TcArgs& a, int b, double* d1
         if constexpr (PT > 0) {
             double w[PT];
 #pragma unroll
-            for (int k = 0; k < PT; ++k) w[k] = a.tt64[jt * PT + k];
+            for (int k = 0; k < PT; ++k) w[k] = Tt[jt * PT + k];
 #pragma unroll
             for (int k = 0; k < PT; ++k) acc += w[k] * d2[k * C + jc];
         } else {
 #pragma unroll 8
-            for (int k = 0; k < P; ++k) acc += a.tt64[jt * P + k] * d2[k * C + jc];
+            for (int k = 0; k < P; ++k) acc += Tt[jt * P + k] * d2[k * C + jc];
         }
-        const double lam = a.lamc64[jc] + a.lamt64[jt];
+        const double lam = lamc[jc] + lamt[jt];
         d1[e] = lam > 0.0 ? acc / lam : 0.0;
     }
     __syncthreads();
@@ -314,12 +321,12 @@ __device__ __forceinline__ void dc_solve_fp64(const TcArgs& a, int b, double* d1
         if constexpr (PT > 0) {
             double w[PT];
 #pragma unroll
-            for (int jt = 0; jt < PT; ++jt) w[jt] = a.tt64[jt * PT + k];
+            for (int jt = 0; jt < PT; ++jt) w[jt] = Tt[jt * PT + k];
 #pragma unroll
             for (int jt = 0; jt < PT; ++jt) acc += w[jt] * d1[jt * C + jc];
         } else {
 #pragma unroll 8
-            for (int jt = 0; jt < P; ++jt) acc += a.tt64[jt * P + k] * d1[jt * C + jc];
+            for (int jt = 0; jt < P; ++jt) acc += Tt[jt * P + k] * d1[jt * C + jc];
         }
         d2[e] = acc;
     }
@@ -335,8 +342,61 @@ __device__ __forceinline__ void dc_solve_fp64(const TcArgs& a, int b, double* d1
     for (int e = threadIdx.x; e < m; e += nt) {      // colour inverse, store
         const int k = e / C, c = e - k * C;
         double acc = 0.0;
-        for (int jc = 0; jc < C; ++jc) acc += a.tc64[jc * C + c] * d2[k * C + jc];
+        for (int jc = 0; jc < C; ++jc) acc += Tc[jc * C + c] * d2[k * C + jc];
         base[(long long)k * g.slice + (long long)c * g.plane] = (float)(acc * scale);
+    }
+}
+
+// dc_solve_fp64 with the tables in LDS (tab as there) for a block of NT >=
+// 8 P C threads: every time product (P terms) is split over 8 consecutive
+// lanes, P / 8 terms each, and summed by shuffles, so that each phase is a
+// few dependent steps instead of P.  Output to ct_out as dc_solve_fp64.
+template <int P, int C, int NT>
+__device__ __forceinline__ void dc_solve_wide(const TcArgs& a, double* d1, float* ct_out,
+                                              const double* tab) {
+    constexpr int m = P * C, KL = P / 8;
+    static_assert(NT >= 8 * m && P % 8 == 0, "eight lanes per output");
+    const double* Tt = tab;
+    const double* lamt = tab + P * P;
+    const double* Tc = tab + P * P + P;
+    const double* lamc = Tc + C * C;
+    double* d2 = d1 + m;
+    const int tid = threadIdx.x, o = tid >> 3, l = tid & 7;
+    if (tid < m) {                                   // colour forward
+        const int k = tid / C, jc = tid - k * C;
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc += Tc[jc * C + c] * d1[k * C + c];
+        d2[tid] = acc;
+    }
+    __syncthreads();
+    if (o < m) {                                     // time forward, divide
+        const int jt = o / C, jc = o - jt * C;
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < KL; ++i) {
+            const int k = l + 8 * i;
+            acc += Tt[jt * P + k] * d2[k * C + jc];
+        }
+        acc += __shfl_xor(acc, 4, 8);
+        acc += __shfl_xor(acc, 2, 8);
+        acc += __shfl_xor(acc, 1, 8);
+        const double lam = lamc[jc] + lamt[jt];
+        if (l == 0) d1[o] = lam > 0.0 ? acc / lam : 0.0;
+    }
+    __syncthreads();
+    if (o < m) {                                     // time inverse
+        const int k = o / C, jc = o - k * C;
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < KL; ++i) {
+            const int jt = l + 8 * i;
+            acc += Tt[jt * P + k] * d1[jt * C + jc];
+        }
+        acc += __shfl_xor(acc, 4, 8);
+        acc += __shfl_xor(acc, 2, 8);
+        acc += __shfl_xor(acc, 1, 8);
+        if (l == 0) ct_out[jc * P + k] = (float)(acc * (1.0 / sqrt((double)a.g.plane)));
     }
 }
 
@@ -558,8 +618,13 @@ static bool tc_reg_dispatch(const TcArgs& a, hipStream_t st) {
 // its Y x P values are contiguous in Rt; it transforms along y, then along t
 // in registers (one thread per y line), divides by the eigenvalues of A A^T,
 // inverts t and y, and writes back in place.  The third pass mirrors the
-// first.  The spatial-DC line is solved in FP64 by an extra block of the
-// first pass and substituted by the second.
+// first.  The spatial-DC line (jx, jy) = (0, 0) is solved in FP64 from the
+// plane sums of r: the first pass reduces the divergence kernel's block
+// partials of each plane in place (spread over its row blocks), the second
+// leaves the line zero, and every block of the third solves it (a few small
+// loads issued before its tile's, so the solve runs while the tile arrives)
+// and adds it to the jx = 0 column, where after the inverse y transform it is
+// the same value at every y.
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
@@ -581,6 +646,37 @@ __device__ __forceinline__ int x_row_block(int hw, int n) {
     return xcd * q + (xcd < r ? xcd : r) + slot;
 }
 
+// Slot j < S of a plane's sum of the nbx block partials pp[]: the partials
+// j + u S of every run of 16 S, summed in order from `first` (the first run,
+// already loaded); as dc_line_fp64 sums them.
+template <int S>
+__device__ __forceinline__ double plane_slot(const double* pp, int nbx, int j,
+                                             const double (&first)[16]) {
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc += first[u];
+    for (int i = j + 16 * S; i < nbx; i += 16 * S) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int ii = i + u * S;
+            v[u] = ii < nbx ? pp[ii] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += v[u];
+    }
+    return acc;
+}
+
+template <int S>
+__device__ __forceinline__ void plane_first(const double* pp, int nbx, int j, double (&v)[16]) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int ii = j + u * S;
+        v[u] = ii < nbx ? pp[ii] : 0.0;
+    }
+}
+
 template <int M1, int M2, int C, int P, int PS>
 __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
     constexpr int L = 2 * M1 * M2, T = M2, NL = PS * C, NT = NL * T, PITCH = fused_pitch<L>();
@@ -588,17 +684,24 @@ __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
     static_assert(PITCH >= M1 * (2 * M2 + XP), "exchange fits the line");
     constexpr int NE = L / T;                      // tile floats per thread
     static_assert(NE * NT == NL * L && NT % PS == 0, "tile split");
-    constexpr int LDSF = cmax(NL * PITCH, 2 * dc_scratch_doubles(P * C));
-    __shared__ __align__(16) float lds[LDSF];
+    constexpr int MP = P * C, S = dc_slots(MP);
+    static_assert(S >= 2 && S <= NT, "plane-sum slots");
+    __shared__ __align__(16) float lds[NL * PITCH];
+    __shared__ double pslot[S];
     const Geom& g = a.g;
     const int b = blockIdx.y;
-    if ((int)blockIdx.x == g.Y * (P / PS)) {
-        dc_line_fp64<P>(a, b, reinterpret_cast<double*>(lds), a.dc + (long long)b * C * P);
-        return;
-    }
     // block: row index y, time slices t0 .. t0 + PS - 1
-    const int lb = x_row_block(blockIdx.x, g.Y * (P / PS));
+    const int nb = g.Y * (P / PS);
+    const int lb = x_row_block(blockIdx.x, nb);
     const int y = lb / (P / PS), t0 = (lb - y * (P / PS)) * PS;
+    // The plane sums of r for the DC line: this block reduces planes lb,
+    // lb + nb, ... < P C in place (the sum replaces the plane's first
+    // partial).  The first plane's partials are loaded before the tile, so
+    // that waiting for them does not wait for the tile.
+    double* const part = a.part_slice + (long long)b * MP * a.nbx;
+    const bool psum = lb < MP && (int)threadIdx.x < S;
+    double pv[16];
+    if (psum) plane_first<S>(part + (long long)lb * a.nbx, a.nbx, threadIdx.x, pv);
     const float* src = a.R + (long long)b * g.nc + (long long)t0 * g.slice + (long long)y * L;
     // single floats, consecutive over the threads (coalesced loads, all in
     // flight; conflict-free LDS writes).  Offsets within a problem fit in 32
@@ -612,12 +715,32 @@ __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
         const unsigned line = e / L, col = e % L, t = line / C, c = line % C;
         buf[j] = src[t * slice + c * plane + col];
     }
+    if (psum) pslot[threadIdx.x] = plane_slot<S>(part + (long long)lb * a.nbx, a.nbx, threadIdx.x, pv);
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
         const int e = (int)threadIdx.x + NT * j;
         lds[(e / L) * PITCH + (e % L)] = buf[j];
     }
     __syncthreads();
+    if (lb < MP && threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int j = 0; j < S; ++j) acc += pslot[j];
+        part[(long long)lb * a.nbx] = acc;
+    }
+    // further planes when the row blocks are fewer than the planes
+    for (int q = lb + nb; q < MP; q += nb) {
+        __syncthreads();                       // pslot is free again
+        if ((int)threadIdx.x < S) {
+            plane_first<S>(part + (long long)q * a.nbx, a.nbx, threadIdx.x, pv);
+            pslot[threadIdx.x] = plane_slot<S>(part + (long long)q * a.nbx, a.nbx, threadIdx.x, pv);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double acc = 0.0;
+            for (int j = 0; j < S; ++j) acc += pslot[j];
+            part[(long long)q * a.nbx] = acc;
+        }
+    }
     const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
     line_xform<M1, M2, 0, XP>(lds + line * PITCH, tt, a.tx.tw);
     if constexpr (C > 1) {
@@ -660,9 +783,24 @@ __global__ void __launch_bounds__(PS * C * M2) k_xi_tr(TcArgs a) {
     static_assert(NE * NT == NL * L && NT % PS == 0, "tile split");
     __shared__ __align__(16) float lds[NL * PITCH];
     const Geom& g = a.g;
+    // the DC line: plane sums (reduced in place by the forward pass) and the
+    // FP64 time and colour tables, staged in LDS
+    constexpr int MP = P * C, NTT = P * P + P, NTAB = NTT + C * C + C;
+    constexpr int NDC = (MP + NTAB + NT - 1) / NT;     // DC inputs per thread
+    __shared__ double dsh[2 * MP + NTAB];
+    __shared__ float dcl[MP];                          // the line, [jc][t], scaled
     const int b = blockIdx.y;
     const int lb = x_row_block(blockIdx.x, g.Y * (P / PS));
     const int y = lb / (P / PS), t0 = (lb - y * (P / PS)) * PS;
+    // its loads first: waiting for them then does not wait for the tile's
+    const double* part = a.part_slice + (long long)b * MP * a.nbx;
+    double dv[NDC];
+#pragma unroll
+    for (int r = 0; r < NDC; ++r) {
+        const int i = threadIdx.x + NT * r;
+        dv[r] = i < MP ? part[(long long)i * a.nbx]
+                       : i < MP + NTT ? a.tt64[i - MP] : i < MP + NTAB ? a.tc64[i - MP - NTT] : 0.0;
+    }
     // transposed load, the mirror of the forward pass's store: all loads in
     // flight before the first LDS write
     // (32-bit offsets from a uniform base, as in the forward pass)
@@ -672,10 +810,28 @@ __global__ void __launch_bounds__(PS * C * M2) k_xi_tr(TcArgs a) {
     float buf[NE];
 #pragma unroll
     for (int j = 0; j < NE; ++j) buf[j] = src[o0 + j * step];
+    // the DC line while the tile arrives; the plane sums go to dsh[0, MP),
+    // the tables behind the solve's scratch
+#pragma unroll
+    for (int r = 0; r < NDC; ++r) {
+        const int i = threadIdx.x + NT * r;
+        if (i < MP) dsh[i] = dv[r];
+        else if (i < MP + NTAB) dsh[MP + i] = dv[r];
+    }
+    __syncthreads();
+    if constexpr (NT >= 8 * MP) dc_solve_wide<P, C, NT>(a, dsh, dcl, dsh + 2 * MP);
+    else dc_solve_fp64<0, true>(a, b, dsh, dcl, dsh + 2 * MP);
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
         const unsigned r = r0 + (NT / PS) * j, jx = r % L, jc = r / L;
         lds[(tq * C + jc) * PITCH + jx] = buf[j];
+    }
+    __syncthreads();
+    // after the inverse y transform the line's coefficient c is c / sqrt(Y)
+    // at every y (jx = 0 column, colour mode jc)
+    if ((int)threadIdx.x < NL) {
+        const int t = threadIdx.x / C, jc = threadIdx.x - t * C;
+        lds[(t * C + jc) * PITCH] += dcl[jc * P + t0 + t] * (float)(1.0 / sqrt((double)g.Y));
     }
     __syncthreads();
     if constexpr (C > 1) {
@@ -741,9 +897,9 @@ __global__ void __launch_bounds__(NT) k_yt(TcArgs a) {
     const float lcx = a.tx.lam[jx] + a.tc.lam[jc];
     for (int jy = threadIdx.x; jy < L; jy += NT) {
         float u[P];
-        if (jx == 0 && jy == 0) {
+        if (jx == 0 && jy == 0) {      // the DC line: added by the inverse x pass
 #pragma unroll
-            for (int t = 0; t < P; ++t) u[t] = a.dc[((long long)b * g.C + jc) * P + t];
+            for (int t = 0; t < P; ++t) u[t] = 0.f;
         } else {
 #pragma unroll
             for (int t = 0; t < P; ++t) u[t] = lds[t * PITCH + jy];
@@ -1099,8 +1255,6 @@ void launch_poisson_1d(const Geom& g, float* R, const AxisTab& tx, const AxisTab
     a.g = g; a.R = R; a.tx = tx; a.ty = ty; a.tc = tc; a.tt = tt;
     a.tc64 = tc64;
     a.tt64 = tt64;
-    a.lamc64 = tc64 + (long long)g.C * g.C;
-    a.lamt64 = tt64 + (long long)g.P * g.P;
     a.frz = frz;
     a.twt = tt.tw;
     if (!tx.tw && tx.twm) {
@@ -1127,8 +1281,8 @@ static void xpair_launch(const TcArgs& a, int inverse, hipStream_t st) {
     constexpr int PS = P, NT = PS * C * M2;
     const unsigned nb = (unsigned)a.g.Y * (P / PS);
     if (!inverse)
-        hipLaunchKernelGGL((k_xf_tr<M1, M2, C, P, PS>), dim3(nb + 1, (unsigned)a.g.B), dim3(NT), 0,
-                           st, a);
+        hipLaunchKernelGGL((k_xf_tr<M1, M2, C, P, PS>), dim3(nb, (unsigned)a.g.B), dim3(NT), 0, st,
+                           a);
     else
         hipLaunchKernelGGL((k_xi_tr<M1, M2, C, P, PS>), dim3(nb, (unsigned)a.g.B), dim3(NT), 0, st,
                            a);
@@ -1163,35 +1317,33 @@ bool fused_poisson_ok(const Geom& g, const AxisTab& tx, const AxisTab& ty, const
            (g.P == 8 || g.P == 16 || g.P == 32) && (g.C == 1 || g.C == 3);
 }
 
-static TcArgs fused_args(const Geom& g, float* R, float* Rt, float* dc, const AxisTab& tx,
+static TcArgs fused_args(const Geom& g, float* R, float* Rt, const AxisTab& tx,
                          const AxisTab& ty, const AxisTab& tc, const AxisTab& tt,
-                         const double* tc64, const double* tt64, const double* part_slice,
+                         const double* tc64, const double* tt64, double* part_slice,
                          int nbx) {
     TcArgs a{};
-    a.g = g; a.R = R; a.Rt = Rt; a.dc = dc; a.tx = tx; a.ty = ty; a.tc = tc; a.tt = tt;
+    a.g = g; a.R = R; a.Rt = Rt; a.tx = tx; a.ty = ty; a.tc = tc; a.tt = tt;
     a.tc64 = tc64;
     a.tt64 = tt64;
-    a.lamc64 = tc64 + (long long)g.C * g.C;
-    a.lamt64 = tt64 + (long long)g.P * g.P;
     a.part_slice = part_slice;
     a.nbx = nbx;
     a.twt = tt.tw;
     return a;
 }
 
-void launch_fused_x(const Geom& g, float* R, float* Rt, float* dc, const AxisTab& tx,
+void launch_fused_x(const Geom& g, float* R, float* Rt, const AxisTab& tx,
                     const AxisTab& ty, const AxisTab& tc, const AxisTab& tt, const double* tc64,
-                    const double* tt64, const double* part_slice, int nbx, int inverse,
+                    const double* tt64, double* part_slice, int nbx, int inverse,
                     hipStream_t st) {
-    const TcArgs a = fused_args(g, R, Rt, dc, tx, ty, tc, tt, tc64, tt64, part_slice, nbx);
+    const TcArgs a = fused_args(g, R, Rt, tx, ty, tc, tt, tc64, tt64, part_slice, nbx);
 #define OTD_FX(CC, PP) if (g.C == CC && g.P == PP) { x_dispatch<CC, PP>(a, inverse, st); return; }
     OTD_FX(1, 8) OTD_FX(1, 16) OTD_FX(1, 32) OTD_FX(3, 8) OTD_FX(3, 16) OTD_FX(3, 32)
 #undef OTD_FX
 }
 
-void launch_fused_yt(const Geom& g, float* Rt, float* dc, const AxisTab& tx, const AxisTab& ty,
+void launch_fused_yt(const Geom& g, float* Rt, const AxisTab& tx, const AxisTab& ty,
                      const AxisTab& tc, const AxisTab& tt, hipStream_t st) {
-    const TcArgs a = fused_args(g, nullptr, Rt, dc, tx, ty, tc, tt, nullptr, nullptr, nullptr, 0);
+    const TcArgs a = fused_args(g, nullptr, Rt, tx, ty, tc, tt, nullptr, nullptr, nullptr, 0);
     if (g.P == 8) y_dispatch<8>(a, st);
     else if (g.P == 16) y_dispatch<16>(a, st);
     else y_dispatch<32>(a, st);
@@ -1252,14 +1404,12 @@ bool launch_cols(float* R, long long outer, long long inner, const AxisTab& t, i
 
 void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty, const AxisTab& tc,
                const AxisTab& tt, const double* tc64, const double* tt64,
-               const double* part_slice, int nbx, int presummed, const float* frz,
+               double* part_slice, int nbx, int presummed, const float* frz,
                hipStream_t st) {
     TcArgs a{};
     a.g = g; a.R = R; a.tx = tx; a.ty = ty; a.tc = tc; a.tt = tt;
     a.tc64 = tc64;
     a.tt64 = tt64;
-    a.lamc64 = tc64 + (long long)g.C * g.C;
-    a.lamt64 = tt64 + (long long)g.P * g.P;
     a.part_slice = part_slice;
     a.nbx = nbx;
     a.presummed = presummed;
