@@ -38,13 +38,22 @@ __device__ __forceinline__ void fft_core(float* s, int t, const float2* tw4, Loa
                                          float2 (&out)[M1 / M2][M2], bool act = true) {
     constexpr int M = M1 * M2, L = 2 * M, RW = M2 + XP / 2;   // exchange row, complex units
     static_assert(XP % 2 == 0, "exchange padding in whole complex values");
+    static_assert(M1 == fft_m1(L) && M1 % 2 == 0, "the split the host's twiddle table is laid out for");
     float2 a[M1];
     if (act) {
+        // this thread's first-stage twiddles, contiguous (16-byte aligned:
+        // the table is, and 4 L and t M1 are even), two to a load
+        const float4* const tw1 = reinterpret_cast<const float4*>(tw4 + 4 * L + t * M1);
+        float4 w[M1 / 2];
+#pragma unroll
+        for (int i = 0; i < M1 / 2; ++i) w[i] = tw1[i];
 #pragma unroll
         for (int n1 = 0; n1 < M1; ++n1) a[n1] = load(n1);
         dft<M1>(a);
 #pragma unroll
-        for (int k1 = 1; k1 < M1; ++k1) a[k1] = cmul(a[k1], tw4[(8 * t * k1) & (4 * L - 1)]);
+        for (int k1 = 1; k1 < M1; ++k1)
+            a[k1] = cmul(a[k1], k1 & 1 ? make_float2(w[k1 / 2].z, w[k1 / 2].w)
+                                       : make_float2(w[k1 / 2].x, w[k1 / 2].y));
     }
     __syncthreads();
     if (act) {

@@ -196,6 +196,11 @@ void launch_poisson_1d(const Geom& g, float* R, const AxisTab& tx, const AxisTab
 
 // Fast power-of-two passes (fastdct.hip); kind 0 DCT-II, 1 DCT-III, 2 Hartley.
 bool fast_len(int L);
+// The four-step split M1 x M2 (M1 M2 = L / 2) of the power-of-two line
+// transforms of length L (32..512), shared by the kernels and the host: the
+// fast twiddle table of an axis has, after its 4 L entries, the first-stage
+// twiddles e^{-2 pi i t k1 / (L / 2)} at [4 L + t M1 + k1], t < M2, k1 < M1.
+__host__ __device__ constexpr int fft_m1(int L) { return L == 32 ? 4 : L <= 128 ? 8 : 16; }
 void launch_rows_fast(float* R, long long rows, int L, const float2* tw, int kind, hipStream_t st,
                       const PlaneSums* sums = nullptr, RowSkip skip = RowSkip{nullptr, 1});
 void launch_cols_fast(float* R, long long outer, long long inner, int L, const float2* tw, int kind,

@@ -180,7 +180,7 @@ Layout layout_of(const ot_dyn_desc& d) {
     const int ns[4] = {d.X, d.Y, d.C, d.P};
     for (int a = 0; a < 4; ++a) {
         L.off_tab[a] = take((2 * (size_t)ns[a] * ns[a] + ns[a]) * sizeof(float));
-        L.off_tw[a] = take(4 * (size_t)ns[a] * 2 * sizeof(float));
+        L.off_tw[a] = take((4 * (size_t)ns[a] + ns[a] / 2) * 2 * sizeof(float));
     }
     L.off_tc64 = take(((size_t)d.C * d.C + d.C) * sizeof(double));
     L.off_tt64 = take(((size_t)d.P * d.P + d.P) * sizeof(double));
@@ -726,11 +726,20 @@ int ot_dyn_create(const ot_dyn_desc* d, void* stream, void* workspace, size_t ws
         p->tab[a].tw = nullptr;
         p->tab[a].twm = nullptr;
         if (fast || mixed) {
-            std::vector<float> tw(8 * (size_t)n);
+            std::vector<float> tw(2 * (4 * (size_t)n + n / 2));
             const double pi = 3.14159265358979323846;
             for (int j = 0; j < 4 * n; ++j) {
                 tw[2 * j] = (float)std::cos(pi * j / (2.0 * n));
                 tw[2 * j + 1] = (float)-std::sin(pi * j / (2.0 * n));
+            }
+            if (fast && a < 2) {   // the first-stage twiddles of the line transforms
+                const int M1 = fft_m1(n), M2 = n / (2 * M1);
+                for (int t = 0; t < M2; ++t)
+                    for (int k1 = 0; k1 < M1; ++k1) {
+                        const int j = (8 * t * k1) % (4 * n), q = 4 * n + t * M1 + k1;
+                        tw[2 * q] = tw[2 * j];
+                        tw[2 * q + 1] = tw[2 * j + 1];
+                    }
             }
             float* tdst = (float*)(p->ws + L.off_tw[a]);
             e = hipMemcpyAsync(tdst, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice,

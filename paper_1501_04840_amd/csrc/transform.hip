@@ -459,12 +459,23 @@ __device__ void dc_line_fp64(const TcArgs& a, int b, double* d1, float* ct_out) 
     dc_solve_fp64<PT>(a, b, d1, ct_out);
 }
 
+// dct3_reg<P>(diag(d) dct2_reg<P>(x)) = dct3_reg<P, true>(diag(d s) dct2_reg<P, true>(x))
+// with s = dct2_scale<P>(j): the output scales of both and the factor sqrt 2
+// the inverse applies to X[0], for a caller that scales every frequency anyway.
+template <int P>
+__device__ __forceinline__ constexpr float dct2_scale(int j) {
+    constexpr float M = P / 2;
+    const float sc = 0.5f * __builtin_sqrtf(0.5f * P) / M;
+    return j == 0 ? sc * 1.41421356237309515f * 0.5f * __builtin_sqrtf(1.f / P)
+                  : sc * 0.5f * __builtin_sqrtf(2.f / P);
+}
+
 // Orthonormal DCT-II of a register line of length P (Makhoul's reordering
 // and a P/2-point packed DFT; every index is a compile-time constant).  The
 // frequencies k and M - k are unpacked together: with 2 ve = Z[k] +
 // conj Z[M-k] and 2 vo = -i (Z[k] - conj Z[M-k]), V[k] = ve + w vo and
 // V[M-k] = conj(ve - w vo) for w = e^{-2 pi i k / P}.
-template <int P>
+template <int P, bool RAW = false>
 __device__ __forceinline__ void dct2_reg(float (&x)[P], const float2* tw4) {
     constexpr int M = P / 2;
     float2 z[M];
@@ -476,7 +487,8 @@ __device__ __forceinline__ void dct2_reg(float (&x)[P], const float2* tw4) {
     }
     dft<M>(z);
     // a = 2 V[k], b = 2 V[M-k]: the factor 1/2 is folded into the scales
-    const float h = 0.5f * sqrtf(2.f / P), h0 = 0.5f * sqrtf(1.f / P);
+    // (RAW: no scales, the caller applies dct2_scale)
+    const float h = RAW ? 1.f : 0.5f * sqrtf(2.f / P), h0 = RAW ? 1.f : 0.5f * sqrtf(1.f / P);
 #pragma unroll
     for (int k = 0; k <= M / 2; ++k) {
         const float2 zk = z[k], zm = z[(M - k) % M];
@@ -499,13 +511,13 @@ __device__ __forceinline__ void dct2_reg(float (&x)[P], const float2* tw4) {
 // (sqrt(P) for X[0]): conj Z[k] = conj(ve + i vo) and conj Z[M-k] =
 // ve - i vo, 2 ve = V(k) + conj V(M-k), 2 vo = (V(k) - conj V(M-k)) conj(w_k);
 // the factor sqrt(P / 2) / 2 is applied to the outputs.
-template <int P>
+template <int P, bool RAW = false>
 __device__ __forceinline__ void dct3_reg(float (&x)[P], const float2* tw4) {
     constexpr int M = P / 2;
     float2 zc[M];
 #pragma unroll
     for (int k = 0; k <= M / 2; ++k) {
-        const float xk = k == 0 ? 1.41421356237309515f * x[0] : x[k];
+        const float xk = k == 0 && !RAW ? 1.41421356237309515f * x[0] : x[k];
         const float xl = k == 0 ? 0.f : x[P - k];                 // X[P-k]
         const float2 v = cmul(cconj(tw4[k]), make_float2(xk, -xl));
         const float2 w = cmul(cconj(tw4[M - k]), make_float2(x[M - k], -x[M + k]));   // V(M-k)
@@ -515,7 +527,7 @@ __device__ __forceinline__ void dct3_reg(float (&x)[P], const float2* tw4) {
         if (k > 0 && k < M / 2) zc[M - k] = make_float2(ve.x + vo.y, ve.y - vo.x);
     }
     dft<M>(zc);
-    const float sc = 0.5f * sqrtf(0.5f * P) / M;
+    const float sc = RAW ? 1.f : 0.5f * sqrtf(0.5f * P) / M;
 #pragma unroll
     for (int n = 0; n < M; ++n) {
         const int m0 = 2 * n, m1 = 2 * n + 1;
@@ -903,14 +915,14 @@ __global__ void __launch_bounds__(NT) k_yt(TcArgs a) {
         } else {
 #pragma unroll
             for (int t = 0; t < P; ++t) u[t] = lds[t * PITCH + jy];
-            dct2_reg<P>(u, a.twt);
+            dct2_reg<P, true>(u, a.twt);
             const float lc = lcx + a.ty.lam[jy];
+            // the eigenvalue sum is > 0 off the DC line (every lambda >= 0,
+            // and jx or jy is not 0); the transforms' scales ride along
 #pragma unroll
-            for (int jt = 0; jt < P; ++jt) {
-                const float lam = lc + a.tt.lam[jt];   // > 0 off the DC line
-                u[jt] = lam > 0.f ? u[jt] * __builtin_amdgcn_rcpf(lam) : 0.f;
-            }
-            dct3_reg<P>(u, a.twt);
+            for (int jt = 0; jt < P; ++jt)
+                u[jt] = u[jt] * (dct2_scale<P>(jt) * __builtin_amdgcn_rcpf(lc + a.tt.lam[jt]));
+            dct3_reg<P, true>(u, a.twt);
         }
 #pragma unroll
         for (int t = 0; t < P; ++t) lds[t * PITCH + jy] = u[t];
