@@ -26,6 +26,19 @@
 
 namespace otd {
 
+// Orders the LDS accesses of the threads of one line.  Every access of a
+// power-of-two line transform stays in its line's region, and a line's M2
+// threads are consecutive lanes of one wave (M2 divides 64), whose LDS
+// instructions the hardware executes in order: a compiler barrier with
+// wavefront-scope fences is enough, so the waves of a block do not wait for
+// each other inside a transform (each transform still ends with a block
+// barrier, after which other lines' data may be read).
+__device__ __forceinline__ void line_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Four-step DFT of length M = M1 M2 on one line.  Stage-1 input n = M2 n1 + t
 // comes from load(n1) (the caller knows t); on return out[q][k2] =
 // Z[k1 + M1 k2] with k1 = t + M2 q.  The line's LDS region s is used for the
@@ -39,6 +52,7 @@ __device__ __forceinline__ void fft_core(float* s, int t, const float2* tw4, Loa
     constexpr int M = M1 * M2, L = 2 * M, RW = M2 + XP / 2;   // exchange row, complex units
     static_assert(XP % 2 == 0, "exchange padding in whole complex values");
     static_assert(M1 == fft_m1(L) && M1 % 2 == 0, "the split the host's twiddle table is laid out for");
+    static_assert(64 % M2 == 0, "a line's threads within one wave (line_sync)");
     float2 a[M1];
     if (act) {
         // this thread's first-stage twiddles, contiguous (16-byte aligned:
@@ -55,13 +69,13 @@ __device__ __forceinline__ void fft_core(float* s, int t, const float2* tw4, Loa
             a[k1] = cmul(a[k1], k1 & 1 ? make_float2(w[k1 / 2].z, w[k1 / 2].w)
                                        : make_float2(w[k1 / 2].x, w[k1 / 2].y));
     }
-    __syncthreads();
+    line_sync();
     if (act) {
         float* const sw = s + 2 * t;                  // Z1[k1][t]
 #pragma unroll
         for (int k1 = 0; k1 < M1; ++k1) st2(sw, k1 * RW, a[k1]);
     }
-    __syncthreads();
+    line_sync();
     if (act) {
         const float* const sr = s + 2 * RW * t;       // Z1[t + M2 q][n2]
 #pragma unroll
@@ -111,9 +125,9 @@ __device__ __forceinline__ void line_dct2(float* s, int t, const float2* tw4, bo
         return n1 < M1 / 2 ? make_float2(sp[4 * M2 * n1], sp[4 * M2 * n1 + 2])
                            : make_float2(sm[2 * L - 1 - 4 * M2 * n1], sm[2 * L - 3 - 4 * M2 * n1]);
     }, z, act);
-    __syncthreads();
+    line_sync();
     if (act) store_z<M1, M2>(s, t, z);
-    __syncthreads();
+    line_sync();
     // 2 V[k] = a and 2 V[M-k] = b; the factor 1/2 is folded into the scales
     const float h = 0.5f * sqrtf(2.f / L), h0 = 0.5f * sqrtf(1.f / L);
     float o[NP][4];
@@ -134,7 +148,7 @@ __device__ __forceinline__ void line_dct2(float* s, int t, const float2* tw4, bo
             o[j][3] = -h * xb.y;                    // X[M+k]
         }
     }
-    __syncthreads();
+    line_sync();
     float* const op = s + t;
     float* const om = s - t;
 #pragma unroll
@@ -180,7 +194,7 @@ __device__ __forceinline__ void line_dct3(float* s, int t, const float2* tw4) {
             zc[j][1] = make_float2(ve.x + vo.y, ve.y - vo.x);
         }
     }
-    __syncthreads();
+    line_sync();
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const int k = t + T * j;
@@ -189,11 +203,11 @@ __device__ __forceinline__ void line_dct3(float* s, int t, const float2* tw4) {
             if (k > 0 && k < M / 2) st2(s - 2 * t, M - T * j, zc[j][1]);
         }
     }
-    __syncthreads();
+    line_sync();
     float2 r[M1 / M2][M2];
     const float* const sl = s + 2 * t;
     fft_core<M1, M2, XP>(s, t, tw4, [&](int n1) { return ld2(sl, M2 * n1); }, r);
-    __syncthreads();
+    line_sync();
     // output n = t + M2 q + M1 k2: x[pos(2n)] = Re r / M, x[pos(2n+1)] = -Im r / M
     // with pos(m) = 2m (m < M), 2(L-1-m)+1 (m >= M); m < M iff the
     // compile-time part B = 2 (M2 q + M1 k2) is below M
@@ -224,9 +238,9 @@ __device__ __forceinline__ void line_dht(float* s, int t, const float2* tw4, boo
     float2 z[M1 / M2][M2];
     const float* const sl = s + 2 * t;
     fft_core<M1, M2>(s, t, tw4, [&](int n1) { return ld2(sl, M2 * n1); }, z, act);
-    __syncthreads();
+    line_sync();
     if (act) store_z<M1, M2>(s, t, z);
-    __syncthreads();
+    line_sync();
     // 2 F[k] = a and 2 F[M-k] = b; H[k] = (Re F - Im F) / sqrt(L) and
     // H[L-k] = (Re F + Im F) / sqrt(L)
     const float h = 0.5f * sqrtf(1.f / L);
@@ -248,7 +262,7 @@ __device__ __forceinline__ void line_dht(float* s, int t, const float2* tw4, boo
             o[j][3] = h * (b.x + b.y);              // H[M+k]
         }
     }
-    __syncthreads();
+    line_sync();
     float* const op = s + t;
     float* const om = s - t;
 #pragma unroll
