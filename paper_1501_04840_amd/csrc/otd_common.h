@@ -75,6 +75,9 @@ struct StepArgs {
     // or null when the x pass runs on its own; kind 0 DCT-II, 2 Hartley
     const float2* twx;
     int xkind;
+    // the fused Poisson solve: the divergence kernels write r already
+    // transformed across colours, cmix[c C + jc] = M_c[jc][c] (else null)
+    const float* cmix;
 };
 
 // ---- stencil kernels (stencil.hip) -------------------------------------
@@ -167,13 +170,14 @@ void launch_tc(const Geom& g, float* R, const AxisTab& tx, const AxisTab& ty,
 // Fused Poisson passes (transform.hip) for Neumann x and y of length 32..256,
 // P in {8, 16, 32}, C in {1, 3}: x (+ colour) pass with a transposed write to
 // Rt ([B][C][X][Y][P]; the forward pass also reduces the plane sums of r in
-// part_slice in place), the y + t pass in place on Rt, and the mirrored
-// inverse, which also solves the spatial-DC line in FP64 and adds it.
+// part_slice in place; with premixed r is already in colour modes, see
+// StepArgs::cmix), the y + t pass in place on Rt, and the mirrored inverse,
+// which also solves the spatial-DC line in FP64 and adds it.
 bool fused_poisson_ok(const Geom& g, const AxisTab& tx, const AxisTab& ty, const AxisTab& tt);
 void launch_fused_x(const Geom& g, float* R, float* Rt, const AxisTab& tx,
                     const AxisTab& ty, const AxisTab& tc, const AxisTab& tt, const double* tc64,
                     const double* tt64, double* part_slice, int nbx, int inverse,
-                    hipStream_t st);
+                    bool premixed, hipStream_t st);
 void launch_fused_yt(const Geom& g, float* Rt, const AxisTab& tx, const AxisTab& ty,
                      const AxisTab& tc, const AxisTab& tt, hipStream_t st);
 

@@ -276,6 +276,7 @@ StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     s.row_bx = p->row_bx;
     s.twx = p->xfold ? p->tab[0].tw : nullptr;
     s.xkind = p->tab[0].periodic ? 2 : 0;
+    s.cmix = p->fused && p->g.C > 1 ? p->tab[2].mat : nullptr;
     return s;
 }
 
@@ -314,8 +315,9 @@ void poisson(ot_dyn_plan* p, float* R) {
     }
     if (p->fused) {     // three passes: x (+ colour), y + t, inverse x (+ colour)
         auto x_pass = [&](int inverse) {
+            // the divergence kernels wrote r in colour modes (StepArgs::cmix)
             launch_fused_x(g, R, p->Rt, p->tab[0], p->tab[1], p->tab[2], p->tab[3],
-                           p->tc64, p->tt64, p->part_slice, p->nbx, inverse, st);
+                           p->tc64, p->tt64, p->part_slice, p->nbx, inverse, g.C > 1, st);
         };
         timed(p, OT_PHASE_XFORM_X, [&] { x_pass(0); });
         timed(p, OT_PHASE_TC, [&] {

@@ -66,6 +66,22 @@ __device__ inline Nbr neighbours(const Geom& g, int x, int y) {
     return n;
 }
 
+// The residual of a node in colour modes for the fused Poisson solve: out
+// at colour stride plane gets sum_c M_c[jc][c] r[c] (cm[c C + jc] =
+// M_c[jc][c]), the colour transform the solve's first pass would apply (the
+// same products in the same order).
+template <int C>
+__device__ __forceinline__ void colour_modes(const float (&cm)[C * C], const float (&r)[C],
+                                             float* out, long long plane) {
+#pragma unroll
+    for (int jc = 0; jc < C; ++jc) {
+        float acc = 0.f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc = fmaf(cm[c * C + jc], r[c], acc);
+        out[(long long)jc * plane] = acc;
+    }
+}
+
 // r = A a - f_b^- with a = x - tau sigma K^T b_bar (MODE 0: also writes a to A
 // and r to R), a = A + grad phi_1 (MODE 1, refinement: writes r to R2) or
 // a = x - tau sigma K^T b_bar + grad Phi with the carried potential Phi
@@ -82,6 +98,12 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
     __shared__ float xl[XL > 0 ? C * XP : 1];
     if (s.frz_run && s.frz_run[r.b] != 0.f) return;   // frozen problem (block-uniform)
     const float ts = 0.5f * s.tau_sigma;
+    // the colour transform of r (fused Poisson solve), read before the first
+    // store: the compiler cannot tell the stores from these loads
+    float cm[C * C];
+    const bool mix = XL == 0 && C > 1 && s.cmix != nullptr;
+#pragma unroll
+    for (int q = 0; q < C * C; ++q) cm[q] = mix ? s.cmix[q] : 0.f;
     float rv[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) rv[c] = 0.f;
@@ -158,9 +180,10 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
                 s.A[2][i] = acv[c];
                 s.A[3][i] = k0 ? 0.f : af0;
                 if constexpr (XL > 0) xl[c * XP + r.x] = rr;
-                else s.R[i] = rr;
+                else if (!mix) s.R[i] = rr;
                 rv[c] = rr;
             }
+            if (mix) colour_modes<C>(cm, rv, s.R + r.i0, g.plane);
         } else {
             // colour faces first: own face c of every colour, into registers
             float acv[C];
@@ -193,9 +216,10 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
                 const float rr = g.sx * (ax1 - ax0) + g.sy * (ay1 - ay0) + g.sc * (ac1 - acv[c]) +
                                  g.st * (af1 - af0);
                 if constexpr (XL > 0) xl[c * XP + r.x] = rr;
-                else s.R2[i] = rr;
+                else if (!mix) s.R2[i] = rr;
                 rv[c] = rr;
             }
+            if (mix) colour_modes<C>(cm, rv, s.R2 + r.i0, g.plane);
         }
     }
     const long long col = (long long)r.y * nxb + r.xb;

@@ -192,6 +192,7 @@ struct TcArgs {
     int presummed;           // 1: part_slice[q nbx] already holds the sum of plane q
     const float* frz;        // per problem: nonzero = frozen, skipped (or null)
     int W;
+    int premixed;            // fused x pass: r is already in colour modes
     const float2* twt;       // time-axis twiddles e^{-i pi j / (2P)}, j < 4P
 };
 
@@ -755,7 +756,7 @@ __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
     }
     const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
     line_xform<M1, M2, 0, XP>(lds + line * PITCH, tt, a.tx.tw);
-    if constexpr (C > 1) {
+    if (C > 1 && !a.premixed) {
         const float* Tc = a.tc.mat;                    // Tc[c * C + jc] = M_c[jc][c]
         for (int q = threadIdx.x; q < PS * L; q += NT) {
             const int t = q / L, jx = q - t * L;
@@ -1346,8 +1347,9 @@ static TcArgs fused_args(const Geom& g, float* R, float* Rt, const AxisTab& tx,
 void launch_fused_x(const Geom& g, float* R, float* Rt, const AxisTab& tx,
                     const AxisTab& ty, const AxisTab& tc, const AxisTab& tt, const double* tc64,
                     const double* tt64, double* part_slice, int nbx, int inverse,
-                    hipStream_t st) {
-    const TcArgs a = fused_args(g, R, Rt, tx, ty, tc, tt, tc64, tt64, part_slice, nbx);
+                    bool premixed, hipStream_t st) {
+    TcArgs a = fused_args(g, R, Rt, tx, ty, tc, tt, tc64, tt64, part_slice, nbx);
+    a.premixed = !inverse && premixed;
 #define OTD_FX(CC, PP) if (g.C == CC && g.P == PP) { x_dispatch<CC, PP>(a, inverse, st); return; }
     OTD_FX(1, 8) OTD_FX(1, 16) OTD_FX(1, 32) OTD_FX(3, 8) OTD_FX(3, 16) OTD_FX(3, 32)
 #undef OTD_FX
