@@ -516,7 +516,7 @@ def main():
     iter_bytes = iter_words * 4.0 * N
     method_iter_bytes = METHOD_ITERATION_WORDS * 4.0 * N
     out = {
-        "metric": "cell-iters/s at 256x256x3x32",
+        "metric": f"cell-iters/s at {X}x{Y}x{C}x{P}",
         "value": N * K / dt,
         "unit": "cell-iters/s",
         "n_gpus": 1, "steps": K, "warmup": warmup,

@@ -86,6 +86,10 @@ SHAPES = [
     (256, 8, 2, 16, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),  # rows 256, C = 2
     (40, 128, 3, 32, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12), # cols 128, Neumann colour
     (128, 128, 1, 8, (G.PERIODIC, G.PERIODIC, G.NEUMANN), 12),  # Hartley rows and cols
+    # fused three-pass solve with fewer row blocks than planes (Y < P C): the
+    # forward x pass reduces several planes' sums per block
+    (32, 32, 3, 16, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),
+    (64, 32, 3, 32, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),
     # one spatial axis of fast length: the one-block Poisson solve
     (128, 1, 1, 16, (G.NEUMANN, G.NEUMANN, G.NEUMANN), 12),   # DCT along x
     (256, 1, 1, 8, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),   # Hartley along x
