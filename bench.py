@@ -53,18 +53,26 @@ KERNEL_WORDS = {
 }
 
 
-def kernel_name(phase, mode, C, X=0, xfold=False, xkind=0, fused=False):
+def nt_store(N):
+    """Whether the stencil kernels store the iteration's fields non-temporally:
+    one problem's field of N values is 16 MB or more (the library's rule)."""
+    return 4 * N >= 16 << 20
+
+
+def kernel_name(phase, mode, C, X=0, xfold=False, xkind=0, fused=False, nt=False):
     """Full name of the kernel a steady-state iteration launches for `phase`
     (row stencils and power-of-two transforms).  With xfold the divergence
     kernel also does the forward x transform (DCT-II, xkind 0, or Hartley, 2)
     of its rows of length X; with fused the Poisson solve is the three-pass
-    one (x pass with the colour transform into a transposed scratch, the y
-    and time pass, the inverse x pass)."""
+    one (x pass into a transposed scratch, the y and time pass, the inverse x
+    pass with the colour transform); nt: the stencil kernels' non-temporal
+    variant (nt_store)."""
+    f = "true" if nt else "false"
     if phase == "div":
         return f"k_div_rows<{ {0: 0, 1: 0, 3: 2}[mode] }, {C}, {X if xfold else 0}, " \
-               f"{xkind if xfold else 0}>"
+               f"{xkind if xfold else 0}, {f}>"
     if phase == "update":
-        return f"k_update_rows<0, { {0: 1, 1: 2, 3: 3}[mode] }, {C}>"
+        return f"k_update_rows<0, { {0: 1, 1: 2, 3: 3}[mode] }, {C}, {f}>"
     if phase == "refine":
         return f"k_div_rows<1, {C}>"
     if fused:
@@ -479,7 +487,7 @@ def main():
         mw = METHOD_WORDS[name]
         iter_words += kw * n / n_split
         split[name] = {"ms_per_iter": ms / n_split, "launches": n, "avg_launch_us": 1e3 * ms / n,
-                       "kernel": kernel_name(name, mode, C, X, xfold, fused=fused),
+                       "kernel": kernel_name(name, mode, C, X, xfold, fused=fused, nt=nt_store(N)),
                        "method_words_per_launch": mw, "kernel_words_per_launch": kw,
                        "algorithmic_GBs": mw * 4.0 * N * n / (ms * 1e-3) / 1e9,
                        "kernel_GBs": kw * 4.0 * N * n / (ms * 1e-3) / 1e9}

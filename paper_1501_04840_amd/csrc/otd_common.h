@@ -78,6 +78,9 @@ struct StepArgs {
     // the fused Poisson solve: the divergence kernels write r already
     // transformed across colours, cmix[c C + jc] = M_c[jc][c] (else null)
     const float* cmix;
+    // nonzero: the iteration's fields are stored non-temporally (fields of
+    // 16 MB and more, whose working set the caches cannot hold)
+    int nt_store;
 };
 
 // ---- stencil kernels (stencil.hip) -------------------------------------

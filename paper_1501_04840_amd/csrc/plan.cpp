@@ -277,6 +277,7 @@ StepArgs step_args(ot_dyn_plan* p, float* F, float* Mx, float* My, float* Mc) {
     s.twx = p->xfold ? p->tab[0].tw : nullptr;
     s.xkind = p->tab[0].periodic ? 2 : 0;
     s.cmix = p->fused && p->g.C > 1 ? p->tab[2].mat : nullptr;
+    s.nt_store = (long long)p->g.B * p->g.nc * (long long)sizeof(float) >= (16ll << 20) ? 1 : 0;
     return s;
 }
 

@@ -67,12 +67,20 @@ __device__ inline Nbr neighbours(const Geom& g, int x, int y) {
 }
 
 // Stores of the iteration's fields that a later kernel reads (a' and the
-// state, duals and carried potential), marked non-temporal.  Measured at
-// 256 x 256 x 3 x 32: the storing kernel takes a little longer, the kernel
-// that reads the fields next is faster by more (the update's stores made the
-// divergence kernel 8 us faster).  r, which the Poisson solve's first pass
-// reads right away, keeps normal stores.
-__device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+// state, duals and carried potential), marked non-temporal when the fields
+// are too large for the caches to hold an iteration's working set
+// (StepArgs::nt_store; the kernels take it as the template parameter NT: a
+// branch per store measured 4% slower).  Measured at 256 x 256 x 3 x 32: the storing kernel
+// takes a little longer, the kernel that reads the fields next is faster by
+// more (the update's stores made the divergence kernel 8 us faster); at
+// 100 x 100 x 3 x 32, whose fields stay cached, they made the iteration 13%
+// slower.  r, which the Poisson solve's first pass reads right away, keeps
+// normal stores.
+template <bool NT>
+__device__ __forceinline__ void st_f(float* p, float v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 // The residual of a node in colour modes for the fused Poisson solve: out
 // at colour stride plane gets sum_c M_c[jc][c] r[c] (cm[c C + jc] =
@@ -98,7 +106,7 @@ __device__ __forceinline__ void colour_modes(const float (&cm)[C * C], const flo
 // length XL (one per colour), and r is written already transformed along x
 // (the first pass of the Poisson solve of Sec. 3: DCT-II for XK = 0, discrete
 // Hartley for XK = 2) from the rows staged in LDS.
-template <int MODE, int C, int XL, int XK>
+template <int MODE, int C, int XL, int XK, bool NT>
 __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
     const Geom& g = s.g;
     const RowCtx r = row_ctx(g, nxb);
@@ -183,10 +191,10 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
                 const float rr = g.sx * (ax1 - ax0) + g.sy * (ay1 - ay0) + g.sc * (ac1 - acv[c]) +
                                  g.st * (af1 - af0);
                 const long long i = r.i0 + (long long)c * g.plane;
-                st_nt(s.A[0] + i, ax0);
-                st_nt(s.A[1] + i, ay0);
-                st_nt(s.A[2] + i, acv[c]);
-                st_nt(s.A[3] + i, k0 ? 0.f : af0);
+                st_f<NT>(s.A[0] + i, ax0);
+                st_f<NT>(s.A[1] + i, ay0);
+                st_f<NT>(s.A[2] + i, acv[c]);
+                st_f<NT>(s.A[3] + i, k0 ? 0.f : af0);
                 if constexpr (XL > 0) xl[c * XP + r.x] = rr;
                 else if (!mix) s.R[i] = rr;
                 rv[c] = rr;
@@ -258,7 +266,7 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
 // b), b and b_bar updates, for all colours of a node; residual partials when
 // CHECK.  NPHI 3 and 4 (carried potential) also add the potentials into Phi
 // at the own node.
-template <int CHECK, int NPHI_, int C>
+template <int CHECK, int NPHI_, int C, bool NT>
 __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
     constexpr int NPHI = NPHI_ == 4 ? 2 : (NPHI_ == 3 ? 1 : NPHI_);
     constexpr bool CARRY = NPHI_ >= 3;
@@ -343,10 +351,10 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
             float ux, uy, uc, vv;
             prox_J(amx, amy, amc, amf, sigma, ux, uy, uc, vv, s.prox);
             const float nbx = amx - ux, nby = amy - uy, nbc = amc - uc, nbf = amf - vv;
-            st_nt(s.b[0] + i, nbx); st_nt(s.bb[0] + i, nbx + th * (nbx - bx));
-            st_nt(s.b[1] + i, nby); st_nt(s.bb[1] + i, nby + th * (nby - by));
-            st_nt(s.b[2] + i, nbc); st_nt(s.bb[2] + i, nbc + th * (nbc - bc));
-            st_nt(s.b[3] + i, nbf); st_nt(s.bb[3] + i, nbf + th * (nbf - bf));
+            st_f<NT>(s.b[0] + i, nbx); st_f<NT>(s.bb[0] + i, nbx + th * (nbx - bx));
+            st_f<NT>(s.b[1] + i, nby); st_f<NT>(s.bb[1] + i, nby + th * (nby - by));
+            st_f<NT>(s.b[2] + i, nbc); st_f<NT>(s.bb[2] + i, nbc + th * (nbc - bc));
+            st_f<NT>(s.b[3] + i, nbf); st_f<NT>(s.bb[3] + i, nbf + th * (nbf - bf));
             if (CHECK) {
                 const float nf = k0 ? 0.f : f0;
                 const double ddx = (double)mx0 - O0[c], ddy = (double)my0 - O1[c];
@@ -360,11 +368,11 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
                 z2 += u2 + (double)vv * vv;
                 jj += vv > 0.f ? u2 / (2.0 * vv) : 0.0;
             }
-            st_nt(s.Mx + i, mx0);
-            st_nt(s.My + i, my0);
-            st_nt(s.Mc + i, mc0);
-            if (!k0) st_nt(s.F + fi, f0);
-            if (CARRY) st_nt(s.Phi + i, Qc[c] + (TWO ? Rc[c] + Sc[c] : Rc[c]));
+            st_f<NT>(s.Mx + i, mx0);
+            st_f<NT>(s.My + i, my0);
+            st_f<NT>(s.Mc + i, mc0);
+            if (!k0) st_f<NT>(s.F + fi, f0);
+            if (CARRY) st_f<NT>(s.Phi + i, Qc[c] + (TWO ? Rc[c] + Sc[c] : Rc[c]));
         }
     }
     if (CHECK) {
@@ -388,9 +396,16 @@ static dim3 row_grid(const Geom& g, int nxb) {
 
 template <int C, int XL, int XK>
 static void div_rows_x(const StepArgs& s, int mode, int nxb, int bx, hipStream_t st) {
-    if (mode == 0) hipLaunchKernelGGL((k_div_rows<0, C, XL, XK>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
-    else if (mode == 1) hipLaunchKernelGGL((k_div_rows<1, C, XL, XK>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
-    else hipLaunchKernelGGL((k_div_rows<2, C, XL, XK>), row_grid(s.g, nxb), dim3(bx), 0, st, s, nxb);
+    const dim3 gr = row_grid(s.g, nxb), bl(bx);
+    if (s.nt_store) {
+        if (mode == 0) hipLaunchKernelGGL((k_div_rows<0, C, XL, XK, true>), gr, bl, 0, st, s, nxb);
+        else if (mode == 1) hipLaunchKernelGGL((k_div_rows<1, C, XL, XK, true>), gr, bl, 0, st, s, nxb);
+        else hipLaunchKernelGGL((k_div_rows<2, C, XL, XK, true>), gr, bl, 0, st, s, nxb);
+    } else {
+        if (mode == 0) hipLaunchKernelGGL((k_div_rows<0, C, XL, XK, false>), gr, bl, 0, st, s, nxb);
+        else if (mode == 1) hipLaunchKernelGGL((k_div_rows<1, C, XL, XK, false>), gr, bl, 0, st, s, nxb);
+        else hipLaunchKernelGGL((k_div_rows<2, C, XL, XK, false>), gr, bl, 0, st, s, nxb);
+    }
 }
 
 template <int C, int XL>
@@ -415,23 +430,29 @@ bool div_fold_ok(const Geom& g, int row_bx, const AxisTab& tx) {
     return rows_ok(g) && tx.tw != nullptr && bx == g.X && (g.X == 64 || g.X == 128 || g.X == 256);
 }
 
-template <int C>
-static void update_rows_c(const StepArgs& s, int check, int nphi, hipStream_t st) {
+template <int C, bool NT>
+static void update_rows_n(const StepArgs& s, int check, int nphi, hipStream_t st) {
     const int bx = s.row_bx > 0 ? s.row_bx : row_block(s.g.X), nxb = (s.g.X + bx - 1) / bx;
     const dim3 gr = row_grid(s.g, nxb), bl(bx);
     if (nphi == 2) {
-        if (check) hipLaunchKernelGGL((k_update_rows<1, 2, C>), gr, bl, 0, st, s, nxb);
-        else hipLaunchKernelGGL((k_update_rows<0, 2, C>), gr, bl, 0, st, s, nxb);
+        if (check) hipLaunchKernelGGL((k_update_rows<1, 2, C, NT>), gr, bl, 0, st, s, nxb);
+        else hipLaunchKernelGGL((k_update_rows<0, 2, C, NT>), gr, bl, 0, st, s, nxb);
     } else if (nphi == 3) {
-        if (check) hipLaunchKernelGGL((k_update_rows<1, 3, C>), gr, bl, 0, st, s, nxb);
-        else hipLaunchKernelGGL((k_update_rows<0, 3, C>), gr, bl, 0, st, s, nxb);
+        if (check) hipLaunchKernelGGL((k_update_rows<1, 3, C, NT>), gr, bl, 0, st, s, nxb);
+        else hipLaunchKernelGGL((k_update_rows<0, 3, C, NT>), gr, bl, 0, st, s, nxb);
     } else if (nphi == 4) {
-        if (check) hipLaunchKernelGGL((k_update_rows<1, 4, C>), gr, bl, 0, st, s, nxb);
-        else hipLaunchKernelGGL((k_update_rows<0, 4, C>), gr, bl, 0, st, s, nxb);
+        if (check) hipLaunchKernelGGL((k_update_rows<1, 4, C, NT>), gr, bl, 0, st, s, nxb);
+        else hipLaunchKernelGGL((k_update_rows<0, 4, C, NT>), gr, bl, 0, st, s, nxb);
     } else {
-        if (check) hipLaunchKernelGGL((k_update_rows<1, 1, C>), gr, bl, 0, st, s, nxb);
-        else hipLaunchKernelGGL((k_update_rows<0, 1, C>), gr, bl, 0, st, s, nxb);
+        if (check) hipLaunchKernelGGL((k_update_rows<1, 1, C, NT>), gr, bl, 0, st, s, nxb);
+        else hipLaunchKernelGGL((k_update_rows<0, 1, C, NT>), gr, bl, 0, st, s, nxb);
     }
+}
+
+template <int C>
+static void update_rows_c(const StepArgs& s, int check, int nphi, hipStream_t st) {
+    if (s.nt_store) update_rows_n<C, true>(s, check, nphi, st);
+    else update_rows_n<C, false>(s, check, nphi, st);
 }
 
 void launch_div_rows(const StepArgs& s, int mode, hipStream_t st) {
