@@ -266,6 +266,47 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
 // b), b and b_bar updates, for all colours of a node; residual partials when
 // CHECK.  NPHI 3 and 4 (carried potential) also add the potentials into Phi
 // at the own node.
+// FP64 residual sums of a check iteration (the RedSlot quantities).
+struct ResidSums {
+    double db2 = 0, z2 = 0, dx2 = 0, x2 = 0, jj = 0;
+};
+
+// Steps 2 and 3 of Algorithm 1 at one node, given the new x on the node's
+// lower and upper faces (mx0/mx1, my0/my1, mc0/mc1, f0/f1) and the dual bo:
+// z = prox of J at K x + c + bo, the new dual bn = K x + c + bo - z and its
+// extrapolation bbn = bn + theta (bn - bo).  With CHECK the residual sums take
+// the node's terms, o holding the old x on the lower faces (f at k = 0, the
+// boundary slice, counts as 0).
+template <bool CHECK>
+__device__ __forceinline__ void node_dual(float mx0, float mx1, float my0, float my1, float mc0,
+                                          float mc1, float f0, float f1, bool k0,
+                                          const float (&bo)[4], const float (&o)[4], float sigma,
+                                          float th, int prox, float (&bn)[4], float (&bbn)[4],
+                                          ResidSums& rs) {
+    // K x + c at the node, plus b
+    const float bx = bo[0], by = bo[1], bc = bo[2], bf = bo[3];
+    const float amx = 0.5f * (mx0 + mx1) + bx, amy = 0.5f * (my0 + my1) + by;
+    const float amc = 0.5f * (mc0 + mc1) + bc, amf = 0.5f * (f0 + f1) + bf;
+    float ux, uy, uc, vv;
+    prox_J(amx, amy, amc, amf, sigma, ux, uy, uc, vv, prox);
+    bn[0] = amx - ux; bn[1] = amy - uy; bn[2] = amc - uc; bn[3] = amf - vv;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bbn[q] = bn[q] + th * (bn[q] - bo[q]);
+    if constexpr (CHECK) {
+        const float nf = k0 ? 0.f : f0;
+        const double ddx = (double)mx0 - o[0], ddy = (double)my0 - o[1];
+        const double ddc = (double)mc0 - o[2], ddf = (double)nf - o[3];
+        rs.dx2 += ddx * ddx + ddy * ddy + ddc * ddc + ddf * ddf;
+        rs.x2 += (double)mx0 * mx0 + (double)my0 * my0 + (double)mc0 * mc0 + (double)nf * nf;
+        const double ex = (double)bn[0] - bx, ey = (double)bn[1] - by;
+        const double ec = (double)bn[2] - bc, ef = (double)bn[3] - bf;
+        rs.db2 += ex * ex + ey * ey + ec * ec + ef * ef;
+        const double u2 = (double)ux * ux + (double)uy * uy + (double)uc * uc;
+        rs.z2 += u2 + (double)vv * vv;
+        rs.jj += vv > 0.f ? u2 / (2.0 * vv) : 0.0;
+    }
+}
+
 template <int CHECK, int NPHI_, int C, bool NT>
 __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
     constexpr int NPHI = NPHI_ == 4 ? 2 : (NPHI_ == 3 ? 1 : NPHI_);
@@ -274,7 +315,7 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
     const Geom& g = s.g;
     const RowCtx r = row_ctx(g, nxb);
     if (s.frz_run && s.frz_run[r.b] != 0.f) return;   // frozen problem (block-uniform)
-    double db2 = 0, z2 = 0, dx2 = 0, x2 = 0, jj = 0;
+    ResidSums rs;
     if (r.live) {
         const Nbr nb = neighbours(g, r.x, r.y);
         const long long sl = g.slice;
@@ -344,29 +385,16 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
             const float mc0 = mcv[c];
             const float mc1 = C == 1 ? 0.f
                               : (c + 1 < C ? mcv[(c + 1) % C] : (g.perc ? mcv[0] : 0.f));
-            // K x + c at the node, plus b
-            const float bx = B0[c], by = B1[c], bc = B2[c], bf = B3[c];
-            const float amx = 0.5f * (mx0 + mx1) + bx, amy = 0.5f * (my0 + my1) + by;
-            const float amc = 0.5f * (mc0 + mc1) + bc, amf = 0.5f * (f0 + f1) + bf;
-            float ux, uy, uc, vv;
-            prox_J(amx, amy, amc, amf, sigma, ux, uy, uc, vv, s.prox);
-            const float nbx = amx - ux, nby = amy - uy, nbc = amc - uc, nbf = amf - vv;
-            st_f<NT>(s.b[0] + i, nbx); st_f<NT>(s.bb[0] + i, nbx + th * (nbx - bx));
-            st_f<NT>(s.b[1] + i, nby); st_f<NT>(s.bb[1] + i, nby + th * (nby - by));
-            st_f<NT>(s.b[2] + i, nbc); st_f<NT>(s.bb[2] + i, nbc + th * (nbc - bc));
-            st_f<NT>(s.b[3] + i, nbf); st_f<NT>(s.bb[3] + i, nbf + th * (nbf - bf));
-            if (CHECK) {
-                const float nf = k0 ? 0.f : f0;
-                const double ddx = (double)mx0 - O0[c], ddy = (double)my0 - O1[c];
-                const double ddc = (double)mc0 - O2[c], ddf = (double)nf - O3[c];
-                dx2 += ddx * ddx + ddy * ddy + ddc * ddc + ddf * ddf;
-                x2 += (double)mx0 * mx0 + (double)my0 * my0 + (double)mc0 * mc0 + (double)nf * nf;
-                const double ex = (double)nbx - bx, ey = (double)nby - by;
-                const double ec = (double)nbc - bc, ef = (double)nbf - bf;
-                db2 += ex * ex + ey * ey + ec * ec + ef * ef;
-                const double u2 = (double)ux * ux + (double)uy * uy + (double)uc * uc;
-                z2 += u2 + (double)vv * vv;
-                jj += vv > 0.f ? u2 / (2.0 * vv) : 0.0;
+            const float bo[4] = {B0[c], B1[c], B2[c], B3[c]};
+            const float o[4] = {CHECK ? O0[c] : 0.f, CHECK ? O1[c] : 0.f,
+                                CHECK ? O2[c] : 0.f, CHECK ? O3[c] : 0.f};
+            float bn[4], bbn[4];
+            node_dual<CHECK != 0>(mx0, mx1, my0, my1, mc0, mc1, f0, f1, k0, bo, o, sigma, th,
+                                  s.prox, bn, bbn, rs);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                st_f<NT>(s.b[q] + i, bn[q]);
+                st_f<NT>(s.bb[q] + i, bbn[q]);
             }
             st_f<NT>(s.Mx + i, mx0);
             st_f<NT>(s.My + i, my0);
@@ -376,10 +404,157 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
         }
     }
     if (CHECK) {
-        double vals[RS_COUNT] = {db2, z2, dx2, x2, jj};
+        double vals[RS_COUNT] = {rs.db2, rs.z2, rs.dx2, rs.x2, rs.jj};
         block_sums(vals);
         if (threadIdx.x == 0)
             for (int q = 0; q < RS_COUNT; ++q) s.part_red[q * (long long)gridDim.x + r.L] = vals[q];
+    }
+}
+
+// Short vectors of NX nodes consecutive along x (16-byte accesses for NX = 4).
+template <int NX>
+using fvec = float __attribute__((ext_vector_type(NX)));
+
+template <int NX>
+__device__ __forceinline__ fvec<NX> ld_v(const float* p) {
+    return *reinterpret_cast<const fvec<NX>*>(p);
+}
+
+template <int NX, bool NT>
+__device__ __forceinline__ void st_v(float* p, fvec<NX> v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<fvec<NX>*>(p));
+    else *reinterpret_cast<fvec<NX>*>(p) = v;
+}
+
+// The value of v held by the lane d places away along the wavefront (d = +-1,
+// wrapping across the 64 lanes).
+__device__ __forceinline__ float lane_rot(float v, int d) {
+    return __shfl(v, ((int)(threadIdx.x & 63) + d) & 63, 64);
+}
+
+// k_update_rows for rows of X = 64 NX nodes (128 or 256): a wavefront owns a
+// row (b, k, y), lane l the NX nodes from x = NX l, and every field access
+// is an NX-wide vector (one 16-byte access per lane for NX = 4 instead of
+// four 4-byte ones).  The x neighbours in the adjacent lanes come by a lane
+// rotation, which wraps at the row ends as the periodic x axis does (a
+// Neumann wall zeroes the face there).  Same arithmetic per node as
+// k_update_rows (node_dual, the same expressions), so the two give the same
+// bits.  Iterations without a residual check only: with the FP64 sums the
+// kernel would need more than 256 VGPRs, and a check iteration runs
+// k_update_rows, whose partials with one block per row are per row.
+template <int NPHI_, int C, bool NT, int NX>
+__global__ void __launch_bounds__(256) k_update_vec(StepArgs s) {
+    constexpr int NPHI = NPHI_ == 4 ? 2 : (NPHI_ == 3 ? 1 : NPHI_);
+    constexpr bool CARRY = NPHI_ >= 3;
+    constexpr bool TWO = NPHI == 2;
+    using V = fvec<NX>;
+    const Geom& g = s.g;
+    const long long nrows = (long long)g.B * g.Y * g.P;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const long long row = xcd_remap(blockIdx.x, gridDim.x) * (long long)(blockDim.x >> 6) + w;
+    if (row >= nrows) return;
+    const int k = (int)(row % g.P), y = (int)((row / g.P) % g.Y), b = (int)(row / ((long long)g.P * g.Y));
+    if (s.frz_run && s.frz_run[b] != 0.f) return;   // frozen problem (wave-uniform)
+    const int lane = (int)(threadIdx.x & 63);
+    const long long p = (long long)y * g.X + (long long)lane * NX;
+    const long long i0 = (long long)b * g.nc + (long long)k * g.slice + p;
+    const long long f00 = (long long)b * g.nf + (long long)k * g.slice + p;
+    const long long sl = g.slice;
+    const bool k0 = k == 0, k1 = k + 1 == g.P;
+    const long long dtm = k0 ? 0 : -sl, dtp = k1 ? 0 : sl;   // clamped time steps
+    const long long dym = y == 0 ? (long long)(g.Y - 1) * g.X : -(long long)g.X;
+    const long long dyp = y + 1 == g.Y ? -(long long)(g.Y - 1) * g.X : (long long)g.X;
+    const bool wy0 = !g.pery && y == 0, wy1 = !g.pery && y + 1 == g.Y;
+    const bool wx0 = !g.perx && lane == 0, wx1 = !g.perx && lane == 63;   // row ends
+    auto dphi = [&](float hi, float lo, float hi2, float lo2) -> float {
+        return TWO ? (hi - lo) + (hi2 - lo2) : hi - lo;
+    };
+    // r (and phi_2) at the node for every colour, and the colour faces of x
+    V Rc[C], Sc[C], mcv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        Rc[c] = ld_v<NX>(s.R + i0 + (long long)c * g.plane);
+        if constexpr (TWO) Sc[c] = ld_v<NX>(s.R2 + i0 + (long long)c * g.plane);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int cm = c == 0 ? C - 1 : c - 1;
+        const V a2 = ld_v<NX>(s.A[2] + i0 + (long long)c * g.plane);
+#pragma unroll
+        for (int e = 0; e < NX; ++e) {
+            const float v = a2[e] + g.sc * dphi(Rc[c][e], Rc[cm][e], TWO ? Sc[c][e] : 0.f,
+                                                TWO ? Sc[cm][e] : 0.f);
+            mcv[c][e] = ((!g.perc && c == 0) || C == 1) ? 0.f : v;
+        }
+    }
+    const float th = s.theta;
+    const float sigma = s.sig[b];
+    ResidSums rs;   // unused: check iterations run k_update_rows
+    // One colour at a time: its loads, then its stores (which the compiler
+    // must keep ahead of the next colour's loads), so a wavefront holds one
+    // colour's vectors.
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const long long i = i0 + (long long)c * g.plane;
+        const long long fi = f00 + (long long)c * g.plane;
+        const V A0c = ld_v<NX>(s.A[0] + i);
+        const V A1c = ld_v<NX>(s.A[1] + i), A1p = ld_v<NX>(s.A[1] + i + dyp);
+        const V T0 = k0 ? ld_v<NX>(s.F + fi) : ld_v<NX>(s.A[3] + i);
+        const V T1 = k1 ? ld_v<NX>(s.F + fi + sl) : ld_v<NX>(s.A[3] + i + sl);
+        const V Rym = ld_v<NX>(s.R + i + dym), Ryp = ld_v<NX>(s.R + i + dyp);
+        const V Rtm = ld_v<NX>(s.R + i + dtm), Rtp = ld_v<NX>(s.R + i + dtp);
+        V Sym, Syp, Stm, Stp, Qc;
+        if constexpr (TWO) {
+            Sym = ld_v<NX>(s.R2 + i + dym); Syp = ld_v<NX>(s.R2 + i + dyp);
+            Stm = ld_v<NX>(s.R2 + i + dtm); Stp = ld_v<NX>(s.R2 + i + dtp);
+        }
+        const V B0 = ld_v<NX>(s.b[0] + i), B1 = ld_v<NX>(s.b[1] + i);
+        const V B2 = ld_v<NX>(s.b[2] + i), B3 = ld_v<NX>(s.b[3] + i);
+        if constexpr (CARRY) Qc = ld_v<NX>(s.Phi + i);
+        // x neighbours beyond the lane's nodes
+        const float rxm = lane_rot(Rc[c][NX - 1], -1), rxp = lane_rot(Rc[c][0], 1);
+        const float a0p = lane_rot(A0c[0], 1);
+        const float sxm = TWO ? lane_rot(Sc[c][NX - 1], -1) : 0.f;
+        const float sxp = TWO ? lane_rot(Sc[c][0], 1) : 0.f;
+        const V mc1v = C == 1 ? V(0.f)
+                              : (c + 1 < C ? mcv[(c + 1) % C] : (g.perc ? mcv[0] : V(0.f)));
+        V nb[4], nbb[4], vmx, vmy, vmc, vf, vq;
+#pragma unroll
+        for (int e = 0; e < NX; ++e) {
+            const float rc = Rc[c][e];
+            const float rm = e > 0 ? Rc[c][e - 1] : rxm, rp = e + 1 < NX ? Rc[c][e + 1] : rxp;
+            const float s0 = TWO ? Sc[c][e] : 0.f;
+            const float sm = TWO ? (e > 0 ? Sc[c][e - 1] : sxm) : 0.f;
+            const float sp = TWO ? (e + 1 < NX ? Sc[c][e + 1] : sxp) : 0.f;
+            const float a0n = e + 1 < NX ? A0c[e + 1] : a0p;
+            const bool w0 = e == 0 && wx0, w1 = e + 1 == NX && wx1;
+            const float mx0 = w0 ? 0.f : A0c[e] + g.sx * dphi(rc, rm, s0, sm);
+            const float mx1 = w1 ? 0.f : a0n + g.sx * dphi(rp, rc, sp, s0);
+            const float my0 = wy0 ? 0.f : A1c[e] + g.sy * dphi(rc, Rym[e], s0, TWO ? Sym[e] : 0.f);
+            const float my1 = wy1 ? 0.f : A1p[e] + g.sy * dphi(Ryp[e], rc, TWO ? Syp[e] : 0.f, s0);
+            const float f0 = k0 ? T0[e] : T0[e] + g.st * dphi(rc, Rtm[e], s0, TWO ? Stm[e] : 0.f);
+            const float f1 = k1 ? T1[e] : T1[e] + g.st * dphi(Rtp[e], rc, TWO ? Stp[e] : 0.f, s0);
+            const float mc0 = mcv[c][e], mc1 = mc1v[e];
+            const float bo[4] = {B0[e], B1[e], B2[e], B3[e]};
+            const float o[4] = {0.f, 0.f, 0.f, 0.f};
+            float bn[4], bbn[4];
+            node_dual<false>(mx0, mx1, my0, my1, mc0, mc1, f0, f1, k0, bo, o, sigma, th, s.prox,
+                             bn, bbn, rs);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { nb[q][e] = bn[q]; nbb[q][e] = bbn[q]; }
+            vmx[e] = mx0; vmy[e] = my0; vmc[e] = mc0; vf[e] = f0;
+            if constexpr (CARRY) vq[e] = Qc[e] + (TWO ? rc + s0 : rc);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            st_v<NX, NT>(s.b[q] + i, nb[q]);
+            st_v<NX, NT>(s.bb[q] + i, nbb[q]);
+        }
+        st_v<NX, NT>(s.Mx + i, vmx);
+        st_v<NX, NT>(s.My + i, vmy);
+        st_v<NX, NT>(s.Mc + i, vmc);
+        if (!k0) st_v<NX, NT>(s.F + fi, vf);
+        if constexpr (CARRY) st_v<NX, NT>(s.Phi + i, vq);
     }
 }
 
@@ -430,8 +605,39 @@ bool div_fold_ok(const Geom& g, int row_bx, const AxisTab& tx) {
     return rows_ok(g) && tx.tw != nullptr && bx == g.X && (g.X == 64 || g.X == 128 || g.X == 256);
 }
 
+// The vector update applies when a row is one wavefront of NX-node vectors
+// (X = 128 or 256 with one block per row, so the residual partials keep the
+// per-row layout) and every field it touches is aligned to the vector.
+static int update_vec_nx(const StepArgs& s, int nphi) {
+    const Geom& g = s.g;
+    const int bx = s.row_bx > 0 ? s.row_bx : row_block(g.X);
+    if (bx != g.X || (g.X != 128 && g.X != 256)) return 0;
+    const int nx = g.X / 64;
+    const uintptr_t m = (uintptr_t)(4 * nx) - 1;
+    uintptr_t any = (uintptr_t)s.F | (uintptr_t)s.Mx | (uintptr_t)s.My | (uintptr_t)s.Mc |
+                    (uintptr_t)s.R;
+    for (int q = 0; q < 4; ++q) any |= (uintptr_t)s.b[q] | (uintptr_t)s.bb[q] | (uintptr_t)s.A[q];
+    if (nphi == 2 || nphi == 4) any |= (uintptr_t)s.R2;
+    if (nphi >= 3) any |= (uintptr_t)s.Phi;
+    return (any & m) == 0 ? nx : 0;
+}
+
+template <int C, bool NT, int NX>
+static void update_vec_n(const StepArgs& s, int nphi, hipStream_t st) {
+    const long long nrows = (long long)s.g.B * s.g.Y * s.g.P;
+    const int w = nrows % 4 == 0 ? 4 : (nrows % 2 == 0 ? 2 : 1);   // rows (waves) per block
+    const dim3 gr((unsigned)(nrows / w)), bl(64 * w);
+    if (nphi == 2) hipLaunchKernelGGL((k_update_vec<2, C, NT, NX>), gr, bl, 0, st, s);
+    else if (nphi == 3) hipLaunchKernelGGL((k_update_vec<3, C, NT, NX>), gr, bl, 0, st, s);
+    else if (nphi == 4) hipLaunchKernelGGL((k_update_vec<4, C, NT, NX>), gr, bl, 0, st, s);
+    else hipLaunchKernelGGL((k_update_vec<1, C, NT, NX>), gr, bl, 0, st, s);
+}
+
 template <int C, bool NT>
 static void update_rows_n(const StepArgs& s, int check, int nphi, hipStream_t st) {
+    const int nx = check ? 0 : update_vec_nx(s, nphi);
+    if (nx == 4) { update_vec_n<C, NT, 4>(s, nphi, st); return; }
+    if (nx == 2) { update_vec_n<C, NT, 2>(s, nphi, st); return; }
     const int bx = s.row_bx > 0 ? s.row_bx : row_block(s.g.X), nxb = (s.g.X + bx - 1) / bx;
     const dim3 gr = row_grid(s.g, nxb), bl(bx);
     if (nphi == 2) {

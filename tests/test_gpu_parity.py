@@ -86,6 +86,11 @@ SHAPES = [
     (256, 8, 2, 16, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),  # rows 256, C = 2
     (40, 128, 3, 32, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12), # cols 128, Neumann colour
     (128, 128, 1, 8, (G.PERIODIC, G.PERIODIC, G.NEUMANN), 12),  # Hartley rows and cols
+    # the vector update (a wavefront per row of 128 or 256 nodes): C = 3 with
+    # both colour boundaries, periodic and Neumann x, an odd number of rows
+    (128, 12, 3, 8, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),
+    (256, 6, 3, 4, (G.PERIODIC, G.NEUMANN, G.NEUMANN), 12),
+    (128, 3, 2, 5, (G.PERIODIC, G.NEUMANN, G.PERIODIC), 12),
     # fused three-pass solve with fewer row blocks than planes (Y < P C): the
     # forward x pass reduces several planes' sums per block
     (32, 32, 3, 16, (G.NEUMANN, G.NEUMANN, G.PERIODIC), 12),
@@ -157,8 +162,10 @@ def test_cfg1_300_iterations(otdyn, mode):
 @pytest.mark.parametrize("shape", [(64, 1, 1, 16, (G.PERIODIC, G.NEUMANN, G.NEUMANN)),
                                    (180, 1, 1, 16, (G.PERIODIC, G.NEUMANN, G.NEUMANN)),
                                    (360, 1, 1, 32, (G.PERIODIC, G.NEUMANN, G.NEUMANN)),
-                                   (128, 1, 1, 8, (G.NEUMANN, G.NEUMANN, G.NEUMANN))],
-                         ids=["64x1x1x16", "180x1x1x16", "360x1x1x32", "128x1x1x8"])
+                                   (128, 1, 1, 8, (G.NEUMANN, G.NEUMANN, G.NEUMANN)),
+                                   (256, 1, 1, 8, (G.PERIODIC, G.NEUMANN, G.NEUMANN))],
+                         ids=["64x1x1x16", "180x1x1x16", "360x1x1x32", "128x1x1x8",
+                              "256x1x1x8"])
 def test_one_axis_carried_potential_300_iterations(otdyn, shape):
     """One spatial axis in the carried-potential mode past its refined start:
     the solve and the update run in one launch per iteration.  f, the cost
