@@ -66,19 +66,23 @@ def kernel_name(phase, mode, C, X=0, xfold=False, xkind=0, fused=False, nt=False
     of its rows of length X; with fused the Poisson solve is the three-pass
     one (x pass into a transposed scratch, the y and time pass, the inverse x
     pass with the colour transform); nt: the stencil kernels' non-temporal
-    variant (nt_store).  Rows of 128 or 256 nodes take the vector update
-    (one wavefront per row, X / 64 nodes per lane)."""
+    variant (nt_store).  Rows of 128 or 256 nodes take the vector stencil
+    kernels (one wavefront per row, X / 64 nodes per lane), the divergence
+    without the folded x transform."""
     f = "true" if nt else "false"
+    vec = X in (128, 256)
     if phase == "div":
-        return f"k_div_rows<{ {0: 0, 1: 0, 3: 2}[mode] }, {C}, {X if xfold else 0}, " \
-               f"{xkind if xfold else 0}, {f}>"
+        m = {0: 0, 1: 0, 3: 2}[mode]
+        if vec and not xfold:
+            return f"k_div_vec<{m}, {C}, {f}, {X // 64}>"
+        return f"k_div_rows<{m}, {C}, {X if xfold else 0}, {xkind if xfold else 0}, {f}>"
     if phase == "update":
         nphi = {0: 1, 1: 2, 3: 3}[mode]
-        if X in (128, 256):
+        if vec:
             return f"k_update_vec<{nphi}, {C}, {f}, {X // 64}>"
         return f"k_update_rows<0, {nphi}, {C}, {f}>"
     if phase == "refine":
-        return f"k_div_rows<1, {C}>"
+        return f"k_div_vec<1, {C}, {f}, {X // 64}>" if vec and not xfold else f"k_div_rows<1, {C}>"
     if fused:
         return {"xform_x": "k_xf_tr + k_xi_tr", "tc": "k_yt"}[phase]
     return {"xform_x": "k_rows_fft", "xform_y": "k_cols_fft", "tc": "k_tc_reg"}[phase]

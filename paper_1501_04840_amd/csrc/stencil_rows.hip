@@ -98,6 +98,27 @@ __device__ __forceinline__ void colour_modes(const float (&cm)[C * C], const flo
     }
 }
 
+// Short vectors of NX nodes consecutive along x (16-byte accesses for NX = 4).
+template <int NX>
+using fvec = float __attribute__((ext_vector_type(NX)));
+
+template <int NX>
+__device__ __forceinline__ fvec<NX> ld_v(const float* p) {
+    return *reinterpret_cast<const fvec<NX>*>(p);
+}
+
+template <int NX, bool NT>
+__device__ __forceinline__ void st_v(float* p, fvec<NX> v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<fvec<NX>*>(p));
+    else *reinterpret_cast<fvec<NX>*>(p) = v;
+}
+
+// The value of v held by the lane d places away along the wavefront (d = +-1,
+// wrapping across the 64 lanes).
+__device__ __forceinline__ float lane_rot(float v, int d) {
+    return __shfl(v, ((int)(threadIdx.x & 63) + d) & 63, 64);
+}
+
 // r = A a - f_b^- with a = x - tau sigma K^T b_bar (MODE 0: also writes a to A
 // and r to R), a = A + grad phi_1 (MODE 1, refinement: writes r to R2) or
 // a = x - tau sigma K^T b_bar + grad Phi with the carried potential Phi
@@ -262,6 +283,203 @@ __global__ void __launch_bounds__(256) k_div_rows(StepArgs s, int nxb) {
     }
 }
 
+// k_div_rows without the folded x transform (XL = 0) for rows of X = 64 NX
+// nodes (128 or 256), laid out as k_update_vec: a wavefront per row, NX
+// nodes per lane, NX-wide accesses, x neighbours by lane rotation, one
+// colour's loads at a time after the colour faces.  The same expressions per
+// node as k_div_rows; the FP64 plane sums of r are per row (wavefront), the
+// slots k_div_rows fills with one block per row.
+template <int MODE, int C, bool NT, int NX>
+__global__ void __launch_bounds__(256) k_div_vec(StepArgs s) {
+    using V = fvec<NX>;
+    const Geom& g = s.g;
+    const long long nrows = (long long)g.B * g.Y * g.P;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const long long row = xcd_remap(blockIdx.x, gridDim.x) * (long long)(blockDim.x >> 6) + w;
+    if (row >= nrows) return;
+    const int k = (int)(row % g.P), y = (int)((row / g.P) % g.Y), b = (int)(row / ((long long)g.P * g.Y));
+    if (s.frz_run && s.frz_run[b] != 0.f) return;   // frozen problem (wave-uniform)
+    const float ts = 0.5f * s.tau_sigma;
+    float cm[C * C];
+    const bool mix = C > 1 && s.cmix != nullptr;
+#pragma unroll
+    for (int q = 0; q < C * C; ++q) cm[q] = mix ? s.cmix[q] : 0.f;
+    const int lane = (int)(threadIdx.x & 63);
+    const long long p = (long long)y * g.X + (long long)lane * NX;
+    const long long i0 = (long long)b * g.nc + (long long)k * g.slice + p;
+    const long long f00 = (long long)b * g.nf + (long long)k * g.slice + p;
+    const long long sl = g.slice;
+    const bool k0 = k == 0, k1 = k + 1 == g.P;
+    const long long dtm = k0 ? 0 : -sl, dtp = k1 ? 0 : sl;   // clamped time steps
+    const long long dym = y == 0 ? (long long)(g.Y - 1) * g.X : -(long long)g.X;
+    const long long dyp = y + 1 == g.Y ? -(long long)(g.Y - 1) * g.X : (long long)g.X;
+    const bool wy0 = !g.pery && y == 0, wy1 = !g.pery && y + 1 == g.Y;
+    const bool wx0 = !g.perx && lane == 0, wx1 = !g.perx && lane == 63;   // row ends
+    V rv[C];
+    if constexpr (MODE != 1) {
+        constexpr bool Q = MODE == 2;
+        // colour faces of a: own face c of every colour
+        V BC[C], Qc[C], acv[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            BC[c] = ld_v<NX>(s.bb[2] + i0 + (long long)c * g.plane);
+            if constexpr (Q) Qc[c] = ld_v<NX>(s.Phi + i0 + (long long)c * g.plane);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int cm_ = c == 0 ? C - 1 : c - 1;
+            const V MC = ld_v<NX>(s.Mc + i0 + (long long)c * g.plane);
+#pragma unroll
+            for (int e = 0; e < NX; ++e) {
+                float v = MC[e] - ts * (BC[cm_][e] + BC[c][e]);
+                if constexpr (Q) v += g.sc * (Qc[c][e] - Qc[cm_][e]);
+                acv[c][e] = ((!g.perc && c == 0) || C == 1) ? 0.f : v;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const long long i = i0 + (long long)c * g.plane;
+            const long long fi = f00 + (long long)c * g.plane;
+            const V X0 = ld_v<NX>(s.Mx + i);
+            const V Y0 = ld_v<NX>(s.My + i), Y1 = ld_v<NX>(s.My + i + dyp);
+            const V T0 = ld_v<NX>(s.F + fi), T1 = ld_v<NX>(s.F + fi + sl);
+            const V BXc = ld_v<NX>(s.bb[0] + i);
+            const V BYm = ld_v<NX>(s.bb[1] + i + dym), BYc = ld_v<NX>(s.bb[1] + i);
+            const V BYp = ld_v<NX>(s.bb[1] + i + dyp);
+            const V BTm = ld_v<NX>(s.bb[3] + i + dtm), BTc = ld_v<NX>(s.bb[3] + i);
+            const V BTp = ld_v<NX>(s.bb[3] + i + dtp);
+            V Qym, Qyp, Qtm, Qtp;
+            if constexpr (Q) {
+                Qym = ld_v<NX>(s.Phi + i + dym); Qyp = ld_v<NX>(s.Phi + i + dyp);
+                Qtm = ld_v<NX>(s.Phi + i + dtm); Qtp = ld_v<NX>(s.Phi + i + dtp);
+            }
+            // x neighbours beyond the lane's nodes
+            const float x1n = lane_rot(X0[0], 1);
+            const float bxm = lane_rot(BXc[NX - 1], -1), bxp = lane_rot(BXc[0], 1);
+            const float qxm = Q ? lane_rot(Qc[c][NX - 1], -1) : 0.f;
+            const float qxp = Q ? lane_rot(Qc[c][0], 1) : 0.f;
+            const V ac1v = C == 1 ? V(0.f)
+                                  : (c + 1 < C ? acv[(c + 1) % C] : (g.perc ? acv[0] : V(0.f)));
+            V o0, o1, o3;
+#pragma unroll
+            for (int e = 0; e < NX; ++e) {
+                const float x1 = e + 1 < NX ? X0[e + 1] : x1n;
+                const float bm = e > 0 ? BXc[e - 1] : bxm, bp = e + 1 < NX ? BXc[e + 1] : bxp;
+                float ax0 = X0[e] - ts * (bm + BXc[e]);
+                float ax1 = x1 - ts * (BXc[e] + bp);
+                float ay0 = Y0[e] - ts * (BYm[e] + BYc[e]);
+                float ay1 = Y1[e] - ts * (BYc[e] + BYp[e]);
+                float af0 = T0[e] - ts * (BTm[e] + BTc[e]);
+                float af1 = T1[e] - ts * (BTc[e] + BTp[e]);
+                if constexpr (Q) {           // + grad Phi on the unknown faces
+                    const float qc = Qc[c][e];
+                    const float qm = e > 0 ? Qc[c][e - 1] : qxm;
+                    const float qp = e + 1 < NX ? Qc[c][e + 1] : qxp;
+                    ax0 += g.sx * (qc - qm);
+                    ax1 += g.sx * (qp - qc);
+                    ay0 += g.sy * (qc - Qym[e]);
+                    ay1 += g.sy * (Qyp[e] - qc);
+                    af0 += g.st * (qc - Qtm[e]);
+                    af1 += g.st * (Qtp[e] - qc);
+                }
+                ax0 = e == 0 && wx0 ? 0.f : ax0;
+                ax1 = e + 1 == NX && wx1 ? 0.f : ax1;
+                ay0 = wy0 ? 0.f : ay0;
+                ay1 = wy1 ? 0.f : ay1;
+                af0 = k0 ? T0[e] : af0;      // boundary slices are data
+                af1 = k1 ? T1[e] : af1;
+                const float ac1 = ac1v[e];
+                rv[c][e] = g.sx * (ax1 - ax0) + g.sy * (ay1 - ay0) + g.sc * (ac1 - acv[c][e]) +
+                           g.st * (af1 - af0);
+                o0[e] = ax0; o1[e] = ay0; o3[e] = k0 ? 0.f : af0;
+            }
+            st_v<NX, NT>(s.A[0] + i, o0);
+            st_v<NX, NT>(s.A[1] + i, o1);
+            st_v<NX, NT>(s.A[2] + i, acv[c]);
+            st_v<NX, NT>(s.A[3] + i, o3);
+        }
+    } else {
+        // colour faces first: own face c of every colour
+        V W[C], acv[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) W[c] = ld_v<NX>(s.R + i0 + (long long)c * g.plane);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int cm_ = c == 0 ? C - 1 : c - 1;
+            const V A2 = ld_v<NX>(s.A[2] + i0 + (long long)c * g.plane);
+#pragma unroll
+            for (int e = 0; e < NX; ++e) {
+                const float v = A2[e] + g.sc * (W[c][e] - W[cm_][e]);
+                acv[c][e] = ((!g.perc && c == 0) || C == 1) ? 0.f : v;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const long long i = i0 + (long long)c * g.plane;
+            const long long fi = f00 + (long long)c * g.plane;
+            const V A0 = ld_v<NX>(s.A[0] + i);
+            const V A1c = ld_v<NX>(s.A[1] + i), A1p = ld_v<NX>(s.A[1] + i + dyp);
+            const V T0 = k0 ? ld_v<NX>(s.F + fi) : ld_v<NX>(s.A[3] + i);
+            const V T1 = k1 ? ld_v<NX>(s.F + fi + sl) : ld_v<NX>(s.A[3] + i + sl);
+            const V Rym = ld_v<NX>(s.R + i + dym), Ryp = ld_v<NX>(s.R + i + dyp);
+            const V Rtm = ld_v<NX>(s.R + i + dtm), Rtp = ld_v<NX>(s.R + i + dtp);
+            const float rxm = lane_rot(W[c][NX - 1], -1), rxp = lane_rot(W[c][0], 1);
+            const float a0p = lane_rot(A0[0], 1);
+            const V ac1v = C == 1 ? V(0.f)
+                                  : (c + 1 < C ? acv[(c + 1) % C] : (g.perc ? acv[0] : V(0.f)));
+#pragma unroll
+            for (int e = 0; e < NX; ++e) {
+                const float pc = W[c][e];
+                const float rm = e > 0 ? W[c][e - 1] : rxm, rp = e + 1 < NX ? W[c][e + 1] : rxp;
+                const float a0n = e + 1 < NX ? A0[e + 1] : a0p;
+                const float ax0 = e == 0 && wx0 ? 0.f : A0[e] + g.sx * (pc - rm);
+                const float ax1 = e + 1 == NX && wx1 ? 0.f : a0n + g.sx * (rp - pc);
+                const float ay0 = wy0 ? 0.f : A1c[e] + g.sy * (pc - Rym[e]);
+                const float ay1 = wy1 ? 0.f : A1p[e] + g.sy * (Ryp[e] - pc);
+                const float af0 = k0 ? T0[e] : T0[e] + g.st * (pc - Rtm[e]);
+                const float af1 = k1 ? T1[e] : T1[e] + g.st * (Rtp[e] - pc);
+                const float ac1 = ac1v[e];
+                rv[c][e] = g.sx * (ax1 - ax0) + g.sy * (ay1 - ay0) + g.sc * (ac1 - acv[c][e]) +
+                           g.st * (af1 - af0);
+            }
+        }
+    }
+    float* const out = MODE == 1 ? s.R2 : s.R;
+    if (mix) {
+#pragma unroll
+        for (int jc = 0; jc < C; ++jc) {
+            V acc;
+#pragma unroll
+            for (int e = 0; e < NX; ++e) {
+                float a = 0.f;
+#pragma unroll
+                for (int c = 0; c < C; ++c) a = fmaf(cm[c * C + jc], rv[c][e], a);
+                acc[e] = a;
+            }
+            *reinterpret_cast<V*>(out + i0 + (long long)jc * g.plane) = acc;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) *reinterpret_cast<V*>(out + i0 + (long long)c * g.plane) = rv[c];
+    }
+    double sums[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int e = 0; e < NX; ++e) t += (double)rv[c][e];
+        sums[c] = t;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int c = 0; c < C; ++c) sums[c] += __shfl_down(sums[c], o, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            s.part_slice[(((long long)b * g.P + k) * C + c) * s.nbx + y] = sums[c];
+}
+
 // x = a + grad phi_1 (+ grad phi_2 when NPHI is 2 or 4), z = prox(K x + c +
 // b), b and b_bar updates, for all colours of a node; residual partials when
 // CHECK.  NPHI 3 and 4 (carried potential) also add the potentials into Phi
@@ -411,27 +629,6 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
     }
 }
 
-// Short vectors of NX nodes consecutive along x (16-byte accesses for NX = 4).
-template <int NX>
-using fvec = float __attribute__((ext_vector_type(NX)));
-
-template <int NX>
-__device__ __forceinline__ fvec<NX> ld_v(const float* p) {
-    return *reinterpret_cast<const fvec<NX>*>(p);
-}
-
-template <int NX, bool NT>
-__device__ __forceinline__ void st_v(float* p, fvec<NX> v) {
-    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<fvec<NX>*>(p));
-    else *reinterpret_cast<fvec<NX>*>(p) = v;
-}
-
-// The value of v held by the lane d places away along the wavefront (d = +-1,
-// wrapping across the 64 lanes).
-__device__ __forceinline__ float lane_rot(float v, int d) {
-    return __shfl(v, ((int)(threadIdx.x & 63) + d) & 63, 64);
-}
-
 // k_update_rows for rows of X = 64 NX nodes (128 or 256): a wavefront owns a
 // row (b, k, y), lane l the NX nodes from x = NX l, and every field access
 // is an NX-wide vector (one 16-byte access per lane for NX = 4 instead of
@@ -569,6 +766,50 @@ static dim3 row_grid(const Geom& g, int nxb) {
     return dim3((unsigned)((long long)g.B * g.Y * g.P * nxb));
 }
 
+// The vector kernels apply when a row is one wavefront of NX-node vectors
+// (X = 128 or 256 with one block per row, so that the plane and residual
+// partials keep the per-row layout) and every field is aligned to the
+// vector (a null field counts as aligned).  Returns NX, or 0.
+static int row_vec_nx(const StepArgs& s) {
+    const Geom& g = s.g;
+    const int bx = s.row_bx > 0 ? s.row_bx : row_block(g.X);
+    if (bx != g.X || (g.X != 128 && g.X != 256)) return 0;
+    const int nx = g.X / 64;
+    const uintptr_t m = (uintptr_t)(4 * nx) - 1;
+    uintptr_t any = (uintptr_t)s.F | (uintptr_t)s.Mx | (uintptr_t)s.My | (uintptr_t)s.Mc |
+                    (uintptr_t)s.R | (uintptr_t)s.R2 | (uintptr_t)s.Phi;
+    for (int q = 0; q < 4; ++q) any |= (uintptr_t)s.b[q] | (uintptr_t)s.bb[q] | (uintptr_t)s.A[q];
+    return (any & m) == 0 ? nx : 0;
+}
+
+// rows (wavefronts) per block of the vector kernels, and their grid
+static void vec_grid(const Geom& g, dim3& gr, dim3& bl) {
+    const long long nrows = (long long)g.B * g.Y * g.P;
+    const int w = nrows % 4 == 0 ? 4 : (nrows % 2 == 0 ? 2 : 1);
+    gr = dim3((unsigned)(nrows / w));
+    bl = dim3(64 * w);
+}
+
+template <int C, bool NT, int NX>
+static void div_vec_n(const StepArgs& s, int mode, hipStream_t st) {
+    dim3 gr, bl;
+    vec_grid(s.g, gr, bl);
+    if (mode == 0) hipLaunchKernelGGL((k_div_vec<0, C, NT, NX>), gr, bl, 0, st, s);
+    else if (mode == 1) hipLaunchKernelGGL((k_div_vec<1, C, NT, NX>), gr, bl, 0, st, s);
+    else hipLaunchKernelGGL((k_div_vec<2, C, NT, NX>), gr, bl, 0, st, s);
+}
+
+template <int C>
+static void div_vec_c(const StepArgs& s, int mode, int nx, hipStream_t st) {
+    if (s.nt_store) {
+        if (nx == 4) div_vec_n<C, true, 4>(s, mode, st);
+        else div_vec_n<C, true, 2>(s, mode, st);
+    } else {
+        if (nx == 4) div_vec_n<C, false, 4>(s, mode, st);
+        else div_vec_n<C, false, 2>(s, mode, st);
+    }
+}
+
 template <int C, int XL, int XK>
 static void div_rows_x(const StepArgs& s, int mode, int nxb, int bx, hipStream_t st) {
     const dim3 gr = row_grid(s.g, nxb), bl(bx);
@@ -592,7 +833,12 @@ static void div_rows_k(const StepArgs& s, int mode, int nxb, int bx, hipStream_t
 template <int C>
 static void div_rows_c(const StepArgs& s, int mode, hipStream_t st) {
     const int bx = s.row_bx > 0 ? s.row_bx : row_block(s.g.X), nxb = (s.g.X + bx - 1) / bx;
-    if (!s.twx) { div_rows_x<C, 0, 0>(s, mode, nxb, bx, st); return; }
+    if (!s.twx) {
+        const int nx = row_vec_nx(s);
+        if (nx) div_vec_c<C>(s, mode, nx, st);
+        else div_rows_x<C, 0, 0>(s, mode, nxb, bx, st);
+        return;
+    }
     switch (s.g.X) {     // div_fold_ok: X == bx in {64, 128, 256}
         case 64: div_rows_k<C, 64>(s, mode, nxb, bx, st); break;
         case 128: div_rows_k<C, 128>(s, mode, nxb, bx, st); break;
@@ -605,28 +851,10 @@ bool div_fold_ok(const Geom& g, int row_bx, const AxisTab& tx) {
     return rows_ok(g) && tx.tw != nullptr && bx == g.X && (g.X == 64 || g.X == 128 || g.X == 256);
 }
 
-// The vector update applies when a row is one wavefront of NX-node vectors
-// (X = 128 or 256 with one block per row, so the residual partials keep the
-// per-row layout) and every field it touches is aligned to the vector.
-static int update_vec_nx(const StepArgs& s, int nphi) {
-    const Geom& g = s.g;
-    const int bx = s.row_bx > 0 ? s.row_bx : row_block(g.X);
-    if (bx != g.X || (g.X != 128 && g.X != 256)) return 0;
-    const int nx = g.X / 64;
-    const uintptr_t m = (uintptr_t)(4 * nx) - 1;
-    uintptr_t any = (uintptr_t)s.F | (uintptr_t)s.Mx | (uintptr_t)s.My | (uintptr_t)s.Mc |
-                    (uintptr_t)s.R;
-    for (int q = 0; q < 4; ++q) any |= (uintptr_t)s.b[q] | (uintptr_t)s.bb[q] | (uintptr_t)s.A[q];
-    if (nphi == 2 || nphi == 4) any |= (uintptr_t)s.R2;
-    if (nphi >= 3) any |= (uintptr_t)s.Phi;
-    return (any & m) == 0 ? nx : 0;
-}
-
 template <int C, bool NT, int NX>
 static void update_vec_n(const StepArgs& s, int nphi, hipStream_t st) {
-    const long long nrows = (long long)s.g.B * s.g.Y * s.g.P;
-    const int w = nrows % 4 == 0 ? 4 : (nrows % 2 == 0 ? 2 : 1);   // rows (waves) per block
-    const dim3 gr((unsigned)(nrows / w)), bl(64 * w);
+    dim3 gr, bl;
+    vec_grid(s.g, gr, bl);
     if (nphi == 2) hipLaunchKernelGGL((k_update_vec<2, C, NT, NX>), gr, bl, 0, st, s);
     else if (nphi == 3) hipLaunchKernelGGL((k_update_vec<3, C, NT, NX>), gr, bl, 0, st, s);
     else if (nphi == 4) hipLaunchKernelGGL((k_update_vec<4, C, NT, NX>), gr, bl, 0, st, s);
@@ -635,7 +863,7 @@ static void update_vec_n(const StepArgs& s, int nphi, hipStream_t st) {
 
 template <int C, bool NT>
 static void update_rows_n(const StepArgs& s, int check, int nphi, hipStream_t st) {
-    const int nx = check ? 0 : update_vec_nx(s, nphi);
+    const int nx = check ? 0 : row_vec_nx(s);
     if (nx == 4) { update_vec_n<C, NT, 4>(s, nphi, st); return; }
     if (nx == 2) { update_vec_n<C, NT, 2>(s, nphi, st); return; }
     const int bx = s.row_bx > 0 ? s.row_bx : row_block(s.g.X), nxb = (s.g.X + bx - 1) / bx;
