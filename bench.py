@@ -164,8 +164,9 @@ def cpu_baseline(f0, f1, X, Y, C, P, iters):
 
 
 def copy_ceiling(nbytes: int = 1 << 30, reps: int = 10) -> float:
-    """Device-to-device copy rate (read + write bytes / s) of a 1 GiB buffer:
-    the practical HBM ceiling on this GPU, for context."""
+    """Device-to-device copy rate (read + write bytes / s) of a 1 GiB buffer
+    by torch's copy kernel (4-byte lanes), for context: kernels with 16-byte
+    lanes and non-temporal stores move more on this GPU."""
     import torch
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").uniform_()
     dst = torch.empty_like(src)

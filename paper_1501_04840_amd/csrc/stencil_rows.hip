@@ -635,8 +635,7 @@ __global__ void __launch_bounds__(256) k_update_rows(StepArgs s, int nxb) {
 // four 4-byte ones).  The x neighbours in the adjacent lanes come by a lane
 // rotation, which wraps at the row ends as the periodic x axis does (a
 // Neumann wall zeroes the face there).  Same arithmetic per node as
-// k_update_rows (node_dual, the same expressions), so the two give the same
-// bits.  Iterations without a residual check only: with the FP64 sums the
+// k_update_rows (node_dual, the same expressions).  Iterations without a residual check only: with the FP64 sums the
 // kernel would need more than 256 VGPRs, and a check iteration runs
 // k_update_rows, whose partials with one block per row are per row.
 template <int NPHI_, int C, bool NT, int NX>

@@ -124,6 +124,52 @@ def test_autotune_keeps_results(otdyn, tmp_path, monkeypatch):
     bt.close()
 
 
+def test_vector_and_scalar_row_kernels_agree(otdyn, tmp_path, monkeypatch):
+    """Rows of 256 and 128 nodes under the fused Poisson solve: the default
+    launch shape runs the vector stencil kernels (a wavefront per row), row
+    blocks of 64 the scalar ones.  The per-node arithmetic is the same; only
+    the FP64 plane sums are added in another order, so the two states agree
+    to FP32 rounding."""
+    _say("vector vs scalar row kernels")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("OT_DYN_TUNE_CACHE", str(cache))
+    dims = [(256, 32, 3, 8), (128, 32, 1, 8)]
+    f0s, f1s = [], []
+    for i, (X, Y, C, P) in enumerate(dims):
+        a, b = inputs.random_pair(70 + i, X, Y, C)
+        f0s.append(a)
+        f1s.append(b)
+    base = otdyn.ot_dyn_default_desc(1, 1, 1, 2)
+    base.adapt = 0
+
+    def run(force64):
+        bt = otdyn.Batch(base, dims)
+        bt.set_boundary(f0s, f1s)
+        if force64:
+            bt.autotune(1)                     # writes the cache keys of both groups
+            keys = [ln.split()[0] for ln in cache.read_text().splitlines() if ln.strip()]
+            assert len(keys) == len(dims)
+            cache.write_text("".join(f"{k} 64 0\n" for k in keys))
+            bt.close()
+            bt = otdyn.Batch(base, dims)
+            bt.set_boundary(f0s, f1s)
+            bt.autotune(1)                     # takes the cached shapes
+            for i in range(len(dims)):
+                assert otdyn.ot_dyn_batch_tuning(bt.bt, i) == (64, 0)
+        else:
+            for i, (X, _, _, _) in enumerate(dims):
+                assert otdyn.ot_dyn_batch_tuning(bt.bt, i)[0] == X
+        bt.solve(100, chunk=50)
+        out = [bt.state(i) for i in range(len(dims))]
+        bt.close()
+        return out
+
+    vec, sca = run(False), run(True)
+    for i in range(len(dims)):
+        for u, v in zip(vec[i], sca[i]):
+            assert rel(u, v) < 1e-5, i
+
+
 def test_batch_certifies_each_problem(otdyn):
     _say("batch certification")
     probs = hue_problems(8, seed=3, bins=(64, 37), steps=(8,))
