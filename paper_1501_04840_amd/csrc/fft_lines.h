@@ -166,8 +166,10 @@ __device__ __forceinline__ void line_dct2(float* s, int t, const float2* tw4, bo
     __syncthreads();
 }
 
-// Orthonormal DCT-III (inverse of line_dct2) in place.
-template <int M1, int M2, int XP = 0>
+// Orthonormal DCT-III (inverse of line_dct2) in place.  BLOCK_END false: end
+// with a wavefront sync only, for callers that afterwards read nothing but
+// the lines of their own wavefront.
+template <int M1, int M2, int XP = 0, bool BLOCK_END = true>
 __device__ __forceinline__ void line_dct3(float* s, int t, const float2* tw4) {
     constexpr int M = M1 * M2, L = 2 * M, T = M2, NP = (M / 2 + T) / T;
     // inputs scaled by sqrt(L / 2) (sqrt(L) for X[0]); with V(k) =
@@ -227,7 +229,8 @@ __device__ __forceinline__ void line_dct3(float* s, int t, const float2* tw4) {
                 wm[2 * L - 3 - 2 * B] = -r[q][k2].y * sc;
             }
         }
-    __syncthreads();
+    if constexpr (BLOCK_END) __syncthreads();
+    else line_sync();
 }
 
 // Orthonormal discrete Hartley transform (its own inverse) in place.
@@ -483,11 +486,12 @@ __device__ __forceinline__ void line_xform_mix(float* s, int t, const float2* tw
 
 // XP: exchange padding of the DCTs (fft_core); the line's LDS region then
 // needs max(2 M, M1 (2 M2 + XP)) floats.
-template <int M1, int M2, int KIND, int XP = 0>
+template <int M1, int M2, int KIND, int XP = 0, bool BLOCK_END = true>
 __device__ __forceinline__ void line_xform(float* s, int t, const float2* tw4) {
     static_assert(KIND != 2 || XP == 0, "no padded exchange for the Hartley transform");
+    static_assert(BLOCK_END || KIND == 1, "a wavefront-sync end only for the DCT-III");
     if constexpr (KIND == 0) line_dct2<M1, M2, XP>(s, t, tw4);
-    else if constexpr (KIND == 1) line_dct3<M1, M2, XP>(s, t, tw4);
+    else if constexpr (KIND == 1) line_dct3<M1, M2, XP, BLOCK_END>(s, t, tw4);
     else line_dht<M1, M2>(s, t, tw4);
 }
 

@@ -716,25 +716,37 @@ __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
     double pv[16];
     if (psum) plane_first<S>(part + (long long)lb * a.nbx, a.nbx, threadIdx.x, pv);
     const float* src = a.R + (long long)b * g.nc + (long long)t0 * g.slice + (long long)y * L;
-    // single floats, consecutive over the threads (coalesced loads, all in
-    // flight; conflict-free LDS writes).  Offsets within a problem fit in 32
-    // bits (at most 256 x 256 x 3 x 32 values), so the loads take a uniform
-    // base and a 32-bit offset.
+    // Single floats consecutive over the lanes (coalesced, all in flight,
+    // conflict-free LDS writes).  When the block is whole wavefronts, each
+    // wavefront loads exactly the LW lines it transforms and needs only a
+    // wavefront sync before its transform, so that wavefronts whose loads
+    // have arrived transform while the others still load; a smaller block
+    // stages the tile together.  Offsets within a problem fit in 32 bits (at
+    // most 256 x 256 x 3 x 32 values), so the loads take a uniform base and a
+    // 32-bit offset.
+    constexpr bool PERWAVE = NT % 64 == 0;
+    constexpr int LANES = PERWAVE ? 64 : NT, LW = LANES / T;   // lines per staging group
+    static_assert(LW * L == LANES * NE, "a group's lines are its lanes' loads");
     const unsigned slice = (unsigned)g.slice, plane = (unsigned)g.plane;
+    const unsigned lane = threadIdx.x % LANES, l0 = (threadIdx.x / LANES) * LW;
     float buf[NE];
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
-        const unsigned e = threadIdx.x + NT * j;
-        const unsigned line = e / L, col = e % L, t = line / C, c = line % C;
+        const unsigned e = lane + LANES * j;
+        const unsigned line = l0 + e / L, col = e % L, t = line / C, c = line % C;
         buf[j] = src[t * slice + c * plane + col];
     }
     if (psum) pslot[threadIdx.x] = plane_slot<S>(part + (long long)lb * a.nbx, a.nbx, threadIdx.x, pv);
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
-        const int e = (int)threadIdx.x + NT * j;
-        lds[(e / L) * PITCH + (e % L)] = buf[j];
+        const unsigned e = lane + LANES * j;
+        lds[(l0 + e / L) * PITCH + (e % L)] = buf[j];
     }
-    __syncthreads();
+    if constexpr (PERWAVE) line_sync();            // the wavefront's own lines are staged
+    else __syncthreads();
+    const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
+    line_xform<M1, M2, 0, XP>(lds + line * PITCH, tt, a.tx.tw);
+    // (the transform ends with a block barrier: pslot is complete)
     if (lb < MP && threadIdx.x == 0) {
         double acc = 0.0;
         for (int j = 0; j < S; ++j) acc += pslot[j];
@@ -754,8 +766,6 @@ __global__ void __launch_bounds__(PS * C * M2) k_xf_tr(TcArgs a) {
             part[(long long)q * a.nbx] = acc;
         }
     }
-    const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
-    line_xform<M1, M2, 0, XP>(lds + line * PITCH, tt, a.tx.tw);
     if (C > 1 && !a.premixed) {
         const float* Tc = a.tc.mat;                    // Tc[c * C + jc] = M_c[jc][c]
         for (int q = threadIdx.x; q < PS * L; q += NT) {
@@ -864,18 +874,25 @@ __global__ void __launch_bounds__(PS * C * M2) k_xi_tr(TcArgs a) {
         }
         __syncthreads();
     }
+    // When the block is whole wavefronts, each wavefront stores the LW lines it
+    // transformed as soon as they are done (the transform then ends with a
+    // wavefront sync, not a block barrier); a smaller block stores together.
+    constexpr bool PERWAVE = NT % 64 == 0;
+    constexpr int LANES = PERWAVE ? 64 : NT, LW = LANES / T;
+    static_assert(LW * L == LANES * NE, "a group's lines are its lanes' stores");
     const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
-    line_xform<M1, M2, 1, XP>(lds + line * PITCH, tt, a.tx.tw);
+    line_xform<M1, M2, 1, XP, !PERWAVE>(lds + line * PITCH, tt, a.tx.tw);
     float* dstb = a.R + (long long)b * g.nc + (long long)t0 * g.slice + (long long)y * L;
+    const unsigned lane = threadIdx.x % LANES, l0 = (threadIdx.x / LANES) * LW;
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
-        const int e = (int)threadIdx.x + NT * j;
-        buf[j] = lds[(e / L) * PITCH + (e % L)];
+        const unsigned e = lane + LANES * j;
+        buf[j] = lds[(l0 + e / L) * PITCH + (e % L)];
     }
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
-        const int e = (int)threadIdx.x + NT * j;
-        const unsigned ln = (unsigned)e / L, col = (unsigned)e % L, ts = ln / C, c = ln % C;
+        const unsigned e = lane + LANES * j;
+        const unsigned ln = l0 + e / L, col = e % L, ts = ln / C, c = ln % C;
         dstb[ts * (unsigned)g.slice + c * (unsigned)g.plane + col] = buf[j];
     }
 }
