@@ -908,20 +908,38 @@ __global__ void __launch_bounds__(NT) k_yt(TcArgs a) {
     const Geom& g = a.g;
     const int b = blockIdx.y, jc = blockIdx.x / g.X, jx = blockIdx.x - jc * g.X;
     float* base = a.Rt + (long long)b * g.nc + (long long)blockIdx.x * L * P;
+    // When the block's lines are exactly P time lines, LW to a wavefront
+    // (LW a multiple of 4), each wavefront stages its own lines t0w ..
+    // t0w + LW - 1 (LW / 4 float4 per y) and transforms them after a
+    // wavefront sync, and stores them after its inverse transform the same
+    // way; otherwise the block stages and stores the tile together.
+    constexpr int LW = 64 / T;
+    constexpr bool PERWAVE = NT % 64 == 0 && NT / T == P && LW % 4 == 0;
+    constexpr int H = PERWAVE ? LW / 4 : 1;        // float4 per y and wavefront
+    const int lane = (int)(threadIdx.x & 63), t0w = (int)(threadIdx.x >> 6) * LW;
+    auto vidx = [&](int j) {                       // float4 index of the j-th load
+        if constexpr (PERWAVE) {
+            const int q = lane + 64 * j;
+            return (q / H) * (P / 4) + t0w / 4 + q % H;
+        } else {
+            return (int)threadIdx.x + NT * j;
+        }
+    };
     float4 buf[NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) buf[j] = reinterpret_cast<const float4*>(base)[threadIdx.x + NT * j];
+    for (int j = 0; j < NV; ++j) buf[j] = reinterpret_cast<const float4*>(base)[vidx(j)];
     for (int e = P * PITCH + threadIdx.x; e < NLINES * PITCH; e += NT) lds[e] = 0.f;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-        const int e = 4 * ((int)threadIdx.x + NT * j);
+        const int e = 4 * vidx(j);
         const int y = e / P, t = e - y * P;
         lds[t * PITCH + y] = buf[j].x;
         lds[(t + 1) * PITCH + y] = buf[j].y;
         lds[(t + 2) * PITCH + y] = buf[j].z;
         lds[(t + 3) * PITCH + y] = buf[j].w;
     }
-    __syncthreads();
+    if constexpr (PERWAVE) line_sync();            // the wavefront's own lines are staged
+    else __syncthreads();
     const int line = threadIdx.x / T, tt = threadIdx.x - line * T;
     line_xform<M1, M2, 0, XP>(lds + line * PITCH, tt, a.ty.tw);
     const float lcx = a.tx.lam[jx] + a.tc.lam[jc];
@@ -946,12 +964,12 @@ __global__ void __launch_bounds__(NT) k_yt(TcArgs a) {
         for (int t = 0; t < P; ++t) lds[t * PITCH + jy] = u[t];
     }
     __syncthreads();
-    line_xform<M1, M2, 1, XP>(lds + line * PITCH, tt, a.ty.tw);
+    line_xform<M1, M2, 1, XP, !PERWAVE>(lds + line * PITCH, tt, a.ty.tw);
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-        const int e = 4 * ((int)threadIdx.x + NT * j);
+        const int e = 4 * vidx(j);
         const int y = e / P, t = e - y * P;
-        reinterpret_cast<float4*>(base)[threadIdx.x + NT * j] =
+        reinterpret_cast<float4*>(base)[vidx(j)] =
             make_float4(lds[t * PITCH + y], lds[(t + 1) * PITCH + y], lds[(t + 2) * PITCH + y],
                         lds[(t + 3) * PITCH + y]);
     }
