@@ -107,6 +107,13 @@ __device__ __forceinline__ fvec<NX> ld_v(const float* p) {
     return *reinterpret_cast<const fvec<NX>*>(p);
 }
 
+// Non-temporal vector load, for a field the kernel reads once at the node
+// and no other wavefront reads in this kernel.
+template <int NX>
+__device__ __forceinline__ fvec<NX> ld_ntv(const float* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const fvec<NX>*>(p));
+}
+
 template <int NX, bool NT>
 __device__ __forceinline__ void st_v(float* p, fvec<NX> v) {
     if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<fvec<NX>*>(p));
@@ -322,13 +329,13 @@ __global__ void __launch_bounds__(256) k_div_vec(StepArgs s) {
         V BC[C], Qc[C], acv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            BC[c] = ld_v<NX>(s.bb[2] + i0 + (long long)c * g.plane);
+            BC[c] = ld_ntv<NX>(s.bb[2] + i0 + (long long)c * g.plane);
             if constexpr (Q) Qc[c] = ld_v<NX>(s.Phi + i0 + (long long)c * g.plane);
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int cm_ = c == 0 ? C - 1 : c - 1;
-            const V MC = ld_v<NX>(s.Mc + i0 + (long long)c * g.plane);
+            const V MC = ld_ntv<NX>(s.Mc + i0 + (long long)c * g.plane);
 #pragma unroll
             for (int e = 0; e < NX; ++e) {
                 float v = MC[e] - ts * (BC[cm_][e] + BC[c][e]);
@@ -340,10 +347,10 @@ __global__ void __launch_bounds__(256) k_div_vec(StepArgs s) {
         for (int c = 0; c < C; ++c) {
             const long long i = i0 + (long long)c * g.plane;
             const long long fi = f00 + (long long)c * g.plane;
-            const V X0 = ld_v<NX>(s.Mx + i);
+            const V X0 = ld_ntv<NX>(s.Mx + i);
             const V Y0 = ld_v<NX>(s.My + i), Y1 = ld_v<NX>(s.My + i + dyp);
             const V T0 = ld_v<NX>(s.F + fi), T1 = ld_v<NX>(s.F + fi + sl);
-            const V BXc = ld_v<NX>(s.bb[0] + i);
+            const V BXc = ld_ntv<NX>(s.bb[0] + i);
             const V BYm = ld_v<NX>(s.bb[1] + i + dym), BYc = ld_v<NX>(s.bb[1] + i);
             const V BYp = ld_v<NX>(s.bb[1] + i + dyp);
             const V BTm = ld_v<NX>(s.bb[3] + i + dtm), BTc = ld_v<NX>(s.bb[3] + i);
