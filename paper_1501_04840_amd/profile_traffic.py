@@ -11,7 +11,9 @@ runs 70 iterations of the 256 x 256 x 3 x 32 workload (past the refined
 start of the default projection mode, so the steady-state kernels are
 counted) and then a plain
 elementwise copy of known size (256 MiB read, 256 MiB written), whose
-counter values calibrate the solver kernels' readings.  ``summarise`` turns
+counter values calibrate the solver kernels' readings, and an add of two
+such arrays, whose calibrated reading checks the scales on a kernel with
+two read streams.  ``summarise`` turns
 the two counter CSVs into bytes per launch per kernel.
 """
 from __future__ import annotations
@@ -41,12 +43,22 @@ def run(iters: int = 70, size=(256, 256, 3, 32)):
     prob.init(otdyn.OT_INIT_COLD)
     prob.step(iters)
     torch.cuda.synchronize()
+    _calibration_kernels(torch)
+    prob.close()
+    print("profile_traffic: done", flush=True)
+
+
+def _calibration_kernels(torch):
+    """The copy that calibrates the counters (COPY_ELEMS floats read and
+    written), then an add of two such arrays into a third, whose calibrated
+    reading is checked against its own known bytes (two read streams, one
+    write stream)."""
     src = torch.rand(COPY_ELEMS, device="cuda:0")
     dst = torch.empty_like(src)
     torch.mul(src, 1.0, out=dst)
+    src2 = torch.rand(COPY_ELEMS, device="cuda:0")
+    torch.add(src, src2, out=dst)
     torch.cuda.synchronize()
-    prob.close()
-    print("profile_traffic: done", flush=True)
 
 
 def _sources_hash() -> str:
@@ -78,10 +90,7 @@ def run_hue(H: int = 2160, W: int = 3840, n: int = 360, frames: int = 33, calls:
     for _ in range(calls):
         othue.ot_hue_render(r.h, tg, frames, out)
     torch.cuda.synchronize()
-    src = torch.rand(COPY_ELEMS, device="cuda:0")
-    dst = torch.empty_like(src)
-    torch.mul(src, 1.0, out=dst)
-    torch.cuda.synchronize()
+    _calibration_kernels(torch)
     r.close()
     print("profile_traffic hue: done", flush=True)
 
@@ -126,6 +135,14 @@ def summarise(fetch_dir: str, write_dir: str, out_json: str, out_md: str, cmd: s
     # counters are in KiB per dispatch; scale so the copy reads and writes nbytes
     f_scale = nbytes / (max(fetch[ck]) * 1024.0)
     w_scale = nbytes / (max(write[ck]) * 1024.0)
+    check = None
+    add = [k for k in fetch if "add" in k.lower() and ("Functor" in k or "functor" in k)
+           and k != ck]
+    if add and add[0] in write:
+        ak = add[0]
+        check = {"kernel": ak, "fetch_expected": 2 * nbytes, "write_expected": nbytes,
+                 "fetch_calibrated": max(fetch[ak]) * 1024.0 * f_scale,
+                 "write_calibrated": max(write[ak]) * 1024.0 * w_scale}
     kernels = {}
     hue = workload == "hue"
     for k in fetch:
@@ -141,14 +158,21 @@ def summarise(fetch_dir: str, write_dir: str, out_json: str, out_md: str, cmd: s
     res = {"sources": hue_sources_hash() if hue else _sources_hash(),
            "workload": "hue_render_3840x2160_360" if hue else "rgb_256x256x3x32",
            "calibration": {"kernel": ck, "bytes_each_way": nbytes,
-                           "fetch_scale": f_scale, "write_scale": w_scale},
+                           "fetch_scale": f_scale, "write_scale": w_scale,
+                           "check": check},
            "kernels": kernels}
     with open(out_json, "w") as fh:
         json.dump(res, fh, indent=1)
     lines = [f"# HBM traffic per launch: {title}", "",
              "Commands (repository root, one MI355X):", "", f"    {cmd}", "",
              f"Calibration: `{ck}` copies {nbytes} B each way; FETCH_SIZE scale "
-             f"{f_scale:.4f}, WRITE_SIZE scale {w_scale:.4f}.", "",
+             f"{f_scale:.4f}, WRITE_SIZE scale {w_scale:.4f}."]
+    if check:
+        lines[-1] += (f" Check: `{check['kernel']}` (reads {2 * nbytes} B, writes {nbytes} B) "
+                      f"reads {check['fetch_calibrated'] / check['fetch_expected']:.4f} and "
+                      f"writes {check['write_calibrated'] / check['write_expected']:.4f} of its "
+                      "bytes under the same scales.")
+    lines += ["",
              "| kernel | fetch MB | write MB | total MB / launch |", "|---|---|---|---|"]
     for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["bytes_per_launch"]):
         lines.append(f"| `{k}` | {v['fetch_bytes'] / 1e6:.1f} | {v['write_bytes'] / 1e6:.1f} | "

@@ -357,9 +357,14 @@ def test_trained_network_gains_over_the_coarse_start(N):
     held-out 64 x 64 x 3 x 16 pairs: its correction brings the prolonged
     coarse solution closer to the certified solution, and the warm-started
     solves certify.  Prints the iterations to the certified tolerance from
-    the cold, coarse and network starts (the gain in iterations is small:
-    the iteration removes smooth relative errors quickly and sharp-feature
-    errors slowly, and the network's error is of the second kind)."""
+    the cold, coarse and network starts, and checks the network's start
+    saves iterations over the cold one: fewer in total, and for no pair more
+    than two residual checks (200 iterations) beyond cold, room for
+    rounding-order changes of the kernels (the training record's 64 held-out
+    pairs: none above cold, -2.4% on average).  The gain is small: the
+    iteration removes smooth relative errors quickly and sharp-feature errors
+    slowly, and the network's error is of the second kind; it does not cover
+    the coarse solve and the inference in wall time."""
     import json
     import torch
     from paper_1501_04840_amd import otnet
@@ -378,3 +383,6 @@ def test_trained_network_gains_over_the_coarse_start(N):
         assert err["warm_" + g] < 0.9 * err["coarse_" + g], (g, err)
     assert res["warm"]["certified"] == len(pairs)
     assert res["cold"]["certified"] == len(pairs)
+    cold, warm = res["cold"]["iterations"], res["warm"]["iterations"]
+    assert sum(warm) < sum(cold), (cold, warm)
+    assert all(w <= c + 200 for c, w in zip(cold, warm)), (cold, warm)
