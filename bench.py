@@ -270,7 +270,7 @@ def hue_batch(args):
     }
     if cpu:
         out["cpu_baseline"] = cpu
-    print(json.dumps(out))
+    return out
 
 
 def hue_cpu_baseline(probs, idx, args, iters: int = 600):
@@ -401,7 +401,29 @@ def hue_render(args):
                                     "kind": "oracle", "host": host_cpu(),
                                     "sample": f"{sample} frames of the same {W}x{H} image "
                                               "(source preparation not timed)"}
-    print(json.dumps(out_json))
+    return out_json
+
+
+def side_workloads(args) -> dict:
+    """Short runs of the two other GPU workloads after the main line's timed
+    region (default parameters otherwise): the 1024 batched hue problems to
+    the certified tolerance (one looped problem for the looped rate) and 20
+    calls of the 4K hue rendering.  Only their GPU figures, no CPU oracle."""
+    import argparse as _ap
+    hb = hue_batch(_ap.Namespace(**{**vars(args), "hue_loop_sample": 1, "no_cpu": True}))
+    hr = hue_render(_ap.Namespace(**{**vars(args), "steps": 20, "warmup": 3, "no_cpu": True}))
+    c = hb["config"]
+    return {
+        "hue_batch": {"metric": hb["metric"], "value": hb["value"], "unit": hb["unit"],
+                      "certified": c["certified"], "count": args.hue_count,
+                      "iters_median": c["iters_median"], "iters_max": c["iters_max"],
+                      "cell_iters_per_s": c["cell_iters_per_s"], "autotune_s": c["autotune_s"],
+                      "looped_s_per_problem": hb["looped_plain_solver"]["s_per_problem"],
+                      "looped_sample": hb["looped_plain_solver"]["sample"]},
+        "hue_render": {"metric": hr["metric"], "value": hr["value"], "unit": hr["unit"],
+                       "ms_per_call": hr["ms_per_step"], "source_prep_s": hr["config"]["source_prep_s"],
+                       "roofline": hr["roofline"]},
+    }
 
 
 def main():
@@ -433,6 +455,8 @@ def main():
                     metavar=("X", "Y", "C", "P"))
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-side", action="store_true",
+                    help="rgb: skip the short hue batch and hue rendering runs after the timed region")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver has no "
@@ -447,13 +471,13 @@ def main():
         from paper_1501_04840_amd import build
         build.build()
     if args.workload == "hue_batch":
-        hue_batch(args)
+        print(json.dumps(hue_batch(args)))
         return
     if args.workload == "warm":
         warm_start(args)
         return
     if args.workload == "hue_render":
-        hue_render(args)
+        print(json.dumps(hue_render(args)))
         return
     X, Y, C, P = args.size
     if (X, Y) == (256, 256):
@@ -558,6 +582,8 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f0, f1, X, Y, C, P, args.cpu_iters)
+    if not args.no_side:
+        out["side_workloads"] = side_workloads(args)
     print(json.dumps(out))
 
 
