@@ -583,7 +583,10 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f0, f1, X, Y, C, P, args.cpu_iters)
     if not args.no_side:
-        out["side_workloads"] = side_workloads(args)
+        try:
+            out["side_workloads"] = side_workloads(args)
+        except Exception as e:          # the main line is printed whatever they do
+            out["side_workloads"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(out))
 
 
